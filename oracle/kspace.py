@@ -1,0 +1,314 @@
+"""FP64 CPU oracle of the periodic DMET lattice-to-embedding transformation.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this module.  It shares no code with the HIP
+library: it is a plain, slow, literal numpy transcription of the paper's
+equations, in the paper's order and notation (Cui, Zhu & Chan, "Efficient
+implementation of ab initio quantum embedding in periodic systems: density
+matrix embedding theory", Sec. 2.1):
+
+* Eq. ``bath R SVD``   : gamma^{R!=0,0} = B^{R!=0} Lambda V^{0 dagger}
+* Eq. ``C loemb R``    : C^{R,LO,EO} = [[1, 0], [0, B^{R!=0}]]
+* Eq. ``C loemb k``    : C^{k,LO,EO} = sum_R exp(-i k.R) C^{R,LO,EO};
+                         C^{k,AO,EO} = C^{k,AO,LO} C^{k,LO,EO}
+* Eq. ``fock transform``: F^{0,EO} = 1/N_k sum_k C^{k dagger} F^k C^k
+* Alg. 1 (GDF embedding ERI): k-AO -> k-EO transform of (L|mu k_mu, nu k_nu),
+  Fourier sum to the reference cell with 1/N_k, contraction with 1/N_k.
+
+Readings of points the paper leaves open (k ordering, Fourier sign of gamma,
+normalisation of the 3-index tensor, which index of (0i0j|L) is conjugated,
+the bath sign gauge) are the ones listed in the design notes; they are the
+unique choices for which Alg. 1 equals the real-space supercell transform of
+``oracle.supercell``, which pins them.
+
+Array conventions: complex arrays are numpy complex128, row-major; k and R
+are flattened row-major over the mesh; lmunu[q][k][L][mu][nu] = (L|mu k, nu k-q).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+# --------------------------------------------------------------------------
+# k-mesh bookkeeping (Gamma-centred mesh, Sec. 2.2)
+# --------------------------------------------------------------------------
+def mesh_points(kmesh):
+    """Integer coordinates (n1, n2, n3) of the mesh points, row-major."""
+    pts = []
+    for a in range(kmesh[0]):
+        for b in range(kmesh[1]):
+            for c in range(kmesh[2]):
+                pts.append((a, b, c))
+    return np.array(pts, dtype=np.int64)
+
+
+def mesh_index(kmesh, n):
+    """Row-major index of integer point n, wrapped per axis."""
+    a, b, c = (int(n[0]) % kmesh[0], int(n[1]) % kmesh[1], int(n[2]) % kmesh[2])
+    return (a * kmesh[1] + b) * kmesh[2] + c
+
+
+def phase_matrix(kmesh):
+    """P[k, R] = exp(i k.R) = exp(2 pi i sum_d n_d m_d / N_d)."""
+    pts = mesh_points(kmesh)
+    nk = len(pts)
+    p = np.empty((nk, nk), dtype=np.complex128)
+    for ik in range(nk):
+        for ir in range(nk):
+            x = sum(pts[ik][d] * pts[ir][d] / kmesh[d] for d in range(3))
+            p[ik, ir] = np.exp(2j * np.pi * x)
+    return p
+
+
+# --------------------------------------------------------------------------
+# Step a1: real-space density matrix gamma^{R,0} (Eq. bath R SVD, left side)
+# --------------------------------------------------------------------------
+def real_space_dm(dm_k, kmesh):
+    """gamma^{R,0} = 1/N_k sum_k exp(+i k.R) gamma(k)   (per spin).
+
+    dm_k: [nspin][N_k][nao][nao] complex.  Returns (real [nspin][N_k R][nao][nao],
+    max |Im|).  The imaginary part vanishes for time-reversal-symmetric input.
+    """
+    nk = dm_k.shape[1]
+    p = phase_matrix(kmesh)
+    g = np.einsum("kR,skij->sRij", p, dm_k) / nk
+    return g.real.copy(), float(np.abs(g.imag).max())
+
+
+def supercell_block(dm_r, kmesh, nao, rows, cols):
+    """gamma_sup[(R,mu),(R',nu)] = gamma^{R-R',0}_{mu nu} for the listed
+    supercell orbitals (index = cell*nao + mu), by translation invariance."""
+    pts = mesh_points(kmesh)
+    out = np.empty((len(rows), len(cols)))
+    for a, r in enumerate(rows):
+        cr, mu = divmod(int(r), nao)
+        for b, c in enumerate(cols):
+            cc, nu = divmod(int(c), nao)
+            d = mesh_index(kmesh, pts[cr] - pts[cc])
+            out[a, b] = dm_r[d, mu, nu]
+    return out
+
+
+# --------------------------------------------------------------------------
+# Step a2: bath orbitals from the SVD of the impurity-environment block
+# --------------------------------------------------------------------------
+def sign_fix(u):
+    """Gauge of each singular vector: the entry of largest modulus is made
+    positive (ties within 1e-12 of the maximum: lowest index wins)."""
+    u = u.copy()
+    for j in range(u.shape[1]):
+        a = np.abs(u[:, j])
+        m = a.max()
+        i = int(np.nonzero(a >= m - 1e-12 * m)[0][0])
+        if u[i, j] < 0:
+            u[:, j] = -u[:, j]
+    return u
+
+
+def bath_orbitals(dm_r, kmesh, nao, imp_idx=None, val_idx=None, sv_tol=0.0):
+    """Eq. ``bath R SVD`` for one spin.
+
+    Rows of M are every supercell orbital outside the impurity, in supercell
+    order (for a cell-0 impurity: R != 0, then mu); columns are the impurity
+    valence LOs ``imp_idx[val_idx]`` (valence-only SVD, Sec. 2.1 "DMET bath and
+    truncation").  Returns (env_rows, B [n_env][n_bath], sigma [n_val]).
+    Singular values are sorted descending; vectors with sigma <= sv_tol are
+    dropped (sv_tol = 0 keeps all n_val).
+    """
+    nk = int(np.prod(kmesh))
+    nsup = nk * nao
+    imp = np.arange(nao) if imp_idx is None else np.asarray(imp_idx)
+    val = np.arange(len(imp)) if val_idx is None else np.asarray(val_idx)
+    imp_set = set(int(i) for i in imp)
+    env = np.array([r for r in range(nsup) if r not in imp_set], dtype=np.int64)
+    m = supercell_block(dm_r, kmesh, nao, env, imp[val])
+    u, s, _vt = np.linalg.svd(m, full_matrices=False)
+    order = np.argsort(-s, kind="stable")
+    s = s[order]
+    u = u[:, order]
+    nb = int(np.count_nonzero(s > sv_tol)) if sv_tol > 0 else len(s)
+    b = sign_fix(u[:, :nb])
+    return env, b, s
+
+
+# --------------------------------------------------------------------------
+# Step a3: embedding coefficients (Eqs. C loemb R, C loemb k)
+# --------------------------------------------------------------------------
+def emb_coeffs_real(env, b, kmesh, nao, imp_idx=None):
+    """C^{R,LO,EO} [N_k R][nao][neo]: impurity columns are unit vectors on the
+    impurity LOs (the identity block), bath columns carry B on the
+    environment rows (Eq. ``C loemb R``)."""
+    nk = int(np.prod(kmesh))
+    imp = np.arange(nao) if imp_idx is None else np.asarray(imp_idx)
+    nimp, nb = len(imp), b.shape[1]
+    c = np.zeros((nk * nao, nimp + nb))
+    for i, r in enumerate(imp):
+        c[int(r), i] = 1.0
+    c[env, nimp:] = b
+    return c.reshape(nk, nao, nimp + nb)
+
+
+def lowdin(c_r):
+    """Loewdin orthonormalisation C <- C S^{-1/2}, S = sum_R C^{R T} C^R."""
+    s = np.einsum("Rmi,Rmj->ij", c_r, c_r)
+    w, v = np.linalg.eigh(s)
+    return np.einsum("Rmi,ij->Rmj", c_r, (v / np.sqrt(w)) @ v.T)
+
+
+def emb_coeffs_k(c_r, kmesh, c_ao_lo=None):
+    """C^k = sum_R exp(-i k.R) C^R, then C^{k,AO,EO} = C^{k,AO,LO} C^{k,LO,EO}."""
+    p = phase_matrix(kmesh)
+    ck = np.einsum("kR,Rmi->kmi", p.conj(), c_r.astype(np.complex128))
+    if c_ao_lo is not None:
+        ck = np.einsum("kmn,kni->kmi", c_ao_lo, ck)
+    return ck
+
+
+def build_bath(dm_k, kmesh, nao, imp_idx=None, val_idx=None, sv_tol=0.0, c_ao_lo=None):
+    """Steps a1-a3 for every spin.  Returns dict with c_k [nspin][N_k][nao][neo],
+    c_r, sigma [nspin][n_val], dm_r, neo list and the max |Im gamma^{R,0}|."""
+    dm_r, im = real_space_dm(dm_k, kmesh)
+    out = {"c_k": [], "c_r": [], "sigma": [], "neo": [], "dm_r": dm_r, "max_imag_dm": im}
+    for s in range(dm_k.shape[0]):
+        env, b, sig = bath_orbitals(dm_r[s], kmesh, nao, imp_idx, val_idx, sv_tol)
+        c_r = lowdin(emb_coeffs_real(env, b, kmesh, nao, imp_idx))
+        out["c_r"].append(c_r)
+        out["c_k"].append(emb_coeffs_k(c_r, kmesh, c_ao_lo))
+        out["sigma"].append(sig)
+        out["neo"].append(c_r.shape[2])
+    if len(set(out["neo"])) == 1:
+        out["c_k"] = np.array(out["c_k"])
+        out["c_r"] = np.array(out["c_r"])
+    out["sigma"] = np.array(out["sigma"])
+    return out
+
+
+# --------------------------------------------------------------------------
+# Step a4: one-body transform (Eq. fock transform) and E1
+# --------------------------------------------------------------------------
+def transform_1e(c_k, op_k):
+    """X^{0,EO} = 1/N_k sum_k C^{k dagger} X^k C^k, per spin.
+
+    Returns (real [nspin][neo][neo], max |Im|)."""
+    nk = c_k.shape[1]
+    x = 0
+    for k in range(nk):
+        x = x + c_k[:, k].conj().transpose(0, 2, 1) @ op_k[:, k] @ c_k[:, k]
+    x = x / nk
+    return x.real.copy(), float(np.abs(x.imag).max())
+
+
+def energy_1e(h_eo, dm_eo):
+    """E1 = sum_spin sum_ij h_ij gamma_ji (per-spin density matrices)."""
+    return float(np.einsum("sij,sji->", h_eo, dm_eo))
+
+
+# --------------------------------------------------------------------------
+# Steps a5-a7: Alg. 1, embedding ERIs from the k-point GDF 3-index tensor
+# --------------------------------------------------------------------------
+def alg1_embedded_3index(lmunu, c_k, kmesh, q):
+    """Alg. 1 inner loop for one fitting momentum q:
+
+        (L|0i 0j) = 1/N_k sum_k [C^{k dagger} (L|k, k-q) C^{k-q}]_{ij}
+
+    i.e. transform the 3-index to the k-EO basis with C^{k,AO,EO} and Fourier
+    sum to the reference cell.  Returns X [L][neo][neo] complex."""
+    nk = lmunu.shape[0]
+    pts = mesh_points(kmesh)
+    x = 0
+    for k in range(nk):
+        kmq = mesh_index(kmesh, pts[k] - pts[q])
+        t = lmunu[q, k] @ c_k[kmq]                      # k-AO -> k-EO, right index
+        x = x + (c_k[k].conj().T @ t) / nk              # left index, FT to R = 0
+    return x
+
+
+def alg1_eri(lmunu, c_k_a, kmesh, c_k_b=None):
+    """Embedding ERI (ij|kl) by Alg. 1:
+
+        (ij|kl) += 1/N_k sum_L (0i 0j|L)(L|0k 0l)   for every q,
+
+    with (0i 0j|L) = conj((L|0i 0j)).  With a second spin's C^k the mixed
+    (alpha alpha|beta beta) block is returned.  Returns (real [n][n][n][n],
+    max |Im|)."""
+    nk = lmunu.shape[0]
+    eri = 0
+    for q in range(nk):
+        xa = alg1_embedded_3index(lmunu, c_k_a, kmesh, q)
+        xb = xa if c_k_b is None else alg1_embedded_3index(lmunu, c_k_b, kmesh, q)
+        naux, n = xa.shape[0], xa.shape[1]
+        m = xb.shape[1]
+        eri = eri + (xa.reshape(naux, n * n).conj().T @ xb.reshape(naux, m * m)) / nk
+    n = c_k_a.shape[2]
+    m = n if c_k_b is None else c_k_b.shape[2]
+    eri = eri.reshape(n, n, m, m)
+    return eri.real.copy(), float(np.abs(eri.imag).max())
+
+
+def alg1_eri_columns(lmunu, c_k_a, kmesh, pairs_a, c_k_b=None, pairs_b=None):
+    """The same contraction restricted to listed pairs: returns
+    E[p, r] = (i_p j_p | k_r l_r) for p in pairs_a, r in pairs_b.
+
+    Needed at sizes where the full 4-index tensor does not fit; the embedded
+    3-index is only formed for the pair columns that are asked for."""
+    nk = lmunu.shape[0]
+    pts = mesh_points(kmesh)
+    c_k_b = c_k_a if c_k_b is None else c_k_b
+    pairs_b = pairs_a if pairs_b is None else pairs_b
+    ia, ja = np.array([p[0] for p in pairs_a]), np.array([p[1] for p in pairs_a])
+    ib, jb = np.array([p[0] for p in pairs_b]), np.array([p[1] for p in pairs_b])
+    out = 0
+    for q in range(nk):
+        xa = 0
+        xb = 0
+        for k in range(nk):
+            kmq = mesh_index(kmesh, pts[k] - pts[q])
+            a = lmunu[q, k]
+            ta = a @ c_k_a[kmq][:, ja]                                   # [L][m][p]
+            xa = xa + (c_k_a[k][:, ia].conj()[None] * ta).sum(axis=1) / nk
+            tb = a @ c_k_b[kmq][:, jb]
+            xb = xb + (c_k_b[k][:, ib].conj()[None] * tb).sum(axis=1) / nk
+        out = out + (xa.conj().T @ xb) / nk
+    return out.real.copy(), float(np.abs(out.imag).max())
+
+
+# --------------------------------------------------------------------------
+# Output packing (8-fold / 4-fold symmetric storage)
+# --------------------------------------------------------------------------
+def pair_index(i, j):
+    """Packed pair index of (i, j), i >= j: i(i+1)/2 + j."""
+    if i < j:
+        i, j = j, i
+    return i * (i + 1) // 2 + j
+
+
+def pack_s8(eri):
+    """Packed lower triangle over pairs: eri8[IJ(IJ+1)/2 + KL], IJ >= KL."""
+    n = eri.shape[0]
+    npair = n * (n + 1) // 2
+    tri = np.tril_indices(n)
+    mat = eri[tri[0], tri[1]][:, tri[0], tri[1]]          # [npair][npair]
+    assert mat.shape == (npair, npair)
+    r, c = np.tril_indices(npair)
+    return mat[r, c].copy()
+
+
+def pack_s4(eri):
+    """[ij][kl] over pairs i >= j, k >= l (mixed-spin block)."""
+    n = eri.shape[0]
+    tri = np.tril_indices(n)
+    return eri[tri[0], tri[1]][:, tri[0], tri[1]].copy()
+
+
+def unpack_s8(eri8, n):
+    """Full [n][n][n][n] tensor from the packed s8 vector."""
+    npair = n * (n + 1) // 2
+    mat = np.zeros((npair, npair))
+    r, c = np.tril_indices(npair)
+    mat[r, c] = eri8
+    mat[c, r] = eri8
+    tri = np.tril_indices(n)
+    pidx = np.zeros((n, n), dtype=np.int64)
+    pidx[tri[0], tri[1]] = np.arange(npair)
+    pidx[tri[1], tri[0]] = np.arange(npair)
+    return mat[pidx][:, :, pidx]

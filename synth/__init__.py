@@ -1,0 +1,277 @@
+"""Seeded synthetic inputs for the periodic DMET embedding transform.
+
+This module is shared by the FP64 CPU oracle (``oracle/``), the tests and the
+benchmark.  It holds none of the embedding method's arithmetic (no bath, no
+embedding-orbital construction, no integral transformation): it only draws
+random real-space lattice quantities and hands them over in the k-space form
+that the embedding transform consumes.
+
+Stand-ins.  The paper computes its inputs with PySCF (Gaussian density fitting
+of GTH-DZVP crystal AOs, Sec. 2.2).  None of that is available here, so every
+workload is synthetic, with the paper's shapes: a Gamma-centred k-mesh
+(Sec. 2.2), nao crystal AOs per cell, an auxiliary basis about ten times the AO
+count (Sec. 2.2) and up to ~300 embedding orbitals (the BN example after
+Alg. 1).
+
+Conventions (the paper fixes only the sign of the LO->EO Fourier transform,
+Eq. ``C loemb k``; the rest is this project's reading, chosen so that
+Alg. 1 reproduces the real-space supercell transform exactly):
+
+* k-mesh: Gamma-centred, N_k = N1*N2*N3 points, k index (n1*N2 + n2)*N3 + n3;
+  cells R indexed the same way over the Born-von Karman (BvK) supercell;
+  exp(i k.R) = exp(2 pi i sum_d n_d m_d / N_d).
+* one-body: t_{mu nu}(R) = <mu,0|h|nu,R> (real, t(-R) = t(R)^T) and
+  h(k) = sum_R exp(+i k.R) t(R).
+* 3-index: (L|mu k1, nu k2) = sum_{R1,R2} exp(-i k1.R1) exp(+i k2.R2)
+  B_L(mu R1, nu R2), with the fitting function L in cell 0, B real and
+  symmetric under (mu R1) <-> (nu R2), so that the lattice 4-index integral is
+  sum_{L,R_L} B_L(..-R_L) B_L(..-R_L) (Eq. ``density fitting``).  It is stored
+  as lmunu[q][k][L][mu][nu] = (L| mu k, nu k-q), the momentum transfer of the
+  fitting function being q = k_mu - k_nu (Sec. 2.1, text before Alg. 1).
+"""
+from __future__ import annotations
+
+import math
+import os
+from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+__all__ = [
+    "Workload", "CONFIGS", "cells", "min_image_length", "kq_index",
+    "make_lattice", "three_index", "three_index_block", "Lattice",
+]
+
+
+@dataclass(frozen=True)
+class Workload:
+    """Shape of one synthetic workload (all sizes per unit cell)."""
+    name: str
+    kmesh: tuple
+    nao: int
+    naux: int
+    nimp: int
+    nval: int
+    nspin: int
+    xi: float            # decay length of hopping and 3-index, in cells
+    seed: int
+    dtype: str = "c128"  # storage type of the 3-index tensor
+
+    @property
+    def nk(self) -> int:
+        return int(np.prod(self.kmesh))
+
+    @property
+    def neo(self) -> int:
+        return self.nimp + self.nval
+
+    @property
+    def npair(self) -> int:
+        return self.neo * (self.neo + 1) // 2
+
+
+# Shapes of the paper's three solids (Sec. 2.2 / Sec. 3): a 2D h-BN monolayer
+# with 26 AOs per cell (GTH-DZVP, B and N), a Si crystal with 2x26 AOs and an
+# AFM NiO rhombohedral cell with two formula units, spin unrestricted.  The
+# auxiliary size is about 8-10x nao (Sec. 2.2).  Impurity = all LOs of cell 0,
+# bath = one SVD column per impurity LO, so neo = 2 nao.
+CONFIGS = {
+    "tiny": Workload("tiny", (2, 2, 1), 8, 40, 8, 8, 1, 1.5, 1000),
+    "hbn": Workload("hbn", (4, 4, 1), 26, 200, 26, 26, 1, 2.0, 1001),
+    "si": Workload("si", (3, 3, 3), 52, 400, 52, 52, 1, 2.0, 1002),
+    "nio": Workload("nio", (2, 2, 2), 150, 1200, 150, 150, 2, 2.0, 1003),
+}
+
+
+def cells(kmesh) -> np.ndarray:
+    """Integer coordinates (row-major) of the N_k cells / k-points, [N_k][3]."""
+    n1, n2, n3 = kmesh
+    g = np.indices((n1, n2, n3)).reshape(3, -1).T
+    return g.astype(np.int64)
+
+
+def min_image_length(kmesh) -> np.ndarray:
+    """Minimum-image length |R| (cell units, orthonormal axes) on the BvK torus."""
+    c = cells(kmesh).astype(np.float64)
+    n = np.asarray(kmesh, dtype=np.float64)
+    c = np.minimum(c, n - c)
+    return np.sqrt((c * c).sum(axis=1))
+
+
+def kq_index(kmesh) -> np.ndarray:
+    """kmq[q][k] = index of k - q, wrapped per axis modulo N_d."""
+    c = cells(kmesh)
+    n = np.asarray(kmesh)
+    nk = len(c)
+    out = np.empty((nk, nk), dtype=np.int64)
+    for iq in range(nk):
+        d = (c - c[iq]) % n
+        out[iq] = (d[:, 0] * n[1] + d[:, 1]) * n[2] + d[:, 2]
+    return out
+
+
+def neg_index(kmesh) -> np.ndarray:
+    """Index of -k (wrapped)."""
+    c = cells(kmesh)
+    n = np.asarray(kmesh)
+    d = (-c) % n
+    return (d[:, 0] * n[1] + d[:, 1]) * n[2] + d[:, 2]
+
+
+def _phase_kR(kmesh) -> np.ndarray:
+    """exp(+i k.R) as a [N_k(k)][N_k(R)] matrix (generator use only)."""
+    c = cells(kmesh)
+    n = np.asarray(kmesh)
+    nk = len(c)
+    num = np.zeros((nk, nk), dtype=np.int64)
+    for d in range(3):
+        num += np.outer(c[:, d], c[:, d]) * (nk // n[d])
+    num %= nk
+    return np.exp(2j * np.pi * num / nk)
+
+
+def _hopping(rng, kmesh, nao, xi, scale) -> np.ndarray:
+    """Real t(R) [N_k][nao][nao] with t(-R) = t(R)^T and an exp(-|R|/xi) envelope."""
+    nk = int(np.prod(kmesh))
+    env = np.exp(-min_image_length(kmesh) / xi)
+    g = rng.standard_normal((nk, nao, nao)) * scale * env[:, None, None]
+    neg = neg_index(kmesh)
+    return 0.5 * (g + g[neg].transpose(0, 2, 1))
+
+
+@dataclass
+class Lattice:
+    """One-body inputs of a workload (all FP64/complex128)."""
+    wl: Workload
+    t_h: np.ndarray          # [N_k R][nao][nao] real hopping of h
+    t_f: np.ndarray          # [nspin][N_k R][nao][nao] real Fock in real space
+    h_k: np.ndarray          # [nspin][N_k][nao][nao] complex128 (same for both spins)
+    f_k: np.ndarray          # [nspin][N_k][nao][nao] complex128
+    dm_k: np.ndarray         # [nspin][N_k][nao][nao] complex128, per-spin projector
+    mo_energy: np.ndarray    # [nspin][N_k][nao]
+    attempts: int = 1
+    extra: dict = field(default_factory=dict)
+
+
+def make_lattice(wl: Workload, spin_split: float = 0.2, v_scale: float = 0.05,
+                 hop_scale: float = 0.1, min_gap: float = 1e-4) -> Lattice:
+    """Random insulating mean-field on the k-mesh.
+
+    h(k) from a decaying random hopping t(R) (std ``hop_scale`` Ha), a Fock
+    matrix F_s(k) = h(k) + v(k) + s*Delta*diag(m) with v an independent draw
+    (std ``v_scale``) and, for nspin = 2, an antiferromagnetic staggered field
+    m = +1 on AOs [0, nao/4), -1 on [nao/4, nao/2), 0 elsewhere (the two Ni
+    sublattices of AFM NiO).  The per-spin density matrix gamma_s(k) is the
+    projector onto the lowest nao/2 bands of F_s(k); a draw whose per-k gap
+    is below ``min_gap`` is rejected and redrawn with seed + 1000*attempt.
+    """
+    nk, nao = wl.nk, wl.nao
+    ph = _phase_kR(wl.kmesh)
+    nocc = nao // 2
+    for attempt in range(20):
+        seed = wl.seed + 1000 * attempt
+        t_h = _hopping(np.random.default_rng([seed, 0]), wl.kmesh, nao, wl.xi, hop_scale)
+        t_v = _hopping(np.random.default_rng([seed, 1]), wl.kmesh, nao, wl.xi, v_scale)
+        m = np.zeros(nao)
+        m[: nao // 4] = 1.0
+        m[nao // 4: nao // 2] = -1.0
+        t_f = np.empty((wl.nspin, nk, nao, nao))
+        for s in range(wl.nspin):
+            sign = 1.0 if s == 0 else -1.0
+            t_f[s] = t_h + t_v
+            if wl.nspin == 2:
+                t_f[s, 0] += sign * spin_split * np.diag(m)
+        h_k1 = np.einsum("kR,Rij->kij", ph, t_h)
+        h_k = np.broadcast_to(h_k1, (wl.nspin, nk, nao, nao)).copy()
+        f_k = np.einsum("kR,sRij->skij", ph, t_f)
+        f_k = 0.5 * (f_k + f_k.conj().transpose(0, 1, 3, 2))
+        h_k = 0.5 * (h_k + h_k.conj().transpose(0, 1, 3, 2))
+        dm_k = np.empty_like(f_k)
+        mo_e = np.empty((wl.nspin, nk, nao))
+        ok = True
+        for s in range(wl.nspin):
+            for k in range(nk):
+                e, v = np.linalg.eigh(f_k[s, k])
+                mo_e[s, k] = e
+                if e[nocc] - e[nocc - 1] < min_gap:
+                    ok = False
+                occ = v[:, :nocc]
+                dm_k[s, k] = occ @ occ.conj().T
+        if ok:
+            return Lattice(wl, t_h, t_f, h_k, f_k, dm_k, mo_e, attempts=attempt + 1)
+    raise RuntimeError("could not draw a gapped mean-field")
+
+
+def _three_index_scale(wl: Workload) -> float:
+    """s_B such that the expected on-site (mu0 mu0|mu0 mu0) = sum_{L,R} B_L(muR,muR)^2 is 1 Ha."""
+    e4 = np.exp(-4.0 * min_image_length(wl.kmesh) / wl.xi).sum()
+    return 1.0 / math.sqrt(2.0 * wl.naux * e4)
+
+
+def three_index_block(wl: Workload, l0: int, l1: int, real_space: bool = False):
+    """3-index quantities for auxiliary functions L in [l0, l1).
+
+    Returns ``(kspace, B)`` where kspace has shape [L][N_k k1][nao][N_k k2][nao]
+    (complex128, (L|mu k1, nu k2)) and B (only if ``real_space``) has shape
+    [L][N_k R1][nao][N_k R2][nao] (real).  Each L draws from its own stream
+    default_rng([seed, 100, L]), so any block can be produced independently.
+    """
+    n1, n2, n3 = wl.kmesh
+    nk, nao = wl.nk, wl.nao
+    env = np.exp(-min_image_length(wl.kmesh) / wl.xi).reshape(n1, n2, n3)
+    sb = _three_index_scale(wl)
+    envb = (env[:, :, :, None, None, None, None, None]
+            * env[None, None, None, None, :, :, :, None])
+    nl = l1 - l0
+    ks = np.empty((nl, nk, nao, nk, nao), dtype=np.complex128)
+    bs = np.empty((nl, nk, nao, nk, nao)) if real_space else None
+    for i, L in enumerate(range(l0, l1)):
+        g = np.random.default_rng([wl.seed, 100, L]).standard_normal(
+            (n1, n2, n3, nao, n1, n2, n3, nao))
+        b = (g + g.transpose(4, 5, 6, 7, 0, 1, 2, 3)) * (sb / math.sqrt(2.0))
+        b *= envb
+        if real_space:
+            bs[i] = b.reshape(nk, nao, nk, nao)
+        # sum_R1 exp(-i k1.R1): forward DFT; sum_R2 exp(+i k2.R2): N_k * inverse DFT
+        a = np.fft.fftn(b, axes=(0, 1, 2))
+        a = np.fft.ifftn(a, axes=(4, 5, 6)) * nk
+        ks[i] = a.reshape(nk, nao, nk, nao)
+    return ks, bs
+
+
+def three_index(wl: Workload, real_space: bool = False, dtype=np.complex128,
+                threads: Optional[int] = None, out: Optional[np.ndarray] = None):
+    """Full lmunu[q][k][L][mu][nu] = (L|mu k, nu k-q) tensor (and optionally B).
+
+    Built in auxiliary blocks on a thread pool; ``out`` may be a preallocated
+    (e.g. pinned) array of the right shape and dtype.
+    """
+    nk, nao, naux = wl.nk, wl.nao, wl.naux
+    kmq = kq_index(wl.kmesh)
+    if out is None:
+        out = np.empty((nk, nk, naux, nao, nao), dtype=dtype)
+    bfull = np.empty((naux, nk, nao, nk, nao)) if real_space else None
+    blk = max(1, min(32, naux // 8))
+    starts = list(range(0, naux, blk))
+
+    def work(l0):
+        l1 = min(naux, l0 + blk)
+        ks, bs = three_index_block(wl, l0, l1, real_space)
+        for q in range(nk):
+            for k in range(nk):
+                out[q, k, l0:l1] = ks[:, k, :, kmq[q, k], :]
+        if real_space:
+            bfull[l0:l1] = bs
+
+    nthr = threads or min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(nthr) as ex:
+        list(ex.map(work, starts))
+    return (out, bfull) if real_space else out
+
+
+def random_orthonormal(rng, n, m) -> np.ndarray:
+    """n x m real matrix with orthonormal columns (QR of a Gaussian draw)."""
+    q, r = np.linalg.qr(rng.standard_normal((n, m)))
+    return q * np.sign(np.diag(r))[None, :]
