@@ -1,0 +1,187 @@
+/*
+ * dmet.h -- C ABI of the MI355X periodic-DMET embedding library (libdmet.so).
+ *
+ * The library computes the lattice-to-embedding integral transformation of
+ * periodic ab initio density matrix embedding theory (Cui, Zhu & Chan,
+ * "Efficient implementation of ab initio quantum embedding in periodic
+ * systems: density matrix embedding theory", Sec. 2.1):
+ *
+ *   dmet_build_bath      Eq. "bath R SVD", Eq. "C loemb R", Eq. "C loemb k"
+ *   dmet_transform_1e    Eq. "fock transform"
+ *   dmet_energy_1e       one-body energy of the embedding Hamiltonian, Eq. "emb Ham"
+ *   dmet_transform_eri   Alg. 1 (GDF embedding ERI), Eq. "density fitting"
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * k-mesh   Gamma-centred, N_k = kmesh[0]*kmesh[1]*kmesh[2]; k (and cell R)
+ *          index (n1*N2 + n2)*N3 + n3; exp(i k.R) = exp(2 pi i sum_d n_d m_d/N_d);
+ *          k - q wraps per axis modulo N_d.
+ * complex  interleaved (re, im) pairs, as torch.complex128 / complex64.
+ * layout   every array is row-major, last index fastest.
+ * density  dm_k is per spin (occupations <= 1); a restricted caller passes
+ *          gamma_total / 2 with nspin = 1.
+ * 3-index  lmunu[q][k][L][mu][nu] = (L | mu k, nu k-q), the Gaussian density
+ *          fitting tensor of the fitting function L with momentum q = k_mu - k_nu
+ *          (Sec. 2.1), normalised so that the lattice 4-index integral is
+ *          sum_L (mu k1 nu k2 | L)(L | kappa k3 lambda k4) with
+ *          (mu k1 nu k2 | L) = conj((L | nu k2 mu k1)); it must be the transform of
+ *          a real, (mu R1)<->(nu R2)-symmetric real-space tensor (time-reversal
+ *          symmetric input), which makes the embedding ERIs real and 8-fold
+ *          symmetric.
+ * packing  pair index ij = i(i+1)/2 + j (i >= j), npair = neo(neo+1)/2;
+ *          s8: eri8[IJ(IJ+1)/2 + KL] for IJ >= KL (same-spin blocks);
+ *          s4: eri4[IJ*npair + KL] (mixed alpha-beta block, alpha pair first).
+ *
+ * Ownership: every array argument is a caller-owned DEVICE pointer unless its
+ * comment says "host".  The library never allocates device memory in these
+ * calls: scratch comes from the caller's workspace (size from the matching
+ * *_workspace query, 256-byte aligned).  Calls are enqueued on `stream` and are
+ * asynchronous unless stated otherwise.
+ *
+ * Errors: arguments are validated on the host before anything is enqueued; a
+ * non-DMET_OK status means nothing (or nothing further) was enqueued.  The
+ * message of the last error of the calling thread is dmet_last_error().  No
+ * entry point aborts or throws across the ABI.
+ */
+#ifndef DMET_H
+#define DMET_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DMET_OK = 0,
+    DMET_E_ARG = 1,          /* invalid argument (shape, index list, null pointer) */
+    DMET_E_HIP = 2,          /* a HIP runtime call failed                           */
+    DMET_E_NOCONV = 3,       /* the Jacobi SVD did not converge                      */
+    DMET_E_RANK = 4,         /* sv_tol removed every bath orbital                    */
+    DMET_E_NONFINITE = 5,    /* NaN/Inf in an input                                  */
+    DMET_E_WORKSPACE = 6,    /* workspace missing or smaller than the query          */
+    DMET_E_UNSUPPORTED = 7   /* valid request outside what this build implements    */
+} dmet_status;
+
+typedef enum {
+    DMET_FP64 = 0,           /* complex GEMMs as 4 real FP64 MFMA products              */
+    DMET_FP32_3M = 1,        /* complex GEMMs as 3 real FP32 products, FP32 accumulate   */
+    DMET_BF16X3_3M = 2       /* 3M with each FP32 operand split into bf16 hi + lo and
+                                the products hi*hi + hi*lo + lo*hi, FP32 accumulate     */
+} dmet_precision;
+
+typedef enum {
+    DMET_C128 = 0,           /* complex double */
+    DMET_C64 = 1             /* complex float  */
+} dmet_dtype;
+
+typedef struct {
+    int kmesh[3];            /* Monkhorst-Pack mesh, Gamma-centred (Sec. 2.2)  */
+    int nao;                 /* crystal AOs (= LOs) per cell                   */
+    int naux;                /* auxiliary (fitting) functions per cell         */
+    int nspin;               /* 1 (restricted) or 2 (unrestricted)            */
+} dmet_lattice;
+
+/* Message describing the last error of the calling thread ("" if none). */
+const char* dmet_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int dmet_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Bath and embedding coefficients (Eqs. "bath R SVD", "C loemb R", "C loemb k").
+ *
+ * gamma^{R,0} = 1/N_k sum_k exp(+i k.R) gamma(k) is formed for every cell; the
+ * block M = gamma_sup[env, imp[val]] of the supercell density matrix
+ * (rows: every supercell orbital not in the impurity, in supercell order
+ * cell*nao + mu; columns: the impurity LOs selected by val_idx -- the
+ * valence-only SVD of Sec. 2.1) is decomposed M = B Lambda V^T by a one-sided
+ * Jacobi SVD in FP64.  Bath vectors are sorted by descending singular value;
+ * each is signed so that its entry of largest modulus is positive (ties within
+ * 1e-12 relative: lowest row).  C^R = [[1, 0], [0, B]] is Loewdin
+ * orthonormalised and Fourier transformed, C^k = sum_R exp(-i k.R) C^R, and
+ * optionally composed with the AO->LO rotation: C^{k,AO,EO} = C^{k,AO,LO} C^k.
+ *
+ * dm_k     [nspin][N_k][nao][nao] complex128, Hermitian per k, per spin.
+ * nimp     impurity size; imp_idx (host, nimp ints) lists supercell orbitals
+ *          cell*nao + mu, or NULL for the LOs of cell 0 (nimp must then be nao).
+ * nval     number of SVD columns; val_idx (host) lists positions in the
+ *          impurity list, or NULL for all (nval must then be nimp).
+ * sv_tol   0 keeps all nval bath orbitals; > 0 drops those with sigma <= sv_tol.
+ * c_ao_lo  [N_k][nao][nao] complex128 AO->LO rotation (Eq. "C aolo"), or NULL
+ *          for the identity.
+ * c_k      out [nspin][N_k][nao][nimp+nval] complex128.  Columns 0..nimp-1 are
+ *          the impurity, then the bath; columns beyond neo[s] are zero.
+ * sv       out [nspin][nval] float64 singular values, descending.
+ * neo      out HOST [nspin]: nimp + number of kept bath orbitals.
+ * workspace/ws_bytes: device scratch, at least dmet_build_bath_workspace().
+ *
+ * This call synchronises `stream` before returning (it reads back the
+ * convergence status and the kept bath count).  Returns DMET_E_NOCONV if the
+ * SVD needs more than 60 sweeps, DMET_E_NONFINITE for NaN/Inf in dm_k,
+ * DMET_E_RANK if sv_tol removes every bath orbital.
+ * ------------------------------------------------------------------------- */
+dmet_status dmet_build_bath_workspace(const dmet_lattice* lat, int nimp, int nval,
+                                      size_t* bytes);
+dmet_status dmet_build_bath(const dmet_lattice* lat, const void* dm_k,
+                            int nimp, const int* imp_idx, int nval, const int* val_idx,
+                            double sv_tol, const void* c_ao_lo,
+                            void* c_k, double* sv, int* neo,
+                            void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * One-body transform (Eq. "fock transform", without the double-counting term):
+ *   X^{0,EO} = 1/N_k sum_k C^{k dagger} X^k C^k          per spin.
+ *
+ * c_k      [nspin][N_k][nao][neo] complex128.
+ * op_k     [nspin][N_k][nao][nao] complex128 (h(k), F(k) or gamma(k)).
+ * op_eo    out [nspin][neo][neo] float64, the real part.
+ * max_imag out DEVICE [1] float64 max |Im X^{0,EO}| (0 for real-symmetric
+ *          lattices), or NULL.
+ * Asynchronous.
+ * ------------------------------------------------------------------------- */
+dmet_status dmet_transform_1e(const dmet_lattice* lat, int neo, const void* c_k,
+                              const void* op_k, double* op_eo, double* max_imag,
+                              hipStream_t stream);
+
+/* E1 = sum_spin sum_ij h_ij gamma_ji (one-body energy of Eq. "emb Ham" with
+ * per-spin density matrices).  h_eo, dm_eo: [nspin][neo][neo] float64;
+ * e1: out DEVICE [1] float64.  Asynchronous. */
+dmet_status dmet_energy_1e(int nspin, int neo, const double* h_eo, const double* dm_eo,
+                           double* e1, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Embedding ERIs (Alg. 1):
+ *   (L|0i 0j)(q) = 1/N_k sum_k [C^{k dagger} (L|k, k-q) C^{k-q}]_{ij}
+ *   (ij|kl)     = 1/N_k sum_q sum_L conj((L|0i 0j)(q)) (L|0k 0l)(q)
+ *
+ * Only the imaginary-part-free result is formed: q and -q contribute complex
+ * conjugate terms, so each pair {q, -q} is transformed once, and the real
+ * contraction runs over N_k*naux rows.
+ *
+ * neo      embedding orbitals per spin (same for both spins).
+ * lmunu    [N_k q][N_k k][naux][nao][nao], dtype per `dtype` (complex128 or 64).
+ * c_k      [nspin][N_k][nao][neo] complex128.
+ * prec     arithmetic of the transform and contraction GEMMs (dmet_precision);
+ *          accumulation across q-blocks of the contraction is FP64 in every form.
+ * eri_aa   out s8 [npair(npair+1)/2] float64 (spin alpha, or the only spin).
+ * eri_bb   out s8 float64 (spin beta) -- required iff nspin == 2, else NULL.
+ * eri_ab   out s4 [npair][npair] float64 (alpha-beta) -- optional when
+ *          nspin == 2, must be NULL when nspin == 1.
+ * workspace/ws_bytes: device scratch, at least dmet_transform_eri_workspace().
+ * Asynchronous.
+ * ------------------------------------------------------------------------- */
+dmet_status dmet_transform_eri_workspace(const dmet_lattice* lat, int neo,
+                                         dmet_precision prec, dmet_dtype dtype,
+                                         size_t* bytes);
+dmet_status dmet_transform_eri(const dmet_lattice* lat, int neo, const void* lmunu,
+                               dmet_dtype dtype, const void* c_k, dmet_precision prec,
+                               double* eri_aa, double* eri_bb, double* eri_ab,
+                               void* workspace, size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMET_H */

@@ -1,0 +1,177 @@
+// extern "C" entry points of libdmet: argument validation, planning and
+// dispatch.  Every compute step runs in the kernels of bath.hip, onebody.hip
+// and eri_*.hip.
+#include <math.h>
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "eri.h"
+
+namespace dmet {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+dmet_status fail(dmet_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+dmet_status hip_fail(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return DMET_E_HIP;
+}
+
+__global__ void k_fill_zero(unsigned int* p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+void fill_zero(void* p, size_t bytes, hipStream_t s) {
+    const size_t n = bytes / 4;
+    const unsigned blocks = (unsigned)((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024);
+    k_fill_zero<<<blocks ? blocks : 1, 256, 0, s>>>(static_cast<unsigned int*>(p), n);
+}
+
+static dmet_status check_lattice(const dmet_lattice* lat) {
+    if (!lat) return fail(DMET_E_ARG, "lattice is NULL");
+    for (int d = 0; d < 3; ++d)
+        if (lat->kmesh[d] < 1 || lat->kmesh[d] > 64) return fail(DMET_E_ARG, "kmesh entries must be in [1, 64]");
+    const long nk = (long)lat->kmesh[0] * lat->kmesh[1] * lat->kmesh[2];
+    if (nk > 4096) return fail(DMET_E_ARG, "more than 4096 k-points");
+    if (lat->nao < 1 || lat->nao > 4096) return fail(DMET_E_ARG, "nao must be in [1, 4096]");
+    if (lat->nspin != 1 && lat->nspin != 2) return fail(DMET_E_ARG, "nspin must be 1 or 2");
+    return DMET_OK;
+}
+
+EriPlan make_eri_plan(const dmet_lattice* lat, int neo, dmet_precision prec, dmet_dtype dtype) {
+    EriPlan p;
+    p.mesh = make_mesh(lat->kmesh);
+    p.nao = lat->nao;
+    p.naux = lat->naux;
+    p.neo = neo;
+    p.nspin = lat->nspin;
+    p.npair = neo * (neo + 1) / 2;
+    p.zrows = p.mesh.nk * lat->naux;
+    p.dtype = dtype;
+    p.prec = prec;
+    const double nk = (double)p.mesh.nk;
+    size_t row = 0;
+    for (int q = 0; q < p.mesh.nk; ++q) {
+        const int nq = mesh_neg(p.mesh, q);
+        if (nq < q) continue;
+        QBlock b;
+        b.q = q;
+        b.self_conj = nq == q;
+        b.zrow0 = row;
+        b.weight = (b.self_conj ? 1.0 : sqrt(2.0)) / (nk * sqrt(nk));
+        row += (size_t)(b.self_conj ? 1 : 2) * lat->naux;
+        p.qblocks.push_back(b);
+    }
+    return p;
+}
+
+static dmet_status check_eri_args(const dmet_lattice* lat, int neo, dmet_precision prec, dmet_dtype dtype) {
+    dmet_status s = check_lattice(lat);
+    if (s != DMET_OK) return s;
+    if (lat->naux < 1) return fail(DMET_E_ARG, "naux must be positive");
+    if (neo < 1 || neo > 2048) return fail(DMET_E_ARG, "neo must be in [1, 2048]");
+    if (prec != DMET_FP64 && prec != DMET_FP32_3M && prec != DMET_BF16X3_3M)
+        return fail(DMET_E_ARG, "unknown precision");
+    if (dtype != DMET_C128 && dtype != DMET_C64) return fail(DMET_E_ARG, "unknown dtype");
+    const double zbytes = (double)lat->kmesh[0] * lat->kmesh[1] * lat->kmesh[2] * lat->naux *
+                          (double)neo * (neo + 1) / 2 * 8.0;
+    if (zbytes > 1.0e12) return fail(DMET_E_ARG, "problem too large for one device");
+    return DMET_OK;
+}
+
+}  // namespace dmet
+
+using namespace dmet;
+
+extern "C" {
+
+const char* dmet_last_error(void) { return g_last_error.c_str(); }
+
+int dmet_version(void) { return 100; }
+
+dmet_status dmet_build_bath_workspace(const dmet_lattice* lat, int nimp, int nval, size_t* bytes) {
+    dmet_status s = check_lattice(lat);
+    if (s != DMET_OK) return s;
+    if (!bytes) return fail(DMET_E_ARG, "bytes is NULL");
+    if (nimp < 1 || nval < 1 || nval > nimp) return fail(DMET_E_ARG, "need 1 <= nval <= nimp");
+    *bytes = bath_workspace_bytes(lat, nimp, nval);
+    return DMET_OK;
+}
+
+dmet_status dmet_build_bath(const dmet_lattice* lat, const void* dm_k, int nimp, const int* imp_idx, int nval,
+                            const int* val_idx, double sv_tol, const void* c_ao_lo, void* c_k, double* sv,
+                            int* neo, void* workspace, size_t ws_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    dmet_status s = check_lattice(lat);
+    if (s != DMET_OK) return s;
+    const int nsup = lat->kmesh[0] * lat->kmesh[1] * lat->kmesh[2] * lat->nao;
+    if (!dm_k || !c_k || !sv || !neo) return fail(DMET_E_ARG, "null array argument");
+    if (nimp < 1 || nimp >= nsup) return fail(DMET_E_ARG, "nimp must be in [1, N_k*nao)");
+    if (!imp_idx && nimp != lat->nao) return fail(DMET_E_ARG, "imp_idx == NULL requires nimp == nao");
+    if (nval < 1 || nval > nimp) return fail(DMET_E_ARG, "nval must be in [1, nimp]");
+    if (!val_idx && nval != nimp) return fail(DMET_E_ARG, "val_idx == NULL requires nval == nimp");
+    if (!(sv_tol >= 0.0)) return fail(DMET_E_ARG, "sv_tol must be >= 0");
+    if (nval > 1024) return fail(DMET_E_UNSUPPORTED, "more than 1024 SVD columns");
+    if (!workspace) return fail(DMET_E_WORKSPACE, "workspace is NULL");
+    return build_bath(lat, static_cast<const double2*>(dm_k), nimp, imp_idx, nval, val_idx, sv_tol,
+                      static_cast<const double2*>(c_ao_lo), static_cast<double2*>(c_k), sv, neo, workspace,
+                      ws_bytes, stream);
+}
+
+dmet_status dmet_transform_1e(const dmet_lattice* lat, int neo, const void* c_k, const void* op_k, double* op_eo,
+                              double* max_imag, hipStream_t stream) {
+    g_last_error.clear();
+    dmet_status s = check_lattice(lat);
+    if (s != DMET_OK) return s;
+    if (neo < 1 || neo > 4096) return fail(DMET_E_ARG, "neo must be in [1, 4096]");
+    if (!c_k || !op_k || !op_eo) return fail(DMET_E_ARG, "null array argument");
+    return transform_1e(lat, neo, static_cast<const double2*>(c_k), static_cast<const double2*>(op_k), op_eo,
+                        max_imag, stream);
+}
+
+dmet_status dmet_energy_1e(int nspin, int neo, const double* h_eo, const double* dm_eo, double* e1,
+                           hipStream_t stream) {
+    g_last_error.clear();
+    if (nspin != 1 && nspin != 2) return fail(DMET_E_ARG, "nspin must be 1 or 2");
+    if (neo < 1) return fail(DMET_E_ARG, "neo must be positive");
+    if (!h_eo || !dm_eo || !e1) return fail(DMET_E_ARG, "null array argument");
+    return energy_1e(nspin, neo, h_eo, dm_eo, e1, stream);
+}
+
+dmet_status dmet_transform_eri_workspace(const dmet_lattice* lat, int neo, dmet_precision prec, dmet_dtype dtype,
+                                         size_t* bytes) {
+    dmet_status s = check_eri_args(lat, neo, prec, dtype);
+    if (s != DMET_OK) return s;
+    if (!bytes) return fail(DMET_E_ARG, "bytes is NULL");
+    EriPlan p = make_eri_plan(lat, neo, prec, dtype);
+    *bytes = prec == DMET_FP64 ? eri_f64_workspace(p) : eri_lp_workspace(p);
+    return DMET_OK;
+}
+
+dmet_status dmet_transform_eri(const dmet_lattice* lat, int neo, const void* lmunu, dmet_dtype dtype,
+                               const void* c_k, dmet_precision prec, double* eri_aa, double* eri_bb,
+                               double* eri_ab, void* workspace, size_t ws_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    dmet_status s = check_eri_args(lat, neo, prec, dtype);
+    if (s != DMET_OK) return s;
+    if (!lmunu || !c_k || !eri_aa) return fail(DMET_E_ARG, "null array argument");
+    if (lat->nspin == 2 && !eri_bb) return fail(DMET_E_ARG, "nspin == 2 requires eri_bb");
+    if (lat->nspin == 1 && (eri_bb || eri_ab)) return fail(DMET_E_ARG, "nspin == 1 takes no eri_bb / eri_ab");
+    if (!workspace) return fail(DMET_E_WORKSPACE, "workspace is NULL");
+    EriPlan p = make_eri_plan(lat, neo, prec, dtype);
+    if (prec == DMET_FP64)
+        return eri_f64(p, lmunu, static_cast<const double*>(c_k), eri_aa, eri_bb, eri_ab, workspace, ws_bytes,
+                       stream);
+    return eri_lp(p, lmunu, static_cast<const double*>(c_k), eri_aa, eri_bb, eri_ab, workspace, ws_bytes, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,403 @@
+// Bath construction and embedding coefficients on the GPU, FP64 throughout.
+//
+//   gamma^{R,0} = 1/N_k sum_k exp(+i k.R) gamma(k)            (left side of Eq. "bath R SVD")
+//   M = gamma_sup[env, imp[val]] = B Lambda V^T               (Eq. "bath R SVD", valence columns)
+//   C^R = [[1, 0], [0, B]]  -> Loewdin -> C^k = sum_R exp(-i k.R) C^R   (Eqs. "C loemb R/k")
+//
+// The SVD is a one-sided (Hestenes) Jacobi iteration on the columns of M,
+// stored column-major so that every column is one contiguous vector; pairs are
+// visited in round-robin order, so the n/2 rotations of a round touch
+// disjoint columns and run on separate wavefronts of one workgroup.
+#include <vector>
+
+#include "common.h"
+
+namespace dmet {
+
+// ---------------------------------------------------------------- step a1
+// dm_r[s][R][mu][nu] = Re(1/N_k sum_k exp(i k.R) dm_k[s][k][mu][nu]); also
+// the largest |Im| and a non-finite flag.
+__global__ void k_dm_real(Mesh mesh, int nao, const double2* __restrict__ dm_k,
+                          double* __restrict__ dm_r, int* flags, double* max_imag) {
+    const int s = blockIdx.z, r = blockIdx.y;
+    const int nn = nao * nao;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    double im_abs = 0.0;
+    if (e < nn) {
+        double re = 0.0, im = 0.0;
+        bool finite = true;
+        for (int k = 0; k < mesh.nk; ++k) {
+            double2 g = dm_k[((size_t)s * mesh.nk + k) * nn + e];
+            finite = finite && isfinite(g.x) && isfinite(g.y);
+            double2 p = phase_kR(mesh, k, r);
+            re += p.x * g.x - p.y * g.y;
+            im += p.x * g.y + p.y * g.x;
+        }
+        if (!finite) atomicOr(flags, FLAG_NONFINITE);
+        dm_r[((size_t)s * mesh.nk + r) * nn + e] = re / mesh.nk;
+        im_abs = fabs(im / mesh.nk);
+    }
+    im_abs = wave_max(im_abs);
+    if ((threadIdx.x & 63) == 0) atomic_max_nonneg(max_imag, im_abs);
+}
+
+// ---------------------------------------------------------------- step a2
+// Mt[s][c][r] = gamma^{R_r - R_c, 0}[mu_r][mu_c]  (column-major M)
+__global__ void k_build_m(Mesh mesh, int nao, int nenv, int nval, const int* __restrict__ env,
+                          const int* __restrict__ cols, const double* __restrict__ dm_r,
+                          double* __restrict__ mt) {
+    const int s = blockIdx.z, c = blockIdx.y;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nenv) return;
+    const int er = env[r], ec = cols[c];
+    const int cell = mesh_sub(mesh, er / nao, ec / nao);
+    mt[((size_t)s * nval + c) * nenv + r] =
+        dm_r[(((size_t)s * mesh.nk + cell) * nao + er % nao) * nao + ec % nao];
+}
+
+// Round-robin schedule: seat 0 holds player 0, seats 1..n-1 rotate.
+__device__ inline int rr_player(int seat, int round, int n) {
+    return seat == 0 ? 0 : 1 + (seat - 1 + round) % (n - 1);
+}
+
+// One workgroup per spin.  On exit the columns of mt are mutually orthogonal
+// (|a.b| <= tol |a||b|), flags[1 + s] holds the sweeps used.
+__global__ void __launch_bounds__(1024) k_jacobi(int m, int n, double* __restrict__ mt,
+                                                 int max_sweeps, double tol, int* flags) {
+    const int s = blockIdx.x;
+    double* a_base = mt + (size_t)s * n * m;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    const int np = n + (n & 1);  // even player count (a dummy column when n is odd)
+    __shared__ int rotations;
+    int sweep = 0;
+    bool converged = false;
+    for (; sweep < max_sweeps; ++sweep) {
+        if (threadIdx.x == 0) rotations = 0;
+        __syncthreads();
+        for (int round = 0; round < np - 1; ++round) {
+            for (int p = wave; p < np / 2; p += nwave) {
+                int ca = rr_player(p, round, np), cb = rr_player(np - 1 - p, round, np);
+                if (ca >= n || cb >= n) continue;
+                double* a = a_base + (size_t)ca * m;
+                double* b = a_base + (size_t)cb * m;
+                double al = 0.0, be = 0.0, ga = 0.0;
+                for (int i = lane; i < m; i += 64) {
+                    double x = a[i], y = b[i];
+                    al += x * x;
+                    be += y * y;
+                    ga += x * y;
+                }
+                al = wave_sum(al);
+                be = wave_sum(be);
+                ga = wave_sum(ga);
+                if (al == 0.0 || be == 0.0 || fabs(ga) <= tol * sqrt(al) * sqrt(be)) continue;
+                double zeta = (be - al) / (2.0 * ga);
+                double t;
+                if (fabs(zeta) > 1e150) t = 0.5 / zeta;
+                else t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+                for (int i = lane; i < m; i += 64) {
+                    double x = a[i], y = b[i];
+                    a[i] = c * x - sn * y;
+                    b[i] = sn * x + c * y;
+                }
+                if (lane == 0) atomicAdd(&rotations, 1);
+            }
+            __syncthreads();
+        }
+        if (rotations == 0) {
+            converged = true;
+            break;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        flags[2 + s] = sweep + 1;
+        if (!converged) atomicOr(flags, FLAG_NOCONV);
+    }
+}
+
+// sigma, descending order, normalised and sign-fixed left vectors.
+// One workgroup per spin.  ub[s][b][r] = u_b, sv[s][b] = sigma_b, and
+// flags[4 + s] = number of kept bath vectors (sigma > sv_tol, or all).
+__global__ void __launch_bounds__(1024) k_svd_finalize(int m, int n, const double* __restrict__ mt,
+                                                       double* __restrict__ ub, double* __restrict__ sv,
+                                                       double sv_tol, int* flags) {
+    const int s = blockIdx.x;
+    const double* a_base = mt + (size_t)s * n * m;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    extern __shared__ double sh[];
+    double* sig = sh;                                // [n]
+    int* order = reinterpret_cast<int*>(sig + n);    // [n]
+    for (int c = wave; c < n; c += nwave) {
+        const double* a = a_base + (size_t)c * m;
+        double ss = 0.0;
+        for (int i = lane; i < m; i += 64) ss += a[i] * a[i];
+        ss = wave_sum(ss);
+        if (lane == 0) sig[c] = sqrt(ss);
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        int rank = 0;
+        for (int d = 0; d < n; ++d)
+            rank += (sig[d] > sig[c]) || (sig[d] == sig[c] && d < c);
+        order[rank] = c;
+    }
+    __syncthreads();
+    for (int b = wave; b < n; b += nwave) {
+        const int c = order[b];
+        const double* a = a_base + (size_t)c * m;
+        const double inv = sig[c] > 0.0 ? 1.0 / sig[c] : 0.0;
+        double amax = 0.0;
+        for (int i = lane; i < m; i += 64) amax = fmax(amax, fabs(a[i]));
+        amax = wave_max(amax);
+        int first = m;
+        for (int i = lane; i < m; i += 64)
+            if (fabs(a[i]) >= amax - 1e-12 * amax) first = min(first, i);
+        first = wave_min_int(first);
+        const double sgn = (first < m && a[first] < 0.0) ? -inv : inv;
+        double* u = ub + ((size_t)s * n + b) * m;
+        for (int i = lane; i < m; i += 64) u[i] = a[i] * sgn;
+        if (lane == 0) sv[(size_t)s * n + b] = sig[c];
+    }
+    if (threadIdx.x == 0) {
+        int kept = n;
+        if (sv_tol > 0.0) {
+            kept = 0;
+            for (int c = 0; c < n; ++c) kept += sig[c] > sv_tol;
+        }
+        flags[4 + s] = kept;
+    }
+}
+
+// ---------------------------------------------------------------- step a3
+// Loewdin: S = U^T U over the kept bath vectors; E = S - I.
+__global__ void k_overlap(int m, int n, const double* __restrict__ ub, double* __restrict__ e_out,
+                          const int* flags, double* __restrict__ emax) {
+    const int s = blockIdx.y;
+    const int nb = flags[4 + s];
+    const int lane = threadIdx.x & 63;
+    const int pair = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (pair >= n * n) return;
+    const int i = pair / n, j = pair % n;
+    double acc = 0.0;
+    if (i < nb && j < nb) {
+        const double* a = ub + ((size_t)s * n + i) * m;
+        const double* b = ub + ((size_t)s * n + j) * m;
+        for (int r = lane; r < m; r += 64) acc += a[r] * b[r];
+        acc = wave_sum(acc);
+    }
+    const double e = (i < nb && j < nb) ? acc - (i == j) : 0.0;
+    if (lane == 0) {
+        e_out[((size_t)s * n + i) * n + j] = e;
+        atomic_max_nonneg(emax, fabs(e));
+    }
+}
+
+// C <- C S^{-1/2} with S = I + E, |E| ~ 1e-15:  S^{-1/2} = I - E/2 + O(E^2).
+// Writes C^R[s][R][mu][col] for every supercell orbital (R, mu) and column.
+__global__ void k_assemble_cr(int nsup, int nimp, int n, int ldc, int m,
+                              const int* __restrict__ imp, const int* __restrict__ envpos,
+                              const double* __restrict__ ub, const double* __restrict__ e_mat,
+                              const int* flags, double* __restrict__ cr) {
+    const int s = blockIdx.z;
+    const int col = blockIdx.y;
+    const int sup = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sup >= nsup) return;
+    double v = 0.0;
+    if (col < nimp) {
+        v = (imp[col] == sup) ? 1.0 : 0.0;
+    } else {
+        const int b = col - nimp;
+        const int nb = flags[4 + s];
+        const int r = envpos[sup];
+        if (b < nb && r >= 0) {
+            const double* e = e_mat + (size_t)s * n * n;
+            double corr = 0.0;
+            for (int i = 0; i < nb; ++i) corr += ub[((size_t)s * n + i) * m + r] * e[i * n + b];
+            v = ub[((size_t)s * n + b) * m + r] - 0.5 * corr;
+        }
+    }
+    cr[((size_t)s * nsup + sup) * ldc + col] = v;
+}
+
+// C^k[s][k][mu][i] = sum_R exp(-i k.R) C^R[s][R][mu][i]
+__global__ void k_cr_to_ck(Mesh mesh, int nao, int ldc, const double* __restrict__ cr,
+                           double2* __restrict__ ck) {
+    const int s = blockIdx.z, k = blockIdx.y;
+    const int per = nao * ldc;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= per) return;
+    double re = 0.0, im = 0.0;
+    for (int r = 0; r < mesh.nk; ++r) {
+        const double c = cr[((size_t)s * mesh.nk + r) * per + e];
+        const double2 p = phase_kR(mesh, k, r);
+        re += p.x * c;
+        im -= p.y * c;
+    }
+    ck[((size_t)s * mesh.nk + k) * per + e] = make_double2(re, im);
+}
+
+// out[s][k] = a[k] (nao x nao) * b[s][k] (nao x ldc), complex FP64.
+__global__ void k_compose_ao_lo(int nk, int nao, int ldc, const double2* __restrict__ a,
+                                const double2* __restrict__ b, double2* __restrict__ out) {
+    const int s = blockIdx.z, k = blockIdx.y;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nao * ldc) return;
+    const int mu = e / ldc, i = e % ldc;
+    const double2* ak = a + (size_t)k * nao * nao + (size_t)mu * nao;
+    const double2* bk = b + ((size_t)s * nk + k) * nao * ldc;
+    double re = 0.0, im = 0.0;
+    for (int nu = 0; nu < nao; ++nu) {
+        double2 x = ak[nu], y = bk[(size_t)nu * ldc + i];
+        re += x.x * y.x - x.y * y.y;
+        im += x.x * y.y + x.y * y.x;
+    }
+    out[((size_t)s * nk + k) * nao * ldc + e] = make_double2(re, im);
+}
+
+// ---------------------------------------------------------------- host side
+struct BathPlan {
+    Mesh mesh;
+    int nao, nspin, nimp, nval, nenv, ldc, nsup;
+};
+
+struct BathWs {
+    double* dm_r;
+    int* flags;        // [0] status bits, [2+s] sweeps, [4+s] kept bath
+    double* scal;      // [0] max |Im gamma^R|, [1] max |S - I|
+    int* env;
+    int* cols;
+    int* imp;
+    int* envpos;
+    double* mt;
+    double* ub;
+    double* emat;
+    double* cr;
+    double2* ck_lo;
+};
+
+static BathWs carve_bath(Carve& cv, const BathPlan& p, bool with_ao_lo) {
+    BathWs w;
+    w.dm_r = cv.take<double>((size_t)p.nspin * p.mesh.nk * p.nao * p.nao);
+    w.flags = cv.take<int>(16);
+    w.scal = cv.take<double>(4);
+    w.env = cv.take<int>(p.nenv);
+    w.cols = cv.take<int>(p.nval);
+    w.imp = cv.take<int>(p.nimp);
+    w.envpos = cv.take<int>(p.nsup);
+    w.mt = cv.take<double>((size_t)p.nspin * p.nval * p.nenv);
+    w.ub = cv.take<double>((size_t)p.nspin * p.nval * p.nenv);
+    w.emat = cv.take<double>((size_t)p.nspin * p.nval * p.nval);
+    w.cr = cv.take<double>((size_t)p.nspin * p.nsup * p.ldc);
+    w.ck_lo = with_ao_lo ? cv.take<double2>((size_t)p.nspin * p.nsup * p.ldc) : nullptr;
+    return w;
+}
+
+size_t bath_workspace_bytes(const dmet_lattice* lat, int nimp, int nval) {
+    BathPlan p;
+    p.mesh = make_mesh(lat->kmesh);
+    p.nao = lat->nao;
+    p.nspin = lat->nspin;
+    p.nimp = nimp;
+    p.nval = nval;
+    p.nsup = p.mesh.nk * p.nao;
+    p.nenv = p.nsup - nimp;
+    p.ldc = nimp + nval;
+    Carve cv(nullptr, 0);
+    carve_bath(cv, p, true);
+    return cv.bytes();
+}
+
+dmet_status build_bath(const dmet_lattice* lat, const double2* dm_k, int nimp, const int* imp_idx,
+                       int nval, const int* val_idx, double sv_tol, const double2* c_ao_lo,
+                       double2* c_k, double* sv, int* neo, void* ws, size_t ws_bytes,
+                       hipStream_t st) {
+    BathPlan p;
+    p.mesh = make_mesh(lat->kmesh);
+    p.nao = lat->nao;
+    p.nspin = lat->nspin;
+    p.nimp = nimp;
+    p.nval = nval;
+    p.nsup = p.mesh.nk * p.nao;
+    p.nenv = p.nsup - nimp;
+    p.ldc = nimp + nval;
+
+    // host index lists: impurity, SVD columns, environment rows (supercell order)
+    std::vector<int> imp(nimp), cols(nval), env, envpos(p.nsup, -1);
+    std::vector<char> is_imp(p.nsup, 0);
+    for (int i = 0; i < nimp; ++i) {
+        imp[i] = imp_idx ? imp_idx[i] : i;
+        if (imp[i] < 0 || imp[i] >= p.nsup) return fail(DMET_E_ARG, "imp_idx entry out of range");
+        if (is_imp[imp[i]]) return fail(DMET_E_ARG, "imp_idx has a repeated orbital");
+        is_imp[imp[i]] = 1;
+    }
+    for (int c = 0; c < nval; ++c) {
+        int v = val_idx ? val_idx[c] : c;
+        if (v < 0 || v >= nimp) return fail(DMET_E_ARG, "val_idx entry out of range");
+        cols[c] = imp[v];
+    }
+    for (int r = 0; r < p.nsup; ++r)
+        if (!is_imp[r]) {
+            envpos[r] = (int)env.size();
+            env.push_back(r);
+        }
+    if ((int)env.size() != p.nenv) return fail(DMET_E_ARG, "impurity list inconsistent");
+    if (p.nenv < nval) return fail(DMET_E_ARG, "fewer environment orbitals than SVD columns");
+
+    Carve cv(ws, ws_bytes);
+    BathWs w = carve_bath(cv, p, c_ao_lo != nullptr);
+    if (cv.bytes() > ws_bytes) return fail(DMET_E_WORKSPACE, "build_bath workspace too small");
+
+    DMET_HIP(hipMemcpyAsync(w.env, env.data(), sizeof(int) * env.size(), hipMemcpyHostToDevice, st));
+    DMET_HIP(hipMemcpyAsync(w.cols, cols.data(), sizeof(int) * nval, hipMemcpyHostToDevice, st));
+    DMET_HIP(hipMemcpyAsync(w.imp, imp.data(), sizeof(int) * nimp, hipMemcpyHostToDevice, st));
+    DMET_HIP(hipMemcpyAsync(w.envpos, envpos.data(), sizeof(int) * p.nsup, hipMemcpyHostToDevice, st));
+    fill_zero(w.flags, 16 * sizeof(int), st);
+    fill_zero(w.scal, 4 * sizeof(double), st);
+
+    const int nn = p.nao * p.nao;
+    k_dm_real<<<dim3((nn + 255) / 256, p.mesh.nk, p.nspin), 256, 0, st>>>(p.mesh, p.nao, dm_k, w.dm_r,
+                                                                          w.flags, w.scal);
+    DMET_LAUNCH_CHECK("k_dm_real");
+    k_build_m<<<dim3((p.nenv + 255) / 256, nval, p.nspin), 256, 0, st>>>(
+        p.mesh, p.nao, p.nenv, nval, w.env, w.cols, w.dm_r, w.mt);
+    DMET_LAUNCH_CHECK("k_build_m");
+    const double tol = fmax(1e-15, sqrt((double)p.nenv) * 2.220446049250313e-16);
+    k_jacobi<<<p.nspin, 1024, 0, st>>>(p.nenv, nval, w.mt, 60, tol, w.flags);
+    DMET_LAUNCH_CHECK("k_jacobi");
+    const size_t shm = (size_t)nval * (sizeof(double) + sizeof(int));
+    k_svd_finalize<<<p.nspin, 1024, shm, st>>>(p.nenv, nval, w.mt, w.ub, sv, sv_tol, w.flags);
+    DMET_LAUNCH_CHECK("k_svd_finalize");
+    k_overlap<<<dim3((nval * nval + 3) / 4, p.nspin), 256, 0, st>>>(p.nenv, nval, w.ub, w.emat, w.flags,
+                                                                     w.scal + 1);
+    DMET_LAUNCH_CHECK("k_overlap");
+    k_assemble_cr<<<dim3((p.nsup + 255) / 256, p.ldc, p.nspin), 256, 0, st>>>(
+        p.nsup, nimp, nval, p.ldc, p.nenv, w.imp, w.envpos, w.ub, w.emat, w.flags, w.cr);
+    DMET_LAUNCH_CHECK("k_assemble_cr");
+    const int per = p.nao * p.ldc;
+    double2* ck_out = c_ao_lo ? w.ck_lo : c_k;
+    k_cr_to_ck<<<dim3((per + 255) / 256, p.mesh.nk, p.nspin), 256, 0, st>>>(p.mesh, p.nao, p.ldc, w.cr,
+                                                                             ck_out);
+    DMET_LAUNCH_CHECK("k_cr_to_ck");
+    if (c_ao_lo) {
+        k_compose_ao_lo<<<dim3((per + 255) / 256, p.mesh.nk, p.nspin), 256, 0, st>>>(
+            p.mesh.nk, p.nao, p.ldc, c_ao_lo, w.ck_lo, c_k);
+        DMET_LAUNCH_CHECK("k_compose_ao_lo");
+    }
+    int flags[16];
+    double scal[4];
+    DMET_HIP(hipMemcpyAsync(flags, w.flags, sizeof(flags), hipMemcpyDeviceToHost, st));
+    DMET_HIP(hipMemcpyAsync(scal, w.scal, sizeof(scal), hipMemcpyDeviceToHost, st));
+    DMET_HIP(hipStreamSynchronize(st));
+    if (flags[0] & FLAG_NONFINITE) return fail(DMET_E_NONFINITE, "non-finite entry in dm_k");
+    if (flags[0] & FLAG_NOCONV) return fail(DMET_E_NOCONV, "Jacobi SVD did not converge in 60 sweeps");
+    if (scal[1] > 1e-6) return fail(DMET_E_NOCONV, "bath vectors lost orthogonality (|S - I| > 1e-6)");
+    for (int s = 0; s < p.nspin; ++s) {
+        if (flags[4 + s] == 0) return fail(DMET_E_RANK, "sv_tol removed every bath orbital");
+        neo[s] = nimp + flags[4 + s];
+    }
+    return DMET_OK;
+}
+
+}  // namespace dmet

@@ -1,0 +1,49 @@
+// Internal plan of the embedding-ERI transformation (Alg. 1).
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace dmet {
+
+// One fitting momentum q that is transformed: either q = -q (self-conjugate,
+// real embedded 3-index, one Z row per L) or the representative of the pair
+// {q, -q} (two rows per L: real and imaginary part, weight sqrt(2)).
+struct QBlock {
+    int q;
+    int self_conj;
+    size_t zrow0;     // first Z row of this block
+    double weight;    // 1/(N_k sqrt(N_k)) or sqrt(2)/(N_k sqrt(N_k))
+};
+
+struct EriPlan {
+    Mesh mesh;
+    int nao, naux, neo, nspin;
+    int npair;
+    int zrows;        // N_k * naux
+    dmet_dtype dtype;
+    dmet_precision prec;
+    std::vector<QBlock> qblocks;
+};
+
+EriPlan make_eri_plan(const dmet_lattice* lat, int neo, dmet_precision prec, dmet_dtype dtype);
+
+size_t eri_f64_workspace(const EriPlan& p);
+dmet_status eri_f64(const EriPlan& p, const void* lmunu, const double* ck, double* eri_aa, double* eri_bb,
+                    double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st);
+
+size_t eri_lp_workspace(const EriPlan& p);
+dmet_status eri_lp(const EriPlan& p, const void* lmunu, const double* ck, double* eri_aa, double* eri_bb,
+                   double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st);
+
+// bath / one-body (bath.hip, onebody.hip)
+size_t bath_workspace_bytes(const dmet_lattice* lat, int nimp, int nval);
+dmet_status build_bath(const dmet_lattice* lat, const double2* dm_k, int nimp, const int* imp_idx,
+                       int nval, const int* val_idx, double sv_tol, const double2* c_ao_lo,
+                       double2* c_k, double* sv, int* neo, void* ws, size_t ws_bytes, hipStream_t st);
+dmet_status transform_1e(const dmet_lattice* lat, int neo, const double2* ck, const double2* op,
+                         double* out, double* max_imag, hipStream_t st);
+dmet_status energy_1e(int nspin, int neo, const double* h, const double* g, double* e1, hipStream_t st);
+
+}  // namespace dmet

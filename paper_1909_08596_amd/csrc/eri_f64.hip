@@ -1,0 +1,301 @@
+// Embedding ERIs by Alg. 1, FP64 form: every complex product is carried out as
+// a real FP64 MFMA GEMM (v_mfma_f64_16x16x4f64) on the 2x2 real embedding of
+// complex numbers (4 real products per complex MAC).
+//
+// For each q in {q : q <= -q} (q and -q give complex-conjugate terms):
+//   stage 1 (batched over k):  T_k[(L,mu)][j]  = sum_nu (L|mu k, nu k-q) C^{k-q}_{nu j}
+//   stage 2 (sum over k, mu):  X[i][(L,j)]     = sum_{k,mu} conj(C^k_{mu i}) T_k[(L,mu)][j]
+//                              i.e. (L|0i 0j)(q) = X / N_k, kept for i >= j only
+//   rows of Z:                 Z[(q,L,re/im)][ij] = w_q Re/Im X,
+//                              w_q = 1/(N_k sqrt N_k) (q = -q) or sqrt(2)/(N_k sqrt N_k)
+// then the contraction (ij|kl) = sum_rows Z[r][ij] Z[r][kl] as a packed SYRK
+// (same spin) or GEMM (alpha-beta).
+#include <vector>
+
+#include "common.h"
+#include "eri.h"
+
+namespace dmet {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// 256 threads = 4 waves in a 2 x 2 grid; each wave owns a (BM/2) x (BN/2)
+// block of 16 x 16 MFMA tiles.  Operands are staged in LDS K-major:
+// As[k][m], Bs[k][n].
+template <int BM, int BN, int BK>
+struct F64Tile {
+    static constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
+    static constexpr int LDA = BM + 2, LDB = BN + 2;
+};
+
+template <int BM, int BN, int BK>
+__device__ inline void f64_mma(const double* As, const double* Bs, d4 (&acc)[BM / 32][BN / 32]) {
+    using T = F64Tile<BM, BN, BK>;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm0 = (wave >> 1) * T::WM, wn0 = (wave & 1) * T::WN;
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        double a[T::TM], b[T::TN];
+#pragma unroll
+        for (int i = 0; i < T::TM; ++i) a[i] = As[kr * T::LDA + wm0 + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < T::TN; ++j) b[j] = Bs[kr * T::LDB + wn0 + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < T::TM; ++i)
+#pragma unroll
+            for (int j = 0; j < T::TN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+}
+
+// Visit the accumulator: fn(row, col, value) in tile-local coordinates.
+// v_mfma_f64_16x16x4f64 result layout: register r of lane l holds
+// D[4 r + l / 16][l % 16] (operands: A[l % 16][l / 16], B[l / 16][l % 16]).
+template <int BM, int BN, int BK, class Fn>
+__device__ inline void f64_visit(const d4 (&acc)[BM / 32][BN / 32], Fn fn) {
+    using T = F64Tile<BM, BN, BK>;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm0 = (wave >> 1) * T::WM, wn0 = (wave & 1) * T::WN;
+#pragma unroll
+    for (int i = 0; i < T::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < T::TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                fn(wm0 + i * 16 + r * 4 + (lane >> 4), wn0 + j * 16 + (lane & 15), acc[i][j][r]);
+}
+
+template <int BM, int BN>
+__device__ inline void zero_acc(d4 (&acc)[BM / 32][BN / 32]) {
+#pragma unroll
+    for (int i = 0; i < BM / 32; ++i)
+#pragma unroll
+        for (int j = 0; j < BN / 32; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+}
+
+template <class T>
+__device__ inline double ld(const T* p, size_t i);
+template <>
+__device__ inline double ld<double>(const double* p, size_t i) { return p[i]; }
+template <>
+__device__ inline double ld<float>(const float* p, size_t i) { return (double)p[i]; }
+
+// ---------------------------------------------------------------- stage 1
+// A: lmunu[q][k] rows (L,mu), K = (nu, re/im) contiguous; B: real embedding
+// of C^{k-q}: B[(nu,c')][(j,c)] = [[Cr, Ci], [-Ci, Cr]][c'][c].
+// Output T[k][mu][L][(j,c)] (interleaved complex, row length 2 neo).
+template <int BM, int BN, int BK, class TIn>
+__global__ void __launch_bounds__(256) k_xform1_f64(Mesh mesh, int q, int nao, int naux, int neo,
+                                                    const TIn* __restrict__ lmunu,
+                                                    const double* __restrict__ ck,
+                                                    double* __restrict__ tout) {
+    using T = F64Tile<BM, BN, BK>;
+    __shared__ double As[BK * T::LDA];
+    __shared__ double Bs[BK * T::LDB];
+    const int k = blockIdx.z;
+    const int kmq = mesh_sub(mesh, k, q);
+    const int M = naux * nao, K = 2 * nao, N = 2 * neo;
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const TIn* a_base = lmunu + ((size_t)q * mesh.nk + k) * (size_t)M * K;
+    const double* c_base = ck + (size_t)kmq * nao * neo * 2;
+    d4 acc[BM / 32][BN / 32];
+    zero_acc<BM, BN>(acc);
+    const int tid = threadIdx.x;
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        for (int e = tid; e < BM * BK; e += 256) {
+            const int kk = e % BK, mm = e / BK;
+            const int gm = m0 + mm, gk = k0 + kk;
+            As[kk * T::LDA + mm] = (gm < M && gk < K) ? ld(a_base, (size_t)gm * K + gk) : 0.0;
+        }
+        for (int e = tid; e < BK * BN; e += 256) {
+            const int nn = e % BN, kk = e / BN;
+            const int gn = n0 + nn, gk = k0 + kk;
+            double v = 0.0;
+            if (gn < N && gk < K) {
+                const int nu = gk >> 1, cp = gk & 1, j = gn >> 1, c = gn & 1;
+                const double cr = c_base[((size_t)nu * neo + j) * 2], ci = c_base[((size_t)nu * neo + j) * 2 + 1];
+                v = cp == 0 ? (c == 0 ? cr : ci) : (c == 0 ? -ci : cr);
+            }
+            Bs[kk * T::LDB + nn] = v;
+        }
+        __syncthreads();
+        f64_mma<BM, BN, BK>(As, Bs, acc);
+        __syncthreads();
+    }
+    f64_visit<BM, BN, BK>(acc, [&](int r, int c, double v) {
+        const int gm = m0 + r, gn = n0 + c;
+        if (gm < M && gn < N) {
+            const int L = gm / nao, mu = gm % nao;
+            tout[(((size_t)k * nao + mu) * naux + L) * N + gn] = v;
+        }
+    });
+}
+
+// ---------------------------------------------------------------- stage 2
+// A[(k,mu,c')][i] = (Cr, Ci)[c'] of C^k_{mu i}; B[(k,mu,c')][(j,c)] from T:
+// row c'=0 is (Tr, Ti), row c'=1 is (Ti, -Tr).  Grid: (i tiles, L * j tiles).
+// Writes Z rows for i >= j.
+template <int BM, int BN, int BK>
+__global__ void __launch_bounds__(256) k_xform2_f64(Mesh mesh, int nao, int naux, int neo, int self_conj,
+                                                    size_t zrow0, double wq, const double* __restrict__ ck,
+                                                    const double* __restrict__ tin, double* __restrict__ z,
+                                                    size_t ldz) {
+    using T = F64Tile<BM, BN, BK>;
+    __shared__ double As[BK * T::LDA];
+    __shared__ double Bs[BK * T::LDB];
+    const int N2 = 2 * neo;
+    const int njt = (N2 + BN - 1) / BN;
+    const int L = blockIdx.y / njt, jt = blockIdx.y % njt;
+    const int m0 = blockIdx.x * BM, n0 = jt * BN;     // n within this L: (j, c)
+    const int j_first = n0 >> 1;
+    if (m0 + BM - 1 < j_first) return;                  // tile entirely above the diagonal
+    const int K = 2 * mesh.nk * nao;
+    d4 acc[BM / 32][BN / 32];
+    zero_acc<BM, BN>(acc);
+    const int tid = threadIdx.x;
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        for (int e = tid; e < BK * BM; e += 256) {
+            const int mm = e % BM, kk = e / BM;
+            const int gm = m0 + mm, gk = k0 + kk;
+            double v = 0.0;
+            if (gm < neo && gk < K) {
+                const int kmu = gk >> 1, cp = gk & 1;
+                v = ck[((size_t)kmu * neo + gm) * 2 + cp];
+            }
+            As[kk * T::LDA + mm] = v;
+        }
+        for (int e = tid; e < BK * BN; e += 256) {
+            const int nn = e % BN, kk = e / BN;
+            const int gn = n0 + nn, gk = k0 + kk;
+            double v = 0.0;
+            if (gn < N2 && gk < K) {
+                const int kmu = gk >> 1, cp = gk & 1, j = gn >> 1, c = gn & 1;
+                const double* row = tin + ((size_t)kmu * naux + L) * N2 + 2 * j;
+                v = cp == 0 ? row[c] : (c == 0 ? row[1] : -row[0]);
+            }
+            Bs[kk * T::LDB + nn] = v;
+        }
+        __syncthreads();
+        f64_mma<BM, BN, BK>(As, Bs, acc);
+        __syncthreads();
+    }
+    f64_visit<BM, BN, BK>(acc, [&](int r, int c, double v) {
+        const int i = m0 + r, gn = n0 + c;
+        if (i >= neo || gn >= N2) return;
+        const int j = gn >> 1, part = gn & 1;
+        if (j > i) return;
+        if (self_conj && part == 1) return;
+        const size_t row = zrow0 + (self_conj ? (size_t)L : (size_t)2 * L + part);
+        z[row * ldz + (size_t)i * (i + 1) / 2 + j] = wq * v;
+    });
+}
+
+// ---------------------------------------------------------------- contraction
+// out = Za^T Zb over rows, Za/Zb [K][ldz].  mode 0: packed s8 (IJ >= KL, lower
+// triangle of tiles only, Za == Zb); mode 1: full s4 [IJ][KL].
+template <int BM, int BN, int BK>
+__global__ void __launch_bounds__(256) k_contract_f64(int npair, int krows, const double* __restrict__ za,
+                                                      const double* __restrict__ zb, size_t ldz, int mode,
+                                                      double* __restrict__ out) {
+    using T = F64Tile<BM, BN, BK>;
+    __shared__ double As[BK * T::LDA];
+    __shared__ double Bs[BK * T::LDB];
+    int mt, nt;
+    if (mode == 0) {
+        // linear block id -> (mt, nt) with mt >= nt
+        const long b = blockIdx.x;
+        mt = (int)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+        while ((long)mt * (mt + 1) / 2 > b) --mt;
+        while ((long)(mt + 1) * (mt + 2) / 2 <= b) ++mt;
+        nt = (int)(b - (long)mt * (mt + 1) / 2);
+    } else {
+        mt = blockIdx.x;
+        nt = blockIdx.y;
+    }
+    const int m0 = mt * BM, n0 = nt * BN;
+    d4 acc[BM / 32][BN / 32];
+    zero_acc<BM, BN>(acc);
+    const int tid = threadIdx.x;
+    for (int k0 = 0; k0 < krows; k0 += BK) {
+        for (int e = tid; e < BK * BM; e += 256) {
+            const int mm = e % BM, kk = e / BM;
+            const int gm = m0 + mm, gk = k0 + kk;
+            As[kk * T::LDA + mm] = (gm < npair && gk < krows) ? za[(size_t)gk * ldz + gm] : 0.0;
+        }
+        for (int e = tid; e < BK * BN; e += 256) {
+            const int nn = e % BN, kk = e / BN;
+            const int gn = n0 + nn, gk = k0 + kk;
+            Bs[kk * T::LDB + nn] = (gn < npair && gk < krows) ? zb[(size_t)gk * ldz + gn] : 0.0;
+        }
+        __syncthreads();
+        f64_mma<BM, BN, BK>(As, Bs, acc);
+        __syncthreads();
+    }
+    f64_visit<BM, BN, BK>(acc, [&](int r, int c, double v) {
+        const int IJ = m0 + r, KL = n0 + c;
+        if (IJ >= npair || KL >= npair) return;
+        if (mode == 0) {
+            if (KL <= IJ) out[(size_t)IJ * (IJ + 1) / 2 + KL] = v;
+        } else {
+            out[(size_t)IJ * npair + KL] = v;
+        }
+    });
+}
+
+// ---------------------------------------------------------------- driver
+constexpr int X1_BM = 64, X1_BN = 64, X1_BK = 16;
+constexpr int X2_BM = 64, X2_BN = 64, X2_BK = 16;
+constexpr int C_BM = 64, C_BN = 64, C_BK = 16;
+
+size_t eri_f64_workspace(const EriPlan& p) {
+    Carve cv(nullptr, 0);
+    cv.take<double>((size_t)p.mesh.nk * p.nao * p.naux * 2 * p.neo);     // T
+    cv.take<double>((size_t)p.nspin * p.zrows * p.npair);                 // Z per spin
+    return cv.bytes();
+}
+
+dmet_status eri_f64(const EriPlan& p, const void* lmunu, const double* ck, double* eri_aa, double* eri_bb,
+                    double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st) {
+    Carve cv(ws, ws_bytes);
+    double* t = cv.take<double>((size_t)p.mesh.nk * p.nao * p.naux * 2 * p.neo);
+    double* z = cv.take<double>((size_t)p.nspin * p.zrows * p.npair);
+    if (cv.bytes() > ws_bytes) return fail(DMET_E_WORKSPACE, "transform_eri workspace too small");
+    const size_t ldz = (size_t)p.npair;
+    const int M1 = p.naux * p.nao, N1 = 2 * p.neo;
+    for (int s = 0; s < p.nspin; ++s) {
+        const double* cks = ck + (size_t)s * p.mesh.nk * p.nao * p.neo * 2;
+        double* zs = z + (size_t)s * p.zrows * ldz;
+        for (const QBlock& qb : p.qblocks) {
+            dim3 g1((M1 + X1_BM - 1) / X1_BM, (N1 + X1_BN - 1) / X1_BN, p.mesh.nk);
+            if (p.dtype == DMET_C128)
+                k_xform1_f64<X1_BM, X1_BN, X1_BK, double><<<g1, 256, 0, st>>>(
+                    p.mesh, qb.q, p.nao, p.naux, p.neo, static_cast<const double*>(lmunu), cks, t);
+            else
+                k_xform1_f64<X1_BM, X1_BN, X1_BK, float><<<g1, 256, 0, st>>>(
+                    p.mesh, qb.q, p.nao, p.naux, p.neo, static_cast<const float*>(lmunu), cks, t);
+            DMET_LAUNCH_CHECK("k_xform1_f64");
+            const int njt = (N1 + X2_BN - 1) / X2_BN;
+            dim3 g2((p.neo + X2_BM - 1) / X2_BM, p.naux * njt);
+            k_xform2_f64<X2_BM, X2_BN, X2_BK><<<g2, 256, 0, st>>>(p.mesh, p.nao, p.naux, p.neo, qb.self_conj,
+                                                                  qb.zrow0, qb.weight, cks, t, zs, ldz);
+            DMET_LAUNCH_CHECK("k_xform2_f64");
+        }
+    }
+    const int nt = (p.npair + C_BM - 1) / C_BM;
+    for (int s = 0; s < p.nspin; ++s) {
+        const double* zs = z + (size_t)s * p.zrows * ldz;
+        double* out = s == 0 ? eri_aa : eri_bb;
+        k_contract_f64<C_BM, C_BN, C_BK><<<dim3((unsigned)((long)nt * (nt + 1) / 2)), 256, 0, st>>>(
+            p.npair, p.zrows, zs, zs, ldz, 0, out);
+        DMET_LAUNCH_CHECK("k_contract_f64 s8");
+    }
+    if (p.nspin == 2 && eri_ab) {
+        k_contract_f64<C_BM, C_BN, C_BK><<<dim3(nt, nt), 256, 0, st>>>(p.npair, p.zrows, z, z + p.zrows * ldz,
+                                                                     ldz, 1, eri_ab);
+        DMET_LAUNCH_CHECK("k_contract_f64 s4");
+    }
+    return DMET_OK;
+}
+
+}  // namespace dmet

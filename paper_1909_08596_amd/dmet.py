@@ -1,0 +1,191 @@
+"""ctypes binding of libdmet.so (argument marshalling only).
+
+Every function takes and returns torch tensors that live on the current HIP
+device; torch provides device memory and the stream, the library does all
+arithmetic.  The binding refuses to run without the compiled library: there is
+no CPU fallback.  Names and arguments mirror include/dmet.h.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdmet.so")
+
+DMET_FP64, DMET_FP32_3M, DMET_BF16X3_3M = 0, 1, 2
+DMET_C128, DMET_C64 = 0, 1
+PRECISIONS = {"fp64": DMET_FP64, "fp32": DMET_FP32_3M, "bf16x3": DMET_BF16X3_3M}
+STATUS = {0: "DMET_OK", 1: "DMET_E_ARG", 2: "DMET_E_HIP", 3: "DMET_E_NOCONV", 4: "DMET_E_RANK",
+          5: "DMET_E_NONFINITE", 6: "DMET_E_WORKSPACE", 7: "DMET_E_UNSUPPORTED"}
+
+# every symbol include/dmet.h declares
+EXPORTS = ("dmet_last_error", "dmet_version", "dmet_build_bath_workspace", "dmet_build_bath",
+           "dmet_transform_1e", "dmet_energy_1e", "dmet_transform_eri_workspace", "dmet_transform_eri")
+
+
+class DmetError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Lattice(ctypes.Structure):
+    _fields_ = [("kmesh", ctypes.c_int * 3), ("nao", ctypes.c_int), ("naux", ctypes.c_int),
+                ("nspin", ctypes.c_int)]
+
+
+def lattice(kmesh: Sequence[int], nao: int, naux: int = 1, nspin: int = 1) -> Lattice:
+    lat = Lattice()
+    for d in range(3):
+        lat.kmesh[d] = int(kmesh[d])
+    lat.nao, lat.naux, lat.nspin = int(nao), int(naux), int(nspin)
+    return lat
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libdmet.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1909_08596_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    lp = ctypes.POINTER(Lattice)
+    lib.dmet_last_error.restype = ctypes.c_char_p
+    lib.dmet_last_error.argtypes = []
+    lib.dmet_version.restype = i
+    lib.dmet_build_bath_workspace.argtypes = [lp, i, i, ctypes.POINTER(sz)]
+    lib.dmet_build_bath.argtypes = [lp, vp, i, vp, i, vp, d, vp, vp, vp, vp, vp, sz, vp]
+    lib.dmet_transform_1e.argtypes = [lp, i, vp, vp, vp, vp, vp]
+    lib.dmet_energy_1e.argtypes = [i, i, vp, vp, vp, vp]
+    lib.dmet_transform_eri_workspace.argtypes = [lp, i, i, i, ctypes.POINTER(sz)]
+    lib.dmet_transform_eri.argtypes = [lp, i, vp, i, vp, i, vp, vp, vp, vp, sz, vp]
+    for name in EXPORTS:
+        if name not in ("dmet_last_error", "dmet_version"):
+            getattr(lib, name).restype = i
+    _lib = lib
+    return lib
+
+
+def _check(st: int):
+    if st != 0:
+        raise DmetError(st, load().dmet_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(t: torch.Tensor, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def dmet_build_bath(kmesh, nao, dm_k: torch.Tensor, imp_idx=None, val_idx=None, sv_tol: float = 0.0,
+                    c_ao_lo: Optional[torch.Tensor] = None, stream=None):
+    """Bath SVD and embedding coefficients.  Returns (c_k, sv, neo list);
+    c_k has nimp + nval columns, those past neo[s] are zero."""
+    lib = load()
+    _dev(dm_k, torch.complex128, "dm_k")
+    nspin = dm_k.shape[0]
+    lat = lattice(kmesh, nao, 1, nspin)
+    nimp = nao if imp_idx is None else len(imp_idx)
+    nval = nimp if val_idx is None else len(val_idx)
+    imp_arr = None if imp_idx is None else (ctypes.c_int * nimp)(*[int(x) for x in imp_idx])
+    val_arr = None if val_idx is None else (ctypes.c_int * nval)(*[int(x) for x in val_idx])
+    nk = int(kmesh[0]) * int(kmesh[1]) * int(kmesh[2])
+    if c_ao_lo is not None:
+        _dev(c_ao_lo, torch.complex128, "c_ao_lo")
+    c_k = torch.empty((nspin, nk, nao, nimp + nval), dtype=torch.complex128, device=dm_k.device)
+    sv = torch.empty((nspin, nval), dtype=torch.float64, device=dm_k.device)
+    nb = ctypes.c_size_t()
+    _check(lib.dmet_build_bath_workspace(ctypes.byref(lat), nimp, nval, ctypes.byref(nb)))
+    ws = _workspace(nb.value, dm_k.device)
+    neo = (ctypes.c_int * nspin)()
+    _check(lib.dmet_build_bath(ctypes.byref(lat), _ptr(dm_k), nimp, imp_arr, nval, val_arr, float(sv_tol),
+                               _ptr(c_ao_lo), _ptr(c_k), _ptr(sv), neo, _ptr(ws), ws.numel(), _stream(stream)))
+    return c_k, sv, [int(x) for x in neo]
+
+
+def dmet_transform_1e(kmesh, nao, c_k: torch.Tensor, op_k: torch.Tensor, want_imag: bool = True, stream=None):
+    """X^{0,EO} = 1/N_k sum_k C^k^H X^k C^k.  Returns (op_eo, max_imag or None)."""
+    lib = load()
+    _dev(c_k, torch.complex128, "c_k")
+    _dev(op_k, torch.complex128, "op_k")
+    nspin, nk, _, neo = c_k.shape
+    lat = lattice(kmesh, nao, 1, nspin)
+    out = torch.empty((nspin, neo, neo), dtype=torch.float64, device=c_k.device)
+    mi = torch.empty(1, dtype=torch.float64, device=c_k.device) if want_imag else None
+    _check(lib.dmet_transform_1e(ctypes.byref(lat), neo, _ptr(c_k), _ptr(op_k), _ptr(out), _ptr(mi),
+                                 _stream(stream)))
+    return out, mi
+
+
+def dmet_energy_1e(h_eo: torch.Tensor, dm_eo: torch.Tensor, stream=None) -> torch.Tensor:
+    lib = load()
+    _dev(h_eo, torch.float64, "h_eo")
+    _dev(dm_eo, torch.float64, "dm_eo")
+    e1 = torch.empty(1, dtype=torch.float64, device=h_eo.device)
+    _check(lib.dmet_energy_1e(h_eo.shape[0], h_eo.shape[1], _ptr(h_eo), _ptr(dm_eo), _ptr(e1), _stream(stream)))
+    return e1
+
+
+def dmet_transform_eri_workspace(kmesh, nao, naux, nspin, neo, precision="fp64", dtype=torch.complex128) -> int:
+    lib = load()
+    lat = lattice(kmesh, nao, naux, nspin)
+    nb = ctypes.c_size_t()
+    dt = DMET_C128 if dtype == torch.complex128 else DMET_C64
+    _check(lib.dmet_transform_eri_workspace(ctypes.byref(lat), int(neo), PRECISIONS[precision], dt,
+                                            ctypes.byref(nb)))
+    return nb.value
+
+
+def dmet_transform_eri(kmesh, nao, naux, lmunu: torch.Tensor, c_k: torch.Tensor, precision: str = "fp64",
+                       eri_ab: bool = True, workspace: Optional[torch.Tensor] = None, out=None, stream=None):
+    """Packed embedding ERIs by Alg. 1.  Returns dict with 'aa' (s8), and for
+    two spins 'bb' (s8) and 'ab' (s4, if requested)."""
+    lib = load()
+    if lmunu.dtype not in (torch.complex128, torch.complex64):
+        raise ValueError("lmunu must be complex128 or complex64")
+    _dev(lmunu, lmunu.dtype, "lmunu")
+    _dev(c_k, torch.complex128, "c_k")
+    nspin, nk, _, neo = c_k.shape
+    lat = lattice(kmesh, nao, naux, nspin)
+    dt = DMET_C128 if lmunu.dtype == torch.complex128 else DMET_C64
+    npair = neo * (neo + 1) // 2
+    dev = c_k.device
+    if out is None:
+        out = {"aa": torch.empty(npair * (npair + 1) // 2, dtype=torch.float64, device=dev)}
+        if nspin == 2:
+            out["bb"] = torch.empty_like(out["aa"])
+            if eri_ab:
+                out["ab"] = torch.empty((npair, npair), dtype=torch.float64, device=dev)
+    if workspace is None:
+        workspace = _workspace(dmet_transform_eri_workspace(kmesh, nao, naux, nspin, neo, precision,
+                                                            lmunu.dtype), dev)
+    _check(lib.dmet_transform_eri(ctypes.byref(lat), neo, _ptr(lmunu), dt, _ptr(c_k), PRECISIONS[precision],
+                                  _ptr(out["aa"]), _ptr(out.get("bb")), _ptr(out.get("ab")), _ptr(workspace),
+                                  workspace.numel(), _stream(stream)))
+    return out

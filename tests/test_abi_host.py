@@ -1,0 +1,87 @@
+"""Host-side tests of the C ABI: the library loads, exports every symbol of
+include/dmet.h, and validates arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1909_08596_amd import dmet
+    if not os.path.exists(dmet.LIB_PATH):
+        pytest.skip("libdmet.so not built")
+    return dmet.load()
+
+
+def test_exports_match_header(lib):
+    from paper_1909_08596_amd import dmet
+    hdr = open(os.path.join(ROOT, "include", "dmet.h")).read()
+    declared = set(re.findall(r"\b(dmet_[a-z0-9_]+)\s*\(", hdr))
+    assert declared == set(dmet.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name)
+
+
+def test_version(lib):
+    assert lib.dmet_version() >= 100
+
+
+def _lat(kmesh=(2, 2, 1), nao=8, naux=40, nspin=1):
+    from paper_1909_08596_amd import dmet
+    return dmet.lattice(kmesh, nao, naux, nspin)
+
+
+def test_eri_argument_validation(lib):
+    nb = ctypes.c_size_t()
+    assert lib.dmet_transform_eri_workspace(ctypes.byref(_lat()), 16, 0, 0, ctypes.byref(nb)) == 0
+    assert nb.value > 0
+    assert lib.dmet_transform_eri_workspace(ctypes.byref(_lat()), 0, 0, 0, ctypes.byref(nb)) == 1
+    assert b"neo" in lib.dmet_last_error()
+    assert lib.dmet_transform_eri_workspace(ctypes.byref(_lat()), 16, 9, 0, ctypes.byref(nb)) == 1
+    assert lib.dmet_transform_eri_workspace(ctypes.byref(_lat(kmesh=(0, 1, 1))), 16, 0, 0, ctypes.byref(nb)) == 1
+    assert lib.dmet_transform_eri_workspace(ctypes.byref(_lat(nspin=3)), 16, 0, 0, ctypes.byref(nb)) == 1
+    # null pointers and spin-block consistency are rejected before any launch
+    assert lib.dmet_transform_eri(ctypes.byref(_lat()), 16, None, 0, None, 0, None, None, None, None, 0, None) == 1
+    fake = ctypes.c_void_p(0x1000)
+    st = lib.dmet_transform_eri(ctypes.byref(_lat()), 16, fake, 0, fake, 0, fake, fake, None, fake, 1 << 30, None)
+    assert st == 1 and b"nspin == 1" in lib.dmet_last_error()
+    st = lib.dmet_transform_eri(ctypes.byref(_lat(nspin=2)), 16, fake, 0, fake, 0, fake, None, None, fake, 1 << 30,
+                                None)
+    assert st == 1 and b"eri_bb" in lib.dmet_last_error()
+    st = lib.dmet_transform_eri(ctypes.byref(_lat()), 16, fake, 0, fake, 0, fake, None, None, None, 0, None)
+    assert st == 6
+
+
+def test_bath_argument_validation(lib):
+    nb = ctypes.c_size_t()
+    assert lib.dmet_build_bath_workspace(ctypes.byref(_lat()), 8, 8, ctypes.byref(nb)) == 0
+    assert lib.dmet_build_bath_workspace(ctypes.byref(_lat()), 8, 9, ctypes.byref(nb)) == 1
+    fake = ctypes.c_void_p(0x1000)
+    neo = (ctypes.c_int * 1)()
+    # imp_idx == NULL needs nimp == nao
+    st = lib.dmet_build_bath(ctypes.byref(_lat()), fake, 5, None, 5, None, 0.0, None, fake, fake, neo, fake, 1 << 20,
+                             None)
+    assert st == 1
+    # negative tolerance
+    st = lib.dmet_build_bath(ctypes.byref(_lat()), fake, 8, None, 8, None, -1.0, None, fake, fake, neo, fake, 1 << 20,
+                             None)
+    assert st == 1
+    # out-of-range impurity index is caught on the host
+    imp = (ctypes.c_int * 8)(*range(0, 7), 99)
+    st = lib.dmet_build_bath(ctypes.byref(_lat()), fake, 8, imp, 8, None, 0.0, None, fake, fake, neo, fake, 1 << 20,
+                             None)
+    assert st == 1 and b"imp_idx" in lib.dmet_last_error()
+    # repeated impurity orbital
+    imp = (ctypes.c_int * 8)(0, 1, 2, 3, 4, 5, 6, 6)
+    st = lib.dmet_build_bath(ctypes.byref(_lat()), fake, 8, imp, 8, None, 0.0, None, fake, fake, neo, fake, 1 << 20,
+                             None)
+    assert st == 1 and b"repeated" in lib.dmet_last_error()
+
+
+def test_onebody_argument_validation(lib):
+    assert lib.dmet_transform_1e(ctypes.byref(_lat()), 0, None, None, None, None, None) == 1
+    assert lib.dmet_energy_1e(3, 4, None, None, None, None) == 1
