@@ -1,0 +1,271 @@
+#!/usr/bin/env python3
+"""Benchmark of the embedding-ERI build (Alg. 1) on one MI355X.
+
+One step = one call of dmet_transform_eri on the resident inputs: the k-AO to
+k-EO transform of the GDF 3-index tensor for every fitting momentum q and the
+packed contraction, for every spin block (alpha-alpha, beta-beta, alpha-beta).
+The bath and one-body steps run once before the timed region and are
+reported alongside.
+
+Prints ONE JSON line.  ``value`` is the useful throughput W / t in TFLOP/s,
+W = W_T + W_C with W_T = 8 N_k^2 naux (nao^2 neo + nao neo^2) per spin (all
+(q, k) pairs of Alg. 1, 8 real flops per complex MAC) and W_C the minimal real
+contraction count N_k naux npair (npair + 1) per same-spin block plus
+2 N_k naux npair^2 for the alpha-beta block.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "embedding-ERI build s + TFLOP/s, split-BF16/FP32 vs FP64 at ≤1e-6 max err"
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}   # dense MFMA TFLOP/s (MI355X spec)
+
+
+def work_counts(wl):
+    nk, nao, naux, neo, ns = wl.nk, wl.nao, wl.naux, wl.neo, wl.nspin
+    npair = neo * (neo + 1) // 2
+    wt = 8.0 * nk * nk * naux * (nao * nao * neo + nao * neo * neo) * ns
+    wc = nk * naux * npair * (npair + 1.0) * ns + (2.0 * nk * naux * npair * npair if ns == 2 else 0.0)
+    return wt, wc
+
+
+def kernel_flops(wl, name):
+    """Algorithmic flops of ONE launch of the named kernel."""
+    nk, nao, naux, neo = wl.nk, wl.nao, wl.naux, wl.neo
+    npair = neo * (neo + 1) // 2
+    if name.startswith("xform1"):
+        return 8.0 * nk * naux * nao * nao * neo
+    if name.startswith("xform2"):
+        return 8.0 * nk * naux * nao * neo * (neo + 1) / 2
+    if name.startswith("contract_s8"):
+        return nk * naux * npair * (npair + 1.0)
+    if name.startswith("contract_s4"):
+        return 2.0 * nk * naux * npair * float(npair)
+    return None
+
+
+MFMA_PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}   # executed products per algorithmic one
+
+
+def traffic_bytes(kernel, workload):
+    """HBM bytes per launch of `kernel` from profiles/traffic.json, if the
+    counters were taken on this workload with the current kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        tr = json.load(open(path))
+        e = tr[kernel]
+        sha = hashlib.sha1(open(os.path.join(ROOT, e["source"]), "rb").read()).hexdigest()
+    except (OSError, KeyError, ValueError):
+        return None
+    if e.get("workload") != workload or e.get("source_sha1") != sha:
+        return None
+    return e["fetch_bytes"] + e["write_bytes"]
+
+
+def host_info():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    mem = 0
+    try:
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                mem = int(line.split()[1]) // (1024 * 1024)
+    except OSError:
+        pass
+    return model, mem
+
+
+def cpu_baseline(wl, lat, lm, n_l, n_rows):
+    """Time the FP64 oracle on a bounded sample of the same workload:
+    Alg. 1's transform for q = 0 over the first n_l fitting functions, then
+    the contraction of that block for n_rows output pair rows."""
+    from threadpoolctl import threadpool_info
+    from oracle import kspace as ok
+    bath = ok.build_bath(lat.dm_k, wl.kmesh, wl.nao)
+    ck = bath["c_k"][0]
+    sub = lm[:, :, :n_l]
+    t0 = time.perf_counter()
+    x = ok.alg1_embedded_3index(sub, ck, wl.kmesh, 0)
+    xm = x.reshape(n_l, -1)
+    e = (xm[:, :n_rows].conj().T @ xm) / wl.nk
+    t1 = time.perf_counter()
+    n = wl.neo
+    flops = 8.0 * wl.nk * n_l * (wl.nao * wl.nao * n + wl.nao * n * n) + 8.0 * n_l * n_rows * n * n
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    del e
+    return {"value": flops / (t1 - t0) / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"oracle Alg. 1 transform of q=0 for {n_l} of {wl.naux} fitting functions over all "
+                      f"{wl.nk} k, plus the contraction of that block for {n_rows} of {n * n} pair rows "
+                      f"(spin alpha); {flops:.3e} flop in {t1 - t0:.2f} s",
+            "seconds": t1 - t0}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="nio", help="synthetic workload (tiny, hbn, si, nio)")
+    ap.add_argument("--precision", default="bf16x6", choices=["fp64", "fp32", "bf16x3", "bf16x6"],
+                    help="form whose throughput is `value` (bf16x6: the fastest form within 1e-6 Ha)")
+    ap.add_argument("--compare", default="fp64,fp32,bf16x3",
+                    help="comma list of other precisions to time and compare against fp64 ('' for none)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-l", type=int, default=0, help="fitting functions in the CPU sample (0: naux/2)")
+    ap.add_argument("--cpu-sample-rows", type=int, default=16384)
+    ap.add_argument("--copy-calib-gib", type=float, default=0.0,
+                    help="only run a plain device-to-device copy of this many GiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    if args.copy_calib_gib > 0:
+        import torch
+        n = int(args.copy_calib_gib * (1 << 30)) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 4 * n}))
+        return
+
+    import torch
+    import synth
+    from paper_1909_08596_amd import dmet
+
+    wl = synth.CONFIGS[args.config]
+    dev = torch.device("cuda:0")
+    dmet.load()
+    print(f"[bench] generating {wl.name} inputs", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    lat = synth.make_lattice(wl)
+    lm = synth.three_index(wl)
+    t_gen = time.perf_counter() - t0
+    print(f"[bench] inputs generated in {t_gen:.1f} s; copying {lm.nbytes / 1e9:.1f} GB to HBM",
+          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    lm_d = torch.from_numpy(lm).to(dev)
+    torch.cuda.synchronize()
+    t_h2d = time.perf_counter() - t0
+    dm_d = torch.from_numpy(lat.dm_k).to(dev)
+    h_d = torch.from_numpy(lat.h_k).to(dev)
+
+    # bath + one-body (not in the timed region)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    ck, sv, neo = dmet.dmet_build_bath(wl.kmesh, wl.nao, dm_d)
+    ev[1].record()
+    h_eo, _ = dmet.dmet_transform_1e(wl.kmesh, wl.nao, ck, h_d)
+    g_eo, _ = dmet.dmet_transform_1e(wl.kmesh, wl.nao, ck, dm_d)
+    e1 = dmet.dmet_energy_1e(h_eo, g_eo)
+    ev[2].record()
+    torch.cuda.synchronize()
+    t_bath = ev[0].elapsed_time(ev[1])
+    t_1e = ev[1].elapsed_time(ev[2])
+    print(f"[bench] bath {t_bath:.2f} ms, one-body {t_1e:.2f} ms, E1 = {float(e1.cpu()):.10f}",
+          file=sys.stderr, flush=True)
+
+    def run_form(prec, steps, warmup, keep=False):
+        ws = torch.empty(dmet.dmet_transform_eri_workspace(wl.kmesh, wl.nao, wl.naux, wl.nspin, wl.neo, prec,
+                                                           lm_d.dtype), dtype=torch.uint8, device=dev)
+        out = None
+        for _ in range(warmup):
+            out = dmet.dmet_transform_eri(wl.kmesh, wl.nao, wl.naux, lm_d, ck, prec, workspace=ws, out=out)
+        torch.cuda.synchronize()
+        dmet.dmet_profile_reset()
+        dmet.dmet_profile_enable(True)
+        st = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1_ = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        e0.record(st)
+        for _ in range(steps):
+            out = dmet.dmet_transform_eri(wl.kmesh, wl.nao, wl.naux, lm_d, ck, prec, workspace=ws, out=out)
+        e1_.record(st)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        dmet.dmet_profile_enable(False)
+        prof = dmet.dmet_profile_report()
+        ms = e0.elapsed_time(e1_) / steps
+        del ws
+        if not keep:
+            out = None
+        return ms, wall, prof, out
+
+    forms = [args.precision] + [p for p in args.compare.split(",") if p and p != args.precision]
+    results = {}
+    for prec in forms:
+        print(f"[bench] timing {prec}: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+        ms, wall, prof, out = run_form(prec, args.steps, args.warmup, keep=len(forms) > 1)
+        results[prec] = (ms, wall, prof, out)
+        print(f"[bench] {prec}: {ms:.2f} ms/step; kernels {prof}", file=sys.stderr, flush=True)
+
+    wt, wc = work_counts(wl)
+    ms, wall, prof, _ = results[args.precision]
+    value = (wt + wc) / (ms * 1e-3) / 1e12
+    # dominant kernel: largest total time in the timed region
+    dom = max(prof.items(), key=lambda kv: kv[1][1])
+    dname, (dn, dms) = dom
+    avg_ms = dms / dn
+    kf = kernel_flops(wl, dname)
+    achieved = kf / (avg_ms * 1e-3) / 1e12
+    line = {
+        "metric": METRIC, "value": round(value, 4), "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "bf16x6": "bf16x6"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: k-mesh {'x'.join(map(str, wl.kmesh))}, nao {wl.nao}, naux {wl.naux}, "
+                               f"neo {wl.neo}, nspin {wl.nspin}, 3-index {'complex128' if lm.dtype == np.complex128 else 'complex64'}",
+                   "precision": args.precision, "W_flop": wt + wc, "W_T": wt, "W_C": wc},
+        "roofline": {"bound": "mfma", "kernel": dname, "achieved": round(achieved, 3), "peak": PEAK[args.precision],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK[args.precision], 4),
+                     "traffic": traffic_bytes(dname, wl.name),
+                     "mfma_util": round(achieved * MFMA_PRODUCTS[args.precision] / PEAK[args.precision], 4),
+                     "launch_ms": round(avg_ms, 4), "flop_per_launch": kf},
+        "kernels_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in prof.items()},
+        "bath_ms": round(t_bath, 3), "onebody_ms": round(t_1e, 3),
+        "h2d_s": round(t_h2d, 2), "h2d_GBps": round(lm.nbytes / 1e9 / t_h2d, 2),
+    }
+    if len(forms) > 1:
+        ref = results["fp64"][3] if "fp64" in results else None
+        cmp = {}
+        for prec in forms:
+            msp = results[prec][0]
+            entry = {"ms_per_step": round(msp, 3), "TFLOP/s": round((wt + wc) / (msp * 1e-3) / 1e12, 3)}
+            if ref is not None and prec != "fp64":
+                out = results[prec][3]
+                entry["max_abs_err_vs_fp64"] = {k: float((out[k] - ref[k]).abs().max()) for k in out}
+                entry["speedup_vs_fp64"] = round(results["fp64"][0] / msp, 3)
+            cmp[prec] = entry
+        line["forms"] = cmp
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        n_l = args.cpu_sample_l or max(1, wl.naux // 2)
+        line["cpu_baseline"] = cpu_baseline(wl, lat, lm, min(n_l, wl.naux),
+                                            min(args.cpu_sample_rows, wl.neo * wl.neo))
+        model, mem = host_info()
+        line["cpu_baseline"]["host"] = {"model": model, "os_cpu_count": os.cpu_count(), "ram_gb": mem}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

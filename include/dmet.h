@@ -67,8 +67,12 @@ typedef enum {
 typedef enum {
     DMET_FP64 = 0,           /* complex GEMMs as 4 real FP64 MFMA products              */
     DMET_FP32_3M = 1,        /* complex GEMMs as 3 real FP32 products, FP32 accumulate   */
-    DMET_BF16X3_3M = 2       /* 3M with each FP32 operand split into bf16 hi + lo and
-                                the products hi*hi + hi*lo + lo*hi, FP32 accumulate     */
+    DMET_BF16X3_3M = 2,      /* 3M with each FP32 operand split into bf16 hi + lo and
+                                the products hi*hi + hi*lo + lo*hi, FP32 accumulate
+                                (about 2^-17 relative per operand)                   */
+    DMET_BF16X6_3M = 3       /* 3M with a three-way bf16 split hi + mid + lo and the six
+                                products hh, hm, mh, hl, mm, lh, FP32 accumulate
+                                (about FP32 accuracy)                                */
 } dmet_precision;
 
 typedef enum {
@@ -179,6 +183,18 @@ dmet_status dmet_transform_eri(const dmet_lattice* lat, int neo, const void* lmu
                                dmet_dtype dtype, const void* c_k, dmet_precision prec,
                                double* eri_aa, double* eri_bb, double* eri_ab,
                                void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Optional per-kernel timing (not part of the method): when enabled, every
+ * kernel launch of the entry points above is bracketed by a pair of HIP events
+ * recorded on the launch's stream.  dmet_profile_report() waits for those
+ * events and writes one line per kernel name, "name launches total_ms\n", for
+ * all launches since the last reset (truncated to len bytes).  The events
+ * cost a few microseconds per launch; timing is off by default.
+ * ------------------------------------------------------------------------- */
+dmet_status dmet_profile_enable(int on);
+dmet_status dmet_profile_reset(void);
+dmet_status dmet_profile_report(char* buf, size_t len);
 
 #ifdef __cplusplus
 }

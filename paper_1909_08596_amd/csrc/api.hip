@@ -2,7 +2,11 @@
 // dispatch.  Every compute step runs in the kernels of bath.hip, onebody.hip
 // and eri_*.hip.
 #include <math.h>
+#include <stdio.h>
+#include <string.h>
 
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -34,6 +38,46 @@ void fill_zero(void* p, size_t bytes, hipStream_t s) {
     const size_t n = bytes / 4;
     const unsigned blocks = (unsigned)((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024);
     k_fill_zero<<<blocks ? blocks : 1, 256, 0, s>>>(static_cast<unsigned int*>(p), n);
+}
+
+// ---------------------------------------------------------------- profiling
+namespace {
+struct ProfRecord {
+    std::string name;
+    hipEvent_t start, stop;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRecord> g_prof;
+}  // namespace
+
+ProfScope::ProfScope(const char* name, hipStream_t s) : slot(-1), st(s) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on) return;
+    ProfRecord r;
+    r.name = name;
+    if (hipEventCreate(&r.start) != hipSuccess) return;
+    if (hipEventCreate(&r.stop) != hipSuccess) {
+        (void)hipEventDestroy(r.start);
+        return;
+    }
+    (void)hipEventRecord(r.start, s);
+    g_prof.push_back(r);
+    slot = (int)g_prof.size() - 1;
+}
+
+void ProfScope::stop() {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (slot >= 0 && slot < (int)g_prof.size()) (void)hipEventRecord(g_prof[slot].stop, st);
+    slot = -1;
+}
+
+static void prof_clear() {
+    for (auto& r : g_prof) {
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    g_prof.clear();
 }
 
 static dmet_status check_lattice(const dmet_lattice* lat) {
@@ -79,7 +123,7 @@ static dmet_status check_eri_args(const dmet_lattice* lat, int neo, dmet_precisi
     if (s != DMET_OK) return s;
     if (lat->naux < 1) return fail(DMET_E_ARG, "naux must be positive");
     if (neo < 1 || neo > 2048) return fail(DMET_E_ARG, "neo must be in [1, 2048]");
-    if (prec != DMET_FP64 && prec != DMET_FP32_3M && prec != DMET_BF16X3_3M)
+    if (prec != DMET_FP64 && prec != DMET_FP32_3M && prec != DMET_BF16X3_3M && prec != DMET_BF16X6_3M)
         return fail(DMET_E_ARG, "unknown precision");
     if (dtype != DMET_C128 && dtype != DMET_C64) return fail(DMET_E_ARG, "unknown dtype");
     const double zbytes = (double)lat->kmesh[0] * lat->kmesh[1] * lat->kmesh[2] * lat->naux *
@@ -172,6 +216,45 @@ dmet_status dmet_transform_eri(const dmet_lattice* lat, int neo, const void* lmu
         return eri_f64(p, lmunu, static_cast<const double*>(c_k), eri_aa, eri_bb, eri_ab, workspace, ws_bytes,
                        stream);
     return eri_lp(p, lmunu, static_cast<const double*>(c_k), eri_aa, eri_bb, eri_ab, workspace, ws_bytes, stream);
+}
+
+dmet_status dmet_profile_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return DMET_OK;
+}
+
+dmet_status dmet_profile_reset(void) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_clear();
+    return DMET_OK;
+}
+
+dmet_status dmet_profile_report(char* buf, size_t len) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!buf || len == 0) return fail(DMET_E_ARG, "empty report buffer");
+    std::map<std::string, std::pair<int, double>> agg;
+    std::vector<std::string> order;
+    for (auto& r : g_prof) {
+        hipError_t e = hipEventSynchronize(r.stop);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, r.start, r.stop);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        if (!agg.count(r.name)) order.push_back(r.name);
+        agg[r.name].first += 1;
+        agg[r.name].second += ms;
+    }
+    std::string out;
+    for (auto& n : order) {
+        char line[512];
+        snprintf(line, sizeof(line), "%s %d %.6f\n", n.c_str(), agg[n].first, agg[n].second);
+        out += line;
+    }
+    size_t n = out.size() < len - 1 ? out.size() : len - 1;
+    memcpy(buf, out.data(), n);
+    buf[n] = 0;
+    return DMET_OK;
 }
 
 }  // extern "C"

@@ -109,6 +109,15 @@ __device__ inline void atomic_max_nonneg(double* addr, double v) {
 // status word written by device code (0 = ok), read by hosts that sync
 enum DeviceFlag : int { FLAG_NONFINITE = 1, FLAG_NOCONV = 2 };
 
+// Per-launch event timing (enabled by dmet_profile_enable).  Usage:
+//   ProfScope ps("name", stream); kernel<<<...>>>; ps.stop();
+struct ProfScope {
+    int slot;
+    hipStream_t st;
+    ProfScope(const char* name, hipStream_t s);
+    void stop();
+};
+
 // small fill kernel (used instead of hipMemsetAsync so callers may capture)
 void fill_zero(void* p, size_t bytes, hipStream_t s);
 

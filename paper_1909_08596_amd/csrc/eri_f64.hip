@@ -194,15 +194,15 @@ __global__ void __launch_bounds__(256) k_xform2_f64(Mesh mesh, int nao, int naux
 // ---------------------------------------------------------------- contraction
 // out = Za^T Zb over rows, Za/Zb [K][ldz].  mode 0: packed s8 (IJ >= KL, lower
 // triangle of tiles only, Za == Zb); mode 1: full s4 [IJ][KL].
-template <int BM, int BN, int BK>
+template <int BM, int BN, int BK, int mode>
 __global__ void __launch_bounds__(256) k_contract_f64(int npair, int krows, const double* __restrict__ za,
-                                                      const double* __restrict__ zb, size_t ldz, int mode,
+                                                      const double* __restrict__ zb, size_t ldz,
                                                       double* __restrict__ out) {
     using T = F64Tile<BM, BN, BK>;
     __shared__ double As[BK * T::LDA];
     __shared__ double Bs[BK * T::LDB];
     int mt, nt;
-    if (mode == 0) {
+    if constexpr (mode == 0) {
         // linear block id -> (mt, nt) with mt >= nt
         const long b = blockIdx.x;
         mt = (int)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
@@ -268,17 +268,21 @@ dmet_status eri_f64(const EriPlan& p, const void* lmunu, const double* ck, doubl
         double* zs = z + (size_t)s * p.zrows * ldz;
         for (const QBlock& qb : p.qblocks) {
             dim3 g1((M1 + X1_BM - 1) / X1_BM, (N1 + X1_BN - 1) / X1_BN, p.mesh.nk);
+            ProfScope ps1("xform1_f64", st);
             if (p.dtype == DMET_C128)
                 k_xform1_f64<X1_BM, X1_BN, X1_BK, double><<<g1, 256, 0, st>>>(
                     p.mesh, qb.q, p.nao, p.naux, p.neo, static_cast<const double*>(lmunu), cks, t);
             else
                 k_xform1_f64<X1_BM, X1_BN, X1_BK, float><<<g1, 256, 0, st>>>(
                     p.mesh, qb.q, p.nao, p.naux, p.neo, static_cast<const float*>(lmunu), cks, t);
+            ps1.stop();
             DMET_LAUNCH_CHECK("k_xform1_f64");
             const int njt = (N1 + X2_BN - 1) / X2_BN;
             dim3 g2((p.neo + X2_BM - 1) / X2_BM, p.naux * njt);
+            ProfScope ps2("xform2_f64", st);
             k_xform2_f64<X2_BM, X2_BN, X2_BK><<<g2, 256, 0, st>>>(p.mesh, p.nao, p.naux, p.neo, qb.self_conj,
                                                                   qb.zrow0, qb.weight, cks, t, zs, ldz);
+            ps2.stop();
             DMET_LAUNCH_CHECK("k_xform2_f64");
         }
     }
@@ -286,13 +290,17 @@ dmet_status eri_f64(const EriPlan& p, const void* lmunu, const double* ck, doubl
     for (int s = 0; s < p.nspin; ++s) {
         const double* zs = z + (size_t)s * p.zrows * ldz;
         double* out = s == 0 ? eri_aa : eri_bb;
-        k_contract_f64<C_BM, C_BN, C_BK><<<dim3((unsigned)((long)nt * (nt + 1) / 2)), 256, 0, st>>>(
-            p.npair, p.zrows, zs, zs, ldz, 0, out);
+        ProfScope ps("contract_s8_f64", st);
+        k_contract_f64<C_BM, C_BN, C_BK, 0><<<dim3((unsigned)((long)nt * (nt + 1) / 2)), 256, 0, st>>>(
+            p.npair, p.zrows, zs, zs, ldz, out);
+        ps.stop();
         DMET_LAUNCH_CHECK("k_contract_f64 s8");
     }
     if (p.nspin == 2 && eri_ab) {
-        k_contract_f64<C_BM, C_BN, C_BK><<<dim3(nt, nt), 256, 0, st>>>(p.npair, p.zrows, z, z + p.zrows * ldz,
-                                                                     ldz, 1, eri_ab);
+        ProfScope ps("contract_s4_f64", st);
+        k_contract_f64<C_BM, C_BN, C_BK, 1><<<dim3(nt, nt), 256, 0, st>>>(p.npair, p.zrows, z,
+                                                                        z + p.zrows * ldz, ldz, eri_ab);
+        ps.stop();
         DMET_LAUNCH_CHECK("k_contract_f64 s4");
     }
     return DMET_OK;

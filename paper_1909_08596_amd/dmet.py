@@ -16,15 +16,16 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdmet.so")
 
-DMET_FP64, DMET_FP32_3M, DMET_BF16X3_3M = 0, 1, 2
+DMET_FP64, DMET_FP32_3M, DMET_BF16X3_3M, DMET_BF16X6_3M = 0, 1, 2, 3
 DMET_C128, DMET_C64 = 0, 1
-PRECISIONS = {"fp64": DMET_FP64, "fp32": DMET_FP32_3M, "bf16x3": DMET_BF16X3_3M}
+PRECISIONS = {"fp64": DMET_FP64, "fp32": DMET_FP32_3M, "bf16x3": DMET_BF16X3_3M, "bf16x6": DMET_BF16X6_3M}
 STATUS = {0: "DMET_OK", 1: "DMET_E_ARG", 2: "DMET_E_HIP", 3: "DMET_E_NOCONV", 4: "DMET_E_RANK",
           5: "DMET_E_NONFINITE", 6: "DMET_E_WORKSPACE", 7: "DMET_E_UNSUPPORTED"}
 
 # every symbol include/dmet.h declares
 EXPORTS = ("dmet_last_error", "dmet_version", "dmet_build_bath_workspace", "dmet_build_bath",
-           "dmet_transform_1e", "dmet_energy_1e", "dmet_transform_eri_workspace", "dmet_transform_eri")
+           "dmet_transform_1e", "dmet_energy_1e", "dmet_transform_eri_workspace", "dmet_transform_eri",
+           "dmet_profile_enable", "dmet_profile_reset", "dmet_profile_report")
 
 
 class DmetError(RuntimeError):
@@ -68,6 +69,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dmet_energy_1e.argtypes = [i, i, vp, vp, vp, vp]
     lib.dmet_transform_eri_workspace.argtypes = [lp, i, i, i, ctypes.POINTER(sz)]
     lib.dmet_transform_eri.argtypes = [lp, i, vp, i, vp, i, vp, vp, vp, vp, sz, vp]
+    lib.dmet_profile_enable.argtypes = [i]
+    lib.dmet_profile_reset.argtypes = []
+    lib.dmet_profile_report.argtypes = [ctypes.c_char_p, sz]
     for name in EXPORTS:
         if name not in ("dmet_last_error", "dmet_version"):
             getattr(lib, name).restype = i
@@ -188,4 +192,23 @@ def dmet_transform_eri(kmesh, nao, naux, lmunu: torch.Tensor, c_k: torch.Tensor,
     _check(lib.dmet_transform_eri(ctypes.byref(lat), neo, _ptr(lmunu), dt, _ptr(c_k), PRECISIONS[precision],
                                   _ptr(out["aa"]), _ptr(out.get("bb")), _ptr(out.get("ab")), _ptr(workspace),
                                   workspace.numel(), _stream(stream)))
+    return out
+
+
+def dmet_profile_enable(on: bool = True):
+    _check(load().dmet_profile_enable(1 if on else 0))
+
+
+def dmet_profile_reset():
+    _check(load().dmet_profile_reset())
+
+
+def dmet_profile_report() -> dict:
+    """{kernel name: (launches, total ms)} since the last reset (waits for the events)."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(load().dmet_profile_report(buf, len(buf)))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, n, ms = line.split()
+        out[name] = (int(n), float(ms))
     return out
