@@ -812,6 +812,337 @@ constexpr int dl_nbuf() { return NS == 3 ? 3 : 4; }
 template <int NS>
 constexpr size_t dl_lds() { return (size_t)dl_nbuf<NS>() * 2 * NS * 4 * 128 * 16; }
 
+// ------------------------------------------------------------------ packed transform (bf16 forms)
+// Operand packing for the transform.  Every packed operand has the layout
+//   [plane][part][group][x][8]   (bf16; group = 8 consecutive contraction indices)
+// with planes (re, im, re + im) for the 3M products.  nao is padded to
+// nao_p = 8 * ceil(nao / 8) (zero rows / columns) and the group count of each
+// contraction index is padded to an even number (a zero group) so that a
+// stage always holds two groups (16 contraction indices).
+
+// lmunu[q][k][L][mu][nu] -> P1[q][k][plane][part][nu/8][L*nao_p + mu][8]
+template <int NS, class TIn>
+__global__ void k_pack_lmunu(const TIn* __restrict__ lm, int nao, int nao_p, int naux, int ngv,
+                             __bf16* __restrict__ out) {
+    const int M1 = naux * nao_p;
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = blockIdx.y, qk = blockIdx.z;
+    if (row >= M1) return;
+    const int L = row / nao_p, mu = row % nao_p;
+    bf8 part[3][NS];
+    const TIn* src = lm + (((size_t)qk * naux + L) * nao + mu) * (size_t)nao * 2;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const int nu = 8 * g + v;
+        float re = 0.f, im = 0.f;
+        if (mu < nao && nu < nao) {
+            re = (float)src[2 * nu];
+            im = (float)src[2 * nu + 1];
+        }
+        const float pl[3] = {re, im, re + im};
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            __bf16 sp[NS];
+            split_bf16<NS>(pl[p], sp);
+#pragma unroll
+            for (int t = 0; t < NS; ++t) part[p][t][v] = sp[t];
+        }
+    }
+    const size_t pt_stride = (size_t)ngv * M1;
+    __bf16* o = out + (size_t)qk * 3 * NS * pt_stride * 8;
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int t = 0; t < NS; ++t)
+            *reinterpret_cast<bf8*>(o + (((size_t)(p * NS + t) * ngv + g) * M1 + row) * 8) = part[p][t];
+}
+
+// C^k[s][k][nu][j] -> P1c[k][plane][part][nu/8][s*neo + j][8]   (planes Cr, Ci, Cr + Ci)
+template <int NS>
+__global__ void k_pack_c1(const double* __restrict__ ck, int nk, int nspin, int nao, int neo, int ngv,
+                          __bf16* __restrict__ out) {
+    const int nb = nspin * neo;
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = blockIdx.y, k = blockIdx.z;
+    if (col >= nb) return;
+    const int s = col / neo, j = col % neo;
+    bf8 part[3][NS];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const int nu = 8 * g + v;
+        float re = 0.f, im = 0.f;
+        if (nu < nao) {
+            const double* c = ck + ((((size_t)s * nk + k) * nao + nu) * neo + j) * 2;
+            re = (float)c[0];
+            im = (float)c[1];
+        }
+        const float pl[3] = {re, im, re + im};
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            __bf16 sp[NS];
+            split_bf16<NS>(pl[p], sp);
+#pragma unroll
+            for (int t = 0; t < NS; ++t) part[p][t][v] = sp[t];
+        }
+    }
+    const size_t per_k = (size_t)3 * NS * ngv * nb;
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int t = 0; t < NS; ++t)
+            *reinterpret_cast<bf8*>(out + ((size_t)k * per_k + ((size_t)(p * NS + t) * ngv + g) * nb + col) * 8) =
+                part[p][t];
+}
+
+// conj(C^k)[s][(k,mu)][i] -> P2c[s][plane][part][(k*nao_p + mu)/8][i][8]  (planes Cr, -Ci, Cr - Ci)
+template <int NS>
+__global__ void k_pack_c2(const double* __restrict__ ck, int nk, int nao, int nao_p, int neo, int ng2,
+                          __bf16* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = blockIdx.y, s = blockIdx.z;
+    if (i >= neo) return;
+    bf8 part[3][NS];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const int kk = 8 * g + v, k = kk / nao_p, mu = kk % nao_p;
+        float re = 0.f, im = 0.f;
+        if (k < nk && mu < nao) {
+            const double* c = ck + ((((size_t)s * nk + k) * nao + mu) * neo + i) * 2;
+            re = (float)c[0];
+            im = (float)c[1];
+        }
+        const float pl[3] = {re, -im, re - im};
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            __bf16 sp[NS];
+            split_bf16<NS>(pl[p], sp);
+#pragma unroll
+            for (int t = 0; t < NS; ++t) part[p][t][v] = sp[t];
+        }
+    }
+    const size_t per_s = (size_t)3 * NS * ng2 * neo;
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int t = 0; t < NS; ++t)
+            *reinterpret_cast<bf8*>(out + ((size_t)s * per_s + ((size_t)(p * NS + t) * ng2 + g) * neo + i) * 8) =
+                part[p][t];
+}
+
+// One stage of a packed operand (3 planes x NS parts x 2 groups x ROWS rows)
+// moved to LDS [plane*NS + part][group][row] by direct loads; rows clamped.
+template <int NS, int ROWS>
+__device__ inline void pk_issue(const __bf16* base, size_t pt_stride /*chunks per part*/, int X, int x0, int g0,
+                                bf8* dst) {
+    constexpr int CH = 3 * NS * 2 * ROWS;  // chunks in the stage
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int first = wave * 64; first < CH; first += 256) {
+        const int pt = first / (2 * ROWS), g = (first / ROWS) % 2, row0 = first % ROWS;
+        const int x = min(x0 + row0 + lane, X - 1);
+        const __bf16* src = base + ((size_t)pt * pt_stride + (size_t)(g0 + g) * X + x) * 8;
+        __builtin_amdgcn_global_load_lds((const void*)src, DMET_LDS_PTR(dst + first), 16, 0, 0);
+    }
+}
+
+// 3M x NS-split products of one 16-deep stage: acc[p][i][j] += A_p B_p
+template <int NS, int BM, int BN, int TM, int TN>
+__device__ inline void pk_mma3(const bf8* sA, const bf8* sB, int wm0, int wn0, f16v (&acc)[3][TM][TN]) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 5;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        bf8 a[TM][NS], b[TN][NS];
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+#pragma unroll
+            for (int i = 0; i < TM; ++i) a[i][t] = sA[((p * NS + t) * 2 + g) * BM + wm0 + i * 32 + (lane & 31)];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) b[j][t] = sB[((p * NS + t) * 2 + g) * BN + wn0 + j * 32 + (lane & 31)];
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                f16v c = acc[p][i][j];
+                if constexpr (NS == 2) {
+                    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][0], c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][1], c, 0, 0, 0);
+                } else {
+                    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][2], b[j][0], c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][1], c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][2], c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][0], c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][1], c, 0, 0, 0);
+                }
+                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][0], c, 0, 0, 0);
+                acc[p][i][j] = c;
+            }
+    }
+}
+
+// Double-buffered K loop over `nst` stages of two groups each.
+template <int NS, int BM, int BN, int TM, int TN>
+__device__ inline void pk_loop3(const __bf16* pa, size_t pa_pt, int XA, int m0, const __bf16* pb, size_t pb_pt,
+                                int XB, int n0, int nst, bf8* ring, int wm0, int wn0, f16v (&acc)[3][TM][TN]) {
+    constexpr int SA = 3 * NS * 2 * BM, SB = 3 * NS * 2 * BN;
+    pk_issue<NS, BM>(pa, pa_pt, XA, m0, 0, ring);
+    pk_issue<NS, BN>(pb, pb_pt, XB, n0, 0, ring + SA);
+    for (int st = 0; st < nst; ++st) {
+        bf8* cur = ring + (size_t)(st & 1) * (SA + SB);
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // own loads of stage st landed
+        __builtin_amdgcn_s_barrier();         // everyone's loads landed; stage st-1 fully read
+        __builtin_amdgcn_sched_barrier(0);
+        if (st + 1 < nst) {
+            bf8* nxt = ring + (size_t)((st + 1) & 1) * (SA + SB);
+            pk_issue<NS, BM>(pa, pa_pt, XA, m0, 2 * (st + 1), nxt);
+            pk_issue<NS, BN>(pb, pb_pt, XB, n0, 2 * (st + 1), nxt + SA);
+        }
+        pk_mma3<NS, BM, BN, TM, TN>(cur, cur + SA, wm0, wn0, acc);
+    }
+}
+
+// Stage 1 (both spins at once): T[(L,mu)][(s,j)] for one (q, k) from packed
+// lmunu and packed C^{k-q}; 3M combination and split into bf16 parts in the
+// epilogue, written as stage 2's packed B operand
+//   PT[s][plane][part][(k*nao_p + mu)/8][L*neo + j][8].
+// Lanes l and l+32 hold rows 0-3 and 4-7 of each 8-row group of a 32x32
+// result tile; one exchange gives each lane a full 8-row column chunk.
+template <int NS>
+__global__ void __launch_bounds__(256) k_xf1_pk(Mesh mesh, int q, int naux, int nao_p, int neo, int nspin, int ngv,
+                                                int ng2,
+                                                const __bf16* __restrict__ plm, const __bf16* __restrict__ pc1,
+                                                __bf16* __restrict__ pt) {
+    constexpr int BM = 128, BN = 128, TM = 2, TN = 2;
+    extern __shared__ __align__(16) bf8 ring[];
+    const int k = blockIdx.z, nk = mesh.nk;
+    const int kmq = mesh_sub(mesh, k, q);
+    const int M1 = naux * nao_p, NB = nspin * neo;
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
+    const __bf16* pa = plm + ((size_t)q * nk + k) * 3 * NS * (size_t)ngv * M1 * 8;
+    const __bf16* pb = pc1 + (size_t)kmq * 3 * NS * (size_t)ngv * NB * 8;
+    f16v acc[3][TM][TN];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[p][i][j][r] = 0.f;
+    pk_loop3<NS, BM, BN, TM, TN>(pa, (size_t)ngv * M1, M1, m0, pb, (size_t)ngv * NB, NB, n0, ngv / 2, ring, wm0,
+                                 wn0, acc);
+    const int h = lane >> 5;
+    const size_t N2 = (size_t)naux * neo;
+    const size_t per_part = (size_t)ng2 * N2;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int col = n0 + wn0 + j * 32 + (lane & 31);
+            const int s = col / neo, jj = col % neo;
+#pragma unroll
+            for (int qq = 0; qq < 4; qq += 2) {
+                // rows of register groups qq (this lane: h == 0) and qq + 1 (h == 1)
+                float pl[3][8];
+#pragma unroll
+                for (int p3 = 0; p3 < 3; ++p3) {
+                    float mine[4], send[4], recv[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float p1 = acc[0][i][j][4 * qq + r], p2 = acc[1][i][j][4 * qq + r],
+                                    p3v = acc[2][i][j][4 * qq + r];
+                        const float p1b = acc[0][i][j][4 * (qq + 1) + r], p2b = acc[1][i][j][4 * (qq + 1) + r],
+                                    p3b = acc[2][i][j][4 * (qq + 1) + r];
+                        const float va = p3 == 0 ? p1 - p2 : (p3 == 1 ? p3v - p1 - p2 : p3v - 2.f * p2);
+                        const float vb = p3 == 0 ? p1b - p2b : (p3 == 1 ? p3b - p1b - p2b : p3b - 2.f * p2b);
+                        mine[r] = h == 0 ? va : vb;
+                        send[r] = h == 0 ? vb : va;
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) recv[r] = __shfl_xor(send[r], 32, 64);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        pl[p3][h == 0 ? r : 4 + r] = mine[r];
+                        pl[p3][h == 0 ? 4 + r : r] = recv[r];
+                    }
+                }
+                const int grp_row = m0 + wm0 + i * 32 + 8 * (qq + h);   // first row of this lane's 8-row group
+                if (col < NB && grp_row < M1) {
+                    const int L = grp_row / nao_p, mu0 = grp_row % nao_p;
+                    const size_t g2 = ((size_t)k * nao_p + mu0) / 8;
+                    const size_t x = (size_t)L * neo + jj;
+                    __bf16* base = pt + (size_t)s * 3 * NS * per_part * 8;
+#pragma unroll
+                    for (int p3 = 0; p3 < 3; ++p3) {
+                        bf8 part[NS];
+#pragma unroll
+                        for (int v = 0; v < 8; ++v) {
+                            __bf16 sp[NS];
+                            split_bf16<NS>(pl[p3][v], sp);
+#pragma unroll
+                            for (int t = 0; t < NS; ++t) part[t][v] = sp[t];
+                        }
+#pragma unroll
+                        for (int t = 0; t < NS; ++t)
+                            *reinterpret_cast<bf8*>(base + (((size_t)(p3 * NS + t) * ng2 + g2) * N2 + x) * 8) = part[t];
+                    }
+                }
+            }
+        }
+}
+
+// Stage 2: X[i][(L,j)] = sum_{(k,mu)} conj(C^k_{mu i}) T[(k,mu)][(L,j)] for one
+// q and spin, i >= j only; 3M combination; Z rows (FP32).  Tiles of 64 x 64 per
+// L; tiles with every i < every j are skipped.
+template <int NS>
+__global__ void __launch_bounds__(256) k_xf2_pk(int naux, int neo, int ng2, int self_conj, size_t zrow0, float wq,
+                                                const __bf16* __restrict__ pc2, const __bf16* __restrict__ ptt,
+                                                float* __restrict__ z, size_t ldz) {
+    constexpr int BM = 64, BN = 64, TM = 1, TN = 1;
+    extern __shared__ __align__(16) bf8 ring[];
+    const int njt = (neo + BN - 1) / BN, nit = (neo + BM - 1) / BM;
+    // tile id -> (L, jt, it); consecutive ids share L (and so T columns in L2)
+    const long tid_ = blockIdx.x;
+    const int per_l = njt * nit;
+    const int L = (int)(tid_ / per_l), rem = (int)(tid_ % per_l);
+    const int jt = rem / nit, it = rem % nit;
+    if (L >= naux) return;
+    const int m0 = it * BM, j0 = jt * BN;
+    if (m0 + BM - 1 < j0) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
+    const int N2 = naux * neo;
+    f16v acc[3][TM][TN];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[p][0][0][r] = 0.f;
+    pk_loop3<NS, BM, BN, TM, TN>(pc2, (size_t)ng2 * neo, neo, m0, ptt, (size_t)ng2 * N2, N2, L * neo + j0, ng2 / 2,
+                                 ring, wm0, wn0, acc);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = m0 + wm0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int j = j0 + wn0 + (lane & 31);
+        if (i >= neo || j >= neo || j > i) continue;
+        const size_t pair = (size_t)i * (i + 1) / 2 + j;
+        const float p1 = acc[0][0][0][r], p2 = acc[1][0][0][r], p3 = acc[2][0][0][r];
+        const float xr = p1 - p2, xi = p3 - p1 - p2;
+        if (self_conj) {
+            z[(zrow0 + L) * ldz + pair] = wq * xr;
+        } else {
+            z[(zrow0 + 2 * (size_t)L) * ldz + pair] = wq * xr;
+            z[(zrow0 + 2 * (size_t)L + 1) * ldz + pair] = wq * xi;
+        }
+    }
+}
+
+template <int NS>
+constexpr size_t xf1_lds() { return (size_t)2 * 3 * NS * 2 * (128 + 128) * 16; }
+template <int NS>
+constexpr size_t xf2_lds() { return (size_t)2 * 3 * NS * 2 * (64 + 64) * 16; }
+
 // ------------------------------------------------------------------ driver
 constexpr int L1_BM = 128, L1_BN = 64, L1_BK = 16;
 constexpr int L2_BM = 64, L2_BN = 64, L2_BK = 16;
@@ -825,12 +1156,104 @@ static size_t packed_elems(const EriPlan& p) {
     return (size_t)ns * kgroups_of(p.zrows) * 8 * p.npair;
 }
 
+// padded sizes of the packed transform operands
+struct PkDims {
+    int ns, nao_p, ngv, ng2, M1, NB;
+    size_t N2;
+    size_t lm_elems, c1_elems, c2_elems, t_elems;
+};
+
+static PkDims pk_dims(const EriPlan& p) {
+    PkDims d;
+    d.ns = p.prec == DMET_BF16X6_3M ? 3 : 2;
+    d.nao_p = (p.nao + 7) / 8 * 8;
+    d.ngv = (d.nao_p / 8 + 1) / 2 * 2;
+    d.ng2 = (p.mesh.nk * d.nao_p / 8 + 1) / 2 * 2;
+    d.M1 = p.naux * d.nao_p;
+    d.NB = p.nspin * p.neo;
+    d.N2 = (size_t)p.naux * p.neo;
+    const size_t pl = (size_t)3 * d.ns * 8;
+    d.lm_elems = (size_t)p.mesh.nk * p.mesh.nk * pl * d.ngv * d.M1;
+    d.c1_elems = (size_t)p.mesh.nk * pl * d.ngv * d.NB;
+    d.c2_elems = (size_t)p.nspin * pl * d.ng2 * p.neo;
+    d.t_elems = (size_t)p.nspin * pl * d.ng2 * d.N2;
+    return d;
+}
+
 size_t eri_lp_workspace(const EriPlan& p) {
     Carve cv(nullptr, 0);
-    cv.take<float>((size_t)3 * p.mesh.nk * p.nao * p.naux * p.neo);   // T planes
+    if (p.prec == DMET_FP32_3M) {
+        cv.take<float>((size_t)3 * p.mesh.nk * p.nao * p.naux * p.neo);   // T planes
+    } else {
+        PkDims d = pk_dims(p);
+        cv.take<__bf16>(d.lm_elems);
+        cv.take<__bf16>(d.c1_elems);
+        cv.take<__bf16>(d.c2_elems);
+        cv.take<__bf16>(d.t_elems);
+    }
     cv.take<float>((size_t)p.nspin * p.zrows * p.npair);              // Z per spin
     cv.take<__bf16>((size_t)p.nspin * packed_elems(p));               // split parts of Z
     return cv.bytes();
+}
+
+// Transform of the bf16 forms on packed operands (replaces the generic
+// staged kernels for these forms).
+template <int NS>
+static dmet_status xform_packed(const EriPlan& p, const void* lmunu, const double* ck, float* z, Carve& cv,
+                                hipStream_t st) {
+    PkDims d = pk_dims(p);
+    __bf16* plm = cv.take<__bf16>(d.lm_elems);
+    __bf16* pc1 = cv.take<__bf16>(d.c1_elems);
+    __bf16* pc2 = cv.take<__bf16>(d.c2_elems);
+    __bf16* ptt = cv.take<__bf16>(d.t_elems);
+    const int nk = p.mesh.nk;
+    const char* nm = NS == 3 ? "pack_in_bf16x6" : "pack_in_bf16x3";
+    {
+        ProfScope ps(nm, st);
+        if (p.dtype == DMET_C128)
+            k_pack_lmunu<NS, double><<<dim3((d.M1 + 255) / 256, d.ngv, nk * nk), 256, 0, st>>>(
+                static_cast<const double*>(lmunu), p.nao, d.nao_p, p.naux, d.ngv, plm);
+        else
+            k_pack_lmunu<NS, float><<<dim3((d.M1 + 255) / 256, d.ngv, nk * nk), 256, 0, st>>>(
+                static_cast<const float*>(lmunu), p.nao, d.nao_p, p.naux, d.ngv, plm);
+        k_pack_c1<NS><<<dim3((d.NB + 255) / 256, d.ngv, nk), 256, 0, st>>>(ck, nk, p.nspin, p.nao, p.neo, d.ngv, pc1);
+        k_pack_c2<NS><<<dim3((p.neo + 255) / 256, d.ng2, p.nspin), 256, 0, st>>>(ck, nk, p.nao, d.nao_p, p.neo,
+                                                                                 d.ng2, pc2);
+        // the padding group of T (if any) is read by stage 2 against zero A: make it zero
+        if (d.ng2 * 8 > nk * d.nao_p) {
+            const size_t part = (size_t)d.ng2 * d.N2 * 8;
+            for (int sp = 0; sp < p.nspin * 3 * NS; ++sp)
+                fill_zero(ptt + (size_t)sp * part + (size_t)(d.ng2 - 1) * d.N2 * 8, d.N2 * 8 * sizeof(__bf16), st);
+        }
+        ps.stop();
+    }
+    DMET_LAUNCH_CHECK("pack inputs");
+    auto k1 = k_xf1_pk<NS>;
+    auto k2 = k_xf2_pk<NS>;
+    DMET_HIP(hipFuncSetAttribute((const void*)k1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)xf1_lds<NS>()));
+    DMET_HIP(hipFuncSetAttribute((const void*)k2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)xf2_lds<NS>()));
+    const char* n1 = NS == 3 ? "xform1_bf16x6" : "xform1_bf16x3";
+    const char* n2 = NS == 3 ? "xform2_bf16x6" : "xform2_bf16x3";
+    const size_t ldz = (size_t)p.npair;
+    const int njt = (p.neo + 63) / 64, nit = (p.neo + 63) / 64;
+    const size_t t_spin = (size_t)3 * NS * d.ng2 * d.N2 * 8;
+    const size_t c2_spin = (size_t)3 * NS * d.ng2 * p.neo * 8;
+    for (const QBlock& qb : p.qblocks) {
+        ProfScope ps1(n1, st);
+        k1<<<dim3((d.M1 + 127) / 128, (d.NB + 127) / 128, nk), 256, xf1_lds<NS>(), st>>>(
+            p.mesh, qb.q, p.naux, d.nao_p, p.neo, p.nspin, d.ngv, d.ng2, plm, pc1, ptt);
+        ps1.stop();
+        DMET_LAUNCH_CHECK(n1);
+        for (int s = 0; s < p.nspin; ++s) {
+            ProfScope ps2(n2, st);
+            k2<<<dim3((unsigned)((long)p.naux * njt * nit)), 256, xf2_lds<NS>(), st>>>(
+                p.naux, p.neo, d.ng2, qb.self_conj, qb.zrow0, (float)qb.weight, pc2 + s * c2_spin, ptt + s * t_spin,
+                z + (size_t)s * p.zrows * ldz, ldz);
+            ps2.stop();
+            DMET_LAUNCH_CHECK(n2);
+        }
+    }
+    return DMET_OK;
 }
 
 template <int PREC, class K1, class K2, class K3, class K4>
@@ -848,7 +1271,8 @@ static dmet_status set_lds(K1 k1, K2 k2, K3 k3, K4 k4) {
 
 template <int PREC>
 static dmet_status eri_lp_run(const EriPlan& p, const void* lmunu, const double* ck, double* eri_aa,
-                              double* eri_bb, double* eri_ab, float* t, float* z, __bf16* zp, hipStream_t st) {
+                              double* eri_bb, double* eri_ab, float* t, float* z, __bf16* zp, Carve& cv,
+                              hipStream_t st) {
     using C1 = LpCfg<PREC, 3, L1_BM, L1_BN, L1_BK>;
     using C2 = LpCfg<PREC, 3, L2_BM, L2_BN, L2_BK>;
     using C3 = LpCfg<PREC, 1, LC_BM, LC_BN, LC_BK>;
@@ -872,7 +1296,11 @@ static dmet_status eri_lp_run(const EriPlan& p, const void* lmunu, const double*
     const size_t plane = (size_t)p.mesh.nk * p.nao * p.naux * p.neo;
     const size_t ldz = (size_t)p.npair;
     const int M1 = p.naux * p.nao;
-    for (int s = 0; s < p.nspin; ++s) {
+    if constexpr (PREC != LP_F32) {
+        dmet_status xs = xform_packed<NSplit<PREC>::value>(p, lmunu, ck, z, cv, st);
+        if (xs != DMET_OK) return xs;
+    }
+    for (int s = 0; s < (PREC == LP_F32 ? p.nspin : 0); ++s) {
         const double* cks = ck + (size_t)s * p.mesh.nk * p.nao * p.neo * 2;
         float* zs = z + (size_t)s * p.zrows * ldz;
         for (const QBlock& qb : p.qblocks) {
@@ -950,15 +1378,26 @@ static dmet_status eri_lp_run(const EriPlan& p, const void* lmunu, const double*
 
 dmet_status eri_lp(const EriPlan& p, const void* lmunu, const double* ck, double* eri_aa, double* eri_bb,
                    double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st) {
+    if (eri_lp_workspace(p) > ws_bytes) return fail(DMET_E_WORKSPACE, "transform_eri workspace too small");
     Carve cv(ws, ws_bytes);
-    float* t = cv.take<float>((size_t)3 * p.mesh.nk * p.nao * p.naux * p.neo);
+    // layout: [T planes (FP32 form) | packed transform operands (bf16 forms)] [Z] [Z parts]
+    Carve pre(ws, ws_bytes);
+    float* t = nullptr;
+    if (p.prec == DMET_FP32_3M) {
+        t = cv.take<float>((size_t)3 * p.mesh.nk * p.nao * p.naux * p.neo);
+    } else {
+        PkDims d = pk_dims(p);
+        cv.take<__bf16>(d.lm_elems);
+        cv.take<__bf16>(d.c1_elems);
+        cv.take<__bf16>(d.c2_elems);
+        cv.take<__bf16>(d.t_elems);
+    }
     float* z = cv.take<float>((size_t)p.nspin * p.zrows * p.npair);
     __bf16* zp = cv.take<__bf16>((size_t)p.nspin * packed_elems(p));
-    if (cv.bytes() > ws_bytes) return fail(DMET_E_WORKSPACE, "transform_eri workspace too small");
-    if (p.prec == DMET_FP32_3M) return eri_lp_run<LP_F32>(p, lmunu, ck, eri_aa, eri_bb, eri_ab, t, z, zp, st);
+    if (p.prec == DMET_FP32_3M) return eri_lp_run<LP_F32>(p, lmunu, ck, eri_aa, eri_bb, eri_ab, t, z, zp, pre, st);
     if (p.prec == DMET_BF16X3_3M)
-        return eri_lp_run<LP_BF16X3>(p, lmunu, ck, eri_aa, eri_bb, eri_ab, t, z, zp, st);
-    return eri_lp_run<LP_BF16X6>(p, lmunu, ck, eri_aa, eri_bb, eri_ab, t, z, zp, st);
+        return eri_lp_run<LP_BF16X3>(p, lmunu, ck, eri_aa, eri_bb, eri_ab, t, z, zp, pre, st);
+    return eri_lp_run<LP_BF16X6>(p, lmunu, ck, eri_aa, eri_bb, eri_ab, t, z, zp, pre, st);
 }
 
 }  // namespace dmet
