@@ -23,6 +23,8 @@
 // of row l%32).  BF16x3: K-inner, As[p][m][k] (a lane of 32x32x16 reads 8
 // consecutive k of row l%32 with one 16-byte load); K-outer sources are
 // transposed while they are staged (8 rows per thread).
+#include <stdlib.h>
+
 #include <vector>
 
 #include "common.h"
@@ -807,6 +809,131 @@ __global__ void __launch_bounds__(256) k_contract_dl(int npair, int kgroups, con
             }
 }
 
+// Variant sized for two workgroups per CU: 16-deep stages (72 KB ring for the
+// three-way split), at most 256 registers per lane (B fragments of a stage are
+// held, A fragments are loaded one part at a time), so two independent
+// workgroups interleave their waits on each CU.
+template <int NS, int MODE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_contract_d2(int npair, int kgroups, const __bf16* __restrict__ pa, const __bf16* __restrict__ pb, int flush_k,
+              long nblocks, double* __restrict__ out) {
+    constexpr int BM = 128, BN = 128, G = 2, NBUF = 3;
+    constexpr int TM = 2, TN = 2;
+    constexpr int PART = G * BM;
+    constexpr int STAGE = 2 * NS * PART;
+    constexpr int LOADS = 2 * NS * (PART / 256);
+    extern __shared__ __align__(16) bf8 ring[];
+    int mt, nt;
+    const long logical = xcd_logical(blockIdx.x, nblocks);
+    const int ntile = (npair + BM - 1) / BM;
+    if (!tile_of<MODE>(logical, ntile, mt, nt)) return;
+    const int m0 = mt * BM, n0 = nt * BN;
+    const bool diag = mt == nt;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
+    const size_t plane = (size_t)kgroups * npair;
+    const int nkt = kgroups / G;
+
+    auto issue = [&](int kt) {
+        bf8* st = ring + (size_t)(kt % NBUF) * STAGE;
+#pragma unroll
+        for (int t = 0; t < NS; ++t)
+#pragma unroll
+            for (int c = 0; c < PART / 256; ++c) {
+                const int first = wave * 64 + 256 * c;
+                const int g = first / BM, row0 = first % BM;
+                const size_t gg = (size_t)kt * G + g;
+                const int xa = min(m0 + row0 + lane, npair - 1), xb = min(n0 + row0 + lane, npair - 1);
+                __builtin_amdgcn_global_load_lds((const void*)(pa + (t * plane + gg * npair + xa) * 8),
+                                                 DMET_LDS_PTR(st + t * PART + first), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds((const void*)(pb + (t * plane + gg * npair + xb) * 8),
+                                                 DMET_LDS_PTR(st + (NS + t) * PART + first), 16, 0, 0);
+            }
+    };
+
+    f16v acc[TM][TN];
+    double acc64[TM][TN][16];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                acc[i][j][r] = 0.f;
+                acc64[i][j][r] = 0.0;
+            }
+#pragma unroll
+    for (int s2 = 0; s2 < NBUF - 1; ++s2)
+        if (s2 < nkt) issue(s2);
+    int since = 0;
+    const int g = lane >> 5;
+    for (int kt = 0; kt < nkt; ++kt) {
+        const int younger = min(NBUF - 2, nkt - 1 - kt);
+        if (younger >= 1) __builtin_amdgcn_s_waitcnt(0x0F70 | (LOADS & 15) | ((LOADS >> 4) << 14));
+        else __builtin_amdgcn_s_waitcnt(0x0F70);
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_sched_barrier(0);
+        if (kt + NBUF - 1 < nkt) issue(kt + NBUF - 1);
+        const bf8* sA = ring + (size_t)(kt % NBUF) * STAGE;
+        const bf8* sB = sA + NS * PART;
+        bf8 b[NS][TN];
+#pragma unroll
+        for (int t = 0; t < NS; ++t)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) b[t][j] = sB[t * PART + g * BN + wn0 + j * 32 + (lane & 31)];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+#pragma unroll
+            for (int ta = NS - 1; ta >= 0; --ta) {
+                const bf8 a = sA[ta * PART + g * BM + wm0 + i * 32 + (lane & 31)];
+                // products a_ta * b_tb with ta + tb <= NS - 1 (plus lo*lo on diagonal tiles for NS = 2)
+#pragma unroll
+                for (int tb = NS - 1 - ta; tb >= 0; --tb)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[tb][j], acc[i][j], 0, 0, 0);
+                if constexpr (NS == 2) {
+                    if (ta == 1 && diag)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[1][j], acc[i][j], 0, 0, 0);
+                }
+            }
+        }
+        since += 8 * G;
+        if (since >= flush_k || kt + 1 == nkt) {
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        acc64[i][j][r] += (double)acc[i][j][r];
+                        acc[i][j][r] = 0.f;
+                    }
+            since = 0;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int IJ = m0 + wm0 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int KL = n0 + wn0 + j * 32 + (lane & 31);
+                if (IJ >= npair || KL >= npair) continue;
+                if constexpr (MODE == 0) {
+                    if (KL <= IJ) out[(size_t)IJ * (IJ + 1) / 2 + KL] = acc64[i][j][r];
+                } else {
+                    out[(size_t)IJ * npair + KL] = acc64[i][j][r];
+                }
+            }
+}
+
+template <int NS>
+constexpr size_t d2_lds() { return (size_t)3 * 2 * NS * 2 * 128 * 16; }
+
 template <int NS>
 constexpr int dl_nbuf() { return NS == 3 ? 3 : 4; }
 template <int NS>
@@ -1014,10 +1141,18 @@ __global__ void __launch_bounds__(256) k_xf1_pk(Mesh mesh, int q, int naux, int 
                                                 __bf16* __restrict__ pt) {
     constexpr int BM = 128, BN = 128, TM = 2, TN = 2;
     extern __shared__ __align__(16) bf8 ring[];
-    const int k = blockIdx.z, nk = mesh.nk;
-    const int kmq = mesh_sub(mesh, k, q);
+    const int nk = mesh.nk;
     const int M1 = naux * nao_p, NB = nspin * neo;
-    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    // workgroup -> (k, m tile, n tile), n fastest, each XCD a contiguous run:
+    // the n tiles of one m tile share the lmunu panel in that XCD's L2
+    const int nmt = (M1 + BM - 1) / BM, nnt = (NB + BN - 1) / BN;
+    const long logical = xcd_logical(blockIdx.x, gridDim.x);
+    const long nt_all = (long)nk * nmt * nnt;
+    if (logical >= nt_all) return;
+    const int k = (int)(logical / ((long)nmt * nnt));
+    const int rem = (int)(logical % ((long)nmt * nnt));
+    const int m0 = (rem / nnt) * BM, n0 = (rem % nnt) * BN;
+    const int kmq = mesh_sub(mesh, k, q);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
     const __bf16* pa = plm + ((size_t)q * nk + k) * 3 * NS * (size_t)ngv * M1 * 8;
@@ -1104,7 +1239,7 @@ __global__ void __launch_bounds__(256) k_xf2_pk(int naux, int neo, int ng2, int 
     extern __shared__ __align__(16) bf8 ring[];
     const int njt = (neo + BN - 1) / BN, nit = (neo + BM - 1) / BM;
     // tile id -> (L, jt, it); consecutive ids share L (and so T columns in L2)
-    const long tid_ = blockIdx.x;
+    const long tid_ = xcd_logical(blockIdx.x, gridDim.x);
     const int per_l = njt * nit;
     const int L = (int)(tid_ / per_l), rem = (int)(tid_ % per_l);
     const int jt = rem / nit, it = rem % nit;
@@ -1144,6 +1279,13 @@ template <int NS>
 constexpr size_t xf2_lds() { return (size_t)2 * 3 * NS * 2 * (64 + 64) * 16; }
 
 // ------------------------------------------------------------------ driver
+// contraction kernel variant: 1 = k_contract_dl (one workgroup per CU, deep
+// ring), 2 = k_contract_d2 (two workgroups per CU); DMET_CONTRACT overrides.
+static int contract_variant() {
+    const char* e = getenv("DMET_CONTRACT");
+    return e && e[0] == '1' ? 1 : 2;
+}
+
 constexpr int L1_BM = 128, L1_BN = 64, L1_BK = 16;
 constexpr int L2_BM = 64, L2_BN = 64, L2_BK = 16;
 constexpr int LC_BM = 128, LC_BN = 128, LC_BK = 32;
@@ -1240,13 +1382,15 @@ static dmet_status xform_packed(const EriPlan& p, const void* lmunu, const doubl
     const size_t c2_spin = (size_t)3 * NS * d.ng2 * p.neo * 8;
     for (const QBlock& qb : p.qblocks) {
         ProfScope ps1(n1, st);
-        k1<<<dim3((d.M1 + 127) / 128, (d.NB + 127) / 128, nk), 256, xf1_lds<NS>(), st>>>(
+        const long nb1 = ((long)nk * ((d.M1 + 127) / 128) * ((d.NB + 127) / 128) + NXCD - 1) / NXCD * NXCD;
+        k1<<<dim3((unsigned)nb1), 256, xf1_lds<NS>(), st>>>(
             p.mesh, qb.q, p.naux, d.nao_p, p.neo, p.nspin, d.ngv, d.ng2, plm, pc1, ptt);
         ps1.stop();
         DMET_LAUNCH_CHECK(n1);
         for (int s = 0; s < p.nspin; ++s) {
             ProfScope ps2(n2, st);
-            k2<<<dim3((unsigned)((long)p.naux * njt * nit)), 256, xf2_lds<NS>(), st>>>(
+            const long nb2 = ((long)p.naux * njt * nit + NXCD - 1) / NXCD * NXCD;
+            k2<<<dim3((unsigned)nb2), 256, xf2_lds<NS>(), st>>>(
                 p.naux, p.neo, d.ng2, qb.self_conj, qb.zrow0, (float)qb.weight, pc2 + s * c2_spin, ptt + s * t_spin,
                 z + (size_t)s * p.zrows * ldz, ldz);
             ps2.stop();
@@ -1353,14 +1497,16 @@ static dmet_status eri_lp_run(const EriPlan& p, const void* lmunu, const double*
         }
         const int ntile = (p.npair + 127) / 128;
         constexpr int NB = dl_nbuf<NS>();
-        auto kd0 = k_contract_dl<NS, 0, NB>;
-        auto kd1 = k_contract_dl<NS, 1, NB>;
-        DMET_HIP(hipFuncSetAttribute((const void*)kd0, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dl_lds<NS>()));
-        DMET_HIP(hipFuncSetAttribute((const void*)kd1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dl_lds<NS>()));
+        const bool v2 = contract_variant() == 2;
+        auto kd0 = v2 ? k_contract_d2<NS, 0> : k_contract_dl<NS, 0, NB>;
+        auto kd1 = v2 ? k_contract_d2<NS, 1> : k_contract_dl<NS, 1, NB>;
+        const size_t lds = v2 ? d2_lds<NS>() : dl_lds<NS>();
+        DMET_HIP(hipFuncSetAttribute((const void*)kd0, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        DMET_HIP(hipFuncSetAttribute((const void*)kd1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         for (int s = 0; s < p.nspin; ++s) {
             const long nb = tile_grid<0>(ntile);
             ProfScope ps(n3, st);
-            kd0<<<dim3((unsigned)nb), 256, dl_lds<NS>(), st>>>(p.npair, kg, zp + s * per_spin, zp + s * per_spin,
+            kd0<<<dim3((unsigned)nb), 256, lds, st>>>(p.npair, kg, zp + s * per_spin, zp + s * per_spin,
                                                                FLUSH_K, nb, s == 0 ? eri_aa : eri_bb);
             ps.stop();
             DMET_LAUNCH_CHECK(n3);
@@ -1368,7 +1514,7 @@ static dmet_status eri_lp_run(const EriPlan& p, const void* lmunu, const double*
         if (p.nspin == 2 && eri_ab) {
             const long nb = tile_grid<1>(ntile);
             ProfScope ps(n4, st);
-            kd1<<<dim3((unsigned)nb), 256, dl_lds<NS>(), st>>>(p.npair, kg, zp, zp + per_spin, FLUSH_K, nb, eri_ab);
+            kd1<<<dim3((unsigned)nb), 256, lds, st>>>(p.npair, kg, zp, zp + per_spin, FLUSH_K, nb, eri_ab);
             ps.stop();
             DMET_LAUNCH_CHECK(n4);
         }
