@@ -116,12 +116,100 @@ def cpu_baseline(wl, lat, lm, n_l, n_rows):
             "seconds": t1 - t0}
 
 
+def run_batched(args, dev):
+    """Config-5-like batch: 64 fragments, neo ~ U{20..200}, supercell impurities,
+    2x2x2 / 3x3x3 meshes, nao 52, naux 400, complex64 3-index.  Times one batched
+    submission (graph replay, autotuned contraction tile) against the loop of
+    single-fragment calls, for each requested form."""
+    import torch
+    import synth
+    from paper_1909_08596_amd import dmet
+
+    t0 = time.perf_counter()
+    lats = {}
+    for name, wl in synth.BATCH_LATTICES.items():
+        lat = synth.make_lattice(wl)
+        lm = synth.three_index(wl).astype(np.complex64)
+        lats[name] = (wl, lat, torch.from_numpy(lm).to(dev), torch.from_numpy(lat.dm_k).to(dev))
+        del lm
+    specs_in = synth.batched_fragments(args.nfrag)
+    print(f"[bench] batched inputs in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    frags, wsum = [], 0.0
+    t0 = time.perf_counter()
+    for fs in specs_in:
+        wl, lat, lm_d, dm_d = lats[fs["lattice"]]
+        ck, sv, neo = dmet.dmet_build_bath(wl.kmesh, wl.nao, dm_d, imp_idx=fs["imp_idx"], val_idx=fs["val_idx"])
+        ck = ck[0, :, :, : neo[0]].contiguous()
+        frags.append({"kmesh": wl.kmesh, "nao": wl.nao, "naux": wl.naux, "lmunu": lm_d, "c_k": ck})
+        n = neo[0]
+        npair = n * (n + 1) // 2
+        wsum += 8.0 * wl.nk * wl.nk * wl.naux * (wl.nao * wl.nao * n + wl.nao * n * n)
+        wsum += wl.nk * wl.naux * npair * (npair + 1.0)
+    torch.cuda.synchronize()
+    t_bath = time.perf_counter() - t0
+    neos = [f["c_k"].shape[-1] for f in frags]
+    forms = [args.precision] + [p for p in args.compare.split(",") if p and p != args.precision and p != "fp64"]
+    out = {}
+    for prec in forms:
+        ws = torch.empty(dmet.dmet_transform_eri_batched_workspace(frags, prec), dtype=torch.uint8, device=dev)
+        for _ in range(max(1, args.warmup)):
+            dmet.dmet_transform_eri_batched(frags, prec, graph=True, autotune=True, workspace=ws)
+        torch.cuda.synchronize()
+        dmet.dmet_profile_reset()
+        dmet.dmet_profile_enable(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            dmet.dmet_transform_eri_batched(frags, prec, graph=True, autotune=True, workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        dmet.dmet_profile_enable(False)
+        ms_b = e0.elapsed_time(e1) / args.steps
+        ref = [f["eri"].clone() for f in frags]
+        # loop of single-fragment calls, same precision
+        loop_ws = torch.empty(max(dmet.dmet_transform_eri_workspace(f["kmesh"], f["nao"], f["naux"], 1,
+                                                                    f["c_k"].shape[-1], prec, f["lmunu"].dtype)
+                                  for f in frags), dtype=torch.uint8, device=dev)
+        outs = [{"aa": f["eri"]} for f in frags]
+        for f, o in zip(frags, outs):
+            dmet.dmet_transform_eri(f["kmesh"], f["nao"], f["naux"], f["lmunu"], f["c_k"][None], prec,
+                                    workspace=loop_ws, out=o)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            for f, o in zip(frags, outs):
+                dmet.dmet_transform_eri(f["kmesh"], f["nao"], f["naux"], f["lmunu"], f["c_k"][None], prec,
+                                        workspace=loop_ws, out=o)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_l = e0.elapsed_time(e1) / args.steps
+        same = all(torch.equal(a, o["aa"]) for a, o in zip(ref, outs))
+        out[prec] = {"ms_batched": round(ms_b, 3), "ms_loop": round(ms_l, 3),
+                     "speedup_batched_vs_loop": round(ms_l / ms_b, 3),
+                     "TFLOP/s": round(wsum / (ms_b * 1e-3) / 1e12, 3), "batched_equals_loop": bool(same)}
+        print(f"[bench] batched {prec}: {ms_b:.2f} ms vs loop {ms_l:.2f} ms; equal={same}", file=sys.stderr,
+              flush=True)
+        del ws, loop_ws
+    head = out[args.precision]
+    line = {
+        "metric": METRIC, "value": head["TFLOP/s"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_batched"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"bf16x3": "bf16x3", "bf16x6": "bf16x6", "fp32": "f32"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"batched: {len(frags)} fragments, neo {min(neos)}-{max(neos)} (mean "
+                               f"{sum(neos) / len(neos):.0f}), k-meshes 2x2x2 / 3x3x3, nao 52, naux 400, "
+                               f"supercell impurities, 3-index complex64", "W_flop": wsum},
+        "forms": out, "bath_s_all_fragments": round(t_bath, 3),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="nio", help="synthetic workload (tiny, hbn, si, nio)")
+    ap.add_argument("--config", default="nio", help="synthetic workload (tiny, hbn, si, nio, batched)")
     ap.add_argument("--precision", default="bf16x6", choices=["fp64", "fp32", "bf16x3", "bf16x6"],
                     help="form whose throughput is `value` (bf16x6: the fastest form within 1e-6 Ha)")
     ap.add_argument("--compare", default="fp64,fp32,bf16x3",
@@ -129,6 +217,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-l", type=int, default=0, help="fitting functions in the CPU sample (0: naux/2)")
     ap.add_argument("--cpu-sample-rows", type=int, default=16384)
+    ap.add_argument("--nfrag", type=int, default=64, help="fragments of the batched workload")
     ap.add_argument("--copy-calib-gib", type=float, default=0.0,
                     help="only run a plain device-to-device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -150,9 +239,12 @@ def main():
     import synth
     from paper_1909_08596_amd import dmet
 
-    wl = synth.CONFIGS[args.config]
     dev = torch.device("cuda:0")
     dmet.load()
+    if args.config == "batched":
+        run_batched(args, dev)
+        return
+    wl = synth.CONFIGS[args.config]
     print(f"[bench] generating {wl.name} inputs", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     lat = synth.make_lattice(wl)

@@ -185,6 +185,49 @@ dmet_status dmet_transform_eri(const dmet_lattice* lat, int neo, const void* lmu
                                void* workspace, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Batched embedding ERIs (Alg. 1 for many fragments in one submission).
+ *
+ * Every fragment is an embedding problem of its own (its own impurity, bath
+ * and neo) on a lattice that may be shared: fragments whose `lmunu` pointers
+ * are equal share the 3-index tensor, and the k-AO -> k-EO transform of that
+ * tensor is done once for all of them (their C^k are concatenated as one GEMM
+ * operand).  The remaining work of all fragments -- the embedded 3-index for
+ * each q and the packed contraction -- runs in persistent kernels that pop
+ * (fragment, tile) items from a device work queue, largest first.
+ *
+ * frags    host array of nfrag descriptors; lat.nspin must be 1; fragments
+ *          that share lmunu must share lat and dtype.
+ * prec     DMET_BF16X3_3M or DMET_BF16X6_3M run the batched pipeline above;
+ *          DMET_FP64 and DMET_FP32_3M run the single-fragment path for each
+ *          fragment in turn (same results as dmet_transform_eri).
+ * flags    DMET_BATCH_GRAPH: capture the whole submission into a hipGraph on the
+ *            first call with a given batch (descriptors, precision, workspace)
+ *            and replay it on later calls (inputs may change, pointers may not);
+ *          DMET_BATCH_AUTOTUNE: on the first call for a batch shape, time the
+ *            contraction tile variants on this batch and keep the fastest (kept
+ *            per process, and in the file named by $DMET_TUNE_CACHE if set).
+ * workspace at least dmet_transform_eri_batched_workspace(); with
+ *          DMET_BATCH_GRAPH it must stay valid for the replays.
+ * Asynchronous (the first autotuned call synchronises `stream`).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    dmet_lattice lat;        /* kmesh, nao, naux; nspin = 1                    */
+    int neo;                 /* embedding orbitals of this fragment            */
+    const void* lmunu;       /* [N_k q][N_k k][naux][nao][nao], `dtype`        */
+    dmet_dtype dtype;
+    const void* c_k;         /* [N_k][nao][neo] complex128                     */
+    double* eri;             /* out s8 [npair(npair+1)/2] float64              */
+} dmet_fragment;
+
+enum { DMET_BATCH_GRAPH = 1, DMET_BATCH_AUTOTUNE = 2 };
+
+dmet_status dmet_transform_eri_batched_workspace(int nfrag, const dmet_fragment* frags,
+                                                 dmet_precision prec, size_t* bytes);
+dmet_status dmet_transform_eri_batched(int nfrag, const dmet_fragment* frags, dmet_precision prec,
+                                       unsigned flags, void* workspace, size_t ws_bytes,
+                                       hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Optional per-kernel timing (not part of the method): when enabled, every
  * kernel launch of the entry points above is bracketed by a pair of HIP events
  * recorded on the launch's stream.  dmet_profile_report() waits for those

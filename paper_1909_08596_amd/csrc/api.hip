@@ -218,6 +218,44 @@ dmet_status dmet_transform_eri(const dmet_lattice* lat, int neo, const void* lmu
     return eri_lp(p, lmunu, static_cast<const double*>(c_k), eri_aa, eri_bb, eri_ab, workspace, ws_bytes, stream);
 }
 
+static dmet_status check_batch(int nfrag, const dmet_fragment* frags, dmet_precision prec) {
+    if (nfrag < 1 || nfrag > 65535 || !frags) return fail(DMET_E_ARG, "need 1 <= nfrag <= 65535 fragments");
+    for (int f = 0; f < nfrag; ++f) {
+        const dmet_fragment& d = frags[f];
+        dmet_status s = check_eri_args(&d.lat, d.neo, prec, d.dtype);
+        if (s != DMET_OK) return fail(s, "fragment " + std::to_string(f) + ": " + dmet_last_error());
+        if (d.lat.nspin != 1) return fail(DMET_E_ARG, "fragment " + std::to_string(f) + ": nspin must be 1");
+        if (!d.lmunu || !d.c_k || !d.eri) return fail(DMET_E_ARG, "fragment " + std::to_string(f) + ": null pointer");
+        for (int g = 0; g < f; ++g)
+            if (frags[g].lmunu == d.lmunu &&
+                (frags[g].dtype != d.dtype || frags[g].lat.nao != d.lat.nao || frags[g].lat.naux != d.lat.naux ||
+                 frags[g].lat.kmesh[0] != d.lat.kmesh[0] || frags[g].lat.kmesh[1] != d.lat.kmesh[1] ||
+                 frags[g].lat.kmesh[2] != d.lat.kmesh[2]))
+                return fail(DMET_E_ARG, "fragments sharing lmunu must share the lattice and dtype");
+    }
+    return DMET_OK;
+}
+
+dmet_status dmet_transform_eri_batched_workspace(int nfrag, const dmet_fragment* frags, dmet_precision prec,
+                                                 size_t* bytes) {
+    dmet_status s = check_batch(nfrag, frags, prec);
+    if (s != DMET_OK) return s;
+    if (!bytes) return fail(DMET_E_ARG, "bytes is NULL");
+    *bytes = batch_workspace(nfrag, frags, prec);
+    return DMET_OK;
+}
+
+dmet_status dmet_transform_eri_batched(int nfrag, const dmet_fragment* frags, dmet_precision prec, unsigned flags,
+                                       void* workspace, size_t ws_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    dmet_status s = check_batch(nfrag, frags, prec);
+    if (s != DMET_OK) return s;
+    if (flags & ~(unsigned)(DMET_BATCH_GRAPH | DMET_BATCH_AUTOTUNE)) return fail(DMET_E_ARG, "unknown flag bits");
+    if (!workspace) return fail(DMET_E_WORKSPACE, "workspace is NULL");
+    if (batch_workspace(nfrag, frags, prec) > ws_bytes) return fail(DMET_E_WORKSPACE, "batched workspace too small");
+    return eri_batched(nfrag, frags, prec, flags, workspace, ws_bytes, stream);
+}
+
 dmet_status dmet_profile_enable(int on) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_on = on != 0;

@@ -37,6 +37,10 @@ size_t eri_lp_workspace(const EriPlan& p);
 dmet_status eri_lp(const EriPlan& p, const void* lmunu, const double* ck, double* eri_aa, double* eri_bb,
                    double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st);
 
+size_t batch_workspace(int nfrag, const dmet_fragment* frags, dmet_precision prec);
+dmet_status eri_batched(int nfrag, const dmet_fragment* frags, dmet_precision prec, unsigned flags, void* ws,
+                        size_t ws_bytes, hipStream_t st);
+
 // bath / one-body (bath.hip, onebody.hip)
 size_t bath_workspace_bytes(const dmet_lattice* lat, int nimp, int nval);
 dmet_status build_bath(const dmet_lattice* lat, const double2* dm_k, int nimp, const int* imp_idx,

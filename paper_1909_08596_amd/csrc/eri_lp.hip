@@ -23,7 +23,14 @@
 // of row l%32).  BF16x3: K-inner, As[p][m][k] (a lane of 32x32x16 reads 8
 // consecutive k of row l%32 with one 16-byte load); K-outer sources are
 // transposed while they are staged (8 rows per thread).
+#include <stdio.h>
 #include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
 
 #include <vector>
 
@@ -987,7 +994,7 @@ __global__ void k_pack_lmunu(const TIn* __restrict__ lm, int nao, int nao_p, int
 // C^k[s][k][nu][j] -> P1c[k][plane][part][nu/8][s*neo + j][8]   (planes Cr, Ci, Cr + Ci)
 template <int NS>
 __global__ void k_pack_c1(const double* __restrict__ ck, int nk, int nspin, int nao, int neo, int ngv,
-                          __bf16* __restrict__ out) {
+                          __bf16* __restrict__ out, int col0, int nb_total) {
     const int nb = nspin * neo;
     const int col = blockIdx.x * blockDim.x + threadIdx.x;
     const int g = blockIdx.y, k = blockIdx.z;
@@ -1012,13 +1019,13 @@ __global__ void k_pack_c1(const double* __restrict__ ck, int nk, int nspin, int 
             for (int t = 0; t < NS; ++t) part[p][t][v] = sp[t];
         }
     }
-    const size_t per_k = (size_t)3 * NS * ngv * nb;
+    const size_t per_k = (size_t)3 * NS * ngv * nb_total;
 #pragma unroll
     for (int p = 0; p < 3; ++p)
 #pragma unroll
         for (int t = 0; t < NS; ++t)
-            *reinterpret_cast<bf8*>(out + ((size_t)k * per_k + ((size_t)(p * NS + t) * ngv + g) * nb + col) * 8) =
-                part[p][t];
+            *reinterpret_cast<bf8*>(
+                out + ((size_t)k * per_k + ((size_t)(p * NS + t) * ngv + g) * nb_total + col0 + col) * 8) = part[p][t];
 }
 
 // conj(C^k)[s][(k,mu)][i] -> P2c[s][plane][part][(k*nao_p + mu)/8][i][8]  (planes Cr, -Ci, Cr - Ci)
@@ -1273,6 +1280,298 @@ __global__ void __launch_bounds__(256) k_xf2_pk(int naux, int neo, int ng2, int 
     }
 }
 
+// ------------------------------------------------------------------ batched pipeline
+// Per-fragment data read by the batched kernels.
+struct BFrag {
+    const __bf16* pc2;   // packed conj(C) [plane][part][ng2][neo][8]
+    __bf16* ptt;         // packed T of the current q [plane][part][ng2][naux*neo][8]
+    float* z;            // Z rows [zrows][npair]
+    const __bf16* zp;    // packed parts of Z [part][kgroups][npair][8]
+    double* eri;         // s8 output
+    int neo, naux, ng2, npair, zrows, kgroups;
+};
+
+// Per (round, fragment) q-block of the stage-2 items.
+struct BQ {
+    int self_conj;
+    int pad;
+    size_t zrow0;
+    float wq;
+};
+
+// Stage-2 work item: fragment slot, fitting function, j tile, i tile.
+struct BItem2 {
+    int slot, L, jt, it;
+};
+
+// Contraction work item: fragment slot and output tile (mt >= nt).
+struct BItemC {
+    int slot, mt, nt, pad;
+};
+
+// Stage 1 of a group of fragments sharing one 3-index tensor: columns of the
+// concatenated C^{k-q} are routed to their fragment by `colmap` (slot, j).
+template <int NS>
+__global__ void __launch_bounds__(256) k_xf1_batched(Mesh mesh, int q, int naux, int nao_p, int nbtot, int ngv,
+                                                     const int2* __restrict__ colmap,
+                                                     const BFrag* __restrict__ frags,
+                                                     const __bf16* __restrict__ plm, const __bf16* __restrict__ pc1) {
+    constexpr int BM = 128, BN = 128, TM = 2, TN = 2;
+    extern __shared__ __align__(16) bf8 ring[];
+    const int nk = mesh.nk;
+    const int M1 = naux * nao_p, NB = nbtot;
+    const int nmt = (M1 + BM - 1) / BM, nnt = (NB + BN - 1) / BN;
+    const long logical = xcd_logical(blockIdx.x, gridDim.x);
+    if (logical >= (long)nk * nmt * nnt) return;
+    const int k = (int)(logical / ((long)nmt * nnt));
+    const int rem = (int)(logical % ((long)nmt * nnt));
+    const int m0 = (rem / nnt) * BM, n0 = (rem % nnt) * BN;
+    const int kmq = mesh_sub(mesh, k, q);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
+    const __bf16* pa = plm + ((size_t)q * nk + k) * 3 * NS * (size_t)ngv * M1 * 8;
+    const __bf16* pb = pc1 + (size_t)kmq * 3 * NS * (size_t)ngv * NB * 8;
+    f16v acc[3][TM][TN];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[p][i][j][r] = 0.f;
+    pk_loop3<NS, BM, BN, TM, TN>(pa, (size_t)ngv * M1, M1, m0, pb, (size_t)ngv * NB, NB, n0, ngv / 2, ring, wm0,
+                                 wn0, acc);
+    const int h = lane >> 5;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int col = n0 + wn0 + j * 32 + (lane & 31);
+            int2 cm = make_int2(-1, 0);
+            if (col < NB) cm = colmap[col];
+#pragma unroll
+            for (int qq = 0; qq < 4; qq += 2) {
+                float pl[3][8];
+#pragma unroll
+                for (int p3 = 0; p3 < 3; ++p3) {
+                    float mine[4], send[4], recv[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float p1 = acc[0][i][j][4 * qq + r], p2 = acc[1][i][j][4 * qq + r],
+                                    p3v = acc[2][i][j][4 * qq + r];
+                        const float p1b = acc[0][i][j][4 * (qq + 1) + r], p2b = acc[1][i][j][4 * (qq + 1) + r],
+                                    p3b = acc[2][i][j][4 * (qq + 1) + r];
+                        const float va = p3 == 0 ? p1 - p2 : (p3 == 1 ? p3v - p1 - p2 : p3v - 2.f * p2);
+                        const float vb = p3 == 0 ? p1b - p2b : (p3 == 1 ? p3b - p1b - p2b : p3b - 2.f * p2b);
+                        mine[r] = h == 0 ? va : vb;
+                        send[r] = h == 0 ? vb : va;
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) recv[r] = __shfl_xor(send[r], 32, 64);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        pl[p3][h == 0 ? r : 4 + r] = mine[r];
+                        pl[p3][h == 0 ? 4 + r : r] = recv[r];
+                    }
+                }
+                const int grp_row = m0 + wm0 + i * 32 + 8 * (qq + h);
+                if (cm.x >= 0 && grp_row < M1) {
+                    const BFrag fr = frags[cm.x];
+                    const int L = grp_row / nao_p, mu0 = grp_row % nao_p;
+                    const size_t N2 = (size_t)naux * fr.neo;
+                    const size_t g2 = ((size_t)k * nao_p + mu0) / 8;
+                    const size_t x = (size_t)L * fr.neo + cm.y;
+#pragma unroll
+                    for (int p3 = 0; p3 < 3; ++p3) {
+                        bf8 part[NS];
+#pragma unroll
+                        for (int v = 0; v < 8; ++v) {
+                            __bf16 sp[NS];
+                            split_bf16<NS>(pl[p3][v], sp);
+#pragma unroll
+                            for (int t = 0; t < NS; ++t) part[t][v] = sp[t];
+                        }
+#pragma unroll
+                        for (int t = 0; t < NS; ++t)
+                            *reinterpret_cast<bf8*>(fr.ptt + (((size_t)(p3 * NS + t) * fr.ng2 + g2) * N2 + x) * 8) =
+                                part[t];
+                    }
+                }
+            }
+        }
+}
+
+// Stage 2 over the items of one round (all fragments).
+template <int NS>
+__global__ void __launch_bounds__(256) k_xf2_batched(int nitems, const BItem2* __restrict__ items,
+                                                     const BFrag* __restrict__ frags, const BQ* __restrict__ qs) {
+    constexpr int BM = 64, BN = 64, TM = 1, TN = 1;
+    extern __shared__ __align__(16) bf8 ring[];
+    const long it_id = xcd_logical(blockIdx.x, gridDim.x);
+    if (it_id >= nitems) return;
+    const BItem2 item = items[it_id];
+    const BFrag fr = frags[item.slot];
+    const BQ qb = qs[item.slot];
+    const int neo = fr.neo, naux = fr.naux, L = item.L;
+    const int m0 = item.it * BM, j0 = item.jt * BN;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
+    const int N2 = naux * neo;
+    f16v acc[3][TM][TN];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[p][0][0][r] = 0.f;
+    pk_loop3<NS, BM, BN, TM, TN>(fr.pc2, (size_t)fr.ng2 * neo, neo, m0, fr.ptt, (size_t)fr.ng2 * N2, N2,
+                                 L * neo + j0, fr.ng2 / 2, ring, wm0, wn0, acc);
+    const size_t ldz = (size_t)fr.npair;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = m0 + wm0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int j = j0 + wn0 + (lane & 31);
+        if (i >= neo || j >= neo || j > i) continue;
+        const size_t pair = (size_t)i * (i + 1) / 2 + j;
+        const float p1 = acc[0][0][0][r], p2 = acc[1][0][0][r], p3 = acc[2][0][0][r];
+        const float xr = p1 - p2, xi = p3 - p1 - p2;
+        if (qb.self_conj) {
+            fr.z[(qb.zrow0 + L) * ldz + pair] = qb.wq * xr;
+        } else {
+            fr.z[(qb.zrow0 + 2 * (size_t)L) * ldz + pair] = qb.wq * xr;
+            fr.z[(qb.zrow0 + 2 * (size_t)L + 1) * ldz + pair] = qb.wq * xi;
+        }
+    }
+}
+
+// Persistent packed contraction over the tiles of all fragments.  Workgroup b
+// pops items from the queue of XCD b % 8 (items of one 8 x 8 super-block of one
+// fragment are in one queue, so tiles sharing panels run on one XCD).
+// BM = 128: two workgroups per CU, 3-stage ring; BM = 64: 2-stage ring.
+template <int NS, int BM>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_contract_persist(const int* __restrict__ qstart, const int* __restrict__ qlen, int* __restrict__ qctr,
+                   const BItemC* __restrict__ items, const BFrag* __restrict__ frags, int flush_k) {
+    constexpr int BN = BM, G = 2;
+    constexpr int NBUF = BM == 128 ? 3 : 2;
+    constexpr int TM = BM / 64, TN = BN / 64;
+    constexpr int PART = G * BM;
+    constexpr int STAGE = 2 * NS * PART;
+    constexpr int WM = BM / 2, WN = BN / 2;
+    extern __shared__ __align__(16) bf8 ring[];
+    __shared__ int s_item;
+    const int xcd = blockIdx.x % NXCD;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
+    const int g = lane >> 5;
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) s_item = atomicAdd(&qctr[xcd], 1);
+        __syncthreads();
+        const int idx = s_item;
+        if (idx >= qlen[xcd]) break;
+        const BItemC item = items[qstart[xcd] + idx];
+        const BFrag fr = frags[item.slot];
+        const int npair = fr.npair, nkt = fr.kgroups / G;
+        const int m0 = item.mt * BM, n0 = item.nt * BN;
+        const bool diag = item.mt == item.nt;
+        const size_t plane = (size_t)fr.kgroups * npair;
+        const __bf16* pa = fr.zp;
+
+        auto issue = [&](int kt) {
+            bf8* st = ring + (size_t)(kt % NBUF) * STAGE;
+            for (int first = wave * 64; first < NS * PART; first += 256) {
+                const int t = first / PART, w = first % PART, gg = w / BM, row0 = w % BM;
+                const size_t grp = (size_t)kt * G + gg;
+                const int xa = min(m0 + row0 + lane, npair - 1), xb = min(n0 + row0 + lane, npair - 1);
+                __builtin_amdgcn_global_load_lds((const void*)(pa + (t * plane + grp * npair + xa) * 8),
+                                                 DMET_LDS_PTR(st + first), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds((const void*)(pa + (t * plane + grp * npair + xb) * 8),
+                                                 DMET_LDS_PTR(st + NS * PART + first), 16, 0, 0);
+            }
+        };
+
+        f16v acc[TM][TN];
+        double acc64[TM][TN][16];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    acc[i][j][r] = 0.f;
+                    acc64[i][j][r] = 0.0;
+                }
+        for (int s2 = 0; s2 < NBUF - 1; ++s2)
+            if (s2 < nkt) issue(s2);
+        int since = 0;
+        for (int kt = 0; kt < nkt; ++kt) {
+            // with NBUF = 3 the loads of one younger stage may stay in flight; every
+            // wave issues the same number of loads per stage when BM = 128
+            if constexpr (NBUF == 3) {
+                constexpr int LOADS = 2 * NS * (PART / 256);
+                if (kt + 1 < nkt) __builtin_amdgcn_s_waitcnt(0x0F70 | (LOADS & 15) | ((LOADS >> 4) << 14));
+                else __builtin_amdgcn_s_waitcnt(0x0F70);
+            } else {
+                __builtin_amdgcn_s_waitcnt(0x0F70);
+            }
+            __builtin_amdgcn_s_barrier();
+            __builtin_amdgcn_sched_barrier(0);
+            if (kt + NBUF - 1 < nkt) issue(kt + NBUF - 1);
+            const bf8* sA = ring + (size_t)(kt % NBUF) * STAGE;
+            const bf8* sB = sA + NS * PART;
+            bf8 b[NS][TN];
+#pragma unroll
+            for (int t = 0; t < NS; ++t)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) b[t][j] = sB[t * PART + g * BN + wn0 + j * 32 + (lane & 31)];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+#pragma unroll
+                for (int ta = NS - 1; ta >= 0; --ta) {
+                    const bf8 a = sA[ta * PART + g * BM + wm0 + i * 32 + (lane & 31)];
+#pragma unroll
+                    for (int tb = NS - 1 - ta; tb >= 0; --tb)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[tb][j], acc[i][j], 0, 0, 0);
+                    if constexpr (NS == 2) {
+                        if (ta == 1 && diag)
+#pragma unroll
+                            for (int j = 0; j < TN; ++j)
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[1][j], acc[i][j], 0, 0, 0);
+                    }
+                }
+            }
+            since += 8 * G;
+            if (since >= flush_k || kt + 1 == nkt) {
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            acc64[i][j][r] += (double)acc[i][j][r];
+                            acc[i][j][r] = 0.f;
+                        }
+                since = 0;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int IJ = m0 + wm0 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    const int KL = n0 + wn0 + j * 32 + (lane & 31);
+                    if (IJ < npair && KL <= IJ) fr.eri[(size_t)IJ * (IJ + 1) / 2 + KL] = acc64[i][j][r];
+                }
+    }
+}
+
+template <int NS, int BM>
+constexpr size_t persist_lds() { return (size_t)(BM == 128 ? 3 : 2) * 2 * NS * 2 * BM * 16; }
+
 template <int NS>
 constexpr size_t xf1_lds() { return (size_t)2 * 3 * NS * 2 * (128 + 128) * 16; }
 template <int NS>
@@ -1358,7 +1657,8 @@ static dmet_status xform_packed(const EriPlan& p, const void* lmunu, const doubl
         else
             k_pack_lmunu<NS, float><<<dim3((d.M1 + 255) / 256, d.ngv, nk * nk), 256, 0, st>>>(
                 static_cast<const float*>(lmunu), p.nao, d.nao_p, p.naux, d.ngv, plm);
-        k_pack_c1<NS><<<dim3((d.NB + 255) / 256, d.ngv, nk), 256, 0, st>>>(ck, nk, p.nspin, p.nao, p.neo, d.ngv, pc1);
+        k_pack_c1<NS><<<dim3((d.NB + 255) / 256, d.ngv, nk), 256, 0, st>>>(ck, nk, p.nspin, p.nao, p.neo, d.ngv, pc1,
+                                                                          0, d.NB);
         k_pack_c2<NS><<<dim3((p.neo + 255) / 256, d.ng2, p.nspin), 256, 0, st>>>(ck, nk, p.nao, d.nao_p, p.neo,
                                                                                  d.ng2, pc2);
         // the padding group of T (if any) is read by stage 2 against zero A: make it zero
@@ -1544,6 +1844,537 @@ dmet_status eri_lp(const EriPlan& p, const void* lmunu, const double* ck, double
     if (p.prec == DMET_BF16X3_3M)
         return eri_lp_run<LP_BF16X3>(p, lmunu, ck, eri_aa, eri_bb, eri_ab, t, z, zp, pre, st);
     return eri_lp_run<LP_BF16X6>(p, lmunu, ck, eri_aa, eri_bb, eri_ab, t, z, zp, pre, st);
+}
+
+}  // namespace dmet
+
+// ====================================================================== batched driver
+namespace dmet {
+
+struct BatchGroup {
+    const void* lm;
+    dmet_dtype dt;
+    Mesh mesh;
+    int nao, naux, nao_p, ngv, ng2, M1, nbtot;
+    std::vector<int> members;
+    std::vector<QBlock> qbs;
+    size_t off_plm, off_pc1, off_colmap;
+};
+
+struct BatchFrag {
+    int group, neo, npair, zrows, kgroups, col0;
+    size_t off_pc2, off_ptt, off_z, off_zp;
+};
+
+struct BatchPlan {
+    std::vector<dmet_fragment> frags;
+    int prec = 0, ns = 0;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    std::vector<BatchGroup> groups;
+    std::vector<BatchFrag> fs;
+    int rounds = 0;
+    size_t off_bfrag = 0, off_items2 = 0, off_bq = 0, off_itemsc = 0, off_q = 0;
+    std::vector<int> items2_off, items2_cnt;
+    std::vector<BFrag> h_bfrag;
+    std::vector<int2> h_colmap;
+    std::vector<BItem2> h_items2;
+    std::vector<BQ> h_bq;
+    std::vector<BItemC> h_itemsc[2];   // per contraction tile size (128, 64)
+    std::vector<int> h_qstart[2], h_qlen[2];
+    size_t bytes = 0;
+    int variant = 128;
+    bool uploaded = false;
+    hipGraphExec_t exec = nullptr;
+    std::string key;
+};
+
+static std::mutex g_batch_mu;
+static std::map<std::string, BatchPlan*> g_batch_plans;
+static std::map<std::string, int> g_tune;   // shape key -> chosen contraction tile
+
+static std::string batch_key(int nfrag, const dmet_fragment* f, int prec, bool with_ptrs, void* ws, size_t wsb) {
+    std::string k = std::to_string(prec) + ":" + std::to_string(nfrag);
+    char buf[256];
+    for (int i = 0; i < nfrag; ++i) {
+        snprintf(buf, sizeof(buf), "|%d,%d,%d,%d,%d,%d,%d", f[i].lat.kmesh[0], f[i].lat.kmesh[1], f[i].lat.kmesh[2],
+                 f[i].lat.nao, f[i].lat.naux, f[i].neo, (int)f[i].dtype);
+        k += buf;
+        if (with_ptrs) {
+            snprintf(buf, sizeof(buf), "@%p,%p,%p", f[i].lmunu, f[i].c_k, (void*)f[i].eri);
+            k += buf;
+        }
+    }
+    if (with_ptrs) {
+        snprintf(buf, sizeof(buf), "#%p,%zu", ws, wsb);
+        k += buf;
+    }
+    return k;
+}
+
+// Build groups, per-fragment dims, workspace offsets and the work lists.
+static void plan_batch(BatchPlan& bp) {
+    const int nfrag = (int)bp.frags.size();
+    bp.ns = bp.prec == DMET_BF16X6_3M ? 3 : 2;
+    const int NS = bp.ns;
+    // groups by lmunu pointer
+    for (int f = 0; f < nfrag; ++f) {
+        const dmet_fragment& d = bp.frags[f];
+        int g = -1;
+        for (size_t i = 0; i < bp.groups.size(); ++i)
+            if (bp.groups[i].lm == d.lmunu) g = (int)i;
+        if (g < 0) {
+            BatchGroup G;
+            G.lm = d.lmunu;
+            G.dt = d.dtype;
+            G.mesh = make_mesh(d.lat.kmesh);
+            G.nao = d.lat.nao;
+            G.naux = d.lat.naux;
+            G.nao_p = (G.nao + 7) / 8 * 8;
+            G.ngv = (G.nao_p / 8 + 1) / 2 * 2;
+            G.ng2 = (G.mesh.nk * G.nao_p / 8 + 1) / 2 * 2;
+            G.M1 = G.naux * G.nao_p;
+            G.nbtot = 0;
+            dmet_lattice lat1 = d.lat;
+            lat1.nspin = 1;
+            G.qbs = make_eri_plan(&lat1, d.neo, (dmet_precision)bp.prec, d.dtype).qblocks;
+            bp.groups.push_back(G);
+            g = (int)bp.groups.size() - 1;
+        }
+        BatchGroup& G = bp.groups[g];
+        BatchFrag F;
+        F.group = g;
+        F.neo = d.neo;
+        F.npair = d.neo * (d.neo + 1) / 2;
+        F.zrows = G.mesh.nk * G.naux;
+        F.kgroups = (F.zrows + 31) / 32 * 4;
+        F.col0 = G.nbtot;
+        G.nbtot += d.neo;
+        G.members.push_back(f);
+        bp.fs.push_back(F);
+    }
+    bp.rounds = 0;
+    for (auto& G : bp.groups) bp.rounds = std::max(bp.rounds, (int)G.qbs.size());
+    // work lists
+    bp.h_bfrag.resize(nfrag);
+    bp.h_bq.assign((size_t)bp.rounds * nfrag, BQ{0, 0, 0, 0.f});
+    bp.items2_off.assign(bp.rounds, 0);
+    bp.items2_cnt.assign(bp.rounds, 0);
+    for (int r = 0; r < bp.rounds; ++r) {
+        bp.items2_off[r] = (int)bp.h_items2.size();
+        for (int f = 0; f < nfrag; ++f) {
+            const BatchFrag& F = bp.fs[f];
+            const BatchGroup& G = bp.groups[F.group];
+            if (r >= (int)G.qbs.size()) continue;
+            const QBlock& qb = G.qbs[r];
+            bp.h_bq[(size_t)r * nfrag + f] = BQ{qb.self_conj, 0, qb.zrow0, (float)qb.weight};
+            const int nt = (F.neo + 63) / 64;
+            for (int L = 0; L < G.naux; ++L)
+                for (int jt = 0; jt < nt; ++jt)
+                    for (int it = jt; it < nt; ++it) bp.h_items2.push_back(BItem2{f, L, jt, it});
+        }
+        bp.items2_cnt[r] = (int)bp.h_items2.size() - bp.items2_off[r];
+    }
+    for (int v = 0; v < 2; ++v) {
+        const int BM = v == 0 ? 128 : 64;
+        // chunks = 8x8 super-blocks of one fragment, largest contraction depth first
+        struct Chunk {
+            int f, I, J, k;
+        };
+        std::vector<Chunk> ch;
+        for (int f = 0; f < nfrag; ++f) {
+            const int nt = (bp.fs[f].npair + BM - 1) / BM, nsb = (nt + 7) / 8;
+            for (int I = 0; I < nsb; ++I)
+                for (int J = 0; J <= I; ++J) ch.push_back(Chunk{f, I, J, bp.fs[f].zrows});
+        }
+        std::stable_sort(ch.begin(), ch.end(), [](const Chunk& a, const Chunk& b) { return a.k > b.k; });
+        std::vector<std::vector<BItemC>> q(NXCD);
+        for (size_t c = 0; c < ch.size(); ++c) {
+            const int nt = (bp.fs[ch[c].f].npair + BM - 1) / BM;
+            for (int a = 0; a < 8; ++a)
+                for (int b = 0; b < 8; ++b) {
+                    const int mt = ch[c].I * 8 + a, ntt = ch[c].J * 8 + b;
+                    if (mt < nt && ntt < nt && ntt <= mt) q[c % NXCD].push_back(BItemC{ch[c].f, mt, ntt, 0});
+                }
+        }
+        bp.h_itemsc[v].clear();
+        bp.h_qstart[v].assign(NXCD, 0);
+        bp.h_qlen[v].assign(NXCD, 0);
+        for (int x = 0; x < NXCD; ++x) {
+            bp.h_qstart[v][x] = (int)bp.h_itemsc[v].size();
+            bp.h_qlen[v][x] = (int)q[x].size();
+            bp.h_itemsc[v].insert(bp.h_itemsc[v].end(), q[x].begin(), q[x].end());
+        }
+    }
+    // column maps
+    for (auto& G : bp.groups) {
+        G.off_colmap = bp.h_colmap.size();
+        for (int f : G.members)
+            for (int j = 0; j < bp.fs[f].neo; ++j) bp.h_colmap.push_back(make_int2(f, j));
+    }
+    // workspace layout: tables, then per group, then per fragment (256-byte aligned)
+    size_t cur = 0;
+    auto off = [&](size_t bytes) {
+        const size_t o = (cur + 255) & ~size_t(255);
+        cur = o + bytes;
+        return o;
+    };
+    bp.off_bfrag = off(sizeof(BFrag) * nfrag);
+    const size_t colmap_off = off(sizeof(int2) * bp.h_colmap.size());
+    for (auto& G : bp.groups) G.off_colmap = colmap_off + G.off_colmap * sizeof(int2);
+    bp.off_items2 = off(sizeof(BItem2) * std::max<size_t>(1, bp.h_items2.size()));
+    bp.off_bq = off(sizeof(BQ) * std::max<size_t>(1, bp.h_bq.size()));
+    bp.off_itemsc = off(sizeof(BItemC) * std::max(bp.h_itemsc[0].size(), bp.h_itemsc[1].size()) + 16);
+    bp.off_q = off(sizeof(int) * 3 * NXCD);
+    const size_t pl = (size_t)3 * NS * 8;
+    for (auto& G : bp.groups) {
+        G.off_plm = off(sizeof(__bf16) * (size_t)G.mesh.nk * G.mesh.nk * pl * G.ngv * G.M1);
+        G.off_pc1 = off(sizeof(__bf16) * (size_t)G.mesh.nk * pl * G.ngv * G.nbtot);
+    }
+    for (auto& F : bp.fs) {
+        const BatchGroup& G = bp.groups[F.group];
+        F.off_pc2 = off(sizeof(__bf16) * pl * G.ng2 * F.neo);
+        F.off_ptt = off(sizeof(__bf16) * pl * G.ng2 * (size_t)G.naux * F.neo);
+        F.off_z = off(sizeof(float) * (size_t)F.zrows * F.npair);
+        F.off_zp = off(sizeof(__bf16) * (size_t)NS * F.kgroups * 8 * F.npair);
+    }
+    bp.bytes = (cur + 255) & ~size_t(255);
+}
+
+template <class T>
+static T* at(void* ws, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+// Enqueue the whole batched pipeline (bf16 forms) on `st`.  Tables must
+// already be on the device.  When `prof` is false no events are recorded
+// (graph capture).
+// Kernel attributes and the CU count (host calls, kept out of graph capture).
+static int g_ncu = 0;
+
+template <int NS>
+static dmet_status batch_prepare() {
+    DMET_HIP(hipFuncSetAttribute((const void*)k_xf1_batched<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)xf1_lds<NS>()));
+    DMET_HIP(hipFuncSetAttribute((const void*)k_xf2_batched<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)xf2_lds<NS>()));
+    DMET_HIP(hipFuncSetAttribute((const void*)k_contract_persist<NS, 128>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)persist_lds<NS, 128>()));
+    DMET_HIP(hipFuncSetAttribute((const void*)k_contract_persist<NS, 64>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)persist_lds<NS, 64>()));
+    int dev = 0;
+    DMET_HIP(hipGetDevice(&dev));
+    DMET_HIP(hipDeviceGetAttribute(&g_ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    return DMET_OK;
+}
+
+template <int NS>
+static dmet_status batch_enqueue(BatchPlan& bp, int variant, bool prof, hipStream_t st) {
+    void* ws = bp.ws;
+    const int nfrag = (int)bp.frags.size();
+    BFrag* dfr = at<BFrag>(ws, bp.off_bfrag);
+    auto k1 = k_xf1_batched<NS>;
+    auto k2 = k_xf2_batched<NS>;
+    auto kc = variant == 128 ? k_contract_persist<NS, 128> : k_contract_persist<NS, 64>;
+    const size_t lc = variant == 128 ? persist_lds<NS, 128>() : persist_lds<NS, 64>();
+    auto scope = [&](const char* n) { return prof ? new ProfScope(n, st) : nullptr; };
+    auto done = [&](ProfScope* p) {
+        if (p) {
+            p->stop();
+            delete p;
+        }
+    };
+    // 1. pack inputs
+    ProfScope* ps = scope(NS == 3 ? "batch_pack_in_bf16x6" : "batch_pack_in_bf16x3");
+    for (auto& G : bp.groups) {
+        const int nk = G.mesh.nk;
+        __bf16* plm = at<__bf16>(ws, G.off_plm);
+        if (G.dt == DMET_C128)
+            k_pack_lmunu<NS, double><<<dim3((G.M1 + 255) / 256, G.ngv, nk * nk), 256, 0, st>>>(
+                static_cast<const double*>(G.lm), G.nao, G.nao_p, G.naux, G.ngv, plm);
+        else
+            k_pack_lmunu<NS, float><<<dim3((G.M1 + 255) / 256, G.ngv, nk * nk), 256, 0, st>>>(
+                static_cast<const float*>(G.lm), G.nao, G.nao_p, G.naux, G.ngv, plm);
+        for (int f : G.members) {
+            const BatchFrag& F = bp.fs[f];
+            k_pack_c1<NS><<<dim3((F.neo + 255) / 256, G.ngv, nk), 256, 0, st>>>(
+                static_cast<const double*>(bp.frags[f].c_k), nk, 1, G.nao, F.neo, G.ngv, at<__bf16>(ws, G.off_pc1),
+                F.col0, G.nbtot);
+            k_pack_c2<NS><<<dim3((F.neo + 255) / 256, G.ng2, 1), 256, 0, st>>>(
+                static_cast<const double*>(bp.frags[f].c_k), nk, G.nao, G.nao_p, F.neo, G.ng2,
+                at<__bf16>(ws, F.off_pc2));
+            if (G.ng2 * 8 > nk * G.nao_p) {
+                const size_t n2 = (size_t)G.naux * F.neo, part = (size_t)G.ng2 * n2 * 8;
+                __bf16* ptt = at<__bf16>(ws, F.off_ptt);
+                for (int sp = 0; sp < 3 * NS; ++sp)
+                    fill_zero(ptt + (size_t)sp * part + (size_t)(G.ng2 - 1) * n2 * 8, n2 * 8 * sizeof(__bf16), st);
+            }
+        }
+    }
+    done(ps);
+    DMET_LAUNCH_CHECK("batch pack");
+    // 2. rounds of (stage 1 per group, stage 2 for all fragments)
+    for (int r = 0; r < bp.rounds; ++r) {
+        ps = scope(NS == 3 ? "batch_xform1_bf16x6" : "batch_xform1_bf16x3");
+        for (auto& G : bp.groups) {
+            if (r >= (int)G.qbs.size()) continue;
+            const long nb = ((long)G.mesh.nk * ((G.M1 + 127) / 128) * ((G.nbtot + 127) / 128) + NXCD - 1) / NXCD * NXCD;
+            k1<<<dim3((unsigned)nb), 256, xf1_lds<NS>(), st>>>(G.mesh, G.qbs[r].q, G.naux, G.nao_p, G.nbtot, G.ngv,
+                                                               at<int2>(ws, G.off_colmap), dfr,
+                                                               at<__bf16>(ws, G.off_plm), at<__bf16>(ws, G.off_pc1));
+        }
+        done(ps);
+        DMET_LAUNCH_CHECK("batch xform1");
+        if (bp.items2_cnt[r] > 0) {
+            ps = scope(NS == 3 ? "batch_xform2_bf16x6" : "batch_xform2_bf16x3");
+            const long nb = ((long)bp.items2_cnt[r] + NXCD - 1) / NXCD * NXCD;
+            k2<<<dim3((unsigned)nb), 256, xf2_lds<NS>(), st>>>(bp.items2_cnt[r],
+                                                              at<BItem2>(ws, bp.off_items2) + bp.items2_off[r], dfr,
+                                                              at<BQ>(ws, bp.off_bq) + (size_t)r * nfrag);
+            done(ps);
+            DMET_LAUNCH_CHECK("batch xform2");
+        }
+    }
+    // 3. split Z into bf16 parts
+    ps = scope(NS == 3 ? "batch_pack_bf16x6" : "batch_pack_bf16x3");
+    for (int f = 0; f < nfrag; ++f) {
+        const BatchFrag& F = bp.fs[f];
+        k_pack_parts<NS><<<dim3((F.npair + 255) / 256, F.kgroups), 256, 0, st>>>(
+            at<float>(ws, F.off_z), (size_t)F.npair, F.zrows, F.npair, F.kgroups, at<__bf16>(ws, F.off_zp));
+    }
+    done(ps);
+    DMET_LAUNCH_CHECK("batch pack parts");
+    // 4. persistent contraction over every fragment's tiles
+    int* qd = at<int>(ws, bp.off_q);   // [queue starts | queue lengths | counters], counters zeroed here
+    fill_zero(qd + 2 * NXCD, NXCD * sizeof(int), st);
+    const int ncu = g_ncu > 0 ? g_ncu : 256;
+    ps = scope(NS == 3 ? "batch_contract_bf16x6" : "batch_contract_bf16x3");
+    kc<<<dim3((unsigned)(2 * ncu)), 256, lc, st>>>(qd, qd + NXCD, qd + 2 * NXCD, at<BItemC>(ws, bp.off_itemsc), dfr,
+                                                   FLUSH_K);
+    done(ps);
+    DMET_LAUNCH_CHECK("batch contract");
+    return DMET_OK;
+}
+
+// Upload the tables of variant `variant` (synchronous).
+static dmet_status batch_upload(BatchPlan& bp, int variant, hipStream_t st) {
+    void* ws = bp.ws;
+    const int nfrag = (int)bp.frags.size();
+    for (int f = 0; f < nfrag; ++f) {
+        const BatchFrag& F = bp.fs[f];
+        const BatchGroup& G = bp.groups[F.group];
+        BFrag b;
+        b.pc2 = at<__bf16>(ws, F.off_pc2);
+        b.ptt = at<__bf16>(ws, F.off_ptt);
+        b.z = at<float>(ws, F.off_z);
+        b.zp = at<__bf16>(ws, F.off_zp);
+        b.eri = bp.frags[f].eri;
+        b.neo = F.neo;
+        b.naux = G.naux;
+        b.ng2 = G.ng2;
+        b.npair = F.npair;
+        b.zrows = F.zrows;
+        b.kgroups = F.kgroups;
+        bp.h_bfrag[f] = b;
+    }
+    const int v = variant == 128 ? 0 : 1;
+    std::vector<int> q(2 * NXCD);
+    for (int x = 0; x < NXCD; ++x) {
+        q[x] = bp.h_qstart[v][x];
+        q[NXCD + x] = bp.h_qlen[v][x];
+    }
+    DMET_HIP(hipMemcpyAsync(at<char>(ws, bp.off_bfrag), bp.h_bfrag.data(), sizeof(BFrag) * nfrag,
+                            hipMemcpyHostToDevice, st));
+    // the column maps of all groups are one contiguous region
+    size_t cm0 = bp.groups[0].off_colmap;
+    for (auto& G : bp.groups) cm0 = std::min(cm0, G.off_colmap);
+    DMET_HIP(hipMemcpyAsync(at<char>(ws, cm0), bp.h_colmap.data(), sizeof(int2) * bp.h_colmap.size(),
+                            hipMemcpyHostToDevice, st));
+    if (!bp.h_items2.empty())
+        DMET_HIP(hipMemcpyAsync(at<char>(ws, bp.off_items2), bp.h_items2.data(), sizeof(BItem2) * bp.h_items2.size(),
+                                hipMemcpyHostToDevice, st));
+    DMET_HIP(hipMemcpyAsync(at<char>(ws, bp.off_bq), bp.h_bq.data(), sizeof(BQ) * bp.h_bq.size(),
+                            hipMemcpyHostToDevice, st));
+    if (!bp.h_itemsc[v].empty())
+        DMET_HIP(hipMemcpyAsync(at<char>(ws, bp.off_itemsc), bp.h_itemsc[v].data(),
+                                sizeof(BItemC) * bp.h_itemsc[v].size(), hipMemcpyHostToDevice, st));
+    DMET_HIP(hipMemcpyAsync(at<char>(ws, bp.off_q), q.data(), sizeof(int) * 2 * NXCD, hipMemcpyHostToDevice, st));
+    DMET_HIP(hipStreamSynchronize(st));
+    return DMET_OK;
+}
+
+size_t batch_workspace(int nfrag, const dmet_fragment* frags, dmet_precision prec) {
+    if (prec == DMET_FP64 || prec == DMET_FP32_3M) {
+        size_t mx = 256;
+        for (int f = 0; f < nfrag; ++f) {
+            dmet_lattice lat = frags[f].lat;
+            lat.nspin = 1;
+            EriPlan p = make_eri_plan(&lat, frags[f].neo, prec, frags[f].dtype);
+            mx = std::max(mx, prec == DMET_FP64 ? eri_f64_workspace(p) : eri_lp_workspace(p));
+        }
+        return mx;
+    }
+    BatchPlan bp;
+    bp.frags.assign(frags, frags + nfrag);
+    bp.prec = prec;
+    plan_batch(bp);
+    return bp.bytes;
+}
+
+static std::string tune_file() {
+    const char* e = getenv("DMET_TUNE_CACHE");
+    return e ? std::string(e) : std::string();
+}
+
+static void tune_load() {
+    static bool loaded = false;
+    if (loaded) return;
+    loaded = true;
+    std::string fn = tune_file();
+    if (fn.empty()) return;
+    FILE* fp = fopen(fn.c_str(), "r");
+    if (!fp) return;
+    char line[65536];
+    while (fgets(line, sizeof(line), fp)) {
+        char* sp = strrchr(line, ' ');
+        if (!sp) continue;
+        int v = atoi(sp + 1);
+        *sp = 0;
+        if (v == 64 || v == 128) g_tune[line] = v;
+    }
+    fclose(fp);
+}
+
+static void tune_store(const std::string& key, int v, float ms128, float ms64) {
+    std::string fn = tune_file();
+    if (fn.empty()) return;
+    FILE* fp = fopen(fn.c_str(), "a");
+    if (!fp) return;
+    fprintf(fp, "%s %d\n", key.c_str(), v);
+    fclose(fp);
+    (void)ms128;
+    (void)ms64;
+}
+
+dmet_status eri_batched(int nfrag, const dmet_fragment* frags, dmet_precision prec, unsigned flags, void* ws,
+                        size_t ws_bytes, hipStream_t st) {
+    if (prec == DMET_FP64 || prec == DMET_FP32_3M) {
+        for (int f = 0; f < nfrag; ++f) {
+            dmet_lattice lat = frags[f].lat;
+            lat.nspin = 1;
+            EriPlan p = make_eri_plan(&lat, frags[f].neo, prec, frags[f].dtype);
+            dmet_status s = prec == DMET_FP64
+                                ? eri_f64(p, frags[f].lmunu, static_cast<const double*>(frags[f].c_k), frags[f].eri,
+                                          nullptr, nullptr, ws, ws_bytes, st)
+                                : eri_lp(p, frags[f].lmunu, static_cast<const double*>(frags[f].c_k), frags[f].eri,
+                                         nullptr, nullptr, ws, ws_bytes, st);
+            if (s != DMET_OK) return s;
+        }
+        return DMET_OK;
+    }
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    const std::string key = batch_key(nfrag, frags, prec, true, ws, ws_bytes);
+    BatchPlan* bp = nullptr;
+    auto itp = g_batch_plans.find(key);
+    if (itp != g_batch_plans.end()) {
+        bp = itp->second;
+    } else {
+        bp = new BatchPlan();
+        bp->frags.assign(frags, frags + nfrag);
+        bp->prec = prec;
+        bp->ws = ws;
+        bp->ws_bytes = ws_bytes;
+        bp->key = key;
+        plan_batch(*bp);
+        if (bp->bytes > ws_bytes) {
+            delete bp;
+            return fail(DMET_E_WORKSPACE, "batched workspace too small");
+        }
+        if (g_batch_plans.size() >= 32) {  // bounded cache of plans / captured graphs
+            for (auto& kv : g_batch_plans) {
+                if (kv.second->exec) (void)hipGraphExecDestroy(kv.second->exec);
+                delete kv.second;
+            }
+            g_batch_plans.clear();
+        }
+        g_batch_plans[key] = bp;
+    }
+    const bool ns3 = prec == DMET_BF16X6_3M;
+    {
+        dmet_status s = ns3 ? batch_prepare<3>() : batch_prepare<2>();
+        if (s != DMET_OK) return s;
+    }
+    auto enqueue = [&](int variant, bool prof) {
+        return ns3 ? batch_enqueue<3>(*bp, variant, prof, st) : batch_enqueue<2>(*bp, variant, prof, st);
+    };
+    // contraction tile: cached choice, autotune, or default
+    tune_load();
+    const std::string shape = batch_key(nfrag, frags, prec, false, nullptr, 0);
+    int variant = 128;
+    auto itt = g_tune.find(shape);
+    if (itt != g_tune.end()) {
+        variant = itt->second;
+    } else if (flags & DMET_BATCH_AUTOTUNE) {
+        float best = 1e30f;
+        float ms[2] = {0.f, 0.f};
+        for (int v : {128, 64}) {
+            dmet_status s = batch_upload(*bp, v, st);
+            if (s != DMET_OK) return s;
+            hipEvent_t e0, e1;
+            DMET_HIP(hipEventCreate(&e0));
+            DMET_HIP(hipEventCreate(&e1));
+            DMET_HIP(hipEventRecord(e0, st));
+            s = enqueue(v, false);
+            if (s != DMET_OK) return s;
+            DMET_HIP(hipEventRecord(e1, st));
+            DMET_HIP(hipEventSynchronize(e1));
+            float t = 0.f;
+            DMET_HIP(hipEventElapsedTime(&t, e0, e1));
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            ms[v == 128 ? 0 : 1] = t;
+            if (t < best) {
+                best = t;
+                variant = v;
+            }
+        }
+        g_tune[shape] = variant;
+        tune_store(shape, variant, ms[0], ms[1]);
+    }
+    // The work tables live in the caller's workspace, whose contents the caller
+    // may reuse between calls: upload them on every call (a few MB, before any
+    // kernel of this call), graph replays included.
+    if (bp->variant != variant && bp->exec) {
+        (void)hipGraphExecDestroy(bp->exec);
+        bp->exec = nullptr;
+    }
+    bp->variant = variant;
+    {
+        dmet_status s = batch_upload(*bp, variant, st);
+        if (s != DMET_OK) return s;
+    }
+    if (flags & DMET_BATCH_GRAPH) {
+        if (!bp->exec) {
+            // capture on a private stream (the caller's may be the legacy null
+            // stream, which cannot be captured); nothing executes during capture
+            static hipStream_t cap = nullptr;
+            if (!cap) DMET_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            hipGraph_t g = nullptr;
+            DMET_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+            dmet_status s = ns3 ? batch_enqueue<3>(*bp, variant, false, cap) : batch_enqueue<2>(*bp, variant, false, cap);
+            hipError_t e = hipStreamEndCapture(cap, &g);
+            if (s != DMET_OK) return s;
+            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&bp->exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        }
+        ProfScope ps("batch_graph", st);
+        DMET_HIP(hipGraphLaunch(bp->exec, st));
+        ps.stop();
+        return DMET_OK;
+    }
+    return enqueue(variant, true);
 }
 
 }  // namespace dmet

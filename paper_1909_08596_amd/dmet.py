@@ -25,7 +25,9 @@ STATUS = {0: "DMET_OK", 1: "DMET_E_ARG", 2: "DMET_E_HIP", 3: "DMET_E_NOCONV", 4:
 # every symbol include/dmet.h declares
 EXPORTS = ("dmet_last_error", "dmet_version", "dmet_build_bath_workspace", "dmet_build_bath",
            "dmet_transform_1e", "dmet_energy_1e", "dmet_transform_eri_workspace", "dmet_transform_eri",
+           "dmet_transform_eri_batched_workspace", "dmet_transform_eri_batched",
            "dmet_profile_enable", "dmet_profile_reset", "dmet_profile_report")
+DMET_BATCH_GRAPH, DMET_BATCH_AUTOTUNE = 1, 2
 
 
 class DmetError(RuntimeError):
@@ -45,6 +47,11 @@ def lattice(kmesh: Sequence[int], nao: int, naux: int = 1, nspin: int = 1) -> La
         lat.kmesh[d] = int(kmesh[d])
     lat.nao, lat.naux, lat.nspin = int(nao), int(naux), int(nspin)
     return lat
+
+
+class Fragment(ctypes.Structure):
+    _fields_ = [("lat", Lattice), ("neo", ctypes.c_int), ("lmunu", ctypes.c_void_p), ("dtype", ctypes.c_int),
+                ("c_k", ctypes.c_void_p), ("eri", ctypes.c_void_p)]
 
 
 _lib = None
@@ -69,6 +76,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dmet_energy_1e.argtypes = [i, i, vp, vp, vp, vp]
     lib.dmet_transform_eri_workspace.argtypes = [lp, i, i, i, ctypes.POINTER(sz)]
     lib.dmet_transform_eri.argtypes = [lp, i, vp, i, vp, i, vp, vp, vp, vp, sz, vp]
+    fp = ctypes.POINTER(Fragment)
+    lib.dmet_transform_eri_batched_workspace.argtypes = [i, fp, i, ctypes.POINTER(sz)]
+    lib.dmet_transform_eri_batched.argtypes = [i, fp, i, ctypes.c_uint, vp, sz, vp]
     lib.dmet_profile_enable.argtypes = [i]
     lib.dmet_profile_reset.argtypes = []
     lib.dmet_profile_report.argtypes = [ctypes.c_char_p, sz]
@@ -193,6 +203,52 @@ def dmet_transform_eri(kmesh, nao, naux, lmunu: torch.Tensor, c_k: torch.Tensor,
                                   _ptr(out["aa"]), _ptr(out.get("bb")), _ptr(out.get("ab")), _ptr(workspace),
                                   workspace.numel(), _stream(stream)))
     return out
+
+
+def _fragments(frags, precision):
+    for f in frags:
+        if "eri" not in f:
+            neo = f["c_k"].shape[-1]
+            npair = neo * (neo + 1) // 2
+            f["eri"] = torch.empty(npair * (npair + 1) // 2, dtype=torch.float64, device=f["c_k"].device)
+    arr = (Fragment * len(frags))()
+    for n, f in enumerate(frags):
+        lm, ck = f["lmunu"], f["c_k"]
+        if lm.dtype not in (torch.complex128, torch.complex64):
+            raise ValueError("lmunu must be complex128 or complex64")
+        _dev(lm, lm.dtype, "lmunu")
+        _dev(ck, torch.complex128, "c_k")
+        neo = ck.shape[-1]
+        arr[n].lat = lattice(f["kmesh"], f["nao"], f["naux"], 1)
+        arr[n].neo = neo
+        arr[n].lmunu = lm.data_ptr()
+        arr[n].dtype = DMET_C128 if lm.dtype == torch.complex128 else DMET_C64
+        arr[n].c_k = ck.data_ptr()
+        arr[n].eri = f["eri"].data_ptr()
+    return arr
+
+
+def dmet_transform_eri_batched_workspace(frags, precision="bf16x6") -> int:
+    arr = _fragments(frags, precision)
+    nb = ctypes.c_size_t()
+    _check(load().dmet_transform_eri_batched_workspace(len(frags), arr, PRECISIONS[precision], ctypes.byref(nb)))
+    return nb.value
+
+
+def dmet_transform_eri_batched(frags, precision="bf16x6", graph=False, autotune=False,
+                               workspace: Optional[torch.Tensor] = None, stream=None):
+    """Packed s8 ERIs of many fragments in one submission.  `frags` is a list of
+    dicts with kmesh, nao, naux, lmunu, c_k ([N_k][nao][neo] complex128) and an
+    optional preallocated 'eri'; returns the list of output tensors."""
+    arr = _fragments(frags, precision)
+    if workspace is None:
+        nb = ctypes.c_size_t()
+        _check(load().dmet_transform_eri_batched_workspace(len(frags), arr, PRECISIONS[precision], ctypes.byref(nb)))
+        workspace = _workspace(nb.value, frags[0]["c_k"].device)
+    flags = (DMET_BATCH_GRAPH if graph else 0) | (DMET_BATCH_AUTOTUNE if autotune else 0)
+    _check(load().dmet_transform_eri_batched(len(frags), arr, PRECISIONS[precision], flags, _ptr(workspace),
+                                             workspace.numel(), _stream(stream)))
+    return [f["eri"] for f in frags]
 
 
 def dmet_profile_enable(on: bool = True):

@@ -275,3 +275,38 @@ def random_orthonormal(rng, n, m) -> np.ndarray:
     """n x m real matrix with orthonormal columns (QR of a Gaussian draw)."""
     q, r = np.linalg.qr(rng.standard_normal((n, m)))
     return q * np.sign(np.diag(r))[None, :]
+
+
+# Batched workload: many fragments of uneven size on two lattices (an
+# h-BN/Si-sized cell, nao 52, naux 400, on 2x2x2 and 3x3x3 meshes); each
+# fragment is a supercell impurity of ceil(neo/2) LOs taken from the cells
+# nearest the origin (by minimum-image |R|, then mu) and a bath of
+# neo - n_imp orbitals from the first SVD columns (Sec. 2.1: the impurity
+# may be a cell or a supercell).
+BATCH_LATTICES = {
+    "b222": Workload("b222", (2, 2, 2), 52, 400, 52, 52, 1, 2.0, 1004, "c64"),
+    "b333": Workload("b333", (3, 3, 3), 52, 400, 52, 52, 1, 2.0, 1005, "c64"),
+}
+
+
+def supercell_order(kmesh, nao):
+    """Supercell orbitals (cell*nao + mu) ordered by |R| (min image), then cell, then mu."""
+    d = min_image_length(kmesh)
+    cells_sorted = sorted(range(len(d)), key=lambda c: (round(float(d[c]), 12), c))
+    return [c * nao + m for c in cells_sorted for m in range(nao)]
+
+
+def batched_fragments(nfrag=64, seed=1004, neo_range=(20, 200), lattices=("b222", "b333")):
+    """Fragment specs: list of dicts (lattice name, neo, imp_idx, val_idx)."""
+    rng = np.random.default_rng([seed, 7])
+    out = []
+    for f in range(nfrag):
+        neo = int(rng.integers(neo_range[0], neo_range[1] + 1))
+        lat = lattices[int(rng.integers(0, len(lattices)))]
+        wl = BATCH_LATTICES.get(lat)
+        nimp = (neo + 1) // 2
+        nval = neo - nimp
+        order = supercell_order(wl.kmesh, wl.nao) if wl is not None else None
+        out.append({"lattice": lat, "neo": neo, "nimp": nimp, "nval": nval,
+                    "imp_idx": None if order is None else order[:nimp], "val_idx": list(range(nval))})
+    return out

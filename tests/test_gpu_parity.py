@@ -168,3 +168,70 @@ def test_eri_bf16x3_error_as_derived(dmet, key):
     err = np.abs(out["aa"].cpu().numpy() - ok.pack_s8(ref)).max()
     print(f"{key} bf16x3 max abs err {err:.3e}")
     assert err < 1e-5
+
+
+# ------------------------------------------------------------ batched form
+def _small_batch():
+    """Fragments of uneven size on two small lattices, supercell impurities."""
+    import synth
+    lats = {"a": synth.Workload("ba", (2, 2, 1), 8, 24, 8, 8, 1, 1.5, 2101),
+            "b": synth.Workload("bb", (3, 1, 1), 8, 20, 8, 8, 1, 1.5, 2102)}
+    data = {}
+    for key, wl in lats.items():
+        lat = synth.make_lattice(wl)
+        lm = synth.three_index(wl)
+        data[key] = (wl, lat, lm)
+    rng = np.random.default_rng(5)
+    frags = []
+    for f in range(9):
+        key = "ab"[f % 2]
+        wl, lat, lm = data[key]
+        neo = int(rng.integers(4, 17))
+        nimp = (neo + 1) // 2
+        order = synth.supercell_order(wl.kmesh, wl.nao)
+        bath = ok.build_bath(lat.dm_k, wl.kmesh, wl.nao, imp_idx=order[:nimp], val_idx=list(range(neo - nimp)))
+        frags.append((wl, lm, bath["c_k"][0][:, :, :neo]))
+    return frags
+
+
+@pytest.mark.parametrize("prec", ["bf16x6", "bf16x3"])
+def test_batched_matches_single_and_oracle(dmet, prec):
+    frags = _small_batch()
+    dev_lm = {}
+    specs = []
+    for wl, lm, ck in frags:
+        if id(lm) not in dev_lm:
+            dev_lm[id(lm)] = to_dev(lm.astype(np.complex64))
+        specs.append({"kmesh": wl.kmesh, "nao": wl.nao, "naux": wl.naux, "lmunu": dev_lm[id(lm)],
+                      "c_k": to_dev(np.ascontiguousarray(ck))})
+    outs = [o.clone() for o in dmet.dmet_transform_eri_batched(specs, prec)]
+    torch.cuda.synchronize()
+    for (wl, lm, ck), spec, got in zip(frags, specs, outs):
+        single = dmet.dmet_transform_eri(wl.kmesh, wl.nao, wl.naux, spec["lmunu"], spec["c_k"][None], prec)["aa"]
+        assert torch.equal(single, got)   # same kernels' arithmetic, same order
+        ref, _ = ok.alg1_eri(lm.astype(np.complex64).astype(np.complex128), ck, wl.kmesh)
+        err = np.abs(got.cpu().numpy() - ok.pack_s8(ref)).max()
+        assert err < (LP_TOL if prec == "bf16x6" else 1e-5), err
+
+
+def test_batched_graph_replay_and_autotune(dmet, tmp_path, monkeypatch):
+    monkeypatch.setenv("DMET_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    frags = _small_batch()
+    dev_lm = {}
+    specs = []
+    for wl, lm, ck in frags:
+        if id(lm) not in dev_lm:
+            dev_lm[id(lm)] = to_dev(lm.astype(np.complex64))
+        specs.append({"kmesh": wl.kmesh, "nao": wl.nao, "naux": wl.naux, "lmunu": dev_lm[id(lm)],
+                      "c_k": to_dev(np.ascontiguousarray(ck))})
+    eager = [o.clone() for o in dmet.dmet_transform_eri_batched(specs, "bf16x6")]
+    ws = torch.empty(dmet.dmet_transform_eri_batched_workspace(specs, "bf16x6"), dtype=torch.uint8,
+                     device="cuda:0")
+    for rep in range(3):
+        for s in specs:
+            s["eri"].zero_()
+        torch.cuda.synchronize()
+        outs = dmet.dmet_transform_eri_batched(specs, "bf16x6", graph=True, autotune=True, workspace=ws)
+        torch.cuda.synchronize()
+        for a, b in zip(eager, outs):
+            assert torch.equal(a, b), rep
