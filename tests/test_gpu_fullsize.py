@@ -1,0 +1,95 @@
+"""Parity at the full workload sizes (Si-like 3x3x3 and AFM-NiO-like 2x2x2 UHF),
+in the launch configuration the benchmark times, on sampled ERI entries that
+the oracle computes one pair column at a time, plus properties that hold at
+any size (non-negative diagonal, Cauchy-Schwarz on the sampled block).
+
+The oracle's C^k is fed to the GPU so the bath gauge does not enter.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import kspace as ok
+from tests.gpu_common import to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dmet():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1909_08596_amd import dmet as d
+    d.load()
+    return d
+
+
+def _pairs(neo, nimp, rng, n):
+    """Sampled pairs: diagonal, impurity-impurity, bath-bath, mixed, random."""
+    picks = [(0, 0), (nimp - 1, 0), (nimp, nimp), (neo - 1, neo - 1), (neo - 1, 0), (nimp, nimp - 1)]
+    while len(picks) < n:
+        i = int(rng.integers(0, neo))
+        j = int(rng.integers(0, i + 1))
+        picks.append((i, j))
+    return picks
+
+
+def _entries(packed, pa, pb, s4_npair=None):
+    """GPU entries for pairs pa x pb from an s8 (or s4) packed array."""
+    idx = []
+    for a, (i, j) in enumerate(pa):
+        for b, (k, l) in enumerate(pb):
+            IJ, KL = ok.pair_index(i, j), ok.pair_index(k, l)
+            if s4_npair is None:
+                hi, lo = max(IJ, KL), min(IJ, KL)
+                idx.append(hi * (hi + 1) // 2 + lo)
+            else:
+                idx.append(IJ * s4_npair + KL)
+    flat = packed.reshape(-1)
+    assert 0 <= min(idx) and max(idx) < flat.numel()   # checked on the host before the gather
+    vals = flat[torch.tensor(idx, dtype=torch.int64, device=packed.device)].cpu().numpy()
+    return vals.reshape(len(pa), len(pb))
+
+
+@pytest.mark.parametrize("name", ["si", "nio"])
+def test_fullsize_sampled_parity(dmet, name):
+    wl = synth.CONFIGS[name]
+    lat = synth.make_lattice(wl)
+    lm = synth.three_index(wl)
+    bath = ok.build_bath(lat.dm_k, wl.kmesh, wl.nao)
+    ck = bath["c_k"]
+    lm_d = to_dev(lm)
+    ck_d = to_dev(ck)
+    rng = np.random.default_rng(11)
+    pa = _pairs(wl.neo, wl.nimp, rng, 12)
+    pb = _pairs(wl.neo, wl.nimp, rng, 12)
+    spins = [(0, None, "aa")] + ([(1, None, "bb"), (0, 1, "ab")] if wl.nspin == 2 else [])
+    refs = {}
+    for sa, sb, key in spins:
+        cb = None if sb is None else ck[sb]
+        refs[key], im = ok.alg1_eri_columns(lm, ck[sa], wl.kmesh, pa, cb, pb)
+        assert im < 1e-10
+    npair = wl.npair
+    for prec, tol_rel, tol_abs in (("fp64", 1e-10, 0.0), ("bf16x6", 0.0, 1e-6)):
+        out = dmet.dmet_transform_eri(wl.kmesh, wl.nao, wl.naux, lm_d, ck_d, prec)
+        torch.cuda.synchronize()
+        for sa, sb, key in spins:
+            got = _entries(out[key], pa, pb, npair if key == "ab" else None)
+            err = np.abs(got - refs[key]).max()
+            bound = tol_rel * np.abs(refs[key]).max() + tol_abs
+            print(f"{name} {prec} {key}: max err {err:.3e} (bound {bound:.1e})")
+            assert err <= bound, (prec, key, err)
+        # properties at any size: diagonal (ij|ij) >= 0 everywhere, and
+        # Cauchy-Schwarz |(ij|kl)|^2 <= (ij|ij)(kl|kl) on the sampled block
+        for key in [k for _, _, k in spins if k != "ab"]:
+            e = out[key]
+            diag_idx = torch.arange(npair, device=e.device, dtype=torch.int64)
+            diag = e[diag_idx * (diag_idx + 1) // 2 + diag_idx]
+            assert float(diag.min()) >= -1e-12
+            got = _entries(e, pa, pb)
+            da = np.array([_entries(e, [p], [p])[0, 0] for p in pa])
+            db = np.array([_entries(e, [p], [p])[0, 0] for p in pb])
+            assert np.all(got ** 2 <= np.outer(da, db) * (1 + 1e-9) + 1e-14)
+        del out
+        torch.cuda.empty_cache()
