@@ -85,6 +85,24 @@ CONFIGS = {
 }
 
 
+# The paper's own timed example (Sec. 2.1, after Alg. 1): a BN 3x3x1 cluster
+# in a 6x6x1 mean-field mesh, 26 AOs per cell (GTH-DZVP), an auxiliary basis
+# of ~10 x nao, and a valence-only bath of 8 orbitals per impurity cell
+# (GTH-SZV minimal basis): 936 crystal AOs -> 234 + 72 = 306 embedding orbitals.
+BN33 = Workload("bn33", (6, 6, 1), 26, 260, 234, 72, 1, 2.0, 1006)
+
+
+def bn33_impurity():
+    """(imp_idx, val_idx) of the BN 3x3x1 example: the 9 cells (a, b) with
+    a, b < 3, all 26 LOs each; valence = the first 4 AOs (2s2p) of each of the
+    two 13-AO atom blocks of every impurity cell (positions in imp_idx)."""
+    pts = cells(BN33.kmesh)
+    imp_cells = [i for i, p in enumerate(pts) if p[0] < 3 and p[1] < 3]
+    imp = [c * BN33.nao + m for c in imp_cells for m in range(BN33.nao)]
+    val = [ci * BN33.nao + a * 13 + m for ci in range(len(imp_cells)) for a in range(2) for m in range(4)]
+    return imp, val
+
+
 def cells(kmesh) -> np.ndarray:
     """Integer coordinates (row-major) of the N_k cells / k-points, [N_k][3]."""
     n1, n2, n3 = kmesh

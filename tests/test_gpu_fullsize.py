@@ -52,12 +52,14 @@ def _entries(packed, pa, pb, s4_npair=None):
     return vals.reshape(len(pa), len(pb))
 
 
-@pytest.mark.parametrize("name", ["si", "nio"])
+@pytest.mark.parametrize("name", ["si", "nio", "bn33"])
 def test_fullsize_sampled_parity(dmet, name):
-    wl = synth.CONFIGS[name]
+    wl = synth.BN33 if name == "bn33" else synth.CONFIGS[name]
+    imp, val = synth.bn33_impurity() if name == "bn33" else (None, None)
     lat = synth.make_lattice(wl)
     lm = synth.three_index(wl)
-    bath = ok.build_bath(lat.dm_k, wl.kmesh, wl.nao)
+    bath = ok.build_bath(lat.dm_k, wl.kmesh, wl.nao, imp_idx=imp, val_idx=val)
+    assert bath["neo"][0] == wl.neo
     ck = bath["c_k"]
     lm_d = to_dev(lm)
     ck_d = to_dev(ck)
