@@ -185,6 +185,37 @@ dmet_status dmet_transform_eri(const dmet_lattice* lat, int neo, const void* lmu
                                void* workspace, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Density-fitting output of the embedding ERIs (Sec. 2.1: when the impurity
+ * solver works with density fitting, the contraction step of Alg. 1 can be
+ * omitted).  Runs the transform of dmet_transform_eri in the given form and
+ * writes real factors instead of ERIs:
+ *   z [nspin][N_k*naux][npair] float64,   (ij|kl)_st = sum_P z_s[P][ij] z_t[P][kl]
+ * for packed pairs ij = i(i+1)/2 + j (i >= j), i.e. the real, FT-to-R=0
+ * embedded 3-index (L|0i 0j) of every q with q and -q combined.  Workspace:
+ * dmet_transform_eri_workspace() of the same arguments.  Asynchronous.
+ * ------------------------------------------------------------------------- */
+dmet_status dmet_transform_eri_df(const dmet_lattice* lat, int neo, const void* lmunu,
+                                  dmet_dtype dtype, const void* c_k, dmet_precision prec,
+                                  double* z, void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Double-counting-corrected embedding Fock matrix (Eq. "fock double counting"):
+ *   F~_ij = F^{EO}_ij - [sum_kl (ij|kl) gamma_lk - 1/2 sum_kl (ik|lj) gamma_kl]
+ * with gamma the spin-summed embedding density.  Inputs are per spin:
+ * nspin = 1: gamma = 2 dm_eo, F~ = F - (2 J(dm) - K(dm));
+ * nspin = 2: F~_s = F_s - [J_ss(dm_s) + J_st(dm_t) - K_ss(dm_s)] (same Coulomb
+ *            term, exchange of the spin's own density).
+ * The ERIs enter through their density-fitting factors z (as written by
+ * dmet_transform_eri_df, nrows = N_k*naux rows per spin).
+ * f_eo, dm_eo: [nspin][neo][neo] float64 (dm_eo symmetric); f_tilde: out, same
+ * shape.  neo <= 512.  Workspace from dmet_fock_dc_workspace().  Asynchronous.
+ * ------------------------------------------------------------------------- */
+dmet_status dmet_fock_dc_workspace(int nspin, int neo, int nrows, size_t* bytes);
+dmet_status dmet_fock_dc(int nspin, int neo, int nrows, const double* z, const double* f_eo,
+                         const double* dm_eo, double* f_tilde, void* workspace, size_t ws_bytes,
+                         hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Batched embedding ERIs (Alg. 1 for many fragments in one submission).
  *
  * Every fragment is an embedding problem of its own (its own impurity, bath

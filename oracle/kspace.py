@@ -312,3 +312,32 @@ def unpack_s8(eri8, n):
     pidx[tri[0], tri[1]] = np.arange(npair)
     pidx[tri[1], tri[0]] = np.arange(npair)
     return mat[pidx][:, :, pidx]
+
+
+# --------------------------------------------------------------------------
+# Double counting (Eq. fock double counting): F~ = F^EO - [J(gamma) - 1/2 K(gamma)]
+# --------------------------------------------------------------------------
+def fock_double_counting(f_eo, dm_eo, eri):
+    """Eq. ``fock double counting`` written out with a spin-summed density.
+
+    Restricted (nspin = 1): gamma = 2 * dm_eo[0] (dm_eo is per spin), eri the
+    [n][n][n][n] ERI tensor:
+        F~_ij = F_ij - [sum_kl (ij|kl) gamma_lk - 1/2 sum_kl (ik|lj) gamma_kl].
+    Unrestricted (nspin = 2, eri = (aa, bb, ab) tensors): the same Coulomb
+    term with the total density and the exchange term of the spin's own
+    density (per-spin density, so no factor 1/2):
+        F~_s = F_s - [J_ss(g_s) + J_st(g_t) - K_ss(g_s)].
+    """
+    f_eo = np.asarray(f_eo)
+    if f_eo.shape[0] == 1:
+        g = 2.0 * dm_eo[0]
+        j = np.einsum("ijkl,lk->ij", eri, g)
+        k = np.einsum("ikl j,kl->ij".replace(" ", ""), eri, g)
+        return (f_eo[0] - (j - 0.5 * k))[None]
+    aa, bb, ab = eri
+    ga, gb = dm_eo[0], dm_eo[1]
+    ja = np.einsum("ijkl,lk->ij", aa, ga) + np.einsum("ijkl,lk->ij", ab, gb)
+    jb = np.einsum("ijkl,lk->ij", bb, gb) + np.einsum("klij,lk->ij", ab, ga)
+    ka = np.einsum("iklj,kl->ij", aa, ga)
+    kb = np.einsum("iklj,kl->ij", bb, gb)
+    return np.stack([f_eo[0] - (ja - ka), f_eo[1] - (jb - kb)])

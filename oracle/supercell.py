@@ -126,3 +126,23 @@ def eri(b_real, c_sup_a, kmesh, c_sup_b=None):
             "pi,Lpr,rj->Lij", cb, bl, cb, optimize=True).reshape(naux, nb * nb)
         out += za.T @ zb
     return out.reshape(na, na, nb, nb)
+
+
+def coulomb_exchange(b_real, kmesh, gamma_sup):
+    """J[g] and K[g] of the lattice (density-fitted ERIs of Eq. ``density
+    fitting`` in real space) for a real supercell density g:
+        (pq|rs) = sum_{L,R_L} B_L(p - R_L, q - R_L) B_L(r - R_L, s - R_L)
+        J_pq = sum_rs (pq|rs) g_sr,   K_pq = sum_rs (pr|sq) g_rs."""
+    naux, nk, nao = b_real.shape[0], b_real.shape[1], b_real.shape[2]
+    n = nk * nao
+    cells = _cells(kmesh)
+    bl = b_real.reshape(naux, nk, nao, nk, nao)
+    j = np.zeros((n, n))
+    k = np.zeros((n, n))
+    for rl in range(nk):
+        perm = translation(kmesh, cells[rl])      # cell R -> R + R_L
+        inv = np.argsort(perm)                    # cell R -> R - R_L
+        bs = bl[:, inv][:, :, :, inv].reshape(naux, n, n)   # B_L(p - R_L, q - R_L)
+        j += np.einsum("Lpq,L->pq", bs, np.einsum("Lrs,sr->L", bs, gamma_sup))
+        k += np.einsum("Lpr,rs,Lsq->pq", bs, gamma_sup, bs, optimize=True)
+    return j, k

@@ -218,6 +218,44 @@ dmet_status dmet_transform_eri(const dmet_lattice* lat, int neo, const void* lmu
     return eri_lp(p, lmunu, static_cast<const double*>(c_k), eri_aa, eri_bb, eri_ab, workspace, ws_bytes, stream);
 }
 
+dmet_status dmet_transform_eri_df(const dmet_lattice* lat, int neo, const void* lmunu, dmet_dtype dtype,
+                                  const void* c_k, dmet_precision prec, double* z, void* workspace, size_t ws_bytes,
+                                  hipStream_t stream) {
+    g_last_error.clear();
+    dmet_status s = check_eri_args(lat, neo, prec, dtype);
+    if (s != DMET_OK) return s;
+    if (!lmunu || !c_k || !z) return fail(DMET_E_ARG, "null array argument");
+    if (!workspace) return fail(DMET_E_WORKSPACE, "workspace is NULL");
+    EriPlan p = make_eri_plan(lat, neo, prec, dtype);
+    const size_t need = prec == DMET_FP64 ? eri_f64_workspace(p) : eri_lp_workspace(p);
+    if (need > ws_bytes) return fail(DMET_E_WORKSPACE, "transform_eri workspace too small");
+    if (prec == DMET_FP64)
+        return eri_f64(p, lmunu, static_cast<const double*>(c_k), nullptr, nullptr, nullptr, workspace, ws_bytes,
+                       stream, z);
+    return eri_lp(p, lmunu, static_cast<const double*>(c_k), nullptr, nullptr, nullptr, workspace, ws_bytes, stream,
+                  z);
+}
+
+dmet_status dmet_fock_dc_workspace(int nspin, int neo, int nrows, size_t* bytes) {
+    if (nspin != 1 && nspin != 2) return fail(DMET_E_ARG, "nspin must be 1 or 2");
+    if (neo < 1 || neo > 512) return fail(DMET_E_ARG, "neo must be in [1, 512]");
+    if (nrows < 1) return fail(DMET_E_ARG, "nrows must be positive");
+    if (!bytes) return fail(DMET_E_ARG, "bytes is NULL");
+    *bytes = fock_dc_workspace(nspin, neo, nrows);
+    return DMET_OK;
+}
+
+dmet_status dmet_fock_dc(int nspin, int neo, int nrows, const double* z, const double* f_eo, const double* dm_eo,
+                         double* f_tilde, void* workspace, size_t ws_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    size_t need = 0;
+    dmet_status s = dmet_fock_dc_workspace(nspin, neo, nrows, &need);
+    if (s != DMET_OK) return s;
+    if (!z || !f_eo || !dm_eo || !f_tilde) return fail(DMET_E_ARG, "null array argument");
+    if (!workspace || ws_bytes < need) return fail(DMET_E_WORKSPACE, "fock_dc workspace too small");
+    return fock_dc(nspin, neo, nrows, z, f_eo, dm_eo, f_tilde, workspace, ws_bytes, stream);
+}
+
 static dmet_status check_batch(int nfrag, const dmet_fragment* frags, dmet_precision prec) {
     if (nfrag < 1 || nfrag > 65535 || !frags) return fail(DMET_E_ARG, "need 1 <= nfrag <= 65535 fragments");
     for (int f = 0; f < nfrag; ++f) {

@@ -29,13 +29,19 @@ struct EriPlan {
 
 EriPlan make_eri_plan(const dmet_lattice* lat, int neo, dmet_precision prec, dmet_dtype dtype);
 
+// df_out != NULL: write the FP64 DF factors Z [nspin][zrows][npair] there and
+// skip the contraction (eri pointers unused).
 size_t eri_f64_workspace(const EriPlan& p);
 dmet_status eri_f64(const EriPlan& p, const void* lmunu, const double* ck, double* eri_aa, double* eri_bb,
-                    double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st);
+                    double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st, double* df_out = nullptr);
 
 size_t eri_lp_workspace(const EriPlan& p);
 dmet_status eri_lp(const EriPlan& p, const void* lmunu, const double* ck, double* eri_aa, double* eri_bb,
-                   double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st);
+                   double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st, double* df_out = nullptr);
+
+size_t fock_dc_workspace(int nspin, int neo, int nrows);
+dmet_status fock_dc(int nspin, int neo, int nrows, const double* z, const double* f_eo, const double* dm_eo,
+                    double* f_tilde, void* ws, size_t ws_bytes, hipStream_t st);
 
 size_t batch_workspace(int nfrag, const dmet_fragment* frags, dmet_precision prec);
 dmet_status eri_batched(int nfrag, const dmet_fragment* frags, dmet_precision prec, unsigned flags, void* ws,

@@ -256,10 +256,11 @@ size_t eri_f64_workspace(const EriPlan& p) {
 }
 
 dmet_status eri_f64(const EriPlan& p, const void* lmunu, const double* ck, double* eri_aa, double* eri_bb,
-                    double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st) {
+                    double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st, double* df_out) {
     Carve cv(ws, ws_bytes);
     double* t = cv.take<double>((size_t)p.mesh.nk * p.nao * p.naux * 2 * p.neo);
     double* z = cv.take<double>((size_t)p.nspin * p.zrows * p.npair);
+    if (df_out) z = df_out;
     if (cv.bytes() > ws_bytes) return fail(DMET_E_WORKSPACE, "transform_eri workspace too small");
     const size_t ldz = (size_t)p.npair;
     const int M1 = p.naux * p.nao, N1 = 2 * p.neo;
@@ -286,6 +287,7 @@ dmet_status eri_f64(const EriPlan& p, const void* lmunu, const double* ck, doubl
             DMET_LAUNCH_CHECK("k_xform2_f64");
         }
     }
+    if (df_out) return DMET_OK;
     const int nt = (p.npair + C_BM - 1) / C_BM;
     for (int s = 0; s < p.nspin; ++s) {
         const double* zs = z + (size_t)s * p.zrows * ldz;

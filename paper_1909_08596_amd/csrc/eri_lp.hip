@@ -1713,10 +1713,15 @@ static dmet_status set_lds(K1 k1, K2 k2, K3 k3, K4 k4) {
     return DMET_OK;
 }
 
+__global__ void k_f32_to_f64(const float* __restrict__ a, double* __restrict__ b, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        b[i] = (double)a[i];
+}
+
 template <int PREC>
 static dmet_status eri_lp_run(const EriPlan& p, const void* lmunu, const double* ck, double* eri_aa,
                               double* eri_bb, double* eri_ab, float* t, float* z, __bf16* zp, Carve& cv,
-                              hipStream_t st) {
+                              hipStream_t st, double* df_out) {
     using C1 = LpCfg<PREC, 3, L1_BM, L1_BN, L1_BK>;
     using C2 = LpCfg<PREC, 3, L2_BM, L2_BN, L2_BK>;
     using C3 = LpCfg<PREC, 1, LC_BM, LC_BN, LC_BK>;
@@ -1766,6 +1771,12 @@ static dmet_status eri_lp_run(const EriPlan& p, const void* lmunu, const double*
             ps2.stop();
             DMET_LAUNCH_CHECK(n2);
         }
+    }
+    if (df_out) {
+        const size_t n = (size_t)p.nspin * p.zrows * p.npair;
+        k_f32_to_f64<<<1024, 256, 0, st>>>(z, df_out, n);
+        DMET_LAUNCH_CHECK("k_f32_to_f64");
+        return DMET_OK;
     }
     if constexpr (PREC == LP_F32) {
         const int nt = (p.npair + LC_BM - 1) / LC_BM;
@@ -1823,7 +1834,7 @@ static dmet_status eri_lp_run(const EriPlan& p, const void* lmunu, const double*
 }
 
 dmet_status eri_lp(const EriPlan& p, const void* lmunu, const double* ck, double* eri_aa, double* eri_bb,
-                   double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st) {
+                   double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st, double* df_out) {
     if (eri_lp_workspace(p) > ws_bytes) return fail(DMET_E_WORKSPACE, "transform_eri workspace too small");
     Carve cv(ws, ws_bytes);
     // layout: [T planes (FP32 form) | packed transform operands (bf16 forms)] [Z] [Z parts]
@@ -1840,10 +1851,11 @@ dmet_status eri_lp(const EriPlan& p, const void* lmunu, const double* ck, double
     }
     float* z = cv.take<float>((size_t)p.nspin * p.zrows * p.npair);
     __bf16* zp = cv.take<__bf16>((size_t)p.nspin * packed_elems(p));
-    if (p.prec == DMET_FP32_3M) return eri_lp_run<LP_F32>(p, lmunu, ck, eri_aa, eri_bb, eri_ab, t, z, zp, pre, st);
+    if (p.prec == DMET_FP32_3M)
+        return eri_lp_run<LP_F32>(p, lmunu, ck, eri_aa, eri_bb, eri_ab, t, z, zp, pre, st, df_out);
     if (p.prec == DMET_BF16X3_3M)
-        return eri_lp_run<LP_BF16X3>(p, lmunu, ck, eri_aa, eri_bb, eri_ab, t, z, zp, pre, st);
-    return eri_lp_run<LP_BF16X6>(p, lmunu, ck, eri_aa, eri_bb, eri_ab, t, z, zp, pre, st);
+        return eri_lp_run<LP_BF16X3>(p, lmunu, ck, eri_aa, eri_bb, eri_ab, t, z, zp, pre, st, df_out);
+    return eri_lp_run<LP_BF16X6>(p, lmunu, ck, eri_aa, eri_bb, eri_ab, t, z, zp, pre, st, df_out);
 }
 
 }  // namespace dmet

@@ -26,6 +26,7 @@ STATUS = {0: "DMET_OK", 1: "DMET_E_ARG", 2: "DMET_E_HIP", 3: "DMET_E_NOCONV", 4:
 EXPORTS = ("dmet_last_error", "dmet_version", "dmet_build_bath_workspace", "dmet_build_bath",
            "dmet_transform_1e", "dmet_energy_1e", "dmet_transform_eri_workspace", "dmet_transform_eri",
            "dmet_transform_eri_batched_workspace", "dmet_transform_eri_batched",
+           "dmet_transform_eri_df", "dmet_fock_dc_workspace", "dmet_fock_dc",
            "dmet_profile_enable", "dmet_profile_reset", "dmet_profile_report")
 DMET_BATCH_GRAPH, DMET_BATCH_AUTOTUNE = 1, 2
 
@@ -79,6 +80,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     fp = ctypes.POINTER(Fragment)
     lib.dmet_transform_eri_batched_workspace.argtypes = [i, fp, i, ctypes.POINTER(sz)]
     lib.dmet_transform_eri_batched.argtypes = [i, fp, i, ctypes.c_uint, vp, sz, vp]
+    lib.dmet_transform_eri_df.argtypes = [lp, i, vp, i, vp, i, vp, vp, sz, vp]
+    lib.dmet_fock_dc_workspace.argtypes = [i, i, i, ctypes.POINTER(sz)]
+    lib.dmet_fock_dc.argtypes = [i, i, i, vp, vp, vp, vp, vp, sz, vp]
     lib.dmet_profile_enable.argtypes = [i]
     lib.dmet_profile_reset.argtypes = []
     lib.dmet_profile_report.argtypes = [ctypes.c_char_p, sz]
@@ -202,6 +206,44 @@ def dmet_transform_eri(kmesh, nao, naux, lmunu: torch.Tensor, c_k: torch.Tensor,
     _check(lib.dmet_transform_eri(ctypes.byref(lat), neo, _ptr(lmunu), dt, _ptr(c_k), PRECISIONS[precision],
                                   _ptr(out["aa"]), _ptr(out.get("bb")), _ptr(out.get("ab")), _ptr(workspace),
                                   workspace.numel(), _stream(stream)))
+    return out
+
+
+def dmet_transform_eri_df(kmesh, nao, naux, lmunu: torch.Tensor, c_k: torch.Tensor, precision: str = "fp64",
+                          workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Density-fitting factors z [nspin][N_k*naux][npair] (float64) with
+    (ij|kl)_st = sum_P z_s[P][ij] z_t[P][kl] (the contraction of Alg. 1 skipped)."""
+    lib = load()
+    _dev(lmunu, lmunu.dtype, "lmunu")
+    _dev(c_k, torch.complex128, "c_k")
+    nspin, nk, _, neo = c_k.shape
+    lat = lattice(kmesh, nao, naux, nspin)
+    dt = DMET_C128 if lmunu.dtype == torch.complex128 else DMET_C64
+    npair = neo * (neo + 1) // 2
+    z = torch.empty((nspin, nk * naux, npair), dtype=torch.float64, device=c_k.device)
+    if workspace is None:
+        workspace = _workspace(dmet_transform_eri_workspace(kmesh, nao, naux, nspin, neo, precision, lmunu.dtype),
+                               c_k.device)
+    _check(lib.dmet_transform_eri_df(ctypes.byref(lat), neo, _ptr(lmunu), dt, _ptr(c_k), PRECISIONS[precision],
+                                     _ptr(z), _ptr(workspace), workspace.numel(), _stream(stream)))
+    return z
+
+
+def dmet_fock_dc(z: torch.Tensor, f_eo: torch.Tensor, dm_eo: torch.Tensor, stream=None) -> torch.Tensor:
+    """F~ of Eq. "fock double counting" from the DF factors z, F^EO and the
+    per-spin embedding density (all float64 device tensors)."""
+    lib = load()
+    _dev(z, torch.float64, "z")
+    _dev(f_eo, torch.float64, "f_eo")
+    _dev(dm_eo, torch.float64, "dm_eo")
+    nspin, neo = f_eo.shape[0], f_eo.shape[1]
+    nrows = z.shape[1]
+    nb = ctypes.c_size_t()
+    _check(lib.dmet_fock_dc_workspace(nspin, neo, nrows, ctypes.byref(nb)))
+    ws = _workspace(nb.value, f_eo.device)
+    out = torch.empty_like(f_eo)
+    _check(lib.dmet_fock_dc(nspin, neo, nrows, _ptr(z), _ptr(f_eo), _ptr(dm_eo), _ptr(out), _ptr(ws), ws.numel(),
+                            _stream(stream)))
     return out
 
 

@@ -235,3 +235,47 @@ def test_batched_graph_replay_and_autotune(dmet, tmp_path, monkeypatch):
         torch.cuda.synchronize()
         for a, b in zip(eager, outs):
             assert torch.equal(a, b), rep
+
+
+# ------------------------------------------------- DF output and double counting
+@pytest.mark.parametrize("prec", ["fp64", "bf16x6"])
+def test_df_factors_reproduce_eri(dmet, prec):
+    """z^T z equals the oracle's ERI (the contraction skipped, Sec. 2.1)."""
+    wl, lat, lm, bath = case("uodd", kmesh=(3, 2, 1), nao=6, naux=17, nspin=2, seed=19)
+    ck = bath["c_k"]
+    z = dmet.dmet_transform_eri_df(wl.kmesh, wl.nao, wl.naux, to_dev(lm), to_dev(ck), prec).cpu().numpy()
+    assert z.shape == (2, wl.nk * wl.naux, wl.npair)
+    tol = 1e-10 if prec == "fp64" else LP_TOL
+    for a, b in ((0, 0), (1, 1), (0, 1)):
+        ref, _ = ok.alg1_eri(lm, ck[a], wl.kmesh, None if a == b else ck[b])
+        got = z[a].T @ z[b]
+        refp = ok.pack_s4(ref)
+        err = np.abs(got - refp).max()
+        assert err < tol * (np.abs(refp).max() if prec == "fp64" else 1.0), (a, b, err)
+
+
+@pytest.mark.parametrize("nspin", [1, 2])
+def test_fock_dc_parity(dmet, nspin):
+    from tests.test_fock_dc_pins import _hf_lattice
+    import synth
+    wl = synth.Workload("dcg", (3, 2, 1), 5, 14, 5, 5, nspin, 1.5, 311 + nspin)
+    lat, lm, b, hsup, gs, fk = _hf_lattice(wl)
+    bath = ok.build_bath(lat.dm_k, wl.kmesh, wl.nao)
+    ck = bath["c_k"]
+    f_eo, _ = ok.transform_1e(ck, fk)
+    g_eo, _ = ok.transform_1e(ck, lat.dm_k)
+    if nspin == 1:
+        eri = ok.alg1_eri(lm, ck[0], wl.kmesh)[0]
+    else:
+        eri = tuple(ok.alg1_eri(lm, ck[a], wl.kmesh, None if c is None else ck[c])[0]
+                    for a, c in ((0, None), (1, None), (0, 1)))
+    ref = ok.fock_double_counting(f_eo, g_eo, eri)
+    ck_d = to_dev(ck)
+    fe, _ = dmet.dmet_transform_1e(wl.kmesh, wl.nao, ck_d, to_dev(fk))
+    ge, _ = dmet.dmet_transform_1e(wl.kmesh, wl.nao, ck_d, to_dev(lat.dm_k))
+    for prec, tol in (("fp64", 1e-10), ("bf16x6", 1e-5)):
+        z = dmet.dmet_transform_eri_df(wl.kmesh, wl.nao, wl.naux, to_dev(lm), ck_d, prec)
+        ft = dmet.dmet_fock_dc(z, fe, ge).cpu().numpy()
+        err = np.abs(ft - ref).max()
+        print(f"fock_dc nspin={nspin} {prec}: {err:.3e}")
+        assert err < tol, (prec, err)
