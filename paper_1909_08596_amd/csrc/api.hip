@@ -191,13 +191,20 @@ dmet_status dmet_energy_1e(int nspin, int neo, const double* h_eo, const double*
     return energy_1e(nspin, neo, h_eo, dm_eo, e1, stream);
 }
 
+// FP64 and FP32-3M have kernels of their own; the split-BF16 forms share one
+static size_t eri_workspace(const EriPlan& p) {
+    if (p.prec == DMET_FP64) return eri_f64_workspace(p);
+    if (p.prec == DMET_FP32_3M) return eri_f32_workspace(p);
+    return eri_lp_workspace(p);
+}
+
 dmet_status dmet_transform_eri_workspace(const dmet_lattice* lat, int neo, dmet_precision prec, dmet_dtype dtype,
                                          size_t* bytes) {
     dmet_status s = check_eri_args(lat, neo, prec, dtype);
     if (s != DMET_OK) return s;
     if (!bytes) return fail(DMET_E_ARG, "bytes is NULL");
     EriPlan p = make_eri_plan(lat, neo, prec, dtype);
-    *bytes = prec == DMET_FP64 ? eri_f64_workspace(p) : eri_lp_workspace(p);
+    *bytes = eri_workspace(p);
     return DMET_OK;
 }
 
@@ -215,6 +222,9 @@ dmet_status dmet_transform_eri(const dmet_lattice* lat, int neo, const void* lmu
     if (prec == DMET_FP64)
         return eri_f64(p, lmunu, static_cast<const double*>(c_k), eri_aa, eri_bb, eri_ab, workspace, ws_bytes,
                        stream);
+    if (prec == DMET_FP32_3M)
+        return eri_f32(p, lmunu, static_cast<const double*>(c_k), eri_aa, eri_bb, eri_ab, workspace, ws_bytes,
+                       stream);
     return eri_lp(p, lmunu, static_cast<const double*>(c_k), eri_aa, eri_bb, eri_ab, workspace, ws_bytes, stream);
 }
 
@@ -227,10 +237,12 @@ dmet_status dmet_transform_eri_df(const dmet_lattice* lat, int neo, const void* 
     if (!lmunu || !c_k || !z) return fail(DMET_E_ARG, "null array argument");
     if (!workspace) return fail(DMET_E_WORKSPACE, "workspace is NULL");
     EriPlan p = make_eri_plan(lat, neo, prec, dtype);
-    const size_t need = prec == DMET_FP64 ? eri_f64_workspace(p) : eri_lp_workspace(p);
-    if (need > ws_bytes) return fail(DMET_E_WORKSPACE, "transform_eri workspace too small");
+    if (eri_workspace(p) > ws_bytes) return fail(DMET_E_WORKSPACE, "transform_eri workspace too small");
     if (prec == DMET_FP64)
         return eri_f64(p, lmunu, static_cast<const double*>(c_k), nullptr, nullptr, nullptr, workspace, ws_bytes,
+                       stream, z);
+    if (prec == DMET_FP32_3M)
+        return eri_f32(p, lmunu, static_cast<const double*>(c_k), nullptr, nullptr, nullptr, workspace, ws_bytes,
                        stream, z);
     return eri_lp(p, lmunu, static_cast<const double*>(c_k), nullptr, nullptr, nullptr, workspace, ws_bytes, stream,
                   z);

@@ -39,6 +39,10 @@ size_t eri_lp_workspace(const EriPlan& p);
 dmet_status eri_lp(const EriPlan& p, const void* lmunu, const double* ck, double* eri_aa, double* eri_bb,
                    double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st, double* df_out = nullptr);
 
+size_t eri_f32_workspace(const EriPlan& p);
+dmet_status eri_f32(const EriPlan& p, const void* lmunu, const double* ck, double* eri_aa, double* eri_bb,
+                    double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st, double* df_out = nullptr);
+
 size_t fock_dc_workspace(int nspin, int neo, int nrows);
 dmet_status fock_dc(int nspin, int neo, int nrows, const double* z, const double* f_eo, const double* dm_eo,
                     double* f_tilde, void* ws, size_t ws_bytes, hipStream_t st);

@@ -1,28 +1,24 @@
-// Reduced-precision forms of the embedding-ERI transformation (Alg. 1).
+// Split-BF16 forms of the embedding-ERI transformation (Alg. 1).
 //
-//   DMET_FP32_3M   : every complex GEMM as 3 real FP32 GEMMs (3M / Gauss):
-//                    P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi),
-//                    Re = P1 - P2, Im = P3 - P1 - P2; v_mfma_f32_32x32x2f32.
-//   DMET_BF16X3_3M : the same 3M products with every FP32 operand split as
-//                    x = hi + lo (hi = bf16(x), lo = bf16(x - hi)) and each real
+// Every complex GEMM runs as 3 real GEMMs (3M / Gauss): P1 = Ar Br,
+// P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi), Re = P1 - P2, Im = P3 - P1 - P2, with
+// each FP32 operand split into bf16 parts for v_mfma_f32_32x32x16_bf16:
+//   DMET_BF16X3_3M : x = hi + lo (hi = bf16(x), lo = bf16(x - hi)); each real
 //                    product formed as hi*hi + hi*lo + lo*hi with FP32
-//                    accumulation (v_mfma_f32_32x32x16_bf16).  On the diagonal
-//                    tiles of the contraction (which hold (ij|ij), where the
-//                    dropped lo*lo terms are squares and do not average out)
-//                    lo*lo is added as well.  The split leaves ~2^-17 relative
-//                    per operand.
+//                    accumulation.  On the diagonal tiles of the contraction
+//                    (which hold (ij|ij), where the dropped lo*lo terms are
+//                    squares and do not average out) lo*lo is added as well.
+//                    The split leaves ~2^-17 relative per operand.
 //   DMET_BF16X6_3M : three-way split x = hi + mid + lo and the six products
 //                    whose order is at most 2^-16 (hh, hm, mh, hl, mm, lh):
 //                    ~2^-24 relative, FP32-level accuracy on the bf16 pipes.
 //
 // Intermediates are FP32: T (stage-1 output, three planes Tr, Ti, Tr + Ti) and
-// Z (real rows of the contraction).  The contraction accumulates FP32 MFMA
-// partials over chunks of FLUSH_K rows and adds them into FP64 registers.
-//
-// LDS layouts.  FP32: K-outer, As[p][k][m] (a lane of 32x32x2 reads one float
-// of row l%32).  BF16x3: K-inner, As[p][m][k] (a lane of 32x32x16 reads 8
-// consecutive k of row l%32 with one 16-byte load); K-outer sources are
-// transposed while they are staged (8 rows per thread).
+// Z (real rows of the contraction), both stored as packed bf16 parts
+// [plane][part][k/8][x][8] so that one MFMA operand fragment (8 consecutive k
+// of one row) is one aligned 16-byte chunk moved straight from global memory
+// into LDS.  The contraction accumulates FP32 MFMA partials over chunks of
+// FLUSH_K rows and adds them into FP64 registers.
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -41,15 +37,6 @@ namespace dmet {
 
 typedef float f16v __attribute__((ext_vector_type(16)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-typedef double d4v __attribute__((ext_vector_type(4)));
-
-enum { LP_F32 = 0, LP_BF16X3 = 1, LP_BF16X6 = 2 };
-
-// number of bf16 parts an FP32 operand is split into
-template <int PREC>
-struct NSplit {
-    static constexpr int value = PREC == LP_BF16X6 ? 3 : (PREC == LP_BF16X3 ? 2 : 1);
-};
 
 template <int NS>
 __device__ inline void split_bf16(float x, __bf16 (&part)[NS]) {
@@ -59,428 +46,6 @@ __device__ inline void split_bf16(float x, __bf16 (&part)[NS]) {
         part[s] = (__bf16)r;
         r = r - (float)part[s];
     }
-}
-
-// ------------------------------------------------------------------ tile shape
-// 256 threads, 4 waves as 2 x 2; wave tile (BM/2) x (BN/2) made of 32 x 32 MFMA
-// tiles.  NPL independent accumulator planes (3 for the 3M products, 1 for the
-// real contraction).
-template <int PREC, int NPL, int BM, int BN, int BK>
-struct LpCfg {
-    static constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 32, TN = WN / 32;
-    // FP32 K-outer rows: pad keeps consecutive k rows on different banks
-    static constexpr int LDA32 = BM + 4, LDB32 = BN + 4;
-    // BF16 K-inner rows: stride of an odd number of 16-byte units
-    static constexpr int LDK = BK + 8;
-    static constexpr int A_ELEMS = PREC == LP_F32 ? BK * LDA32 : BM * LDK;   // per plane (and per hi/lo)
-    static constexpr int B_ELEMS = PREC == LP_F32 ? BK * LDB32 : BN * LDK;
-    static constexpr int KSTEP = PREC == LP_F32 ? 2 : 16;
-    static constexpr int NS = NSplit<PREC>::value;
-    static constexpr size_t lds_bytes() {
-        return PREC == LP_F32 ? (size_t)NPL * (A_ELEMS + B_ELEMS) * 4 : (size_t)NPL * NS * (A_ELEMS + B_ELEMS) * 2;
-    }
-};
-
-// ------------------------------------------------------------------ staging
-// Operand providers implement
-//   static constexpr bool KINNER;                 // source contiguous along k
-//   void load(int gk, int gx, float (&v)[NPL])     // zero outside the matrix
-// where gx is the row (A) or column (B) index.
-template <int PREC, int NPL, int ROWS, int BK, int LD32, int LDK, class Src>
-__device__ inline void stage(const Src& src, int k0, int x0, float* s32, __bf16* s16) {
-    const int tid = threadIdx.x;
-    if constexpr (PREC == LP_F32) {
-        // LDS [p][k][x]
-        for (int e = tid; e < ROWS * BK; e += 256) {
-            int kk, xx;
-            if constexpr (Src::KINNER) {
-                kk = e % BK;
-                xx = e / BK;
-            } else {
-                xx = e % ROWS;
-                kk = e / ROWS;
-            }
-            float v[NPL];
-            src.load(k0 + kk, x0 + xx, v);
-#pragma unroll
-            for (int p = 0; p < NPL; ++p) s32[(p * BK + kk) * LD32 + xx] = v[p];
-        }
-    } else {
-        // LDS [p][part][x][k]: each thread produces 8 consecutive k of one x
-        constexpr int G = BK / 8;
-        constexpr int NS = NSplit<PREC>::value;
-        for (int e = tid; e < ROWS * G; e += 256) {
-            int xx, g;
-            if constexpr (Src::KINNER) {
-                g = e % G;
-                xx = e / G;
-            } else {
-                xx = e % ROWS;
-                g = e / ROWS;
-            }
-            bf8 part[NPL][NS];
-#pragma unroll
-            for (int v = 0; v < 8; ++v) {
-                float val[NPL];
-                src.load(k0 + 8 * g + v, x0 + xx, val);
-#pragma unroll
-                for (int p = 0; p < NPL; ++p) {
-                    __bf16 sp[NS];
-                    split_bf16<NS>(val[p], sp);
-#pragma unroll
-                    for (int t = 0; t < NS; ++t) part[p][t][v] = sp[t];
-                }
-            }
-#pragma unroll
-            for (int p = 0; p < NPL; ++p)
-#pragma unroll
-                for (int t = 0; t < NS; ++t)
-                    *reinterpret_cast<bf8*>(s16 + ((size_t)(NS * p + t) * ROWS + xx) * LDK + 8 * g) = part[p][t];
-        }
-    }
-}
-
-// ------------------------------------------------------------------ MFMA block
-template <int PREC, int NPL, int BM, int BN, int BK>
-struct LpAcc {
-    using C = LpCfg<PREC, NPL, BM, BN, BK>;
-    f16v a[NPL][C::TM][C::TN];
-    __device__ void zero() {
-#pragma unroll
-        for (int p = 0; p < NPL; ++p)
-#pragma unroll
-            for (int i = 0; i < C::TM; ++i)
-#pragma unroll
-                for (int j = 0; j < C::TN; ++j)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) a[p][i][j][r] = 0.f;
-    }
-};
-
-template <int PREC, int NPL, int BM, int BN, int BK, bool LOLO>
-__device__ inline void lp_mma(const float* As32, const float* Bs32, const __bf16* As16, const __bf16* Bs16,
-                              LpAcc<PREC, NPL, BM, BN, BK>& acc) {
-    using C = LpCfg<PREC, NPL, BM, BN, BK>;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm0 = (wave >> 1) * C::WM, wn0 = (wave & 1) * C::WN;
-    if constexpr (PREC == LP_F32) {
-#pragma unroll
-        for (int kk = 0; kk < BK; kk += 2) {
-            const int kr = kk + (lane >> 5);
-#pragma unroll
-            for (int p = 0; p < NPL; ++p) {
-                float a[C::TM], b[C::TN];
-#pragma unroll
-                for (int i = 0; i < C::TM; ++i) a[i] = As32[(p * BK + kr) * C::LDA32 + wm0 + i * 32 + (lane & 31)];
-#pragma unroll
-                for (int j = 0; j < C::TN; ++j) b[j] = Bs32[(p * BK + kr) * C::LDB32 + wn0 + j * 32 + (lane & 31)];
-#pragma unroll
-                for (int i = 0; i < C::TM; ++i)
-#pragma unroll
-                    for (int j = 0; j < C::TN; ++j)
-                        acc.a[p][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc.a[p][i][j], 0, 0, 0);
-            }
-        }
-    } else {
-        constexpr int NS = NSplit<PREC>::value;
-#pragma unroll
-        for (int kk = 0; kk < BK; kk += 16) {
-            const int ko = kk + 8 * (lane >> 5);
-#pragma unroll
-            for (int p = 0; p < NPL; ++p) {
-                bf8 a[NS][C::TM], b[NS][C::TN];
-#pragma unroll
-                for (int t = 0; t < NS; ++t) {
-#pragma unroll
-                    for (int i = 0; i < C::TM; ++i) {
-                        const int row = wm0 + i * 32 + (lane & 31);
-                        a[t][i] = *reinterpret_cast<const bf8*>(As16 + ((size_t)(NS * p + t) * BM + row) * C::LDK + ko);
-                    }
-#pragma unroll
-                    for (int j = 0; j < C::TN; ++j) {
-                        const int col = wn0 + j * 32 + (lane & 31);
-                        b[t][j] = *reinterpret_cast<const bf8*>(Bs16 + ((size_t)(NS * p + t) * BN + col) * C::LDK + ko);
-                    }
-                }
-#pragma unroll
-                for (int i = 0; i < C::TM; ++i)
-#pragma unroll
-                    for (int j = 0; j < C::TN; ++j) {
-                        f16v c = acc.a[p][i][j];
-                        // smallest terms first
-                        if constexpr (NS == 2) {
-                            if constexpr (LOLO) c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1][i], b[1][j], c, 0, 0, 0);
-                            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1][i], b[0][j], c, 0, 0, 0);
-                            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[1][j], c, 0, 0, 0);
-                        } else {
-                            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2][i], b[0][j], c, 0, 0, 0);
-                            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1][i], b[1][j], c, 0, 0, 0);
-                            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[2][j], c, 0, 0, 0);
-                            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1][i], b[0][j], c, 0, 0, 0);
-                            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[1][j], c, 0, 0, 0);
-                        }
-                        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[0][j], c, 0, 0, 0);
-                        acc.a[p][i][j] = c;
-                    }
-            }
-        }
-    }
-}
-
-// 32x32 MFMA result layout: register r of lane l holds D[8(r/4) + 4(l/32) + r%4][l%32].
-template <int PREC, int NPL, int BM, int BN, int BK, class Fn>
-__device__ inline void lp_visit(const LpAcc<PREC, NPL, BM, BN, BK>& acc, Fn fn) {
-    using C = LpCfg<PREC, NPL, BM, BN, BK>;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm0 = (wave >> 1) * C::WM, wn0 = (wave & 1) * C::WN;
-#pragma unroll
-    for (int i = 0; i < C::TM; ++i)
-#pragma unroll
-        for (int j = 0; j < C::TN; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                float v[NPL];
-#pragma unroll
-                for (int p = 0; p < NPL; ++p) v[p] = acc.a[p][i][j][r];
-                fn(wm0 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), wn0 + j * 32 + (lane & 31), v);
-            }
-}
-
-// Generic K loop (no FP64 flush): stage A and B, multiply.
-template <int PREC, int NPL, int BM, int BN, int BK, class SA, class SB>
-__device__ inline void lp_kloop(const SA& sa, const SB& sb, int K, int m0, int n0, char* smem,
-                                LpAcc<PREC, NPL, BM, BN, BK>& acc) {
-    using C = LpCfg<PREC, NPL, BM, BN, BK>;
-    float* As32 = reinterpret_cast<float*>(smem);
-    float* Bs32 = As32 + NPL * C::A_ELEMS;
-    __bf16* As16 = reinterpret_cast<__bf16*>(smem);
-    __bf16* Bs16 = As16 + C::NS * NPL * C::A_ELEMS;
-    for (int k0 = 0; k0 < K; k0 += BK) {
-        stage<PREC, NPL, BM, BK, C::LDA32, C::LDK>(sa, k0, m0, As32, As16);
-        stage<PREC, NPL, BN, BK, C::LDB32, C::LDK>(sb, k0, n0, Bs32, Bs16);
-        __syncthreads();
-        lp_mma<PREC, NPL, BM, BN, BK, false>(As32, Bs32, As16, Bs16, acc);
-        __syncthreads();
-    }
-}
-
-// ------------------------------------------------------------------ stage 1
-// T_k[(L,mu)][j] = sum_nu (L|mu k, nu k-q) C^{k-q}_{nu j}; planes (Tr, Ti, Tr+Ti)
-// stored as T[p][k*nao + mu][L*neo + j].
-template <class TIn>
-struct X1A {  // rows (L, mu), k = nu; source contiguous along nu
-    static constexpr bool KINNER = true;
-    const TIn* base;  // lmunu[q][k] as interleaved reals
-    int M, K;
-    __device__ void load(int gk, int gm, float (&v)[3]) const {
-        if (gk < K && gm < M) {
-            const float re = (float)base[((size_t)gm * K + gk) * 2], im = (float)base[((size_t)gm * K + gk) * 2 + 1];
-            v[0] = re;
-            v[1] = im;
-            v[2] = re + im;
-        } else {
-            v[0] = v[1] = v[2] = 0.f;
-        }
-    }
-};
-
-struct X1B {  // k = nu, cols j: C^{k-q}[nu][j]
-    static constexpr bool KINNER = false;
-    const double* c;  // [nao][neo] complex
-    int K, N;
-    __device__ void load(int gk, int gn, float (&v)[3]) const {
-        if (gk < K && gn < N) {
-            const double re = c[((size_t)gk * N + gn) * 2], im = c[((size_t)gk * N + gn) * 2 + 1];
-            v[0] = (float)re;
-            v[1] = (float)im;
-            v[2] = (float)(re + im);
-        } else {
-            v[0] = v[1] = v[2] = 0.f;
-        }
-    }
-};
-
-template <int PREC, int BM, int BN, int BK, class TIn>
-__global__ void __launch_bounds__(256) k_xform1_lp(Mesh mesh, int q, int nao, int naux, int neo,
-                                                   const TIn* __restrict__ lmunu, const double* __restrict__ ck,
-                                                   float* __restrict__ t, size_t plane) {
-    extern __shared__ __align__(16) char smem[];
-    const int k = blockIdx.z;
-    const int kmq = mesh_sub(mesh, k, q);
-    const int M = naux * nao;
-    X1A<TIn> sa{lmunu + ((size_t)q * mesh.nk + k) * (size_t)M * nao * 2, M, nao};
-    X1B sb{ck + (size_t)kmq * nao * neo * 2, nao, neo};
-    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-    LpAcc<PREC, 3, BM, BN, BK> acc;
-    acc.zero();
-    lp_kloop<PREC, 3, BM, BN, BK>(sa, sb, nao, m0, n0, smem, acc);
-    const size_t ldt = (size_t)naux * neo;
-    lp_visit(acc, [&](int r, int c, const float (&v)[3]) {
-        const int gm = m0 + r, gn = n0 + c;
-        if (gm < M && gn < neo) {
-            const int L = gm / nao, mu = gm % nao;
-            const size_t off = ((size_t)k * nao + mu) * ldt + (size_t)L * neo + gn;
-            const float tr = v[0] - v[1], ti = v[2] - v[0] - v[1];
-            t[off] = tr;
-            t[plane + off] = ti;
-            t[2 * plane + off] = tr + ti;
-        }
-    });
-}
-
-// ------------------------------------------------------------------ stage 2
-// X[i][(L,j)] = sum_{k,mu} conj(C^k_{mu i}) T[(k,mu)][(L,j)], i >= j -> Z rows.
-struct X2A {  // k = (k,mu), rows i: conj(C) planes (Cr, -Ci, Cr - Ci)
-    static constexpr bool KINNER = false;
-    const double* c;  // [nk*nao][neo] complex
-    int K, M;
-    __device__ void load(int gk, int gm, float (&v)[3]) const {
-        if (gk < K && gm < M) {
-            const double re = c[((size_t)gk * M + gm) * 2], im = c[((size_t)gk * M + gm) * 2 + 1];
-            v[0] = (float)re;
-            v[1] = (float)(-im);
-            v[2] = (float)(re - im);
-        } else {
-            v[0] = v[1] = v[2] = 0.f;
-        }
-    }
-};
-
-struct X2B {  // k = (k,mu), cols j of one L: T planes
-    static constexpr bool KINNER = false;
-    const float* t;  // T plane 0 at column offset L*neo
-    size_t plane, ldt;
-    int K, N;
-    __device__ void load(int gk, int gn, float (&v)[3]) const {
-        if (gk < K && gn < N) {
-            const size_t off = (size_t)gk * ldt + gn;
-            v[0] = t[off];
-            v[1] = t[plane + off];
-            v[2] = t[2 * plane + off];
-        } else {
-            v[0] = v[1] = v[2] = 0.f;
-        }
-    }
-};
-
-template <int PREC, int BM, int BN, int BK>
-__global__ void __launch_bounds__(256) k_xform2_lp(Mesh mesh, int nao, int naux, int neo, int self_conj,
-                                                   size_t zrow0, float wq, const double* __restrict__ ck,
-                                                   const float* __restrict__ t, size_t plane,
-                                                   float* __restrict__ z, size_t ldz) {
-    extern __shared__ __align__(16) char smem[];
-    const int njt = (neo + BN - 1) / BN;
-    const int L = blockIdx.y / njt, jt = blockIdx.y % njt;
-    const int m0 = blockIdx.x * BM, n0 = jt * BN;
-    if (m0 + BM - 1 < n0) return;  // every i < every j: upper triangle
-    const int K = mesh.nk * nao;
-    const size_t ldt = (size_t)naux * neo;
-    X2A sa{ck, K, neo};
-    X2B sb{t + (size_t)L * neo, plane, ldt, K, neo};
-    LpAcc<PREC, 3, BM, BN, BK> acc;
-    acc.zero();
-    lp_kloop<PREC, 3, BM, BN, BK>(sa, sb, K, m0, n0, smem, acc);
-    lp_visit(acc, [&](int r, int c, const float (&v)[3]) {
-        const int i = m0 + r, j = n0 + c;
-        if (i >= neo || j >= neo || j > i) return;
-        const size_t pair = (size_t)i * (i + 1) / 2 + j;
-        const float xr = v[0] - v[1], xi = v[2] - v[0] - v[1];
-        if (self_conj) {
-            z[(zrow0 + L) * ldz + pair] = wq * xr;
-        } else {
-            z[(zrow0 + 2 * (size_t)L) * ldz + pair] = wq * xr;
-            z[(zrow0 + 2 * (size_t)L + 1) * ldz + pair] = wq * xi;
-        }
-    });
-}
-
-// ------------------------------------------------------------------ contraction
-struct ZSrc {  // Z[K][ld], k-outer
-    static constexpr bool KINNER = false;
-    const float* z;
-    size_t ld;
-    int K, N;
-    __device__ void load(int gk, int gx, float (&v)[1]) const {
-        v[0] = (gk < K && gx < N) ? z[(size_t)gk * ld + gx] : 0.f;
-    }
-};
-
-// out = Za^T Zb with FP32 partials over FLUSH_K rows flushed into FP64.
-// MODE 0: packed s8 over tiles mt >= nt; MODE 1: full s4.
-template <int PREC, int BM, int BN, int BK, int MODE>
-__global__ void __launch_bounds__(256) k_contract_lp(int npair, int krows, const float* __restrict__ za,
-                                                     const float* __restrict__ zb, size_t ldz, int flush_k,
-                                                     double* __restrict__ out) {
-    using C = LpCfg<PREC, 1, BM, BN, BK>;
-    extern __shared__ __align__(16) char smem[];
-    int mt, nt;
-    if constexpr (MODE == 0) {
-        const long b = blockIdx.x;
-        mt = (int)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
-        while ((long)mt * (mt + 1) / 2 > b) --mt;
-        while ((long)(mt + 1) * (mt + 2) / 2 <= b) ++mt;
-        nt = (int)(b - (long)mt * (mt + 1) / 2);
-    } else {
-        mt = blockIdx.x;
-        nt = blockIdx.y;
-    }
-    const int m0 = mt * BM, n0 = nt * BN;
-    const bool diag = (mt == nt) && (BM == BN);
-    ZSrc sa{za, ldz, krows, npair}, sb{zb, ldz, krows, npair};
-    float* As32 = reinterpret_cast<float*>(smem);
-    float* Bs32 = As32 + C::A_ELEMS;
-    __bf16* As16 = reinterpret_cast<__bf16*>(smem);
-    __bf16* Bs16 = As16 + C::NS * C::A_ELEMS;
-    LpAcc<PREC, 1, BM, BN, BK> acc;
-    acc.zero();
-    double acc64[C::TM][C::TN][16];
-#pragma unroll
-    for (int i = 0; i < C::TM; ++i)
-#pragma unroll
-        for (int j = 0; j < C::TN; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc64[i][j][r] = 0.0;
-    int since = 0;
-    for (int k0 = 0; k0 < krows; k0 += BK) {
-        stage<PREC, 1, BM, BK, C::LDA32, C::LDK>(sa, k0, m0, As32, As16);
-        stage<PREC, 1, BN, BK, C::LDB32, C::LDK>(sb, k0, n0, Bs32, Bs16);
-        __syncthreads();
-        if (PREC == LP_BF16X3 && diag)
-            lp_mma<PREC, 1, BM, BN, BK, true>(As32, Bs32, As16, Bs16, acc);
-        else
-            lp_mma<PREC, 1, BM, BN, BK, false>(As32, Bs32, As16, Bs16, acc);
-        __syncthreads();
-        since += BK;
-        if (since >= flush_k || k0 + BK >= krows) {
-#pragma unroll
-            for (int i = 0; i < C::TM; ++i)
-#pragma unroll
-                for (int j = 0; j < C::TN; ++j)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        acc64[i][j][r] += (double)acc.a[0][i][j][r];
-                        acc.a[0][i][j][r] = 0.f;
-                    }
-            since = 0;
-        }
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm0 = (wave >> 1) * C::WM, wn0 = (wave & 1) * C::WN;
-#pragma unroll
-    for (int i = 0; i < C::TM; ++i)
-#pragma unroll
-        for (int j = 0; j < C::TN; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int IJ = m0 + wm0 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const int KL = n0 + wn0 + j * 32 + (lane & 31);
-                if (IJ >= npair || KL >= npair) continue;
-                if constexpr (MODE == 0) {
-                    if (KL <= IJ) out[(size_t)IJ * (IJ + 1) / 2 + KL] = acc64[i][j][r];
-                } else {
-                    out[(size_t)IJ * npair + KL] = acc64[i][j][r];
-                }
-            }
 }
 
 // ------------------------------------------------------------------ packed split operands
@@ -552,136 +117,9 @@ inline long tile_grid(int ntile) {
     return (n + NXCD - 1) / NXCD * NXCD;
 }
 
-// Contraction on packed bf16 parts.  256 threads, 128 x 128 tile, BK = 32,
-// the next K tile is fetched into registers while the current one is
-// multiplied.  FP32 partials are flushed into FP64 every flush_k rows.
-template <int NS, int MODE>
-__global__ void __launch_bounds__(256) k_contract_pk(int npair, int kgroups, const __bf16* __restrict__ pa,
-                                                     const __bf16* __restrict__ pb, int flush_k, long nblocks,
-                                                     double* __restrict__ out) {
-    constexpr int BM = 128, BN = 128, BK = 32, G = BK / 8;
-    constexpr int TM = 2, TN = 2;  // wave tile 64 x 64
-    constexpr int CH = G * BM / 256;  // 16-byte chunks per thread per part per operand (= 2)
-    __shared__ __align__(16) bf8 sA[NS][G][BM];
-    __shared__ __align__(16) bf8 sB[NS][G][BN];
-    int mt, nt;
-    const long logical = xcd_logical(blockIdx.x, nblocks);
-    const int ntile = (npair + BM - 1) / BM;
-    if (!tile_of<MODE>(logical, ntile, mt, nt)) return;
-    const int m0 = mt * BM, n0 = nt * BN;
-    const bool diag = mt == nt;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
-    const size_t plane = (size_t)kgroups * npair;
-
-    bf8 ra[NS][CH], rb[NS][CH];
-    auto fetch = [&](int kt) {
-#pragma unroll
-        for (int t = 0; t < NS; ++t)
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const int idx = tid + 256 * c, g = idx / BM, row = idx % BM;
-                const size_t gg = (size_t)kt * G + g;
-                const int xa = m0 + row, xb = n0 + row;
-                ra[t][c] = xa < npair ? *reinterpret_cast<const bf8*>(pa + (t * plane + gg * npair + xa) * 8) : bf8{};
-                rb[t][c] = xb < npair ? *reinterpret_cast<const bf8*>(pb + (t * plane + gg * npair + xb) * 8) : bf8{};
-            }
-    };
-    auto commit = [&]() {
-#pragma unroll
-        for (int t = 0; t < NS; ++t)
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const int idx = tid + 256 * c, g = idx / BM, row = idx % BM;
-                sA[t][g][row] = ra[t][c];
-                sB[t][g][row] = rb[t][c];
-            }
-    };
-
-    f16v acc[TM][TN];
-    double acc64[TM][TN][16];
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                acc[i][j][r] = 0.f;
-                acc64[i][j][r] = 0.0;
-            }
-        }
-    const int nkt = kgroups / G;
-    fetch(0);
-    int since = 0;
-    for (int kt = 0; kt < nkt; ++kt) {
-        commit();
-        __syncthreads();
-        if (kt + 1 < nkt) fetch(kt + 1);
-#pragma unroll
-        for (int ks = 0; ks < G; ks += 2) {
-            const int g = ks + (lane >> 5);
-#pragma unroll
-            for (int i = 0; i < TM; ++i) {
-                bf8 a[NS];
-#pragma unroll
-                for (int t = 0; t < NS; ++t) a[t] = sA[t][g][wm0 + i * 32 + (lane & 31)];
-#pragma unroll
-                for (int j = 0; j < TN; ++j) {
-                    bf8 b[NS];
-#pragma unroll
-                    for (int t = 0; t < NS; ++t) b[t] = sB[t][g][wn0 + j * 32 + (lane & 31)];
-                    f16v c = acc[i][j];
-                    if constexpr (NS == 2) {
-                        if (diag) c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[1], c, 0, 0, 0);
-                        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[0], c, 0, 0, 0);
-                        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[1], c, 0, 0, 0);
-                    } else {
-                        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[0], c, 0, 0, 0);
-                        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[1], c, 0, 0, 0);
-                        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[2], c, 0, 0, 0);
-                        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[0], c, 0, 0, 0);
-                        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[1], c, 0, 0, 0);
-                    }
-                    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[0], c, 0, 0, 0);
-                    acc[i][j] = c;
-                }
-            }
-        }
-        __syncthreads();
-        since += BK;
-        if (since >= flush_k || kt + 1 == nkt) {
-#pragma unroll
-            for (int i = 0; i < TM; ++i)
-#pragma unroll
-                for (int j = 0; j < TN; ++j)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        acc64[i][j][r] += (double)acc[i][j][r];
-                        acc[i][j][r] = 0.f;
-                    }
-            since = 0;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int IJ = m0 + wm0 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const int KL = n0 + wn0 + j * 32 + (lane & 31);
-                if (IJ >= npair || KL >= npair) continue;
-                if constexpr (MODE == 0) {
-                    if (KL <= IJ) out[(size_t)IJ * (IJ + 1) / 2 + KL] = acc64[i][j][r];
-                } else {
-                    out[(size_t)IJ * npair + KL] = acc64[i][j][r];
-                }
-            }
-}
-
-// Same contraction with the operand tiles moved by direct global->LDS loads
-// (global_load_lds_dwordx4: lane l of a wave writes its 16 bytes at the
-// wave's LDS base + 16 l) into a ring of NBUF stages, so that the tiles of
+// Contraction on packed bf16 parts with the operand tiles moved by direct
+// global->LDS loads (global_load_lds_dwordx4: lane l of a wave writes its 16
+// bytes at the wave's LDS base + 16 l) into a ring of NBUF stages, so that the tiles of
 // the next NBUF-1 K steps are in flight while one is multiplied.  Rows past
 // the matrix edge are clamped to the last row: they only feed output rows /
 // columns that are not stored.
@@ -1585,9 +1023,6 @@ static int contract_variant() {
     return e && e[0] == '1' ? 1 : 2;
 }
 
-constexpr int L1_BM = 128, L1_BN = 64, L1_BK = 16;
-constexpr int L2_BM = 64, L2_BN = 64, L2_BK = 16;
-constexpr int LC_BM = 128, LC_BN = 128, LC_BK = 32;
 constexpr int FLUSH_K = 256;
 
 static int kgroups_of(int krows) { return (krows + 31) / 32 * 4; }
@@ -1623,15 +1058,11 @@ static PkDims pk_dims(const EriPlan& p) {
 
 size_t eri_lp_workspace(const EriPlan& p) {
     Carve cv(nullptr, 0);
-    if (p.prec == DMET_FP32_3M) {
-        cv.take<float>((size_t)3 * p.mesh.nk * p.nao * p.naux * p.neo);   // T planes
-    } else {
-        PkDims d = pk_dims(p);
-        cv.take<__bf16>(d.lm_elems);
-        cv.take<__bf16>(d.c1_elems);
-        cv.take<__bf16>(d.c2_elems);
-        cv.take<__bf16>(d.t_elems);
-    }
+    PkDims d = pk_dims(p);
+    cv.take<__bf16>(d.lm_elems);
+    cv.take<__bf16>(d.c1_elems);
+    cv.take<__bf16>(d.c2_elems);
+    cv.take<__bf16>(d.t_elems);
     cv.take<float>((size_t)p.nspin * p.zrows * p.npair);              // Z per spin
     cv.take<__bf16>((size_t)p.nspin * packed_elems(p));               // split parts of Z
     return cv.bytes();
@@ -1700,162 +1131,77 @@ static dmet_status xform_packed(const EriPlan& p, const void* lmunu, const doubl
     return DMET_OK;
 }
 
-template <int PREC, class K1, class K2, class K3, class K4>
-static dmet_status set_lds(K1 k1, K2 k2, K3 k3, K4 k4) {
-    // dynamic LDS above 64 KiB must be opted into per kernel
-    const size_t s1 = LpCfg<PREC, 3, L1_BM, L1_BN, L1_BK>::lds_bytes();
-    const size_t s2 = LpCfg<PREC, 3, L2_BM, L2_BN, L2_BK>::lds_bytes();
-    const size_t s3 = LpCfg<PREC, 1, LC_BM, LC_BN, LC_BK>::lds_bytes();
-    DMET_HIP(hipFuncSetAttribute((const void*)k1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s1));
-    DMET_HIP(hipFuncSetAttribute((const void*)k2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s2));
-    DMET_HIP(hipFuncSetAttribute((const void*)k3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s3));
-    DMET_HIP(hipFuncSetAttribute((const void*)k4, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s3));
-    return DMET_OK;
-}
-
 __global__ void k_f32_to_f64(const float* __restrict__ a, double* __restrict__ b, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         b[i] = (double)a[i];
 }
 
-template <int PREC>
+template <int NS>
 static dmet_status eri_lp_run(const EriPlan& p, const void* lmunu, const double* ck, double* eri_aa,
-                              double* eri_bb, double* eri_ab, float* t, float* z, __bf16* zp, Carve& cv,
-                              hipStream_t st, double* df_out) {
-    using C1 = LpCfg<PREC, 3, L1_BM, L1_BN, L1_BK>;
-    using C2 = LpCfg<PREC, 3, L2_BM, L2_BN, L2_BK>;
-    using C3 = LpCfg<PREC, 1, LC_BM, LC_BN, LC_BK>;
-    auto k1d = k_xform1_lp<PREC, L1_BM, L1_BN, L1_BK, double>;
-    auto k1f = k_xform1_lp<PREC, L1_BM, L1_BN, L1_BK, float>;
-    auto k2 = k_xform2_lp<PREC, L2_BM, L2_BN, L2_BK>;
-    auto k3 = k_contract_lp<PREC, LC_BM, LC_BN, LC_BK, 0>;
-    auto k4 = k_contract_lp<PREC, LC_BM, LC_BN, LC_BK, 1>;
-    dmet_status s = set_lds<PREC>(k1d, k2, k3, k4);
-    if (s != DMET_OK) return s;
-    DMET_HIP(hipFuncSetAttribute((const void*)k1f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)C1::lds_bytes()));
-    static const char* names[3][4] = {
-        {"xform1_f32", "xform2_f32", "contract_s8_f32", "contract_s4_f32"},
-        {"xform1_bf16x3", "xform2_bf16x3", "contract_s8_bf16x3", "contract_s4_bf16x3"},
-        {"xform1_bf16x6", "xform2_bf16x6", "contract_s8_bf16x6", "contract_s4_bf16x6"}};
-    const char* n1 = names[PREC][0];
-    const char* n2 = names[PREC][1];
-    const char* n3 = names[PREC][2];
-    const char* n4 = names[PREC][3];
-    const size_t plane = (size_t)p.mesh.nk * p.nao * p.naux * p.neo;
+                              double* eri_bb, double* eri_ab, float* z, __bf16* zp, Carve& cv, hipStream_t st,
+                              double* df_out) {
+    const char* n3 = NS == 3 ? "contract_s8_bf16x6" : "contract_s8_bf16x3";
+    const char* n4 = NS == 3 ? "contract_s4_bf16x6" : "contract_s4_bf16x3";
     const size_t ldz = (size_t)p.npair;
-    const int M1 = p.naux * p.nao;
-    if constexpr (PREC != LP_F32) {
-        dmet_status xs = xform_packed<NSplit<PREC>::value>(p, lmunu, ck, z, cv, st);
-        if (xs != DMET_OK) return xs;
-    }
-    for (int s = 0; s < (PREC == LP_F32 ? p.nspin : 0); ++s) {
-        const double* cks = ck + (size_t)s * p.mesh.nk * p.nao * p.neo * 2;
-        float* zs = z + (size_t)s * p.zrows * ldz;
-        for (const QBlock& qb : p.qblocks) {
-            dim3 g1((M1 + L1_BM - 1) / L1_BM, (p.neo + L1_BN - 1) / L1_BN, p.mesh.nk);
-            ProfScope ps1(n1, st);
-            if (p.dtype == DMET_C128)
-                k1d<<<g1, 256, C1::lds_bytes(), st>>>(p.mesh, qb.q, p.nao, p.naux, p.neo,
-                                                      static_cast<const double*>(lmunu), cks, t, plane);
-            else
-                k1f<<<g1, 256, C1::lds_bytes(), st>>>(p.mesh, qb.q, p.nao, p.naux, p.neo,
-                                                      static_cast<const float*>(lmunu), cks, t, plane);
-            ps1.stop();
-            DMET_LAUNCH_CHECK(n1);
-            const int njt = (p.neo + L2_BN - 1) / L2_BN;
-            dim3 g2((p.neo + L2_BM - 1) / L2_BM, p.naux * njt);
-            ProfScope ps2(n2, st);
-            k2<<<g2, 256, C2::lds_bytes(), st>>>(p.mesh, p.nao, p.naux, p.neo, qb.self_conj, qb.zrow0,
-                                                 (float)qb.weight, cks, t, plane, zs, ldz);
-            ps2.stop();
-            DMET_LAUNCH_CHECK(n2);
-        }
-    }
+    dmet_status xs = xform_packed<NS>(p, lmunu, ck, z, cv, st);
+    if (xs != DMET_OK) return xs;
     if (df_out) {
         const size_t n = (size_t)p.nspin * p.zrows * p.npair;
         k_f32_to_f64<<<1024, 256, 0, st>>>(z, df_out, n);
         DMET_LAUNCH_CHECK("k_f32_to_f64");
         return DMET_OK;
     }
-    if constexpr (PREC == LP_F32) {
-        const int nt = (p.npair + LC_BM - 1) / LC_BM;
-        for (int s = 0; s < p.nspin; ++s) {
-            const float* zs = z + (size_t)s * p.zrows * ldz;
-            ProfScope ps(n3, st);
-            k3<<<dim3((unsigned)((long)nt * (nt + 1) / 2)), 256, C3::lds_bytes(), st>>>(
-                p.npair, p.zrows, zs, zs, ldz, FLUSH_K, s == 0 ? eri_aa : eri_bb);
-            ps.stop();
-            DMET_LAUNCH_CHECK(n3);
-        }
-        if (p.nspin == 2 && eri_ab) {
-            ProfScope ps(n4, st);
-            k4<<<dim3(nt, nt), 256, C3::lds_bytes(), st>>>(p.npair, p.zrows, z, z + (size_t)p.zrows * ldz, ldz,
-                                                           FLUSH_K, eri_ab);
-            ps.stop();
-            DMET_LAUNCH_CHECK(n4);
-        }
-    } else {
-        constexpr int NS = NSplit<PREC>::value;
-        const int kg = kgroups_of(p.zrows);
-        const size_t per_spin = (size_t)NS * kg * 8 * p.npair;
-        for (int s = 0; s < p.nspin; ++s) {
-            ProfScope ps(PREC == LP_BF16X3 ? "pack_bf16x3" : "pack_bf16x6", st);
-            k_pack_parts<NS><<<dim3((p.npair + 255) / 256, kg), 256, 0, st>>>(
-                z + (size_t)s * p.zrows * ldz, ldz, p.zrows, p.npair, kg, zp + s * per_spin);
-            ps.stop();
-            DMET_LAUNCH_CHECK("k_pack_parts");
-        }
-        const int ntile = (p.npair + 127) / 128;
-        constexpr int NB = dl_nbuf<NS>();
-        const bool v2 = contract_variant() == 2;
-        auto kd0 = v2 ? k_contract_d2<NS, 0> : k_contract_dl<NS, 0, NB>;
-        auto kd1 = v2 ? k_contract_d2<NS, 1> : k_contract_dl<NS, 1, NB>;
-        const size_t lds = v2 ? d2_lds<NS>() : dl_lds<NS>();
-        DMET_HIP(hipFuncSetAttribute((const void*)kd0, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        DMET_HIP(hipFuncSetAttribute((const void*)kd1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        for (int s = 0; s < p.nspin; ++s) {
-            const long nb = tile_grid<0>(ntile);
-            ProfScope ps(n3, st);
-            kd0<<<dim3((unsigned)nb), 256, lds, st>>>(p.npair, kg, zp + s * per_spin, zp + s * per_spin,
-                                                               FLUSH_K, nb, s == 0 ? eri_aa : eri_bb);
-            ps.stop();
-            DMET_LAUNCH_CHECK(n3);
-        }
-        if (p.nspin == 2 && eri_ab) {
-            const long nb = tile_grid<1>(ntile);
-            ProfScope ps(n4, st);
-            kd1<<<dim3((unsigned)nb), 256, lds, st>>>(p.npair, kg, zp, zp + per_spin, FLUSH_K, nb, eri_ab);
-            ps.stop();
-            DMET_LAUNCH_CHECK(n4);
-        }
+    const int kg = kgroups_of(p.zrows);
+    const size_t per_spin = (size_t)NS * kg * 8 * p.npair;
+    for (int s = 0; s < p.nspin; ++s) {
+        ProfScope ps(NS == 2 ? "pack_bf16x3" : "pack_bf16x6", st);
+        k_pack_parts<NS><<<dim3((p.npair + 255) / 256, kg), 256, 0, st>>>(z + (size_t)s * p.zrows * ldz, ldz,
+                                                                         p.zrows, p.npair, kg, zp + s * per_spin);
+        ps.stop();
+        DMET_LAUNCH_CHECK("k_pack_parts");
+    }
+    const int ntile = (p.npair + 127) / 128;
+    constexpr int NB = dl_nbuf<NS>();
+    const bool v2 = contract_variant() == 2;
+    auto kd0 = v2 ? k_contract_d2<NS, 0> : k_contract_dl<NS, 0, NB>;
+    auto kd1 = v2 ? k_contract_d2<NS, 1> : k_contract_dl<NS, 1, NB>;
+    const size_t lds = v2 ? d2_lds<NS>() : dl_lds<NS>();
+    DMET_HIP(hipFuncSetAttribute((const void*)kd0, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    DMET_HIP(hipFuncSetAttribute((const void*)kd1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    for (int s = 0; s < p.nspin; ++s) {
+        const long nb = tile_grid<0>(ntile);
+        ProfScope ps(n3, st);
+        kd0<<<dim3((unsigned)nb), 256, lds, st>>>(p.npair, kg, zp + s * per_spin, zp + s * per_spin, FLUSH_K, nb,
+                                                  s == 0 ? eri_aa : eri_bb);
+        ps.stop();
+        DMET_LAUNCH_CHECK(n3);
+    }
+    if (p.nspin == 2 && eri_ab) {
+        const long nb = tile_grid<1>(ntile);
+        ProfScope ps(n4, st);
+        kd1<<<dim3((unsigned)nb), 256, lds, st>>>(p.npair, kg, zp, zp + per_spin, FLUSH_K, nb, eri_ab);
+        ps.stop();
+        DMET_LAUNCH_CHECK(n4);
     }
     return DMET_OK;
 }
 
 dmet_status eri_lp(const EriPlan& p, const void* lmunu, const double* ck, double* eri_aa, double* eri_bb,
                    double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st, double* df_out) {
+    if (p.prec != DMET_BF16X3_3M && p.prec != DMET_BF16X6_3M) return fail(DMET_E_ARG, "eri_lp: split-bf16 forms only");
     if (eri_lp_workspace(p) > ws_bytes) return fail(DMET_E_WORKSPACE, "transform_eri workspace too small");
+    // layout: [packed transform operands] [Z] [split parts of Z]
     Carve cv(ws, ws_bytes);
-    // layout: [T planes (FP32 form) | packed transform operands (bf16 forms)] [Z] [Z parts]
     Carve pre(ws, ws_bytes);
-    float* t = nullptr;
-    if (p.prec == DMET_FP32_3M) {
-        t = cv.take<float>((size_t)3 * p.mesh.nk * p.nao * p.naux * p.neo);
-    } else {
-        PkDims d = pk_dims(p);
-        cv.take<__bf16>(d.lm_elems);
-        cv.take<__bf16>(d.c1_elems);
-        cv.take<__bf16>(d.c2_elems);
-        cv.take<__bf16>(d.t_elems);
-    }
+    PkDims d = pk_dims(p);
+    cv.take<__bf16>(d.lm_elems);
+    cv.take<__bf16>(d.c1_elems);
+    cv.take<__bf16>(d.c2_elems);
+    cv.take<__bf16>(d.t_elems);
     float* z = cv.take<float>((size_t)p.nspin * p.zrows * p.npair);
     __bf16* zp = cv.take<__bf16>((size_t)p.nspin * packed_elems(p));
-    if (p.prec == DMET_FP32_3M)
-        return eri_lp_run<LP_F32>(p, lmunu, ck, eri_aa, eri_bb, eri_ab, t, z, zp, pre, st, df_out);
-    if (p.prec == DMET_BF16X3_3M)
-        return eri_lp_run<LP_BF16X3>(p, lmunu, ck, eri_aa, eri_bb, eri_ab, t, z, zp, pre, st, df_out);
-    return eri_lp_run<LP_BF16X6>(p, lmunu, ck, eri_aa, eri_bb, eri_ab, t, z, zp, pre, st, df_out);
+    if (p.prec == DMET_BF16X3_3M) return eri_lp_run<2>(p, lmunu, ck, eri_aa, eri_bb, eri_ab, z, zp, pre, st, df_out);
+    return eri_lp_run<3>(p, lmunu, ck, eri_aa, eri_bb, eri_ab, z, zp, pre, st, df_out);
 }
 
 }  // namespace dmet
@@ -2222,7 +1568,7 @@ size_t batch_workspace(int nfrag, const dmet_fragment* frags, dmet_precision pre
             dmet_lattice lat = frags[f].lat;
             lat.nspin = 1;
             EriPlan p = make_eri_plan(&lat, frags[f].neo, prec, frags[f].dtype);
-            mx = std::max(mx, prec == DMET_FP64 ? eri_f64_workspace(p) : eri_lp_workspace(p));
+            mx = std::max(mx, prec == DMET_FP64 ? eri_f64_workspace(p) : eri_f32_workspace(p));
         }
         return mx;
     }
@@ -2278,8 +1624,8 @@ dmet_status eri_batched(int nfrag, const dmet_fragment* frags, dmet_precision pr
             dmet_status s = prec == DMET_FP64
                                 ? eri_f64(p, frags[f].lmunu, static_cast<const double*>(frags[f].c_k), frags[f].eri,
                                           nullptr, nullptr, ws, ws_bytes, st)
-                                : eri_lp(p, frags[f].lmunu, static_cast<const double*>(frags[f].c_k), frags[f].eri,
-                                         nullptr, nullptr, ws, ws_bytes, st);
+                                : eri_f32(p, frags[f].lmunu, static_cast<const double*>(frags[f].c_k), frags[f].eri,
+                                          nullptr, nullptr, ws, ws_bytes, st);
             if (s != DMET_OK) return s;
         }
         return DMET_OK;

@@ -73,7 +73,7 @@ def test_fullsize_sampled_parity(dmet, name):
         refs[key], im = ok.alg1_eri_columns(lm, ck[sa], wl.kmesh, pa, cb, pb)
         assert im < 1e-10
     npair = wl.npair
-    for prec, tol_rel, tol_abs in (("fp64", 1e-10, 0.0), ("bf16x6", 0.0, 1e-6)):
+    for prec, tol_rel, tol_abs in (("fp64", 1e-10, 0.0), ("fp32", 0.0, 1e-6), ("bf16x6", 0.0, 1e-6)):
         out = dmet.dmet_transform_eri(wl.kmesh, wl.nao, wl.naux, lm_d, ck_d, prec)
         torch.cuda.synchronize()
         for sa, sb, key in spins:

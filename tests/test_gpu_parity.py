@@ -194,7 +194,7 @@ def _small_batch():
     return frags
 
 
-@pytest.mark.parametrize("prec", ["bf16x6", "bf16x3"])
+@pytest.mark.parametrize("prec", ["bf16x6", "bf16x3", "fp32"])
 def test_batched_matches_single_and_oracle(dmet, prec):
     frags = _small_batch()
     dev_lm = {}
@@ -211,7 +211,7 @@ def test_batched_matches_single_and_oracle(dmet, prec):
         assert torch.equal(single, got)   # same kernels' arithmetic, same order
         ref, _ = ok.alg1_eri(lm.astype(np.complex64).astype(np.complex128), ck, wl.kmesh)
         err = np.abs(got.cpu().numpy() - ok.pack_s8(ref)).max()
-        assert err < (LP_TOL if prec == "bf16x6" else 1e-5), err
+        assert err < (1e-5 if prec == "bf16x3" else LP_TOL), err
 
 
 def test_batched_graph_replay_and_autotune(dmet, tmp_path, monkeypatch):
@@ -238,7 +238,7 @@ def test_batched_graph_replay_and_autotune(dmet, tmp_path, monkeypatch):
 
 
 # ------------------------------------------------- DF output and double counting
-@pytest.mark.parametrize("prec", ["fp64", "bf16x6"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6"])
 def test_df_factors_reproduce_eri(dmet, prec):
     """z^T z equals the oracle's ERI (the contraction skipped, Sec. 2.1)."""
     wl, lat, lm, bath = case("uodd", kmesh=(3, 2, 1), nao=6, naux=17, nspin=2, seed=19)
