@@ -7,9 +7,12 @@
 //   F~_s = F_s - (J_s - K_s)            (per-spin densities)
 // For nspin = 1 the densities are per spin and the paper's spin-summed
 // gamma = 2 g, so F~ = F - (J(gamma) - K(gamma)/2) = F - (2 J(g) - K(g)).
-// FP64 vector arithmetic throughout (a few percent of the ERI build).
+// FP64 throughout: vector arithmetic for J, FP64 MFMA GEMMs for K.
 #include "common.h"
 #include "eri.h"
+#include "mfma_f64.h"
+
+#include <algorithm>
 
 namespace dmet {
 
@@ -46,108 +49,184 @@ __global__ void k_dc_j(int nrows, int npair, const double* __restrict__ z, const
     jp[kl] = acc;
 }
 
-// K[i][j] += sum_{P in chunk} sum_l W_P[i][l] Z_P[l][j] with W_P = Z_P g.
-// A workgroup owns DC_T rows i of K (all columns j) and a chunk of rows P:
-// per P it stages Z_P(i, :) in LDS, forms W_P(i, :) in LDS once, then each
-// thread accumulates its (i, j) entries in registers; the chunk's partial rows
-// are added to K with FP64 atomics.
-constexpr int DC_T = 16;
-constexpr int DC_MAXJ = 32;   // columns per thread: neo <= 16 * DC_MAXJ
+// Exchange K_s = sum_P Z_P g Z_P (Z_P the symmetric neo x neo matrix of row P)
+// as two FP64 MFMA GEMMs over chunks of rows P:
+//   W[(P,i)][l] = sum_k Z_P[i][k] g[k][l]                       (k_dc_w)
+//   K[i][j]    += sum_{P,l} W[(P,i)][l] Z_P[l][j]                (k_dc_k)
+// K is symmetric, so k_dc_k forms only the 64 x 64 tiles with it >= jt.  Each
+// workgroup of k_dc_k reduces DK_PCW rows P into a partial tile of its own;
+// k_dc_final sums the partials in a fixed order (deterministic result).
+constexpr int DT = 64, DBK = 16;
+constexpr int DK_PCW = 16;                       // rows P per k_dc_k workgroup
+constexpr size_t DW_CAP = size_t(1) << 30;       // bytes of W per chunk of rows P
 
-__global__ void __launch_bounds__(256) k_dc_k(int nrows, int neo, int npair, int pchunk,
-                                               const double* __restrict__ z, const double* __restrict__ g,
-                                               double* __restrict__ kmat) {
-    extern __shared__ double sh[];
-    double* zi = sh;                        // [DC_T][neo]  Z_P(i0 + r, k)
-    double* wi = zi + DC_T * neo;           // [DC_T][neo]  W_P(i0 + r, l)
-    const int i0 = blockIdx.x * DC_T;
-    const int p0 = blockIdx.y * pchunk, p1 = min(nrows, p0 + pchunk);
-    const int tid = threadIdx.x, r = tid / 16, jl = tid % 16;
-    double acc[DC_MAXJ];
-#pragma unroll
-    for (int c = 0; c < DC_MAXJ; ++c) acc[c] = 0.0;
-    for (int P = p0; P < p1; ++P) {
-        const double* zr = z + (size_t)P * npair;
-        __syncthreads();
-        for (int e = tid; e < DC_T * neo; e += 256) {
-            const int rr = e / neo, k = e % neo;
-            zi[e] = (i0 + rr < neo) ? zr[pidx(i0 + rr, k)] : 0.0;
+__global__ void __launch_bounds__(256) k_dc_w(long p0, int np, int neo, int npair, const double* __restrict__ z,
+                                               const double* __restrict__ g, double* __restrict__ w) {
+    using T = F64Tile<DT, DT, DBK>;
+    __shared__ double As[DBK * T::LDA];
+    __shared__ double Bs[DBK * T::LDB];
+    const long M = (long)np * neo;
+    const int n0 = blockIdx.x * DT;          // x fastest: tiles sharing A run together
+    const long m0 = (long)blockIdx.y * DT;
+    d4 acc[DT / 32][DT / 32];
+    zero_acc<DT, DT>(acc);
+    const int tid = threadIdx.x;
+    for (int k0 = 0; k0 < neo; k0 += DBK) {
+        for (int e = tid; e < DBK * DT; e += 256) {
+            const int kk = e % DBK, mm = e / DBK;
+            const long m = m0 + mm;
+            const int k = k0 + kk;
+            double v = 0.0;
+            if (m < M && k < neo) v = z[(p0 + m / neo) * npair + pidx((int)(m % neo), k)];
+            As[kk * T::LDA + mm] = v;
+        }
+        for (int e = tid; e < DBK * DT; e += 256) {
+            const int nn = e % DT, kk = e / DT;
+            const int k = k0 + kk, l = n0 + nn;
+            Bs[kk * T::LDB + nn] = (k < neo && l < neo) ? g[(size_t)k * neo + l] : 0.0;
         }
         __syncthreads();
-        for (int e = tid; e < DC_T * neo; e += 256) {
-            const int rr = e / neo, l = e % neo;
-            double s = 0.0;
-            for (int k = 0; k < neo; ++k) s += zi[rr * neo + k] * g[(size_t)k * neo + l];
-            wi[e] = s;
-        }
+        f64_mma<DT, DT, DBK>(As, Bs, acc);
         __syncthreads();
-        const double* w = wi + r * neo;
-#pragma unroll
-        for (int c = 0; c < DC_MAXJ; ++c) {
-            const int j = jl + 16 * c;
-            if (j < neo) {
-                double s = 0.0;
-                for (int l = 0; l < neo; ++l) s += w[l] * zr[pidx(l, j)];
-                acc[c] += s;
-            }
-        }
     }
-    if (i0 + r < neo) {
-#pragma unroll
-        for (int c = 0; c < DC_MAXJ; ++c) {
-            const int j = jl + 16 * c;
-            if (j < neo) atomicAdd(&kmat[(size_t)(i0 + r) * neo + j], acc[c]);
-        }
-    }
+    f64_visit<DT, DT, DBK>(acc, [&](int r, int c, double v) {
+        const long m = m0 + r;
+        const int l = n0 + c;
+        if (m < M && l < neo) w[m * neo + l] = v;
+    });
 }
 
-// F~[s][i][j] = F[s][i][j] - (cj * J_s[pair(i,j)] - ck * K_s[i][j])
-__global__ void k_dc_final(int neo, const double* __restrict__ f, const double* __restrict__ jp,
-                           const double* __restrict__ kmat, double cj, double ck, double* __restrict__ out) {
+// partial tile (split0 + blockIdx.y, tri) over rows P in
+// [p0 + DK_PCW * blockIdx.y, min(p0 + np, ... + DK_PCW)); W rows are chunk-local
+__global__ void __launch_bounds__(256) k_dc_k(long p0, int np, int neo, int npair, int ntri, long split0,
+                                               const double* __restrict__ z, const double* __restrict__ w,
+                                               double* __restrict__ part) {
+    using T = F64Tile<DT, DT, DBK>;
+    __shared__ double As[DBK * T::LDA];
+    __shared__ double Bs[DBK * T::LDB];
+    const int tri = blockIdx.x;
+    int it = (int)((sqrt(8.0 * tri + 1.0) - 1.0) * 0.5);
+    while (it * (it + 1) / 2 > tri) --it;
+    while ((it + 1) * (it + 2) / 2 <= tri) ++it;
+    const int jt = tri - it * (it + 1) / 2;
+    const int i0 = it * DT, j0 = jt * DT;
+    const int pl0 = blockIdx.y * DK_PCW;                       // chunk-local first row
+    const int npl = min(DK_PCW, np - pl0);
+    const int R = npl * neo;                                   // reduction length (P, l)
+    d4 acc[DT / 32][DT / 32];
+    zero_acc<DT, DT>(acc);
+    const int tid = threadIdx.x;
+    for (int r0 = 0; r0 < R; r0 += DBK) {
+        for (int e = tid; e < DBK * DT; e += 256) {
+            const int kk = e % DBK, mm = e / DBK;
+            const int r = r0 + kk, i = i0 + mm;
+            double v = 0.0;
+            if (r < R && i < neo) {
+                const int pl = pl0 + r / neo, l = r % neo;
+                v = w[((size_t)pl * neo + i) * neo + l];
+            }
+            As[kk * T::LDA + mm] = v;
+        }
+        for (int e = tid; e < DBK * DT; e += 256) {
+            const int nn = e % DT, kk = e / DT;
+            const int r = r0 + kk, j = j0 + nn;
+            double v = 0.0;
+            if (r < R && j < neo) {
+                const long P = p0 + pl0 + r / neo;
+                v = z[P * npair + pidx(r % neo, j)];
+            }
+            Bs[kk * T::LDB + nn] = v;
+        }
+        __syncthreads();
+        f64_mma<DT, DT, DBK>(As, Bs, acc);
+        __syncthreads();
+    }
+    double* out = part + ((size_t)(split0 + blockIdx.y) * ntri + tri) * (DT * DT);
+    f64_visit<DT, DT, DBK>(acc, [&](int r, int c, double v) { out[r * DT + c] = v; });
+}
+
+// F~[s][i][j] = F[s][i][j] - (cj * J_s[pair(i,j)] - K_s[i][j]); K_s[i][j] is the
+// ordered sum of the partial tiles holding (max, min) of (i, j) by tile
+__global__ void k_dc_final(int neo, int ntri, long nsplit, const double* __restrict__ f,
+                           const double* __restrict__ jp, const double* __restrict__ part, double cj,
+                           double* __restrict__ out) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= neo * neo) return;
-    const int i = e / neo, j = e % neo;
-    out[e] = f[e] - (cj * jp[pidx(i, j)] - ck * kmat[e]);
+    int i = e / neo, j = e % neo;
+    const double jv = jp[pidx(i, j)];
+    if (i / DT < j / DT) {
+        const int t = i;
+        i = j;
+        j = t;
+    }
+    const int it = i / DT, jt = j / DT;
+    const size_t off = (size_t)(it * (it + 1) / 2 + jt) * (DT * DT) + (i % DT) * DT + (j % DT);
+    double k = 0.0;
+    for (long s = 0; s < nsplit; ++s) k += part[(size_t)s * ntri * (DT * DT) + off];
+    out[e] = f[e] - (cj * jv - k);
+}
+
+static int dc_rows_per_chunk(int neo, int nrows) {
+    const size_t per = (size_t)neo * neo * sizeof(double);
+    // W bytes per chunk within DW_CAP, and at most 65535 row tiles in grid y
+    long rc = std::min<long>((long)(DW_CAP / per), 65535L * DT / neo) / DK_PCW * DK_PCW;
+    if (rc < DK_PCW) rc = DK_PCW;
+    return (int)std::min<long>(rc, nrows);
+}
+
+static long dc_nsplit(int neo, int nrows) {
+    const int rc = dc_rows_per_chunk(neo, nrows);
+    long n = 0;
+    for (long p0 = 0; p0 < nrows; p0 += rc) n += (std::min<long>(rc, nrows - p0) + DK_PCW - 1) / DK_PCW;
+    return n;
 }
 
 size_t fock_dc_workspace(int nspin, int neo, int nrows) {
     const size_t npair = (size_t)neo * (neo + 1) / 2;
+    const int nt = (neo + DT - 1) / DT;
+    const size_t ntri = (size_t)nt * (nt + 1) / 2;
     Carve cv(nullptr, 0);
-    cv.take<double>(nrows);                       // v
-    cv.take<double>((size_t)nspin * npair);       // J per spin
-    cv.take<double>((size_t)nspin * neo * neo);   // K per spin
+    cv.take<double>(nrows);                                              // v
+    cv.take<double>((size_t)nspin * npair);                              // J per spin
+    cv.take<double>((size_t)dc_rows_per_chunk(neo, nrows) * neo * neo);  // W of one chunk
+    cv.take<double>((size_t)dc_nsplit(neo, nrows) * ntri * DT * DT);     // partial K tiles
     return cv.bytes();
 }
 
 dmet_status fock_dc(int nspin, int neo, int nrows, const double* z, const double* f_eo, const double* dm_eo,
                     double* f_tilde, void* ws, size_t ws_bytes, hipStream_t st) {
     const int npair = neo * (neo + 1) / 2;
+    const int nt = (neo + DT - 1) / DT, ntri = nt * (nt + 1) / 2;
+    const int rc = dc_rows_per_chunk(neo, nrows);
+    const long nsplit = dc_nsplit(neo, nrows);
     Carve cv(ws, ws_bytes);
     double* v = cv.take<double>(nrows);
     double* jp = cv.take<double>((size_t)nspin * npair);
-    double* km = cv.take<double>((size_t)nspin * neo * neo);
+    double* w = cv.take<double>((size_t)rc * neo * neo);
+    double* part = cv.take<double>((size_t)nsplit * ntri * DT * DT);
     if (cv.bytes() > ws_bytes) return fail(DMET_E_WORKSPACE, "fock_dc workspace too small");
     const size_t zs = (size_t)nrows * npair, gs = (size_t)neo * neo;
     fill_zero(v, nrows * sizeof(double), st);
-    fill_zero(km, nspin * gs * sizeof(double), st);
     ProfScope ps("fock_dc", st);
     // Coulomb: one density vector over all spins (the alpha-beta block is Z_a^T Z_b)
     for (int t = 0; t < nspin; ++t)
         k_dc_v<<<(nrows + 3) / 4, 256, 0, st>>>(nrows, neo, npair, z + t * zs, dm_eo + t * gs, 1.0, v);
     for (int s = 0; s < nspin; ++s)
         k_dc_j<<<(npair + 255) / 256, 256, 0, st>>>(nrows, npair, z + s * zs, v, jp + (size_t)s * npair);
-    const int pchunk = 32;
-    const size_t shm = (size_t)2 * DC_T * neo * sizeof(double);
-    if (neo > 16 * DC_MAXJ) return fail(DMET_E_UNSUPPORTED, "neo above 512 is not supported by fock_dc");
-    DMET_HIP(hipFuncSetAttribute((const void*)k_dc_k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-    const int nt = (neo + DC_T - 1) / DC_T;
-    for (int s = 0; s < nspin; ++s)
-        k_dc_k<<<dim3(nt, (nrows + pchunk - 1) / pchunk), 256, shm, st>>>(nrows, neo, npair, pchunk, z + s * zs,
-                                                                          dm_eo + s * gs, km + s * gs);
     const double cj = nspin == 1 ? 2.0 : 1.0;
-    for (int s = 0; s < nspin; ++s)
-        k_dc_final<<<(neo * neo + 255) / 256, 256, 0, st>>>(neo, f_eo + s * gs, jp + (size_t)s * npair, km + s * gs,
-                                                            cj, 1.0, f_tilde + s * gs);
+    for (int s = 0; s < nspin; ++s) {
+        long split = 0;
+        for (long p0 = 0; p0 < nrows; p0 += rc) {
+            const int np = (int)std::min<long>(rc, nrows - p0);
+            const long mt = ((long)np * neo + DT - 1) / DT;
+            k_dc_w<<<dim3(nt, (unsigned)mt), 256, 0, st>>>(p0, np, neo, npair, z + s * zs, dm_eo + s * gs, w);
+            const int nsp = (np + DK_PCW - 1) / DK_PCW;
+            k_dc_k<<<dim3(ntri, nsp), 256, 0, st>>>(p0, np, neo, npair, ntri, split, z + s * zs, w, part);
+            split += nsp;
+        }
+        k_dc_final<<<(neo * neo + 255) / 256, 256, 0, st>>>(neo, ntri, nsplit, f_eo + s * gs, jp + (size_t)s * npair,
+                                                            part, cj, f_tilde + s * gs);
+    }
     ps.stop();
     DMET_LAUNCH_CHECK("fock_dc");
     return DMET_OK;
