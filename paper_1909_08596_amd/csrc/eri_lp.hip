@@ -86,7 +86,7 @@ __device__ inline long xcd_logical(long b, long nblocks) {
     return (b % NXCD) * per + b / NXCD;
 }
 
-template <int MODE>
+template <int MODE, int SB = SB>
 __device__ inline bool tile_of(long logical, int ntile, int& mt, int& nt) {
     const long sb = logical / (SB * SB);
     const int within = (int)(logical % (SB * SB));
@@ -109,7 +109,7 @@ __device__ inline bool tile_of(long logical, int ntile, int& mt, int& nt) {
     return true;
 }
 
-template <int MODE>
+template <int MODE, int SB = SB>
 inline long tile_grid(int ntile) {
     const long nsb = (ntile + SB - 1) / SB;
     const long nsbt = MODE == 0 ? nsb * (nsb + 1) / 2 : nsb * nsb;
@@ -117,142 +117,13 @@ inline long tile_grid(int ntile) {
     return (n + NXCD - 1) / NXCD * NXCD;
 }
 
-// Contraction on packed bf16 parts with the operand tiles moved by direct
+// Contraction on packed bf16 parts.  Operand tiles move by direct
 // global->LDS loads (global_load_lds_dwordx4: lane l of a wave writes its 16
-// bytes at the wave's LDS base + 16 l) into a ring of NBUF stages, so that the tiles of
-// the next NBUF-1 K steps are in flight while one is multiplied.  Rows past
-// the matrix edge are clamped to the last row: they only feed output rows /
+// bytes at the wave's LDS base + 16 l) into a ring of stages, so that the tiles
+// of the next stages are in flight while one is multiplied.  Rows past the
+// matrix edge are clamped to the last row: they only feed output rows /
 // columns that are not stored.
 #define DMET_LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
-
-template <int NS, int MODE, int NBUF>
-__global__ void __launch_bounds__(256) k_contract_dl(int npair, int kgroups, const __bf16* __restrict__ pa,
-                                                     const __bf16* __restrict__ pb, int flush_k, long nblocks,
-                                                     double* __restrict__ out) {
-    constexpr int BM = 128, BN = 128, BK = 32, G = BK / 8;
-    constexpr int TM = 2, TN = 2;
-    constexpr int PART = G * BM;                 // chunks of one part of one operand
-    constexpr int STAGE = 2 * NS * PART;         // chunks per stage (A then B)
-    constexpr int LOADS = 2 * NS * (PART / 256); // load instructions per thread per stage
-    extern __shared__ __align__(16) bf8 ring[];
-    int mt, nt;
-    const long logical = xcd_logical(blockIdx.x, nblocks);
-    const int ntile = (npair + BM - 1) / BM;
-    if (!tile_of<MODE>(logical, ntile, mt, nt)) return;
-    const int m0 = mt * BM, n0 = nt * BN;
-    const bool diag = mt == nt;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
-    const size_t plane = (size_t)kgroups * npair;
-    const int nkt = kgroups / G;
-
-    auto issue = [&](int kt) {
-        bf8* st = ring + (size_t)(kt % NBUF) * STAGE;
-#pragma unroll
-        for (int t = 0; t < NS; ++t)
-#pragma unroll
-            for (int c = 0; c < PART / 256; ++c) {
-                const int first = wave * 64 + 256 * c;        // first chunk of this wave's load
-                const int g = first / BM, row0 = first % BM;  // 64 consecutive rows of one group
-                const size_t gg = (size_t)kt * G + g;
-                const int xa = min(m0 + row0 + lane, npair - 1), xb = min(n0 + row0 + lane, npair - 1);
-                __builtin_amdgcn_global_load_lds((const void*)(pa + (t * plane + gg * npair + xa) * 8),
-                                                 DMET_LDS_PTR(st + t * PART + first), 16, 0, 0);
-                __builtin_amdgcn_global_load_lds((const void*)(pb + (t * plane + gg * npair + xb) * 8),
-                                                 DMET_LDS_PTR(st + (NS + t) * PART + first), 16, 0, 0);
-            }
-    };
-
-    f16v acc[TM][TN];
-    double acc64[TM][TN][16];
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                acc[i][j][r] = 0.f;
-                acc64[i][j][r] = 0.0;
-            }
-#pragma unroll
-    for (int s = 0; s < NBUF - 1; ++s)
-        if (s < nkt) issue(s);
-    int since = 0;
-    for (int kt = 0; kt < nkt; ++kt) {
-        // tile kt has landed when at most the loads of the younger in-flight tiles remain
-        const int younger = min(NBUF - 2, nkt - 1 - kt);
-        if (younger >= 2) __builtin_amdgcn_s_waitcnt(0x0F70 | ((2 * LOADS) & 15) | (((2 * LOADS) >> 4) << 14));
-        else if (younger == 1) __builtin_amdgcn_s_waitcnt(0x0F70 | (LOADS & 15) | ((LOADS >> 4) << 14));
-        else __builtin_amdgcn_s_waitcnt(0x0F70);
-        // Plain s_barrier: each wave has waited for its own loads of tile kt
-        // above and the loop has no ordinary LDS stores, so no fence is needed
-        // (a fenced __syncthreads would wait for the younger tiles as well).
-        __builtin_amdgcn_s_barrier();
-        __builtin_amdgcn_sched_barrier(0);
-        if (kt + NBUF - 1 < nkt) issue(kt + NBUF - 1);
-        const bf8* sA = ring + (size_t)(kt % NBUF) * STAGE;
-        const bf8* sB = sA + NS * PART;
-#pragma unroll
-        for (int ks = 0; ks < G; ks += 2) {
-            const int g = ks + (lane >> 5);
-            bf8 a[TM][NS], b[TN][NS];
-#pragma unroll
-            for (int t = 0; t < NS; ++t) {
-#pragma unroll
-                for (int i = 0; i < TM; ++i) a[i][t] = sA[t * PART + g * BM + wm0 + i * 32 + (lane & 31)];
-#pragma unroll
-                for (int j = 0; j < TN; ++j) b[j][t] = sB[t * PART + g * BN + wn0 + j * 32 + (lane & 31)];
-            }
-#pragma unroll
-            for (int i = 0; i < TM; ++i)
-#pragma unroll
-                for (int j = 0; j < TN; ++j) {
-                    f16v c = acc[i][j];
-                    if constexpr (NS == 2) {
-                        if (diag) c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][1], c, 0, 0, 0);
-                        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][0], c, 0, 0, 0);
-                        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][1], c, 0, 0, 0);
-                    } else {
-                        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][2], b[j][0], c, 0, 0, 0);
-                        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][1], c, 0, 0, 0);
-                        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][2], c, 0, 0, 0);
-                        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][0], c, 0, 0, 0);
-                        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][1], c, 0, 0, 0);
-                    }
-                    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][0], c, 0, 0, 0);
-                    acc[i][j] = c;
-                }
-        }
-        since += BK;
-        if (since >= flush_k || kt + 1 == nkt) {
-#pragma unroll
-            for (int i = 0; i < TM; ++i)
-#pragma unroll
-                for (int j = 0; j < TN; ++j)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        acc64[i][j][r] += (double)acc[i][j][r];
-                        acc[i][j][r] = 0.f;
-                    }
-            since = 0;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int IJ = m0 + wm0 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const int KL = n0 + wn0 + j * 32 + (lane & 31);
-                if (IJ >= npair || KL >= npair) continue;
-                if constexpr (MODE == 0) {
-                    if (KL <= IJ) out[(size_t)IJ * (IJ + 1) / 2 + KL] = acc64[i][j][r];
-                } else {
-                    out[(size_t)IJ * npair + KL] = acc64[i][j][r];
-                }
-            }
-}
 
 // Variant sized for two workgroups per CU: 16-deep stages (72 KB ring for the
 // three-way split), at most 256 registers per lane (B fragments of a stage are
@@ -376,13 +247,207 @@ k_contract_d2(int npair, int kgroups, const __bf16* __restrict__ pa, const __bf1
             }
 }
 
+// Tile order of k_contract_w8 (128 x 256 tiles): super-blocks of 8 x 4 tiles
+// (1024 x 1024 outputs), lower-triangular order of super-blocks for s8.  A
+// tile is kept for s8 if it holds any KL <= IJ.
+template <int MODE>
+__device__ inline bool w8_tile_of(long logical, int ntm, int ntn, int& mt, int& nt) {
+    const long sb = logical / 32;
+    const int within = (int)(logical % 32);
+    const int nsb = (ntm + 7) / 8;
+    long I, J;
+    if constexpr (MODE == 0) {
+        I = (long)((sqrt(8.0 * (double)sb + 1.0) - 1.0) * 0.5);
+        while (I * (I + 1) / 2 > sb) --I;
+        while ((I + 1) * (I + 2) / 2 <= sb) ++I;
+        J = sb - I * (I + 1) / 2;
+    } else {
+        I = sb / nsb;
+        J = sb % nsb;
+    }
+    if (I >= nsb) return false;
+    mt = (int)(I * 8 + within / 4);
+    nt = (int)(J * 4 + within % 4);
+    if (mt >= ntm || nt >= ntn) return false;
+    if (MODE == 0 && nt * 256 > mt * 128 + 127) return false;
+    return true;
+}
+
+inline long w8_grid(int mode, int npair) {
+    const long nsb = ((npair + 127) / 128 + 7) / 8;
+    const long n = (mode == 0 ? nsb * (nsb + 1) / 2 : nsb * nsb) * 32;
+    return (n + NXCD - 1) / NXCD * NXCD;
+}
+
+// Variant with 128 x 256 output tiles: 8 waves as 2 x 4, wave tile 64 x 64
+// with FP64 flush registers as in k_contract_d2, one workgroup per CU and a
+// 4-stage ring (36 KB stages for the three-way split).  Against two 128 x 128
+// workgroups per CU it moves 25% fewer operand bytes per flop, and the two
+// column halves that share the A panel run in step by construction.  Waves
+// 0-3 stage A and B, waves 4-7 only B, so their vmcnt budgets differ.
+template <int NS, int MODE, int G, int NBUF>
+__global__ void __launch_bounds__(512) k_contract_w8(int npair, int kgroups, const __bf16* __restrict__ pa,
+                                                     const __bf16* __restrict__ pb, int flush_k, long nblocks,
+                                                     double* __restrict__ out) {
+    constexpr int BM = 128, BN = 256;
+    constexpr int TM = 2, TN = 2;
+    constexpr int PA = G * BM, PB = G * BN;      // 16-byte chunks of one part of A / B per stage
+    constexpr int STAGE = NS * (PA + PB);
+    static_assert(PB % 512 == 0 && (PA % 512 == 0 || PA == 256), "chunk split over 8 waves");
+    // loads per thread per stage (waves 4-7 stage no A when a part of A has 256 chunks)
+    constexpr int LOADS_HI = NS * ((PA + 511) / 512 + PB / 512), LOADS_LO = NS * (PA / 512 + PB / 512);
+    extern __shared__ __align__(16) bf8 ring[];
+    int mt, nt;
+    const long logical = xcd_logical(blockIdx.x, nblocks);
+    const int ntm = (npair + BM - 1) / BM, ntn = (npair + BN - 1) / BN;
+    if (!w8_tile_of<MODE>(logical, ntm, ntn, mt, nt)) return;
+    const int m0 = mt * BM, n0 = nt * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave >> 2) * 64, wn0 = (wave & 3) * 64;
+    const bool hi = wave * 64 < PA % 512 || PA % 512 == 0;
+    const size_t plane = (size_t)kgroups * npair;
+    const int nkt = kgroups / G;
+
+    auto issue = [&](int kt) {
+        bf8* st = ring + (size_t)(kt % NBUF) * STAGE;
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+#pragma unroll
+            for (int f0 = 0; f0 < PA; f0 += 512) {
+                const int f = f0 + wave * 64;
+                if (f < PA) {
+                    const size_t ga = (size_t)kt * G + f / BM;
+                    const int xa = min(m0 + f % BM + lane, npair - 1);
+                    __builtin_amdgcn_global_load_lds((const void*)(pa + (t * plane + ga * npair + xa) * 8),
+                                                     DMET_LDS_PTR(st + t * PA + f), 16, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int f0 = 0; f0 < PB; f0 += 512) {
+                const int f = f0 + wave * 64;
+                const size_t gb = (size_t)kt * G + f / BN;
+                const int xb = min(n0 + f % BN + lane, npair - 1);
+                __builtin_amdgcn_global_load_lds((const void*)(pb + (t * plane + gb * npair + xb) * 8),
+                                                 DMET_LDS_PTR(st + NS * PA + t * PB + f), 16, 0, 0);
+            }
+        }
+    };
+
+    f16v acc[TM][TN];
+    double acc64[TM][TN][16];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                acc[i][j][r] = 0.f;
+                acc64[i][j][r] = 0.0;
+            }
+#pragma unroll
+    for (int s2 = 0; s2 < NBUF - 1; ++s2)
+        if (s2 < nkt) issue(s2);
+    int since = 0;
+    for (int kt = 0; kt < nkt; ++kt) {
+        // stage kt has landed when only the loads of the younger stages in
+        // flight (at most NBUF - 2 of them) remain
+        const int younger = min(NBUF - 2, nkt - 1 - kt);
+        __builtin_amdgcn_sched_barrier(0);
+        if (hi) {
+            if (younger >= 2) __builtin_amdgcn_s_waitcnt(0x0F70 | ((2 * LOADS_HI) & 15) | (((2 * LOADS_HI) >> 4) << 14));
+            else if (younger == 1) __builtin_amdgcn_s_waitcnt(0x0F70 | (LOADS_HI & 15) | ((LOADS_HI >> 4) << 14));
+            else __builtin_amdgcn_s_waitcnt(0x0F70);
+        } else {
+            if (younger >= 2) __builtin_amdgcn_s_waitcnt(0x0F70 | ((2 * LOADS_LO) & 15) | (((2 * LOADS_LO) >> 4) << 14));
+            else if (younger == 1) __builtin_amdgcn_s_waitcnt(0x0F70 | (LOADS_LO & 15) | ((LOADS_LO >> 4) << 14));
+            else __builtin_amdgcn_s_waitcnt(0x0F70);
+        }
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_sched_barrier(0);
+        if (kt + NBUF - 1 < nkt) issue(kt + NBUF - 1);
+        const bf8* sA = ring + (size_t)(kt % NBUF) * STAGE;
+        const bf8* sB = sA + NS * PA;
+#pragma unroll
+        for (int ks = 0; ks < G; ks += 2) {
+            const int g = ks + (lane >> 5);
+            bf8 b[NS][TN];
+#pragma unroll
+            for (int t = 0; t < NS; ++t)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) b[t][j] = sB[t * PB + g * BN + wn0 + j * 32 + (lane & 31)];
+            // parts of A outermost and both row tiles per part, so that four
+            // independent accumulators separate two MFMAs on the same one (the
+            // order of the products per output element is unchanged); the A
+            // fragments of the next part are read before the current MFMAs
+            bf8 a[TM], an[TM];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) a[i] = sA[(NS - 1) * PA + g * BM + wm0 + i * 32 + (lane & 31)];
+#pragma unroll
+            for (int ta = NS - 1; ta >= 0; --ta) {
+                if (ta > 0) {
+#pragma unroll
+                    for (int i = 0; i < TM; ++i) an[i] = sA[(ta - 1) * PA + g * BM + wm0 + i * 32 + (lane & 31)];
+                }
+#pragma unroll
+                for (int tb = NS - 1 - ta; tb >= 0; --tb)
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[tb][j], acc[i][j], 0, 0, 0);
+                if constexpr (NS == 2) {
+                    // lo*lo where the 128 x 128 tile of these outputs is a
+                    // diagonal one (the same elements as in the other kernels)
+                    if (ta == 1 && (n0 + wn0) / 128 == mt)
+#pragma unroll
+                        for (int i = 0; i < TM; ++i)
+#pragma unroll
+                            for (int j = 0; j < TN; ++j)
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[1][j], acc[i][j], 0, 0, 0);
+                }
+                if (ta > 0) {
+#pragma unroll
+                    for (int i = 0; i < TM; ++i) a[i] = an[i];
+                }
+            }
+            since += 16;
+            if (since >= flush_k || (kt + 1 == nkt && ks + 2 >= G)) {
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            acc64[i][j][r] += (double)acc[i][j][r];
+                            acc[i][j][r] = 0.f;
+                        }
+                since = 0;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int IJ = m0 + wm0 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int KL = n0 + wn0 + j * 32 + (lane & 31);
+                if (IJ >= npair || KL >= npair) continue;
+                if constexpr (MODE == 0) {
+                    if (KL <= IJ) out[(size_t)IJ * (IJ + 1) / 2 + KL] = acc64[i][j][r];
+                } else {
+                    out[(size_t)IJ * npair + KL] = acc64[i][j][r];
+                }
+            }
+}
+
+template <int NS, int G, int NBUF>
+constexpr size_t w8_lds() { return (size_t)NBUF * NS * G * (128 + 256) * 16; }
+
 template <int NS>
 constexpr size_t d2_lds() { return (size_t)3 * 2 * NS * 2 * 128 * 16; }
 
-template <int NS>
-constexpr int dl_nbuf() { return NS == 3 ? 3 : 4; }
-template <int NS>
-constexpr size_t dl_lds() { return (size_t)dl_nbuf<NS>() * 2 * NS * 4 * 128 * 16; }
 
 // ------------------------------------------------------------------ packed transform (bf16 forms)
 // Operand packing for the transform.  Every packed operand has the layout
@@ -1016,11 +1081,11 @@ template <int NS>
 constexpr size_t xf2_lds() { return (size_t)2 * 3 * NS * 2 * (64 + 64) * 16; }
 
 // ------------------------------------------------------------------ driver
-// contraction kernel variant: 1 = k_contract_dl (one workgroup per CU, deep
-// ring), 2 = k_contract_d2 (two workgroups per CU); DMET_CONTRACT overrides.
+// contraction kernel: k_contract_w8 (128 x 256 tiles, one workgroup per CU);
+// DMET_CONTRACT=2 selects k_contract_d2 (128 x 128, two workgroups per CU)
 static int contract_variant() {
     const char* e = getenv("DMET_CONTRACT");
-    return e && e[0] == '1' ? 1 : 2;
+    return e && e[0] == '2' ? 2 : 3;
 }
 
 constexpr int FLUSH_K = 256;
@@ -1160,12 +1225,37 @@ static dmet_status eri_lp_run(const EriPlan& p, const void* lmunu, const double*
         ps.stop();
         DMET_LAUNCH_CHECK("k_pack_parts");
     }
+    const int variant = contract_variant();
+    if (variant == 3) {
+        // three-way split: 16-row stages, 4-deep ring; two-way: 32-row stages, 3-deep
+        constexpr int G = NS == 3 ? 2 : 4, NB = NS == 3 ? 4 : 3;
+        auto kw0 = k_contract_w8<NS, 0, G, NB>;
+        auto kw1 = k_contract_w8<NS, 1, G, NB>;
+        constexpr size_t lds = w8_lds<NS, G, NB>();
+        static_assert(lds <= 160 * 1024, "LDS per workgroup");
+        DMET_HIP(hipFuncSetAttribute((const void*)kw0, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        DMET_HIP(hipFuncSetAttribute((const void*)kw1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        for (int s = 0; s < p.nspin; ++s) {
+            const long nb = w8_grid(0, p.npair);
+            ProfScope ps(n3, st);
+            kw0<<<dim3((unsigned)nb), 512, lds, st>>>(p.npair, kg, zp + s * per_spin, zp + s * per_spin, FLUSH_K, nb,
+                                                      s == 0 ? eri_aa : eri_bb);
+            ps.stop();
+            DMET_LAUNCH_CHECK(n3);
+        }
+        if (p.nspin == 2 && eri_ab) {
+            const long nb = w8_grid(1, p.npair);
+            ProfScope ps(n4, st);
+            kw1<<<dim3((unsigned)nb), 512, lds, st>>>(p.npair, kg, zp, zp + per_spin, FLUSH_K, nb, eri_ab);
+            ps.stop();
+            DMET_LAUNCH_CHECK(n4);
+        }
+        return DMET_OK;
+    }
     const int ntile = (p.npair + 127) / 128;
-    constexpr int NB = dl_nbuf<NS>();
-    const bool v2 = contract_variant() == 2;
-    auto kd0 = v2 ? k_contract_d2<NS, 0> : k_contract_dl<NS, 0, NB>;
-    auto kd1 = v2 ? k_contract_d2<NS, 1> : k_contract_dl<NS, 1, NB>;
-    const size_t lds = v2 ? d2_lds<NS>() : dl_lds<NS>();
+    auto kd0 = k_contract_d2<NS, 0>;
+    auto kd1 = k_contract_d2<NS, 1>;
+    const size_t lds = d2_lds<NS>();
     DMET_HIP(hipFuncSetAttribute((const void*)kd0, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     DMET_HIP(hipFuncSetAttribute((const void*)kd1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     for (int s = 0; s < p.nspin; ++s) {
