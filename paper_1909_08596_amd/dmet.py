@@ -209,6 +209,18 @@ def dmet_transform_eri(kmesh, nao, naux, lmunu: torch.Tensor, c_k: torch.Tensor,
     return out
 
 
+def dmet_transform_eri_impurity(kmesh, nao, naux, lmunu: torch.Tensor, c_k: torch.Tensor, nimp: int,
+                                precision: str = "fp64", eri_ab: bool = True, stream=None):
+    """ERIs of the non-interacting-bath formalism (Sec. 2.1): two-particle
+    terms on the impurity orbitals only, i.e. Alg. 1 with C^k cut to its first
+    nimp columns (the impurity block of Eq. ``C loemb k``).  Same return value
+    as dmet_transform_eri with neo = nimp."""
+    if not 1 <= nimp <= c_k.shape[-1]:
+        raise ValueError("need 1 <= nimp <= neo")
+    return dmet_transform_eri(kmesh, nao, naux, lmunu, c_k[..., :nimp].contiguous(), precision, eri_ab=eri_ab,
+                              stream=stream)
+
+
 def dmet_transform_eri_df(kmesh, nao, naux, lmunu: torch.Tensor, c_k: torch.Tensor, precision: str = "fp64",
                           workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
     """Density-fitting factors z [nspin][N_k*naux][npair] (float64) with

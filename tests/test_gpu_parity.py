@@ -314,3 +314,21 @@ def test_fock_dc_chunked_against_torch(dmet):
     scale = ref.abs().max().item()
     print(f"fock_dc chunked: max err {err:.3e} (scale {scale:.2e})")
     assert err < 1e-11 * scale
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x6"])
+def test_non_interacting_bath_impurity_eri(dmet, prec):
+    """Impurity-only ERIs (non-interacting bath, Sec. 2.1) equal the impurity
+    block of the oracle's full embedding ERIs, for both spins and the ab block."""
+    wl, lat, lm, bath = case("uodd", kmesh=(3, 2, 1), nao=6, naux=17, nspin=2, seed=19)
+    ck = bath["c_k"]
+    nimp = wl.nimp
+    out = dmet.dmet_transform_eri_impurity(wl.kmesh, wl.nao, wl.naux, to_dev(lm), to_dev(ck), nimp, prec)
+    torch.cuda.synchronize()
+    tol = 1e-10 if prec == "fp64" else LP_TOL
+    for key, (a, b) in {"aa": (0, None), "bb": (1, None), "ab": (0, 1)}.items():
+        full, _ = ok.alg1_eri(lm, ck[a], wl.kmesh, None if b is None else ck[b])
+        ref = full[:nimp, :nimp, :nimp, :nimp]
+        ref = ok.pack_s8(ref) if b is None else ok.pack_s4(ref)
+        err = np.abs(out[key].cpu().numpy().reshape(ref.shape) - ref).max()
+        assert err < tol * (np.abs(ref).max() if prec == "fp64" else 1.0), (key, err)

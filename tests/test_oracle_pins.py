@@ -293,3 +293,22 @@ def test_valence_subset_and_truncation(odd):
     tol = 0.5 * (out["sigma"][0][1] + out["sigma"][0][2])
     out2 = ok.build_bath(lat.dm_k, wl.kmesh, wl.nao, val_idx=val, sv_tol=tol)
     assert out2["neo"][0] == wl.nimp + 2
+
+
+def test_impurity_columns_give_impurity_block():
+    """Cutting C^k to its impurity columns gives exactly the impurity block of
+    the full embedding ERIs (the non-interacting-bath ERIs, Sec. 2.1), and the
+    real-space brute force with C_sup = the cell-0 unit vectors agrees."""
+    wl = synth.Workload("imp", (3, 2, 1), 6, 17, 6, 6, 1, 1.5, 23)
+    lat = synth.make_lattice(wl)
+    lm, b_real = synth.three_index(wl, real_space=True)
+    bath = ok.build_bath(lat.dm_k, wl.kmesh, wl.nao)
+    ck = bath["c_k"][0]
+    full, _ = ok.alg1_eri(lm, ck, wl.kmesh)
+    imp, _ = ok.alg1_eri(lm, np.ascontiguousarray(ck[:, :, :wl.nimp]), wl.kmesh)
+    n = wl.nimp
+    assert np.abs(imp - full[:n, :n, :n, :n]).max() < 1e-14 * np.abs(full).max()
+    csup = np.zeros((wl.nk * wl.nao, n))
+    csup[np.arange(n), np.arange(n)] = 1.0
+    ref = sc.eri(b_real, csup, wl.kmesh)
+    assert np.abs(imp - ref).max() < 1e-12 * np.abs(ref).max()
