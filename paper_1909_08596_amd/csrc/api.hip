@@ -275,6 +275,9 @@ static dmet_status check_batch(int nfrag, const dmet_fragment* frags, dmet_preci
         dmet_status s = check_eri_args(&d.lat, d.neo, prec, d.dtype);
         if (s != DMET_OK) return fail(s, "fragment " + std::to_string(f) + ": " + dmet_last_error());
         if (d.lat.nspin != 1) return fail(DMET_E_ARG, "fragment " + std::to_string(f) + ": nspin must be 1");
+        if ((prec == DMET_BF16X3_3M || prec == DMET_BF16X6_3M) &&
+            d.lat.kmesh[0] * d.lat.kmesh[1] * d.lat.kmesh[2] > 256)
+            return fail(DMET_E_UNSUPPORTED, "fragment " + std::to_string(f) + ": at most 256 k-points");
         if (!d.lmunu || !d.c_k || !d.eri) return fail(DMET_E_ARG, "fragment " + std::to_string(f) + ": null pointer");
         for (int g = 0; g < f; ++g)
             if (frags[g].lmunu == d.lmunu &&

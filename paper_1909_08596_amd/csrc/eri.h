@@ -29,6 +29,39 @@ struct EriPlan {
 
 EriPlan make_eri_plan(const dmet_lattice* lat, int neo, dmet_precision prec, dmet_dtype dtype);
 
+// k <-> q-k pairing of the k-sum of Alg. 1.  Time reversal of the real basis
+// and the Hermiticity of the 3-index tensor give (L|mu (q-k), nu (-k)) =
+// (L|nu k, mu (k-q)), so the k-sum term at q-k is the plain transpose (in the
+// EO pair ij) of the term at k.  The sum runs over the kept k (k <= q-k as mesh
+// indices): slots [0, npaired) hold the k < q-k in increasing order (their term
+// enters as M + M^T), slots [npaired, npaired + nself) the k = q-k (M is
+// symmetric and enters once).
+__host__ __device__ inline void kpair_counts(const Mesh& m, int q, int& npaired, int& nself) {
+    npaired = nself = 0;
+    for (int k = 0; k < m.nk; ++k) {
+        const int kp = mesh_sub(m, q, k);
+        if (k < kp) ++npaired;
+        else if (k == kp) ++nself;
+    }
+}
+
+__host__ __device__ inline int kpair_slot_k(const Mesh& m, int q, int slot) {
+    for (int pass = 0; pass < 2; ++pass)
+        for (int k = 0; k < m.nk; ++k) {
+            const int kp = mesh_sub(m, q, k);
+            if ((pass == 0 && k < kp) || (pass == 1 && k == kp)) {
+                if (slot == 0) return k;
+                --slot;
+            }
+        }
+    return -1;
+}
+
+// the (q, k) blocks of lmunu that the paired transform reads
+__host__ __device__ inline bool kpair_needed(const Mesh& m, int q, int k) {
+    return mesh_neg(m, q) >= q && k <= mesh_sub(m, q, k);
+}
+
 // df_out != NULL: write the FP64 DF factors Z [nspin][zrows][npair] there and
 // skip the contraction (eri pointers unused).
 size_t eri_f64_workspace(const EriPlan& p);

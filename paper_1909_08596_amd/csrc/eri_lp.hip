@@ -458,13 +458,16 @@ constexpr size_t d2_lds() { return (size_t)3 * 2 * NS * 2 * 128 * 16; }
 // stage always holds two groups (16 contraction indices).
 
 // lmunu[q][k][L][mu][nu] -> P1[q][k][plane][part][nu/8][L*nao_p + mu][8]
+// With only_needed, blocks (q, k) that the k <-> q-k paired transform never
+// reads are skipped (their input is not touched).
 template <int NS, class TIn>
 __global__ void k_pack_lmunu(const TIn* __restrict__ lm, int nao, int nao_p, int naux, int ngv,
-                             __bf16* __restrict__ out) {
+                             __bf16* __restrict__ out, Mesh mesh, int only_needed) {
     const int M1 = naux * nao_p;
     const int row = blockIdx.x * blockDim.x + threadIdx.x;
     const int g = blockIdx.y, qk = blockIdx.z;
     if (row >= M1) return;
+    if (only_needed && !kpair_needed(mesh, qk / mesh.nk, qk % mesh.nk)) return;
     const int L = row / nao_p, mu = row % nao_p;
     bf8 part[3][NS];
     const TIn* src = lm + (((size_t)qk * naux + L) * nao + mu) * (size_t)nao * 2;
@@ -566,6 +569,27 @@ __global__ void k_pack_c2(const double* __restrict__ ck, int nk, int nao, int na
                 part[p][t];
 }
 
+// Kept k of one q for the paired transform (see kpair_counts), by value.
+constexpr int KP_MAX = 256;
+struct KSlots {
+    int npaired, nself;
+    short k[KP_MAX];
+};
+
+// One stage of a packed operand (3 planes x NS parts x 2 groups x ROWS rows)
+// from two explicit groups g0, g1 (a zero group pads an odd count).
+template <int NS, int ROWS>
+__device__ inline void pk_issue_g(const __bf16* base, size_t pt_stride, int X, int x0, int g0, int g1, bf8* dst) {
+    constexpr int CH = 3 * NS * 2 * ROWS;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int first = wave * 64; first < CH; first += 256) {
+        const int pt = first / (2 * ROWS), g = (first / ROWS) % 2, row0 = first % ROWS;
+        const int x = min(x0 + row0 + lane, X - 1);
+        const __bf16* src = base + ((size_t)pt * pt_stride + (size_t)(g ? g1 : g0) * X + x) * 8;
+        __builtin_amdgcn_global_load_lds((const void*)src, DMET_LDS_PTR(dst + first), 16, 0, 0);
+    }
+}
+
 // One stage of a packed operand (3 planes x NS parts x 2 groups x ROWS rows)
 // moved to LDS [plane*NS + part][group][row] by direct loads; rows clamped.
 template <int NS, int ROWS>
@@ -638,28 +662,88 @@ __device__ inline void pk_loop3(const __bf16* pa, size_t pa_pt, int XA, int m0, 
     }
 }
 
+// K loop of stage 2 under the k <-> q-k pairing: pass 1 over the groups of
+// all kept k (A = conj C, rows i; B = T, columns (L, j)), pass 2 over the
+// paired k with the operands swapped (A = T columns (L, i), B = conj C rows j),
+// which adds the transposed terms of the partners.  The 3M planes combine the
+// same way in both passes.  Odd group counts are padded with group zg (zero
+// in both operands).  Double-buffered stages of two groups.
+template <int NS, int BM, int BN, int TM, int TN, class KOf>
+__device__ inline void pk_loop_paired(const __bf16* pc2, size_t cst, int neo, const __bf16* ptt, size_t tst, int N2,
+                                      int L, int m0, int j0, int gpk, int zg, int npaired, int nself, KOf kof,
+                                      bf8* ring, int wm0, int wn0, f16v (&acc)[3][TM][TN]) {
+    constexpr int SA = 3 * NS * 2 * BM, SB = 3 * NS * 2 * BN;
+    const int n1 = (npaired + nself) * gpk, n2 = npaired * gpk;
+    const int s1 = (n1 + 1) / 2, nst = s1 + (n2 + 1) / 2;
+    // running position (no division per stage): pass, group j in the pass,
+    // its slot and group within the slot; stages of the current pass issued
+    int pass = 0, j = 0, slot = 0, gl = 0, cnt = 0;
+    auto next = [&](int& gc, int& gt) {
+        if (j < (pass ? n2 : n1)) {
+            gc = kof(slot) * gpk + gl;
+            gt = j;
+            ++j;
+            if (++gl == gpk) {
+                gl = 0;
+                ++slot;
+            }
+        } else {
+            gc = gt = zg;
+        }
+    };
+    auto issue = [&](bf8* dst) {
+        if (pass == 0 && cnt == s1) {
+            pass = 1;
+            j = slot = gl = cnt = 0;
+        }
+        int gc0, gt0, gc1, gt1;
+        next(gc0, gt0);
+        next(gc1, gt1);
+        ++cnt;
+        if (!pass) {
+            pk_issue_g<NS, BM>(pc2, cst, neo, m0, gc0, gc1, dst);
+            pk_issue_g<NS, BN>(ptt, tst, N2, L * neo + j0, gt0, gt1, dst + SA);
+        } else {
+            pk_issue_g<NS, BM>(ptt, tst, N2, L * neo + m0, gt0, gt1, dst);
+            pk_issue_g<NS, BN>(pc2, cst, neo, j0, gc0, gc1, dst + SA);
+        }
+    };
+    issue(ring);
+    for (int st = 0; st < nst; ++st) {
+        bf8* cur = ring + (size_t)(st & 1) * (SA + SB);
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // own loads of stage st landed
+        __builtin_amdgcn_s_barrier();         // everyone's loads landed; stage st-1 fully read
+        __builtin_amdgcn_sched_barrier(0);
+        if (st + 1 < nst) issue(ring + (size_t)((st + 1) & 1) * (SA + SB));
+        pk_mma3<NS, BM, BN, TM, TN>(cur, cur + SA, wm0, wn0, acc);
+    }
+}
+
 // Stage 1 (both spins at once): T[(L,mu)][(s,j)] for one (q, k) from packed
 // lmunu and packed C^{k-q}; 3M combination and split into bf16 parts in the
 // epilogue, written as stage 2's packed B operand
 //   PT[s][plane][part][(k*nao_p + mu)/8][L*neo + j][8].
 // Lanes l and l+32 hold rows 0-3 and 4-7 of each 8-row group of a 32x32
 // result tile; one exchange gives each lane a full 8-row column chunk.
+// Only the kept k of the k <-> q-k pairing are formed; T slot `slot` (groups
+// slot * nao_p / 8 ...) holds k = ks.k[slot].
 template <int NS>
 __global__ void __launch_bounds__(256) k_xf1_pk(Mesh mesh, int q, int naux, int nao_p, int neo, int nspin, int ngv,
-                                                int ng2,
+                                                int ng2, KSlots ks,
                                                 const __bf16* __restrict__ plm, const __bf16* __restrict__ pc1,
                                                 __bf16* __restrict__ pt) {
     constexpr int BM = 128, BN = 128, TM = 2, TN = 2;
     extern __shared__ __align__(16) bf8 ring[];
     const int nk = mesh.nk;
     const int M1 = naux * nao_p, NB = nspin * neo;
-    // workgroup -> (k, m tile, n tile), n fastest, each XCD a contiguous run:
+    // workgroup -> (slot, m tile, n tile), n fastest, each XCD a contiguous run:
     // the n tiles of one m tile share the lmunu panel in that XCD's L2
     const int nmt = (M1 + BM - 1) / BM, nnt = (NB + BN - 1) / BN;
     const long logical = xcd_logical(blockIdx.x, gridDim.x);
-    const long nt_all = (long)nk * nmt * nnt;
+    const long nt_all = (long)(ks.npaired + ks.nself) * nmt * nnt;
     if (logical >= nt_all) return;
-    const int k = (int)(logical / ((long)nmt * nnt));
+    const int slot = (int)(logical / ((long)nmt * nnt));
+    const int k = ks.k[slot];
     const int rem = (int)(logical % ((long)nmt * nnt));
     const int m0 = (rem / nnt) * BM, n0 = (rem % nnt) * BN;
     const int kmq = mesh_sub(mesh, k, q);
@@ -716,7 +800,7 @@ __global__ void __launch_bounds__(256) k_xf1_pk(Mesh mesh, int q, int naux, int 
                 const int grp_row = m0 + wm0 + i * 32 + 8 * (qq + h);   // first row of this lane's 8-row group
                 if (col < NB && grp_row < M1) {
                     const int L = grp_row / nao_p, mu0 = grp_row % nao_p;
-                    const size_t g2 = ((size_t)k * nao_p + mu0) / 8;
+                    const size_t g2 = ((size_t)slot * nao_p + mu0) / 8;
                     const size_t x = (size_t)L * neo + jj;
                     __bf16* base = pt + (size_t)s * 3 * NS * per_part * 8;
 #pragma unroll
@@ -738,11 +822,15 @@ __global__ void __launch_bounds__(256) k_xf1_pk(Mesh mesh, int q, int naux, int 
         }
 }
 
-// Stage 2: X[i][(L,j)] = sum_{(k,mu)} conj(C^k_{mu i}) T[(k,mu)][(L,j)] for one
-// q and spin, i >= j only; 3M combination; Z rows (FP32).  Tiles of 64 x 64 per
-// L; tiles with every i < every j are skipped.
+// Stage 2 for one q and spin, i >= j only; 3M combination; Z rows (FP32):
+//   X[i][(L,j)] = sum_{kept k, mu} conj(C^k_{mu i}) T_k[mu][(L,j)]
+//               + sum_{paired k, mu} T_k[mu][(L,i)] conj(C^k_{mu j}),
+// the second sum being the transposed terms of the partners q-k (a symmetric
+// rank-2k update).  Tiles of 64 x 64 per L; tiles with every i < every j are
+// skipped.  Group zg is a zero group of both operands (pads odd counts).
 template <int NS>
-__global__ void __launch_bounds__(256) k_xf2_pk(int naux, int neo, int ng2, int self_conj, size_t zrow0, float wq,
+__global__ void __launch_bounds__(256) k_xf2_pk(int naux, int neo, int ng2, int gpk, int zg, KSlots ks,
+                                                int self_conj, size_t zrow0, float wq,
                                                 const __bf16* __restrict__ pc2, const __bf16* __restrict__ ptt,
                                                 float* __restrict__ z, size_t ldz) {
     constexpr int BM = 64, BN = 64, TM = 1, TN = 1;
@@ -764,8 +852,9 @@ __global__ void __launch_bounds__(256) k_xf2_pk(int naux, int neo, int ng2, int 
     for (int p = 0; p < 3; ++p)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[p][0][0][r] = 0.f;
-    pk_loop3<NS, BM, BN, TM, TN>(pc2, (size_t)ng2 * neo, neo, m0, ptt, (size_t)ng2 * N2, N2, L * neo + j0, ng2 / 2,
-                                 ring, wm0, wn0, acc);
+    pk_loop_paired<NS, BM, BN, TM, TN>(pc2, (size_t)ng2 * neo, neo, ptt, (size_t)ng2 * N2, N2, L, m0, j0, gpk, zg,
+                                       ks.npaired, ks.nself, [&](int sl) { return (int)ks.k[sl]; }, ring, wm0, wn0,
+                                       acc);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int i = m0 + wm0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -794,12 +883,14 @@ struct BFrag {
     int neo, naux, ng2, npair, zrows, kgroups;
 };
 
-// Per (round, fragment) q-block of the stage-2 items.
+// Per (round, fragment) q-block of the stage-2 items, with the kept k of the
+// k <-> q-k pairing (k[slot]) and the group layout of T.
 struct BQ {
     int self_conj;
-    int pad;
+    int npaired, nself, gpk, zg;
     size_t zrow0;
     float wq;
+    short k[KP_MAX];
 };
 
 // Stage-2 work item: fragment slot, fitting function, j tile, i tile.
@@ -816,7 +907,7 @@ struct BItemC {
 // concatenated C^{k-q} are routed to their fragment by `colmap` (slot, j).
 template <int NS>
 __global__ void __launch_bounds__(256) k_xf1_batched(Mesh mesh, int q, int naux, int nao_p, int nbtot, int ngv,
-                                                     const int2* __restrict__ colmap,
+                                                     KSlots ks, const int2* __restrict__ colmap,
                                                      const BFrag* __restrict__ frags,
                                                      const __bf16* __restrict__ plm, const __bf16* __restrict__ pc1) {
     constexpr int BM = 128, BN = 128, TM = 2, TN = 2;
@@ -825,8 +916,9 @@ __global__ void __launch_bounds__(256) k_xf1_batched(Mesh mesh, int q, int naux,
     const int M1 = naux * nao_p, NB = nbtot;
     const int nmt = (M1 + BM - 1) / BM, nnt = (NB + BN - 1) / BN;
     const long logical = xcd_logical(blockIdx.x, gridDim.x);
-    if (logical >= (long)nk * nmt * nnt) return;
-    const int k = (int)(logical / ((long)nmt * nnt));
+    if (logical >= (long)(ks.npaired + ks.nself) * nmt * nnt) return;
+    const int slot = (int)(logical / ((long)nmt * nnt));
+    const int k = ks.k[slot];
     const int rem = (int)(logical % ((long)nmt * nnt));
     const int m0 = (rem / nnt) * BM, n0 = (rem % nnt) * BN;
     const int kmq = mesh_sub(mesh, k, q);
@@ -883,7 +975,7 @@ __global__ void __launch_bounds__(256) k_xf1_batched(Mesh mesh, int q, int naux,
                     const BFrag fr = frags[cm.x];
                     const int L = grp_row / nao_p, mu0 = grp_row % nao_p;
                     const size_t N2 = (size_t)naux * fr.neo;
-                    const size_t g2 = ((size_t)k * nao_p + mu0) / 8;
+                    const size_t g2 = ((size_t)slot * nao_p + mu0) / 8;
                     const size_t x = (size_t)L * fr.neo + cm.y;
 #pragma unroll
                     for (int p3 = 0; p3 < 3; ++p3) {
@@ -915,7 +1007,7 @@ __global__ void __launch_bounds__(256) k_xf2_batched(int nitems, const BItem2* _
     if (it_id >= nitems) return;
     const BItem2 item = items[it_id];
     const BFrag fr = frags[item.slot];
-    const BQ qb = qs[item.slot];
+    const BQ& qb = qs[item.slot];
     const int neo = fr.neo, naux = fr.naux, L = item.L;
     const int m0 = item.it * BM, j0 = item.jt * BN;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -926,8 +1018,10 @@ __global__ void __launch_bounds__(256) k_xf2_batched(int nitems, const BItem2* _
     for (int p = 0; p < 3; ++p)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[p][0][0][r] = 0.f;
-    pk_loop3<NS, BM, BN, TM, TN>(fr.pc2, (size_t)fr.ng2 * neo, neo, m0, fr.ptt, (size_t)fr.ng2 * N2, N2,
-                                 L * neo + j0, fr.ng2 / 2, ring, wm0, wn0, acc);
+    const short* kk = qs[item.slot].k;
+    pk_loop_paired<NS, BM, BN, TM, TN>(fr.pc2, (size_t)fr.ng2 * neo, neo, fr.ptt, (size_t)fr.ng2 * N2, N2, L, m0, j0,
+                                       qb.gpk, qb.zg, qb.npaired, qb.nself, [&](int sl) { return (int)kk[sl]; },
+                                       ring, wm0, wn0, acc);
     const size_t ldz = (size_t)fr.npair;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -1109,7 +1203,8 @@ static PkDims pk_dims(const EriPlan& p) {
     d.ns = p.prec == DMET_BF16X6_3M ? 3 : 2;
     d.nao_p = (p.nao + 7) / 8 * 8;
     d.ngv = (d.nao_p / 8 + 1) / 2 * 2;
-    d.ng2 = (p.mesh.nk * d.nao_p / 8 + 1) / 2 * 2;
+    // groups of (k, mu) plus at least one zero group (index nk * nao_p / 8), even
+    d.ng2 = (p.mesh.nk * d.nao_p / 8 + 2) / 2 * 2;
     d.M1 = p.naux * d.nao_p;
     d.NB = p.nspin * p.neo;
     d.N2 = (size_t)p.naux * p.neo;
@@ -1144,25 +1239,27 @@ static dmet_status xform_packed(const EriPlan& p, const void* lmunu, const doubl
     __bf16* pc2 = cv.take<__bf16>(d.c2_elems);
     __bf16* ptt = cv.take<__bf16>(d.t_elems);
     const int nk = p.mesh.nk;
+    if (nk > KP_MAX) return fail(DMET_E_UNSUPPORTED, "split-bf16 transform supports at most 256 k-points");
+    const int gpk = d.nao_p / 8, zg = nk * gpk;   // groups per k; the zero group
     const char* nm = NS == 3 ? "pack_in_bf16x6" : "pack_in_bf16x3";
     {
         ProfScope ps(nm, st);
         if (p.dtype == DMET_C128)
             k_pack_lmunu<NS, double><<<dim3((d.M1 + 255) / 256, d.ngv, nk * nk), 256, 0, st>>>(
-                static_cast<const double*>(lmunu), p.nao, d.nao_p, p.naux, d.ngv, plm);
+                static_cast<const double*>(lmunu), p.nao, d.nao_p, p.naux, d.ngv, plm, p.mesh, 1);
         else
             k_pack_lmunu<NS, float><<<dim3((d.M1 + 255) / 256, d.ngv, nk * nk), 256, 0, st>>>(
-                static_cast<const float*>(lmunu), p.nao, d.nao_p, p.naux, d.ngv, plm);
+                static_cast<const float*>(lmunu), p.nao, d.nao_p, p.naux, d.ngv, plm, p.mesh, 1);
         k_pack_c1<NS><<<dim3((d.NB + 255) / 256, d.ngv, nk), 256, 0, st>>>(ck, nk, p.nspin, p.nao, p.neo, d.ngv, pc1,
                                                                           0, d.NB);
         k_pack_c2<NS><<<dim3((p.neo + 255) / 256, d.ng2, p.nspin), 256, 0, st>>>(ck, nk, p.nao, d.nao_p, p.neo,
                                                                                  d.ng2, pc2);
-        // the padding group of T (if any) is read by stage 2 against zero A: make it zero
-        if (d.ng2 * 8 > nk * d.nao_p) {
-            const size_t part = (size_t)d.ng2 * d.N2 * 8;
-            for (int sp = 0; sp < p.nspin * 3 * NS; ++sp)
-                fill_zero(ptt + (size_t)sp * part + (size_t)(d.ng2 - 1) * d.N2 * 8, d.N2 * 8 * sizeof(__bf16), st);
-        }
+        // groups zg .. ng2-1 of T pad odd group counts in stage 2: make them zero
+        // (stage 1 writes compact slots below zg only; conj C is zero there too)
+        const size_t part = (size_t)d.ng2 * d.N2 * 8;
+        for (int sp = 0; sp < p.nspin * 3 * NS; ++sp)
+            fill_zero(ptt + (size_t)sp * part + (size_t)zg * d.N2 * 8, (size_t)(d.ng2 - zg) * d.N2 * 8 * sizeof(__bf16),
+                      st);
         ps.stop();
     }
     DMET_LAUNCH_CHECK("pack inputs");
@@ -1177,18 +1274,22 @@ static dmet_status xform_packed(const EriPlan& p, const void* lmunu, const doubl
     const size_t t_spin = (size_t)3 * NS * d.ng2 * d.N2 * 8;
     const size_t c2_spin = (size_t)3 * NS * d.ng2 * p.neo * 8;
     for (const QBlock& qb : p.qblocks) {
+        KSlots ks;
+        kpair_counts(p.mesh, qb.q, ks.npaired, ks.nself);
+        for (int sl = 0; sl < ks.npaired + ks.nself; ++sl) ks.k[sl] = (short)kpair_slot_k(p.mesh, qb.q, sl);
         ProfScope ps1(n1, st);
-        const long nb1 = ((long)nk * ((d.M1 + 127) / 128) * ((d.NB + 127) / 128) + NXCD - 1) / NXCD * NXCD;
-        k1<<<dim3((unsigned)nb1), 256, xf1_lds<NS>(), st>>>(
-            p.mesh, qb.q, p.naux, d.nao_p, p.neo, p.nspin, d.ngv, d.ng2, plm, pc1, ptt);
+        const long nb1 = ((long)(ks.npaired + ks.nself) * ((d.M1 + 127) / 128) * ((d.NB + 127) / 128) + NXCD - 1) /
+                         NXCD * NXCD;
+        k1<<<dim3((unsigned)nb1), 256, xf1_lds<NS>(), st>>>(p.mesh, qb.q, p.naux, d.nao_p, p.neo, p.nspin, d.ngv,
+                                                            d.ng2, ks, plm, pc1, ptt);
         ps1.stop();
         DMET_LAUNCH_CHECK(n1);
         for (int s = 0; s < p.nspin; ++s) {
             ProfScope ps2(n2, st);
             const long nb2 = ((long)p.naux * njt * nit + NXCD - 1) / NXCD * NXCD;
-            k2<<<dim3((unsigned)nb2), 256, xf2_lds<NS>(), st>>>(
-                p.naux, p.neo, d.ng2, qb.self_conj, qb.zrow0, (float)qb.weight, pc2 + s * c2_spin, ptt + s * t_spin,
-                z + (size_t)s * p.zrows * ldz, ldz);
+            k2<<<dim3((unsigned)nb2), 256, xf2_lds<NS>(), st>>>(p.naux, p.neo, d.ng2, gpk, zg, ks, qb.self_conj,
+                                                                qb.zrow0, (float)qb.weight, pc2 + s * c2_spin,
+                                                                ptt + s * t_spin, z + (size_t)s * p.zrows * ldz, ldz);
             ps2.stop();
             DMET_LAUNCH_CHECK(n2);
         }
@@ -1380,7 +1481,7 @@ static void plan_batch(BatchPlan& bp) {
             G.naux = d.lat.naux;
             G.nao_p = (G.nao + 7) / 8 * 8;
             G.ngv = (G.nao_p / 8 + 1) / 2 * 2;
-            G.ng2 = (G.mesh.nk * G.nao_p / 8 + 1) / 2 * 2;
+            G.ng2 = (G.mesh.nk * G.nao_p / 8 + 2) / 2 * 2;   // with at least one zero group
             G.M1 = G.naux * G.nao_p;
             G.nbtot = 0;
             dmet_lattice lat1 = d.lat;
@@ -1405,7 +1506,7 @@ static void plan_batch(BatchPlan& bp) {
     for (auto& G : bp.groups) bp.rounds = std::max(bp.rounds, (int)G.qbs.size());
     // work lists
     bp.h_bfrag.resize(nfrag);
-    bp.h_bq.assign((size_t)bp.rounds * nfrag, BQ{0, 0, 0, 0.f});
+    bp.h_bq.assign((size_t)bp.rounds * nfrag, BQ{});
     bp.items2_off.assign(bp.rounds, 0);
     bp.items2_cnt.assign(bp.rounds, 0);
     for (int r = 0; r < bp.rounds; ++r) {
@@ -1415,7 +1516,14 @@ static void plan_batch(BatchPlan& bp) {
             const BatchGroup& G = bp.groups[F.group];
             if (r >= (int)G.qbs.size()) continue;
             const QBlock& qb = G.qbs[r];
-            bp.h_bq[(size_t)r * nfrag + f] = BQ{qb.self_conj, 0, qb.zrow0, (float)qb.weight};
+            BQ& b = bp.h_bq[(size_t)r * nfrag + f];
+            b.self_conj = qb.self_conj;
+            b.zrow0 = qb.zrow0;
+            b.wq = (float)qb.weight;
+            kpair_counts(G.mesh, qb.q, b.npaired, b.nself);
+            for (int sl = 0; sl < b.npaired + b.nself; ++sl) b.k[sl] = (short)kpair_slot_k(G.mesh, qb.q, sl);
+            b.gpk = G.nao_p / 8;
+            b.zg = G.mesh.nk * b.gpk;
             const int nt = (F.neo + 63) / 64;
             for (int L = 0; L < G.naux; ++L)
                 for (int jt = 0; jt < nt; ++jt)
@@ -1539,10 +1647,10 @@ static dmet_status batch_enqueue(BatchPlan& bp, int variant, bool prof, hipStrea
         __bf16* plm = at<__bf16>(ws, G.off_plm);
         if (G.dt == DMET_C128)
             k_pack_lmunu<NS, double><<<dim3((G.M1 + 255) / 256, G.ngv, nk * nk), 256, 0, st>>>(
-                static_cast<const double*>(G.lm), G.nao, G.nao_p, G.naux, G.ngv, plm);
+                static_cast<const double*>(G.lm), G.nao, G.nao_p, G.naux, G.ngv, plm, G.mesh, 1);
         else
             k_pack_lmunu<NS, float><<<dim3((G.M1 + 255) / 256, G.ngv, nk * nk), 256, 0, st>>>(
-                static_cast<const float*>(G.lm), G.nao, G.nao_p, G.naux, G.ngv, plm);
+                static_cast<const float*>(G.lm), G.nao, G.nao_p, G.naux, G.ngv, plm, G.mesh, 1);
         for (int f : G.members) {
             const BatchFrag& F = bp.fs[f];
             k_pack_c1<NS><<<dim3((F.neo + 255) / 256, G.ngv, nk), 256, 0, st>>>(
@@ -1551,11 +1659,14 @@ static dmet_status batch_enqueue(BatchPlan& bp, int variant, bool prof, hipStrea
             k_pack_c2<NS><<<dim3((F.neo + 255) / 256, G.ng2, 1), 256, 0, st>>>(
                 static_cast<const double*>(bp.frags[f].c_k), nk, G.nao, G.nao_p, F.neo, G.ng2,
                 at<__bf16>(ws, F.off_pc2));
-            if (G.ng2 * 8 > nk * G.nao_p) {
+            {
+                // groups zg .. ng2-1 of T pad odd group counts in stage 2: zero
+                const int zg = nk * (G.nao_p / 8);
                 const size_t n2 = (size_t)G.naux * F.neo, part = (size_t)G.ng2 * n2 * 8;
                 __bf16* ptt = at<__bf16>(ws, F.off_ptt);
                 for (int sp = 0; sp < 3 * NS; ++sp)
-                    fill_zero(ptt + (size_t)sp * part + (size_t)(G.ng2 - 1) * n2 * 8, n2 * 8 * sizeof(__bf16), st);
+                    fill_zero(ptt + (size_t)sp * part + (size_t)zg * n2 * 8,
+                              (size_t)(G.ng2 - zg) * n2 * 8 * sizeof(__bf16), st);
             }
         }
     }
@@ -1566,8 +1677,12 @@ static dmet_status batch_enqueue(BatchPlan& bp, int variant, bool prof, hipStrea
         ps = scope(NS == 3 ? "batch_xform1_bf16x6" : "batch_xform1_bf16x3");
         for (auto& G : bp.groups) {
             if (r >= (int)G.qbs.size()) continue;
-            const long nb = ((long)G.mesh.nk * ((G.M1 + 127) / 128) * ((G.nbtot + 127) / 128) + NXCD - 1) / NXCD * NXCD;
-            k1<<<dim3((unsigned)nb), 256, xf1_lds<NS>(), st>>>(G.mesh, G.qbs[r].q, G.naux, G.nao_p, G.nbtot, G.ngv,
+            KSlots ks;
+            kpair_counts(G.mesh, G.qbs[r].q, ks.npaired, ks.nself);
+            for (int sl = 0; sl < ks.npaired + ks.nself; ++sl) ks.k[sl] = (short)kpair_slot_k(G.mesh, G.qbs[r].q, sl);
+            const long nb = ((long)(ks.npaired + ks.nself) * ((G.M1 + 127) / 128) * ((G.nbtot + 127) / 128) + NXCD - 1) /
+                            NXCD * NXCD;
+            k1<<<dim3((unsigned)nb), 256, xf1_lds<NS>(), st>>>(G.mesh, G.qbs[r].q, G.naux, G.nao_p, G.nbtot, G.ngv, ks,
                                                                at<int2>(ws, G.off_colmap), dfr,
                                                                at<__bf16>(ws, G.off_plm), at<__bf16>(ws, G.off_pc1));
         }

@@ -332,3 +332,51 @@ def test_non_interacting_bath_impurity_eri(dmet, prec):
         ref = ok.pack_s8(ref) if b is None else ok.pack_s4(ref)
         err = np.abs(out[key].cpu().numpy().reshape(ref.shape) - ref).max()
         assert err < tol * (np.abs(ref).max() if prec == "fp64" else 1.0), (key, err)
+
+
+def _unread_blocks(kmesh):
+    """(q, k) blocks of lmunu outside the k <-> q-k paired transform: q with
+    -q < q (its partner -q is transformed instead) or k > q - k (its partner
+    q - k carries the transposed term)."""
+    pts = synth_cells(kmesh)
+    km = np.asarray(kmesh)
+
+    def idx(v):
+        v = np.asarray(v) % km
+        return int((v[0] * km[1] + v[1]) * km[2] + v[2])
+    nk = len(pts)
+    out = []
+    for q in range(nk):
+        for k in range(nk):
+            if idx(-pts[q]) < q or k > idx(pts[q] - pts[k]):
+                out.append((q, k))
+    return out
+
+
+def synth_cells(kmesh):
+    import synth
+    return synth.cells(kmesh)
+
+
+@pytest.mark.parametrize("key", ["odd", "hbn"])
+def test_paired_transform_reads_half_the_input(dmet, key):
+    """The split-bf16 transform pairs k with q - k (time reversal and the
+    Hermiticity of the 3-index tensor): the blocks it does not read may hold
+    anything.  Filled with NaN, the ERIs come out bit for bit the same, for the
+    single call and for the batched form."""
+    wl, lat, lm, bath = case(**CASES[key])
+    ck = to_dev(bath["c_k"])
+    unread = _unread_blocks(wl.kmesh)
+    assert 0.45 * wl.nk ** 2 < len(unread) < 0.8 * wl.nk ** 2
+    ref = dmet.dmet_transform_eri(wl.kmesh, wl.nao, wl.naux, to_dev(lm), ck, "bf16x6")["aa"].clone()
+    lm_nan = lm.copy()
+    for q, k in unread:
+        lm_nan[q, k] = np.nan
+    lm_d = to_dev(lm_nan)
+    got = dmet.dmet_transform_eri(wl.kmesh, wl.nao, wl.naux, lm_d, ck, "bf16x6")["aa"]
+    torch.cuda.synchronize()
+    assert torch.equal(ref, got)
+    spec = [{"kmesh": wl.kmesh, "nao": wl.nao, "naux": wl.naux, "lmunu": lm_d, "c_k": ck[0].contiguous()}]
+    bat = dmet.dmet_transform_eri_batched(spec, "bf16x6")[0]
+    torch.cuda.synchronize()
+    assert torch.equal(ref, bat)
