@@ -14,6 +14,9 @@ matrix embedding theory", Sec. 2.1):
 * Eq. ``fock transform``: F^{0,EO} = 1/N_k sum_k C^{k dagger} F^k C^k
 * Alg. 1 (GDF embedding ERI): k-AO -> k-EO transform of (L|mu k_mu, nu k_nu),
   Fourier sum to the reference cell with 1/N_k, contraction with 1/N_k.
+* App. B, Eq. ``FFTDF`` and Alg. 2 (plane-wave embedding ERI): the same
+  transform of the AO pair densities on the real-space grid, FFT, the Coulomb
+  kernel 4 pi / |q + G|^2, inverse FFT and the contraction over the grid.
 
 Readings of points the paper leaves open (k ordering, Fourier sign of gamma,
 normalisation of the 3-index tensor, which index of (0i0j|L) is conjugated,
@@ -270,6 +273,72 @@ def alg1_eri_columns(lmunu, c_k_a, kmesh, pairs_a, c_k_b=None, pairs_b=None):
             xb = xb + (c_k_b[k][:, ib].conj()[None] * tb).sum(axis=1) / nk
         out = out + (xa.conj().T @ xb) / nk
     return out.real.copy(), float(np.abs(out.imag).max())
+
+
+# --------------------------------------------------------------------------
+# NEXT-4: Alg. 2, embedding ERIs with plane-wave density fitting (App. B)
+# --------------------------------------------------------------------------
+def fftdf_frequencies(kmesh, grid_n, q):
+    """Integer supercell frequency j' (one axis per column) of every (q, G):
+    j = N_d g_d + m_d with q = m and G = g on the cell grid, taken in
+    (-(N_d n_d)/2, (N_d n_d)/2] the way a length-N_d n_d FFT orders them.
+    Returns [nr][3] (G row-major over the cell grid)."""
+    m = mesh_points(kmesh)[q]
+    out = []
+    for d in range(3):
+        L = kmesh[d] * grid_n[d]
+        j = kmesh[d] * np.arange(grid_n[d]) + m[d]
+        out.append(np.where(j <= (L - 1) // 2, j, j - L))
+    jx, jy, jz = np.meshgrid(out[0], out[1], out[2], indexing="ij")
+    return np.stack([jx.ravel(), jy.ravel(), jz.ravel()], axis=1)
+
+
+def coulomb_kernel(kmesh, grid_n, cell, q):
+    """4 pi / |q + G|^2 on the cell grid of G (orthorhombic cell lengths in
+    bohr); the q + G = 0 term is dropped (neutralising background)."""
+    j = fftdf_frequencies(kmesh, grid_n, q).astype(float)
+    kvec = 2.0 * np.pi * j / (np.asarray(kmesh, float) * np.asarray(cell, float))[None, :]
+    k2 = (kvec * kvec).sum(axis=1)
+    out = np.zeros_like(k2)
+    nz = k2 > 0
+    out[nz] = 4.0 * np.pi / k2[nz]
+    return out
+
+
+def alg2_eri(rho, c_k_a, kmesh, grid_n, cell, c_k_b=None):
+    """Embedding ERI (ij|kl) by Alg. 2.  For every q:
+
+        X(q)[r] = 1/N_k sum_k C^{k dagger} (r|k, k-q) C^{k-q}      k-AO -> k-EO, FT to R = 0
+        W(q)[G] = sum_r exp(+i (q+G).r) X(q)[r]                     FFT
+        W(q)[G] *= 4 pi / |q + G|^2                                 Coulomb kernel
+        V(q)[r] = 1/n_r sum_G exp(-i (q+G).r) W(q)[G]               inverse FFT
+        (ij|kl) += dV/N_k sum_r conj(X_ij(q)[r]) V_kl(q)[r]         contraction over the grid
+
+    with dV = Omega / n_r the volume per grid point, so that the result is the
+    Coulomb integral of the EO pair densities on the Born-von Karman supercell.
+    rho[q][k][r][mu][nu] = (r|mu k, nu k-q).  Returns (real [n][n][m][m], max |Im|)."""
+    nk = rho.shape[0]
+    grid_n = tuple(grid_n)
+    nr = int(np.prod(grid_n))
+    dv = float(np.prod(cell)) / nr
+    idx = np.indices(grid_n).reshape(3, -1).T
+    eri = 0
+    for q in range(nk):
+        m = mesh_points(kmesh)[q]
+        ph = np.exp(2j * np.pi * (idx * (m / (np.asarray(kmesh) * np.asarray(grid_n)))[None, :]).sum(axis=1))
+        kern = coulomb_kernel(kmesh, grid_n, cell, q)
+        xs = [alg1_embedded_3index(rho, c, kmesh, q) for c in ((c_k_a,) if c_k_b is None else (c_k_a, c_k_b))]
+        xa, xb = xs[0], xs[-1]
+        n, mm = xa.shape[1], xb.shape[1]
+        w = np.fft.ifftn((ph[:, None, None] * xb).reshape(*grid_n, mm, mm), axes=(0, 1, 2)) * nr
+        w = w.reshape(nr, mm, mm) * kern[:, None, None]
+        v = np.fft.fftn(w.reshape(*grid_n, mm, mm), axes=(0, 1, 2)).reshape(nr, mm, mm) / nr
+        v = v * ph.conj()[:, None, None]
+        eri = eri + dv / nk * (xa.reshape(nr, n * n).conj().T @ v.reshape(nr, mm * mm))
+    n = c_k_a.shape[2]
+    m = n if c_k_b is None else c_k_b.shape[2]
+    eri = eri.reshape(n, n, m, m)
+    return eri.real.copy(), float(np.abs(eri.imag).max())
 
 
 # --------------------------------------------------------------------------

@@ -146,3 +146,38 @@ def coulomb_exchange(b_real, kmesh, gamma_sup):
         j += np.einsum("Lpq,L->pq", bs, np.einsum("Lrs,sr->L", bs, gamma_sup))
         k += np.einsum("Lpr,rs,Lsq->pq", bs, gamma_sup, bs, optimize=True)
     return j, k
+
+
+def fftdf_eri(chi_sup, c_sup_a, kmesh, grid_n, cell, c_sup_b=None):
+    """Plane-wave embedding ERIs by brute force on the supercell grid: the EO
+    orbitals phi_i(X) = sum_{R,mu} C_sup[(R,mu),i] chi_mu(X - R) are formed on
+    the whole Born-von Karman grid, their pair densities are Fourier
+    transformed with one supercell FFT, and
+
+        (ij|kl) = dV^2 / Omega_sup sum_{Gs != 0} 4 pi/|Gs|^2 conj(P_ij(Gs)) P_kl(Gs),
+
+    the Coulomb integral of the pair densities under the periodic Coulomb
+    operator of the supercell.  chi_sup: [N_k R][nao][X]."""
+    nk, nao, nx = chi_sup.shape
+    shape = tuple(int(a) * int(b) for a, b in zip(kmesh, grid_n))
+    assert nx == int(np.prod(shape))
+    cell = np.asarray(cell, float)
+    omega_sup = float(np.prod(cell)) * nk
+    dv = float(np.prod(cell)) / int(np.prod(grid_n))
+    freqs = [np.fft.fftfreq(shape[d], 1.0 / shape[d]) for d in range(3)]
+    g = [2.0 * np.pi * freqs[d] / (kmesh[d] * cell[d]) for d in range(3)]
+    g2 = g[0][:, None, None] ** 2 + g[1][None, :, None] ** 2 + g[2][None, None, :] ** 2
+    kern = np.zeros_like(g2)
+    kern[g2 > 0] = 4.0 * np.pi / g2[g2 > 0]
+
+    def pair_hat(c_sup):
+        n = c_sup.shape[1]
+        phi = np.einsum("rmx,rmi->ix", chi_sup, c_sup.reshape(nk, nao, n))
+        pair = (phi[:, None, :] * phi[None, :, :]).reshape(n * n, *shape)
+        return np.fft.fftn(pair, axes=(1, 2, 3)).reshape(n * n, -1), n
+
+    pa, na = pair_hat(c_sup_a)
+    pb, nb = (pa, na) if c_sup_b is None else pair_hat(c_sup_b)
+    eri = (pa.conj() * kern.ravel()[None, :]) @ pb.T * (dv * dv / omega_sup)
+    assert np.abs(eri.imag).max() <= 1e-10 * max(1.0, np.abs(eri.real).max())
+    return eri.real.reshape(na, na, nb, nb)

@@ -42,6 +42,7 @@ import numpy as np
 __all__ = [
     "Workload", "CONFIGS", "cells", "min_image_length", "kq_index",
     "make_lattice", "three_index", "three_index_block", "Lattice",
+    "FftGrid", "FFT_CONFIGS", "fftdf_pair_density", "fftdf_ao_supercell",
 ]
 
 
@@ -328,3 +329,87 @@ def batched_fragments(nfrag=64, seed=1004, neo_range=(20, 200), lattices=("b222"
         out.append({"lattice": lat, "neo": neo, "nimp": nimp, "nval": nval,
                     "imp_idx": None if order is None else order[:nimp], "val_idx": list(range(nval))})
     return out
+
+
+# --------------------------------------------------------------------------
+# Plane-wave (FFTDF) workloads: Gaussian AOs sampled on a real-space grid of an
+# orthorhombic cell.  The "fitting functions" are the grid points r of the
+# reference cell; the 3-index input is the AO pair density
+#   rho[q][k][r][mu][nu] = sum_{R1,R2} e^{-i k.R1} e^{+i (k-q).R2} chi_mu(r - R1) chi_nu(r - R2)
+#                        = A_mu(k, r) conj(A_nu(k-q, r)),  A_mu(k, r) = sum_R e^{-i k.R} chi_mu(r - R),
+# with chi_mu periodic on the Born-von Karman supercell (minimum image).
+# --------------------------------------------------------------------------
+@dataclass(frozen=True)
+class FftGrid:
+    n: tuple             # grid points per cell axis
+    cell: tuple          # orthorhombic cell lengths (bohr)
+
+    @property
+    def nr(self) -> int:
+        return int(np.prod(self.n))
+
+    @property
+    def volume(self) -> float:
+        return float(np.prod(self.cell))
+
+
+# (workload, grid): naux of the workload is the number of grid points
+FFT_CONFIGS = {
+    "fft_tiny": (Workload("fft_tiny", (2, 2, 1), 4, 216, 4, 4, 1, 1.5, 1010), FftGrid((6, 6, 6), (3.0, 3.0, 3.0))),
+    "fft_odd": (Workload("fft_odd", (3, 2, 1), 5, 240, 5, 5, 1, 1.5, 1011), FftGrid((6, 5, 8), (3.0, 2.6, 3.4))),
+    "fft_si": (Workload("fft_si", (2, 2, 2), 26, 4096, 26, 26, 1, 2.0, 1012), FftGrid((16, 16, 16), (5.1, 5.1, 5.1))),
+}
+
+
+def _fft_gaussians(wl: Workload, grid: FftGrid):
+    """Centres (fractional), exponents (bohr^-2) and norms of the cell's AOs."""
+    rng = np.random.default_rng([wl.seed, 300])
+    centres = rng.random((wl.nao, 3))
+    alpha = rng.uniform(0.8, 2.0, wl.nao)
+    norm = (2.0 * alpha / np.pi) ** 0.75
+    return centres, alpha, norm
+
+
+def _chi_on_points(wl: Workload, grid: FftGrid, pts_cart, shift_cells):
+    """chi_mu(x - R) for cartesian points x [np][3] and cell shifts R [nR][3]
+    (integer cell coordinates): [nR][nao][np], minimum image on the supercell."""
+    centres, alpha, norm = _fft_gaussians(wl, grid)
+    cell = np.asarray(grid.cell)
+    sup = cell * np.asarray(wl.kmesh)
+    out = np.empty((len(shift_cells), wl.nao, len(pts_cart)))
+    for ir, rc in enumerate(shift_cells):
+        for mu in range(wl.nao):
+            c = (np.asarray(rc) + centres[mu]) * cell
+            d = pts_cart - c[None, :]
+            d -= sup[None, :] * np.round(d / sup[None, :])
+            out[ir, mu] = norm[mu] * np.exp(-alpha[mu] * (d * d).sum(axis=1))
+    return out
+
+
+def _cell_grid(grid: FftGrid):
+    idx = np.indices(grid.n).reshape(3, -1).T
+    return idx * (np.asarray(grid.cell) / np.asarray(grid.n))[None, :]
+
+
+def fftdf_pair_density(wl: Workload, grid: FftGrid, dtype=np.complex128) -> np.ndarray:
+    """rho[q][k][r][mu][nu] = (r | mu k, nu k-q) on the reference-cell grid."""
+    assert wl.naux == grid.nr
+    nk = wl.nk
+    chi = _chi_on_points(wl, grid, _cell_grid(grid), cells(wl.kmesh))   # [R][mu][r]
+    a = np.fft.fftn(chi.reshape(*wl.kmesh, wl.nao, grid.nr), axes=(0, 1, 2)).reshape(nk, wl.nao, grid.nr)
+    a = a.transpose(0, 2, 1)                                             # A[k][r][mu]
+    kmq = kq_index(wl.kmesh)
+    out = np.empty((nk, nk, grid.nr, wl.nao, wl.nao), dtype=dtype)
+    for q in range(nk):
+        for k in range(nk):
+            out[q, k] = a[k][:, :, None] * a[kmq[q, k]].conj()[:, None, :]
+    return out
+
+
+def fftdf_ao_supercell(wl: Workload, grid: FftGrid) -> np.ndarray:
+    """chi_mu(X - R') on the supercell grid X (row-major over (N_d n_d) per
+    axis): [N_k R'][nao][N_k nr] real."""
+    n = np.asarray(grid.n) * np.asarray(wl.kmesh)
+    idx = np.indices(tuple(n)).reshape(3, -1).T
+    pts = idx * (np.asarray(grid.cell) / np.asarray(grid.n))[None, :]
+    return _chi_on_points(wl, grid, pts, cells(wl.kmesh))
