@@ -199,6 +199,40 @@ dmet_status dmet_transform_eri_df(const dmet_lattice* lat, int neo, const void* 
                                   double* z, void* workspace, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Plane-wave (FFTDF) embedding ERIs, App. B, Eq. "FFTDF" and Alg. 2.
+ *
+ * The fitting functions are the points r of a real-space grid of the
+ * reference cell (orthorhombic, `cell` lengths in bohr, n[0] x n[1] x n[2]
+ * points, row-major), so lat->naux must equal n[0] n[1] n[2].  Input:
+ *   rho [N_k q][N_k k][nr][nao][nao]  (complex128 or complex64, per dtype)
+ *       rho[q][k][r][mu][nu] = (r | mu k, nu k-q), the AO pair density on the
+ *       grid with the conventions of dmet_transform_eri (k-q wrapped per axis);
+ *   c_k as for dmet_transform_eri.
+ * For every q the AO pair densities are transformed to the embedding basis
+ * and Fourier summed to R = 0 (as in Alg. 1), Fourier transformed over the
+ * grid with the phase of q (W(G) = sum_r e^{+i(q+G).r} X(r)), weighted by the
+ * Coulomb kernel 4 pi / (Omega |q+G|^2) (the q+G = 0 term dropped) and
+ * contracted:
+ *   (ij|kl) = dV^2 / (N_k Omega) sum_{q,G} 4 pi/|q+G|^2 conj(W_ij) W_kl,
+ * dV = Omega / nr, i.e. the Coulomb integral of the EO pair densities on the
+ * Born-von Karman supercell.  Outputs as dmet_transform_eri (s8 / s4 float64).
+ * FP64 throughout.  Returns DMET_E_ARG for a grid that does not match naux or
+ * a non-positive cell, DMET_E_WORKSPACE if the workspace is too small.
+ * Asynchronous; the workspace must stay valid until the work completes.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int n[3];          /* grid points per cell axis */
+    double cell[3];    /* orthorhombic cell lengths (bohr) */
+} dmet_pw_grid;
+
+dmet_status dmet_transform_eri_fftdf_workspace(const dmet_lattice* lat, const dmet_pw_grid* grid, int neo,
+                                               dmet_dtype dtype, size_t* bytes);
+dmet_status dmet_transform_eri_fftdf(const dmet_lattice* lat, const dmet_pw_grid* grid, int neo,
+                                     const void* rho, dmet_dtype dtype, const void* c_k,
+                                     double* eri_aa, double* eri_bb, double* eri_ab,
+                                     void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Double-counting-corrected embedding Fock matrix (Eq. "fock double counting"):
  *   F~_ij = F^{EO}_ij - [sum_kl (ij|kl) gamma_lk - 1/2 sum_kl (ik|lj) gamma_kl]
  * with gamma the spin-summed embedding density.  Inputs are per spin:
@@ -208,7 +242,7 @@ dmet_status dmet_transform_eri_df(const dmet_lattice* lat, int neo, const void* 
  * The ERIs enter through their density-fitting factors z (as written by
  * dmet_transform_eri_df, nrows = N_k*naux rows per spin).
  * f_eo, dm_eo: [nspin][neo][neo] float64 (dm_eo symmetric); f_tilde: out, same
- * shape.  neo <= 512.  Workspace from dmet_fock_dc_workspace().  Asynchronous.
+ * shape.  Workspace from dmet_fock_dc_workspace().  Asynchronous.
  * ------------------------------------------------------------------------- */
 dmet_status dmet_fock_dc_workspace(int nspin, int neo, int nrows, size_t* bytes);
 dmet_status dmet_fock_dc(int nspin, int neo, int nrows, const double* z, const double* f_eo,

@@ -248,6 +248,47 @@ dmet_status dmet_transform_eri_df(const dmet_lattice* lat, int neo, const void* 
                   z);
 }
 
+static dmet_status check_pw(const dmet_lattice* lat, const dmet_pw_grid* grid) {
+    if (!grid) return fail(DMET_E_ARG, "grid is NULL");
+    long nr = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (grid->n[a] < 1) return fail(DMET_E_ARG, "grid points per axis must be >= 1");
+        if (!(grid->cell[a] > 0.0)) return fail(DMET_E_ARG, "cell lengths must be positive");
+        nr *= grid->n[a];
+    }
+    if (nr != lat->naux) return fail(DMET_E_ARG, "naux must equal the number of grid points");
+    return DMET_OK;
+}
+
+dmet_status dmet_transform_eri_fftdf_workspace(const dmet_lattice* lat, const dmet_pw_grid* grid, int neo,
+                                               dmet_dtype dtype, size_t* bytes) {
+    dmet_status s = check_eri_args(lat, neo, DMET_FP64, dtype);
+    if (s != DMET_OK) return s;
+    s = check_pw(lat, grid);
+    if (s != DMET_OK) return s;
+    if (!bytes) return fail(DMET_E_ARG, "bytes is NULL");
+    *bytes = fftdf_workspace(make_eri_plan(lat, neo, DMET_FP64, dtype));
+    return DMET_OK;
+}
+
+dmet_status dmet_transform_eri_fftdf(const dmet_lattice* lat, const dmet_pw_grid* grid, int neo, const void* rho,
+                                     dmet_dtype dtype, const void* c_k, double* eri_aa, double* eri_bb,
+                                     double* eri_ab, void* workspace, size_t ws_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    dmet_status s = check_eri_args(lat, neo, DMET_FP64, dtype);
+    if (s != DMET_OK) return s;
+    s = check_pw(lat, grid);
+    if (s != DMET_OK) return s;
+    if (!rho || !c_k || !eri_aa) return fail(DMET_E_ARG, "null array argument");
+    if (lat->nspin == 2 && !eri_bb) return fail(DMET_E_ARG, "nspin == 2 requires eri_bb");
+    if (lat->nspin == 1 && (eri_bb || eri_ab)) return fail(DMET_E_ARG, "nspin == 1 takes no eri_bb / eri_ab");
+    if (!workspace) return fail(DMET_E_WORKSPACE, "workspace is NULL");
+    EriPlan p = make_eri_plan(lat, neo, DMET_FP64, dtype);
+    if (fftdf_workspace(p) > ws_bytes) return fail(DMET_E_WORKSPACE, "fftdf workspace too small");
+    return fftdf_eri(p, grid, rho, static_cast<const double*>(c_k), eri_aa, eri_bb, eri_ab, workspace, ws_bytes,
+                     stream);
+}
+
 dmet_status dmet_fock_dc_workspace(int nspin, int neo, int nrows, size_t* bytes) {
     if (nspin != 1 && nspin != 2) return fail(DMET_E_ARG, "nspin must be 1 or 2");
     if (neo < 1 || neo > 512) return fail(DMET_E_ARG, "neo must be in [1, 512]");

@@ -72,9 +72,17 @@ size_t eri_lp_workspace(const EriPlan& p);
 dmet_status eri_lp(const EriPlan& p, const void* lmunu, const double* ck, double* eri_aa, double* eri_bb,
                    double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st, double* df_out = nullptr);
 
+// (ij|kl) = sum_rows z_s[row][ij] z_t[row][kl] in FP64 for z [nspin][krows][npair]
+dmet_status contract_f64(int nspin, int npair, int krows, const double* z, double* eri_aa, double* eri_bb,
+                         double* eri_ab, hipStream_t st);
+
 size_t eri_f32_workspace(const EriPlan& p);
 dmet_status eri_f32(const EriPlan& p, const void* lmunu, const double* ck, double* eri_aa, double* eri_bb,
                     double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st, double* df_out = nullptr);
+
+size_t fftdf_workspace(const EriPlan& p);
+dmet_status fftdf_eri(const EriPlan& p, const dmet_pw_grid* grid, const void* rho, const double* ck, double* eri_aa,
+                      double* eri_bb, double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st);
 
 size_t fock_dc_workspace(int nspin, int neo, int nrows);
 dmet_status fock_dc(int nspin, int neo, int nrows, const double* z, const double* f_eo, const double* dm_eo,

@@ -232,20 +232,26 @@ dmet_status eri_f64(const EriPlan& p, const void* lmunu, const double* ck, doubl
         }
     }
     if (df_out) return DMET_OK;
-    const int nt = (p.npair + C_BM - 1) / C_BM;
-    for (int s = 0; s < p.nspin; ++s) {
-        const double* zs = z + (size_t)s * p.zrows * ldz;
+    return contract_f64(p.nspin, p.npair, p.zrows, z, eri_aa, eri_bb, eri_ab, st);
+}
+
+dmet_status contract_f64(int nspin, int npair, int krows, const double* z, double* eri_aa, double* eri_bb,
+                         double* eri_ab, hipStream_t st) {
+    const size_t ldz = (size_t)npair;
+    const int nt = (npair + C_BM - 1) / C_BM;
+    for (int s = 0; s < nspin; ++s) {
+        const double* zs = z + (size_t)s * krows * ldz;
         double* out = s == 0 ? eri_aa : eri_bb;
         ProfScope ps("contract_s8_f64", st);
         k_contract_f64<C_BM, C_BN, C_BK, 0><<<dim3((unsigned)((long)nt * (nt + 1) / 2)), 256, 0, st>>>(
-            p.npair, p.zrows, zs, zs, ldz, out);
+            npair, krows, zs, zs, ldz, out);
         ps.stop();
         DMET_LAUNCH_CHECK("k_contract_f64 s8");
     }
-    if (p.nspin == 2 && eri_ab) {
+    if (nspin == 2 && eri_ab) {
         ProfScope ps("contract_s4_f64", st);
-        k_contract_f64<C_BM, C_BN, C_BK, 1><<<dim3(nt, nt), 256, 0, st>>>(p.npair, p.zrows, z,
-                                                                        z + p.zrows * ldz, ldz, eri_ab);
+        k_contract_f64<C_BM, C_BN, C_BK, 1><<<dim3(nt, nt), 256, 0, st>>>(npair, krows, z, z + (size_t)krows * ldz,
+                                                                        ldz, eri_ab);
         ps.stop();
         DMET_LAUNCH_CHECK("k_contract_f64 s4");
     }

@@ -1,0 +1,201 @@
+// Plane-wave (FFTDF) embedding ERIs, App. B, Eq. "FFTDF" and Alg. 2.
+//
+// The grid points r of the reference cell play the role of the fitting
+// functions: the FP64 transform of Alg. 1 turns the AO pair densities
+// (r|mu k, nu k-q) into the real rows Z_r = w_q (Re X, Im X) of the embedded
+// pair densities X(q)[r][ij] (q and -q combined as for GDF).  For each q the
+// rows are Fourier transformed over the grid with the phase of q,
+//   W(G) = sum_r exp(+i (q+G).r) X(r),
+// one axis at a time (a separable 3-D DFT; each output sums the n_d points of
+// its line with a twiddle table held in LDS), and scaled by
+// dV sqrt(4 pi / (Omega |q+G|^2)) into two real rows (Re W, Im W) per G.  The
+// FP64 contraction of those rows gives the ERIs.
+#include <math.h>
+
+#include <algorithm>
+
+#include <vector>
+
+#include "common.h"
+#include "eri.h"
+
+namespace dmet {
+namespace {
+
+constexpr int PW_MAXN = 64;      // grid points per axis (twiddle table nd^2 in LDS)
+
+struct PwAxis {
+    int n[3];          // grid
+    int axis;          // axis transformed by this pass
+    int nmesh, m;      // k-mesh size and q coordinate along the axis
+};
+
+struct PwScale {
+    int n[3], nmesh[3], m[3];
+    double cell[3];
+    double dv, omega;
+};
+
+// dV sqrt(4 pi / (Omega |q+G|^2)) for the grid frequency x (0 at q+G = 0)
+__device__ inline double pw_scale(const PwScale& k, const int x[3]) {
+    double k2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        const long L = (long)k.nmesh[d] * k.n[d], j = (long)k.nmesh[d] * x[d] + k.m[d];
+        const long jp = j <= (L - 1) / 2 ? j : j - L;   // supercell FFT order
+        const double kd = 2.0 * M_PI * (double)jp / ((double)k.nmesh[d] * k.cell[d]);
+        k2 += kd * kd;
+    }
+    return k2 > 0.0 ? k.dv * sqrt(4.0 * M_PI / (k.omega * k2)) : 0.0;
+}
+
+// One axis of W: out[.., g, ..][p] = sum_t exp(+2 pi i (N g + m) t / (N n)) in[.., t, ..][p]
+// over a [x0][x1][x2][pair] layout.  IN: 0 complex buffer, 1 real rows
+// (row zrow0 + r), 2 interleaved Re/Im rows (row zrow0 + 2 r + part).  OUT: 0
+// complex buffer, 1 scaled rows zg0 + 2 G + part.
+template <int IN, int OUT>
+__global__ void __launch_bounds__(256) k_pw_axis(PwAxis ax, int npair, const double2* __restrict__ cin,
+                                                 const double* __restrict__ zin, size_t zrow0, size_t ldz,
+                                                 double2* __restrict__ cout, double* __restrict__ zout, size_t zg0,
+                                                 PwScale ks) {
+    extern __shared__ double2 tw[];   // [g][t], nd^2 entries
+    const int nd = ax.n[ax.axis];
+    const long L = (long)ax.nmesh * nd;
+    for (int e = threadIdx.x; e < nd * nd; e += blockDim.x) {
+        const int g = e / nd, t = e % nd;
+        const long num = (((long)ax.nmesh * g + ax.m) * t) % L;   // exact reduction of (q+G).r
+        double s, c;
+        sincospi(2.0 * (double)num / (double)L, &s, &c);
+        tw[e] = make_double2(c, s);
+    }
+    __syncthreads();
+    const long n12 = (long)ax.n[1] * ax.n[2];
+    const long nr = (long)ax.n[0] * n12;
+    const long stride = ax.axis == 0 ? n12 : (ax.axis == 1 ? ax.n[2] : 1);
+    const long total = nr * npair;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+        const int p = (int)(e % npair);
+        const long r = e / npair;
+        int x[3] = {(int)(r / n12), (int)((r / ax.n[2]) % ax.n[1]), (int)(r % ax.n[2])};
+        const int g = x[ax.axis];
+        const long base = r - (long)g * stride;
+        const double2* w = tw + g * nd;
+        double re = 0.0, im = 0.0;
+        for (int t = 0; t < nd; ++t) {
+            const long rt = base + (long)t * stride;
+            double vr, vi;
+            if (IN == 0) {
+                const double2 v = cin[rt * npair + p];
+                vr = v.x;
+                vi = v.y;
+            } else if (IN == 1) {
+                vr = zin[(zrow0 + rt) * ldz + p];
+                vi = 0.0;
+            } else {
+                vr = zin[(zrow0 + 2 * rt) * ldz + p];
+                vi = zin[(zrow0 + 2 * rt + 1) * ldz + p];
+            }
+            re += w[t].x * vr - w[t].y * vi;
+            im += w[t].x * vi + w[t].y * vr;
+        }
+        if (OUT == 0) {
+            cout[r * npair + p] = make_double2(re, im);
+        } else {
+            const double sc = pw_scale(ks, x);
+            zout[(zg0 + 2 * r) * ldz + p] = sc * re;
+            zout[(zg0 + 2 * r + 1) * ldz + p] = sc * im;
+        }
+    }
+}
+
+struct PwDims {
+    size_t nr, zrows_g, eri_ws, zr, buf, zg;
+};
+
+PwDims pw_dims(const EriPlan& p) {
+    PwDims d;
+    d.nr = (size_t)p.naux;
+    d.zrows_g = 2 * d.nr * p.qblocks.size();
+    d.eri_ws = eri_f64_workspace(p);
+    d.zr = (size_t)p.nspin * p.zrows * p.npair;
+    d.buf = d.nr * p.npair;
+    d.zg = (size_t)p.nspin * d.zrows_g * p.npair;
+    return d;
+}
+
+}  // namespace
+
+size_t fftdf_workspace(const EriPlan& p) {
+    PwDims d = pw_dims(p);
+    Carve cv(nullptr, 0);
+    cv.take<char>(d.eri_ws);
+    cv.take<double>(d.zr);
+    cv.take<double2>(d.buf);
+    cv.take<double2>(d.buf);
+    cv.take<double>(d.zg);
+    return cv.bytes();
+}
+
+dmet_status fftdf_eri(const EriPlan& p, const dmet_pw_grid* grid, const void* rho, const double* ck, double* eri_aa,
+                      double* eri_bb, double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st) {
+    PwDims d = pw_dims(p);
+    Carve cv(ws, ws_bytes);
+    void* ews = cv.take<char>(d.eri_ws);
+    double* zr = cv.take<double>(d.zr);
+    double2* b1 = cv.take<double2>(d.buf);
+    double2* b2 = cv.take<double2>(d.buf);
+    double* zg = cv.take<double>(d.zg);
+    if (cv.bytes() > ws_bytes) return fail(DMET_E_WORKSPACE, "fftdf workspace too small");
+    for (int a = 0; a < 3; ++a)
+        if (grid->n[a] > PW_MAXN) return fail(DMET_E_UNSUPPORTED, "fftdf: at most 64 grid points per axis");
+    // embedded pair densities on the grid, real rows per q block (Alg. 1 transform)
+    dmet_status s = eri_f64(p, rho, ck, nullptr, nullptr, nullptr, ews, d.eri_ws, st, zr);
+    if (s != DMET_OK) return s;
+    PwScale ks;
+    for (int a = 0; a < 3; ++a) {
+        ks.n[a] = grid->n[a];
+        ks.nmesh[a] = p.mesh.n[a];
+        ks.cell[a] = grid->cell[a];
+    }
+    ks.omega = grid->cell[0] * grid->cell[1] * grid->cell[2];
+    ks.dv = ks.omega / (double)d.nr;
+    const long total = (long)d.nr * p.npair;
+    const unsigned nb = (unsigned)std::min<long>((total + 255) / 256, 65535L * 4);
+    for (int sp = 0; sp < p.nspin; ++sp) {
+        const double* zs = zr + (size_t)sp * p.zrows * p.npair;
+        double* zgs = zg + (size_t)sp * d.zrows_g * p.npair;
+        for (size_t b = 0; b < p.qblocks.size(); ++b) {
+            const QBlock& qb = p.qblocks[b];
+            const int q2 = qb.q % p.mesh.n[2], q1 = (qb.q / p.mesh.n[2]) % p.mesh.n[1],
+                      q0 = qb.q / (p.mesh.n[1] * p.mesh.n[2]);
+            const int m[3] = {q0, q1, q2};
+            for (int a = 0; a < 3; ++a) ks.m[a] = m[a];
+            PwAxis ax;
+            for (int a = 0; a < 3; ++a) ax.n[a] = grid->n[a];
+            ProfScope ps("fftdf_dft", st);
+            auto lds = [&](int a) { return (size_t)grid->n[a] * grid->n[a] * sizeof(double2); };
+            ax.axis = 0;
+            ax.nmesh = p.mesh.n[0];
+            ax.m = m[0];
+            if (qb.self_conj)
+                k_pw_axis<1, 0><<<nb, 256, lds(0), st>>>(ax, p.npair, nullptr, zs, qb.zrow0, p.npair, b1, nullptr, 0,
+                                                         ks);
+            else
+                k_pw_axis<2, 0><<<nb, 256, lds(0), st>>>(ax, p.npair, nullptr, zs, qb.zrow0, p.npair, b1, nullptr, 0,
+                                                         ks);
+            ax.axis = 1;
+            ax.nmesh = p.mesh.n[1];
+            ax.m = m[1];
+            k_pw_axis<0, 0><<<nb, 256, lds(1), st>>>(ax, p.npair, b1, nullptr, 0, p.npair, b2, nullptr, 0, ks);
+            ax.axis = 2;
+            ax.nmesh = p.mesh.n[2];
+            ax.m = m[2];
+            k_pw_axis<0, 1><<<nb, 256, lds(2), st>>>(ax, p.npair, b2, nullptr, 0, p.npair, nullptr, zgs, 2 * d.nr * b,
+                                                     ks);
+            ps.stop();
+            DMET_LAUNCH_CHECK("k_pw_axis");
+        }
+    }
+    return contract_f64(p.nspin, p.npair, (int)d.zrows_g, zg, eri_aa, eri_bb, eri_ab, st);
+}
+
+}  // namespace dmet

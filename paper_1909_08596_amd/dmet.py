@@ -26,7 +26,8 @@ STATUS = {0: "DMET_OK", 1: "DMET_E_ARG", 2: "DMET_E_HIP", 3: "DMET_E_NOCONV", 4:
 EXPORTS = ("dmet_last_error", "dmet_version", "dmet_build_bath_workspace", "dmet_build_bath",
            "dmet_transform_1e", "dmet_energy_1e", "dmet_transform_eri_workspace", "dmet_transform_eri",
            "dmet_transform_eri_batched_workspace", "dmet_transform_eri_batched",
-           "dmet_transform_eri_df", "dmet_fock_dc_workspace", "dmet_fock_dc",
+           "dmet_transform_eri_df", "dmet_transform_eri_fftdf_workspace", "dmet_transform_eri_fftdf",
+           "dmet_fock_dc_workspace", "dmet_fock_dc",
            "dmet_profile_enable", "dmet_profile_reset", "dmet_profile_report")
 DMET_BATCH_GRAPH, DMET_BATCH_AUTOTUNE = 1, 2
 
@@ -48,6 +49,18 @@ def lattice(kmesh: Sequence[int], nao: int, naux: int = 1, nspin: int = 1) -> La
         lat.kmesh[d] = int(kmesh[d])
     lat.nao, lat.naux, lat.nspin = int(nao), int(naux), int(nspin)
     return lat
+
+
+class PwGrid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int * 3), ("cell", ctypes.c_double * 3)]
+
+
+def pw_grid(n: Sequence[int], cell: Sequence[float]) -> PwGrid:
+    g = PwGrid()
+    for d in range(3):
+        g.n[d] = int(n[d])
+        g.cell[d] = float(cell[d])
+    return g
 
 
 class Fragment(ctypes.Structure):
@@ -81,6 +94,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dmet_transform_eri_batched_workspace.argtypes = [i, fp, i, ctypes.POINTER(sz)]
     lib.dmet_transform_eri_batched.argtypes = [i, fp, i, ctypes.c_uint, vp, sz, vp]
     lib.dmet_transform_eri_df.argtypes = [lp, i, vp, i, vp, i, vp, vp, sz, vp]
+    gp = ctypes.POINTER(PwGrid)
+    lib.dmet_transform_eri_fftdf_workspace.argtypes = [lp, gp, i, i, ctypes.POINTER(sz)]
+    lib.dmet_transform_eri_fftdf.argtypes = [lp, gp, i, vp, i, vp, vp, vp, vp, vp, sz, vp]
     lib.dmet_fock_dc_workspace.argtypes = [i, i, i, ctypes.POINTER(sz)]
     lib.dmet_fock_dc.argtypes = [i, i, i, vp, vp, vp, vp, vp, sz, vp]
     lib.dmet_profile_enable.argtypes = [i]
@@ -219,6 +235,40 @@ def dmet_transform_eri_impurity(kmesh, nao, naux, lmunu: torch.Tensor, c_k: torc
         raise ValueError("need 1 <= nimp <= neo")
     return dmet_transform_eri(kmesh, nao, naux, lmunu, c_k[..., :nimp].contiguous(), precision, eri_ab=eri_ab,
                               stream=stream)
+
+
+def dmet_transform_eri_fftdf(kmesh, nao, grid_n, cell, rho: torch.Tensor, c_k: torch.Tensor, eri_ab: bool = True,
+                             workspace: Optional[torch.Tensor] = None, stream=None):
+    """Plane-wave (FFTDF) embedding ERIs (App. B, Alg. 2), FP64.  rho is the
+    AO pair density on the cell grid [q][k][r][mu][nu] = (r|mu k, nu k-q),
+    grid_n the grid points per axis and cell the orthorhombic cell lengths
+    (bohr).  Same return value as dmet_transform_eri."""
+    lib = load()
+    if rho.dtype not in (torch.complex128, torch.complex64):
+        raise ValueError("rho must be complex128 or complex64")
+    _dev(rho, rho.dtype, "rho")
+    _dev(c_k, torch.complex128, "c_k")
+    nspin, nk, _, neo = c_k.shape
+    nr = int(grid_n[0]) * int(grid_n[1]) * int(grid_n[2])
+    lat = lattice(kmesh, nao, nr, nspin)
+    grid = pw_grid(grid_n, cell)
+    dt = DMET_C128 if rho.dtype == torch.complex128 else DMET_C64
+    npair = neo * (neo + 1) // 2
+    dev = c_k.device
+    out = {"aa": torch.empty(npair * (npair + 1) // 2, dtype=torch.float64, device=dev)}
+    if nspin == 2:
+        out["bb"] = torch.empty_like(out["aa"])
+        if eri_ab:
+            out["ab"] = torch.empty((npair, npair), dtype=torch.float64, device=dev)
+    if workspace is None:
+        nb = ctypes.c_size_t()
+        _check(lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(grid), neo, dt,
+                                                      ctypes.byref(nb)))
+        workspace = _workspace(nb.value, dev)
+    _check(lib.dmet_transform_eri_fftdf(ctypes.byref(lat), ctypes.byref(grid), neo, _ptr(rho), dt, _ptr(c_k),
+                                        _ptr(out["aa"]), _ptr(out.get("bb")), _ptr(out.get("ab")), _ptr(workspace),
+                                        workspace.numel(), _stream(stream)))
+    return out
 
 
 def dmet_transform_eri_df(kmesh, nao, naux, lmunu: torch.Tensor, c_k: torch.Tensor, precision: str = "fp64",

@@ -85,3 +85,26 @@ def test_bath_argument_validation(lib):
 def test_onebody_argument_validation(lib):
     assert lib.dmet_transform_1e(ctypes.byref(_lat()), 0, None, None, None, None, None) == 1
     assert lib.dmet_energy_1e(3, 4, None, None, None, None) == 1
+
+
+def test_fftdf_argument_validation(lib):
+    """The plane-wave entry points check the grid against naux and the cell on
+    the host (no GPU call)."""
+    from paper_1909_08596_amd import dmet
+    E_ARG = 1   # DMET_E_ARG
+    nb = ctypes.c_size_t()
+    lat = _lat(naux=216)
+    good = dmet.pw_grid((6, 6, 6), (3.0, 3.0, 3.0))
+    assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(good), 16, 0,
+                                                  ctypes.byref(nb)) == 0
+    assert nb.value > 0
+    bad_n = dmet.pw_grid((6, 6, 5), (3.0, 3.0, 3.0))          # 180 points != naux
+    assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(bad_n), 16, 0,
+                                                  ctypes.byref(nb)) == E_ARG
+    bad_c = dmet.pw_grid((6, 6, 6), (3.0, 0.0, 3.0))
+    assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(bad_c), 16, 0,
+                                                  ctypes.byref(nb)) == E_ARG
+    assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), None, 16, 0, ctypes.byref(nb)) == E_ARG
+    # null arrays are rejected before any launch
+    assert lib.dmet_transform_eri_fftdf(ctypes.byref(lat), ctypes.byref(good), 16, None, 0, None, None, None,
+                                        None, None, 0, None) == E_ARG
