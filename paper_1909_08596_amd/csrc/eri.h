@@ -57,6 +57,21 @@ __host__ __device__ inline int kpair_slot_k(const Mesh& m, int q, int slot) {
     return -1;
 }
 
+// Kept k of one q for the paired transform (slot order of kpair_slot_k),
+// passed to kernels by value.
+constexpr int KP_MAX = 256;
+struct KSlots {
+    int npaired, nself;
+    short k[KP_MAX];
+};
+
+inline KSlots kpair_slots(const Mesh& m, int q) {
+    KSlots ks;
+    kpair_counts(m, q, ks.npaired, ks.nself);
+    for (int sl = 0; sl < ks.npaired + ks.nself; ++sl) ks.k[sl] = (short)kpair_slot_k(m, q, sl);
+    return ks;
+}
+
 // the (q, k) blocks of lmunu that the paired transform reads
 __host__ __device__ inline bool kpair_needed(const Mesh& m, int q, int k) {
     return mesh_neg(m, q) >= q && k <= mesh_sub(m, q, k);

@@ -34,12 +34,14 @@ inline int pad4(int n) { return (n + 3) / 4 * 4; }
 // ------------------------------------------------------------------ packing
 // lmunu[qk][L][mu][nu] -> PL[qk][plane][nu (nao_p)][L*nao_p + mu]; 32 rows x 8 nu
 // per workgroup through LDS so both the read and the write are coalesced.
+// Blocks (q, k) that the k <-> q-k paired transform does not read are skipped.
 template <class TIn>
 __global__ void __launch_bounds__(256) k_f32_pack_lmunu(const TIn* __restrict__ lm, int nao, int nao_p, int naux,
-                                                        float* __restrict__ out) {
+                                                        float* __restrict__ out, Mesh mesh) {
     __shared__ float sh[3][8][33];
     const int M1 = naux * nao_p;
     const int row0 = blockIdx.x * 32, nu0 = blockIdx.y * 8, qk = blockIdx.z;
+    if (!kpair_needed(mesh, qk / mesh.nk, qk % mesh.nk)) return;
     const int t = threadIdx.x;
     {
         const int r = t / 8, v = t % 8, row = row0 + r, nu = nu0 + v;
@@ -175,16 +177,18 @@ __device__ inline void f32_loop(const float* pa, size_t pa_st, int XA, int m0, c
 // to T[s][plane][k*nao_p + mu][L*neo_p + j].
 constexpr int S1_BM = 128, S1_BN = 128, S1_BK = 8;
 
+// Only the kept k of the k <-> q-k pairing; T rows slot*nao_p + mu hold k = ks.k[slot].
 __global__ void __launch_bounds__(256) k_f32_xf1(Mesh mesh, int q, int naux, int nao_p, int neo, int neo_p, int nspin,
-                                                 const float* __restrict__ plm, const float* __restrict__ pc1,
-                                                 float* __restrict__ t) {
+                                                 KSlots ks, const float* __restrict__ plm,
+                                                 const float* __restrict__ pc1, float* __restrict__ t) {
     constexpr int BM = S1_BM, BN = S1_BN, BK = S1_BK, TM = 2, TN = 2;
     extern __shared__ __align__(16) float ring[];
     const int nk = mesh.nk, M1 = naux * nao_p, NBp = nspin * neo_p;
     const int nmt = (M1 + BM - 1) / BM, nnt = (NBp + BN - 1) / BN;
     const long logical = xcd_map(blockIdx.x, gridDim.x);
-    if (logical >= (long)nk * nmt * nnt) return;
-    const int k = (int)(logical / ((long)nmt * nnt));
+    if (logical >= (long)(ks.npaired + ks.nself) * nmt * nnt) return;
+    const int slot = (int)(logical / ((long)nmt * nnt));
+    const int k = ks.k[slot];
     const int rem = (int)(logical % ((long)nmt * nnt));
     const int m0 = (rem / nnt) * BM, n0 = (rem % nnt) * BN;
     const int kmq = mesh_sub(mesh, k, q);
@@ -219,7 +223,7 @@ __global__ void __launch_bounds__(256) k_f32_xf1(Mesh mesh, int q, int naux, int
                 const int L = row / nao_p, mu = row % nao_p;
                 const float p1 = acc[0][i][j][r], p2 = acc[1][i][j][r], p3 = acc[2][i][j][r];
                 const float tr = p1 - p2, ti = p3 - p1 - p2;
-                float* o = t + (size_t)s * 3 * plane + ((size_t)k * nao_p + mu) * N2p + (size_t)L * neo_p + jj;
+                float* o = t + (size_t)s * 3 * plane + ((size_t)slot * nao_p + mu) * N2p + (size_t)L * neo_p + jj;
                 o[0] = tr;
                 o[plane] = ti;
                 o[2 * plane] = tr + ti;
@@ -229,10 +233,15 @@ __global__ void __launch_bounds__(256) k_f32_xf1(Mesh mesh, int q, int naux, int
 // ------------------------------------------------------------------ stage 2
 constexpr int S2_BM = 64, S2_BN = 64, S2_BK = 8;
 
-__global__ void __launch_bounds__(256) k_f32_xf2(int naux, int neo, int neo_p, int K2, int self_conj, size_t zrow0,
-                                                 float wq, const float* __restrict__ pc2, const float* __restrict__ t,
-                                                 float* __restrict__ z, size_t ldz) {
+// Stage 2 under the k <-> q-k pairing: pass 1 over the rows (k, mu) of all
+// kept k (A = conj C rows i, B = T columns (L, j)), pass 2 over the paired k
+// with the operands swapped (A = T columns (L, i), B = conj C rows j), which
+// adds the partners' transposed terms.  T rows are compact by slot.
+__global__ void __launch_bounds__(256) k_f32_xf2(int naux, int neo, int neo_p, int nao_p, int K2, KSlots ks,
+                                                 int self_conj, size_t zrow0, float wq, const float* __restrict__ pc2,
+                                                 const float* __restrict__ t, float* __restrict__ z, size_t ldz) {
     constexpr int BM = S2_BM, BN = S2_BN, BK = S2_BK, TM = 1, TN = 1;
+    constexpr int SA = 3 * BK * BM, SB = 3 * BK * BN;
     extern __shared__ __align__(16) float ring[];
     const int njt = (neo + BN - 1) / BN, nit = (neo + BM - 1) / BM;
     const long id = xcd_map(blockIdx.x, gridDim.x);
@@ -250,10 +259,43 @@ __global__ void __launch_bounds__(256) k_f32_xf2(int naux, int neo, int neo_p, i
     for (int p = 0; p < 3; ++p)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[p][0][0][r] = 0.f;
-    // B rows past L's own neo_p columns would belong to L+1: the clamp keeps
-    // them inside the array and the epilogue drops them
-    f32_loop<3, BK, BM, BN, TM, TN>(pc2, (size_t)K2 * neo_p, neo_p, m0, t, (size_t)K2 * N2p, (int)N2p,
-                                    L * neo_p + j0, K2 / BK, ring, wm0, wn0, acc);
+    const int spk = nao_p / BK;                               // stages per k slot
+    const int s1 = (ks.npaired + ks.nself) * spk, nst = s1 + ks.npaired * spk;
+    const size_t cst = (size_t)K2 * neo_p, tst = (size_t)K2 * N2p;
+    // running position: pass, stage within the pass, its slot and row offset
+    int pass = 0, sp = 0, slot = 0, roff = 0;
+    auto issue = [&](float* dst) {
+        if (pass == 0 && sp == s1) {
+            pass = 1;
+            sp = slot = roff = 0;
+        }
+        const int kc = ks.k[slot] * nao_p + roff, kt_ = sp * BK;   // rows of conj C and of T
+        // B columns past L's own neo_p would belong to L+1 (or are clamped at
+        // the end of T): they only reach outputs that are dropped
+        if (!pass) {
+            f32_issue<3, BK, BM>(pc2, cst, neo_p, m0, kc, dst);
+            f32_issue<3, BK, BN>(t, tst, (int)N2p, L * neo_p + j0, kt_, dst + SA);
+        } else {
+            f32_issue<3, BK, BM>(t, tst, (int)N2p, L * neo_p + m0, kt_, dst);
+            f32_issue<3, BK, BN>(pc2, cst, neo_p, j0, kc, dst + SA);
+        }
+        ++sp;
+        roff += BK;
+        if (roff == nao_p) {
+            roff = 0;
+            ++slot;
+        }
+    };
+    issue(ring);
+    for (int st = 0; st < nst; ++st) {
+        float* cur = ring + (size_t)(st & 1) * (SA + SB);
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_sched_barrier(0);
+        if (st + 1 < nst) issue(ring + (size_t)((st + 1) & 1) * (SA + SB));
+        f32_mma<3, BK, BM, BN, TM, TN>(cur, cur + SA, wm0, wn0, acc);
+    }
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int i = m0 + wm0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -464,14 +506,15 @@ dmet_status eri_f32(const EriPlan& p, const void* lmunu, const double* ck, doubl
     float* z = cv.take<float>(d.z);
     if (cv.bytes() > ws_bytes) return fail(DMET_E_WORKSPACE, "transform_eri workspace too small");
     const int nk = p.mesh.nk;
+    if (nk > KP_MAX) return fail(DMET_E_UNSUPPORTED, "FP32-3M transform supports at most 256 k-points");
     {
         ProfScope ps("pack_in_f32", st);
         if (p.dtype == DMET_C128)
             k_f32_pack_lmunu<double><<<dim3((d.M1 + 31) / 32, d.nao_p / 8, nk * nk), 256, 0, st>>>(
-                static_cast<const double*>(lmunu), p.nao, d.nao_p, p.naux, plm);
+                static_cast<const double*>(lmunu), p.nao, d.nao_p, p.naux, plm, p.mesh);
         else
             k_f32_pack_lmunu<float><<<dim3((d.M1 + 31) / 32, d.nao_p / 8, nk * nk), 256, 0, st>>>(
-                static_cast<const float*>(lmunu), p.nao, d.nao_p, p.naux, plm);
+                static_cast<const float*>(lmunu), p.nao, d.nao_p, p.naux, plm, p.mesh);
         k_f32_pack_c1<<<dim3((d.NBp + 255) / 256, d.nao_p, nk), 256, 0, st>>>(ck, nk, p.nspin, p.nao, d.nao_p, p.neo,
                                                                             d.neo_p, pc1);
         k_f32_pack_c2<<<dim3((d.neo_p + 255) / 256, d.K2, p.nspin), 256, 0, st>>>(ck, nk, p.nao, d.nao_p, p.neo,
@@ -489,19 +532,20 @@ dmet_status eri_f32(const EriPlan& p, const void* lmunu, const double* ck, doubl
     const size_t zsp = (size_t)d.rows_p * d.ldz;
     const int njt = (p.neo + S2_BN - 1) / S2_BN, nit = (p.neo + S2_BM - 1) / S2_BM;
     for (const QBlock& qb : p.qblocks) {
-        const long nb1 = ((long)nk * ((d.M1 + S1_BM - 1) / S1_BM) * ((d.NBp + S1_BN - 1) / S1_BN) + NXCD - 1) /
-                         NXCD * NXCD;
+        const KSlots ks = kpair_slots(p.mesh, qb.q);
+        const long nb1 = ((long)(ks.npaired + ks.nself) * ((d.M1 + S1_BM - 1) / S1_BM) *
+                              ((d.NBp + S1_BN - 1) / S1_BN) + NXCD - 1) / NXCD * NXCD;
         ProfScope ps1("xform1_f32", st);
-        k_f32_xf1<<<dim3((unsigned)nb1), 256, lds1, st>>>(p.mesh, qb.q, p.naux, d.nao_p, p.neo, d.neo_p, p.nspin, plm,
-                                                          pc1, t);
+        k_f32_xf1<<<dim3((unsigned)nb1), 256, lds1, st>>>(p.mesh, qb.q, p.naux, d.nao_p, p.neo, d.neo_p, p.nspin, ks,
+                                                          plm, pc1, t);
         ps1.stop();
         DMET_LAUNCH_CHECK("xform1_f32");
         for (int s = 0; s < p.nspin; ++s) {
             const long nb2 = ((long)p.naux * njt * nit + NXCD - 1) / NXCD * NXCD;
             ProfScope ps2("xform2_f32", st);
-            k_f32_xf2<<<dim3((unsigned)nb2), 256, lds2, st>>>(p.naux, p.neo, d.neo_p, d.K2, qb.self_conj, qb.zrow0,
-                                                              (float)qb.weight, pc2 + s * c2sp, t + s * tsp,
-                                                              z + s * zsp, (size_t)d.ldz);
+            k_f32_xf2<<<dim3((unsigned)nb2), 256, lds2, st>>>(p.naux, p.neo, d.neo_p, d.nao_p, d.K2, ks, qb.self_conj,
+                                                              qb.zrow0, (float)qb.weight, pc2 + s * c2sp,
+                                                              t + s * tsp, z + s * zsp, (size_t)d.ldz);
             ps2.stop();
             DMET_LAUNCH_CHECK("xform2_f32");
         }

@@ -569,13 +569,6 @@ __global__ void k_pack_c2(const double* __restrict__ ck, int nk, int nao, int na
                 part[p][t];
 }
 
-// Kept k of one q for the paired transform (see kpair_counts), by value.
-constexpr int KP_MAX = 256;
-struct KSlots {
-    int npaired, nself;
-    short k[KP_MAX];
-};
-
 // One stage of a packed operand (3 planes x NS parts x 2 groups x ROWS rows)
 // from two explicit groups g0, g1 (a zero group pads an odd count).
 template <int NS, int ROWS>
@@ -1274,9 +1267,7 @@ static dmet_status xform_packed(const EriPlan& p, const void* lmunu, const doubl
     const size_t t_spin = (size_t)3 * NS * d.ng2 * d.N2 * 8;
     const size_t c2_spin = (size_t)3 * NS * d.ng2 * p.neo * 8;
     for (const QBlock& qb : p.qblocks) {
-        KSlots ks;
-        kpair_counts(p.mesh, qb.q, ks.npaired, ks.nself);
-        for (int sl = 0; sl < ks.npaired + ks.nself; ++sl) ks.k[sl] = (short)kpair_slot_k(p.mesh, qb.q, sl);
+        const KSlots ks = kpair_slots(p.mesh, qb.q);
         ProfScope ps1(n1, st);
         const long nb1 = ((long)(ks.npaired + ks.nself) * ((d.M1 + 127) / 128) * ((d.NB + 127) / 128) + NXCD - 1) /
                          NXCD * NXCD;
@@ -1677,9 +1668,7 @@ static dmet_status batch_enqueue(BatchPlan& bp, int variant, bool prof, hipStrea
         ps = scope(NS == 3 ? "batch_xform1_bf16x6" : "batch_xform1_bf16x3");
         for (auto& G : bp.groups) {
             if (r >= (int)G.qbs.size()) continue;
-            KSlots ks;
-            kpair_counts(G.mesh, G.qbs[r].q, ks.npaired, ks.nself);
-            for (int sl = 0; sl < ks.npaired + ks.nself; ++sl) ks.k[sl] = (short)kpair_slot_k(G.mesh, G.qbs[r].q, sl);
+            const KSlots ks = kpair_slots(G.mesh, G.qbs[r].q);
             const long nb = ((long)(ks.npaired + ks.nself) * ((G.M1 + 127) / 128) * ((G.nbtot + 127) / 128) + NXCD - 1) /
                             NXCD * NXCD;
             k1<<<dim3((unsigned)nb), 256, xf1_lds<NS>(), st>>>(G.mesh, G.qbs[r].q, G.naux, G.nao_p, G.nbtot, G.ngv, ks,

@@ -358,25 +358,26 @@ def synth_cells(kmesh):
     return synth.cells(kmesh)
 
 
+@pytest.mark.parametrize("prec", ["bf16x6", "fp32"])
 @pytest.mark.parametrize("key", ["odd", "hbn"])
-def test_paired_transform_reads_half_the_input(dmet, key):
-    """The split-bf16 transform pairs k with q - k (time reversal and the
-    Hermiticity of the 3-index tensor): the blocks it does not read may hold
-    anything.  Filled with NaN, the ERIs come out bit for bit the same, for the
-    single call and for the batched form."""
+def test_paired_transform_reads_half_the_input(dmet, key, prec):
+    """The split-bf16 and FP32-3M transforms pair k with q - k (time reversal
+    and the Hermiticity of the 3-index tensor): the blocks they do not read may
+    hold anything.  Filled with NaN, the ERIs come out bit for bit the same, for
+    the single call and for the batched form."""
     wl, lat, lm, bath = case(**CASES[key])
     ck = to_dev(bath["c_k"])
     unread = _unread_blocks(wl.kmesh)
     assert 0.45 * wl.nk ** 2 < len(unread) < 0.8 * wl.nk ** 2
-    ref = dmet.dmet_transform_eri(wl.kmesh, wl.nao, wl.naux, to_dev(lm), ck, "bf16x6")["aa"].clone()
+    ref = dmet.dmet_transform_eri(wl.kmesh, wl.nao, wl.naux, to_dev(lm), ck, prec)["aa"].clone()
     lm_nan = lm.copy()
     for q, k in unread:
         lm_nan[q, k] = np.nan
     lm_d = to_dev(lm_nan)
-    got = dmet.dmet_transform_eri(wl.kmesh, wl.nao, wl.naux, lm_d, ck, "bf16x6")["aa"]
+    got = dmet.dmet_transform_eri(wl.kmesh, wl.nao, wl.naux, lm_d, ck, prec)["aa"]
     torch.cuda.synchronize()
     assert torch.equal(ref, got)
     spec = [{"kmesh": wl.kmesh, "nao": wl.nao, "naux": wl.naux, "lmunu": lm_d, "c_k": ck[0].contiguous()}]
-    bat = dmet.dmet_transform_eri_batched(spec, "bf16x6")[0]
+    bat = dmet.dmet_transform_eri_batched(spec, prec)[0]
     torch.cuda.synchronize()
     assert torch.equal(ref, bat)
