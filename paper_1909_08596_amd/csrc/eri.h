@@ -87,9 +87,12 @@ size_t eri_lp_workspace(const EriPlan& p);
 dmet_status eri_lp(const EriPlan& p, const void* lmunu, const double* ck, double* eri_aa, double* eri_bb,
                    double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st, double* df_out = nullptr);
 
-// (ij|kl) = sum_rows z_s[row][ij] z_t[row][kl] in FP64 for z [nspin][krows][npair]
-dmet_status contract_f64(int nspin, int npair, int krows, const double* z, double* eri_aa, double* eri_bb,
-                         double* eri_ab, hipStream_t st);
+// (ij|kl) = sum_rows z_s[row][ij] z_t[row][kl] in FP64 for z [nspin][krows_p][ldz]
+// (ldz even, krows_p a multiple of 16 with zero rows past the data); `part`
+// holds contract_f64_workspace() doubles for the split-K partials.
+size_t contract_f64_workspace(int nspin, int npair, int krows_p);
+dmet_status contract_f64(int nspin, int npair, int ldz, int krows_p, const double* z, double* eri_aa,
+                         double* eri_bb, double* eri_ab, double* part, hipStream_t st);
 
 size_t eri_f32_workspace(const EriPlan& p);
 dmet_status eri_f32(const EriPlan& p, const void* lmunu, const double* ck, double* eri_aa, double* eri_bb,

@@ -108,17 +108,21 @@ __global__ void __launch_bounds__(256) k_pw_axis(PwAxis ax, int npair, const dou
 }
 
 struct PwDims {
-    size_t nr, zrows_g, eri_ws, zr, buf, zg;
+    size_t nr, eri_ws, zr, buf, zg, part;
+    int zrows_g, krows_p, ldz;
 };
 
 PwDims pw_dims(const EriPlan& p) {
     PwDims d;
     d.nr = (size_t)p.naux;
-    d.zrows_g = 2 * d.nr * p.qblocks.size();
+    d.zrows_g = (int)(2 * d.nr * p.qblocks.size());
+    d.krows_p = (d.zrows_g + 15) / 16 * 16;
+    d.ldz = (p.npair + 1) / 2 * 2;
     d.eri_ws = eri_f64_workspace(p);
     d.zr = (size_t)p.nspin * p.zrows * p.npair;
     d.buf = d.nr * p.npair;
-    d.zg = (size_t)p.nspin * d.zrows_g * p.npair;
+    d.zg = (size_t)p.nspin * d.krows_p * d.ldz;
+    d.part = contract_f64_workspace(p.nspin, p.npair, d.krows_p);
     return d;
 }
 
@@ -132,6 +136,7 @@ size_t fftdf_workspace(const EriPlan& p) {
     cv.take<double2>(d.buf);
     cv.take<double2>(d.buf);
     cv.take<double>(d.zg);
+    cv.take<double>(d.part);
     return cv.bytes();
 }
 
@@ -144,6 +149,7 @@ dmet_status fftdf_eri(const EriPlan& p, const dmet_pw_grid* grid, const void* rh
     double2* b1 = cv.take<double2>(d.buf);
     double2* b2 = cv.take<double2>(d.buf);
     double* zg = cv.take<double>(d.zg);
+    double* part = cv.take<double>(d.part);
     if (cv.bytes() > ws_bytes) return fail(DMET_E_WORKSPACE, "fftdf workspace too small");
     for (int a = 0; a < 3; ++a)
         if (grid->n[a] > PW_MAXN) return fail(DMET_E_UNSUPPORTED, "fftdf: at most 64 grid points per axis");
@@ -162,7 +168,9 @@ dmet_status fftdf_eri(const EriPlan& p, const dmet_pw_grid* grid, const void* rh
     const unsigned nb = (unsigned)std::min<long>((total + 255) / 256, 65535L * 4);
     for (int sp = 0; sp < p.nspin; ++sp) {
         const double* zs = zr + (size_t)sp * p.zrows * p.npair;
-        double* zgs = zg + (size_t)sp * d.zrows_g * p.npair;
+        double* zgs = zg + (size_t)sp * d.krows_p * d.ldz;
+        if (d.krows_p > d.zrows_g)   // zero rows up to a multiple of 16 for the contraction
+            fill_zero(zgs + (size_t)d.zrows_g * d.ldz, (size_t)(d.krows_p - d.zrows_g) * d.ldz * sizeof(double), st);
         for (size_t b = 0; b < p.qblocks.size(); ++b) {
             const QBlock& qb = p.qblocks[b];
             const int q2 = qb.q % p.mesh.n[2], q1 = (qb.q / p.mesh.n[2]) % p.mesh.n[1],
@@ -189,13 +197,13 @@ dmet_status fftdf_eri(const EriPlan& p, const dmet_pw_grid* grid, const void* rh
             ax.axis = 2;
             ax.nmesh = p.mesh.n[2];
             ax.m = m[2];
-            k_pw_axis<0, 1><<<nb, 256, lds(2), st>>>(ax, p.npair, b2, nullptr, 0, p.npair, nullptr, zgs, 2 * d.nr * b,
+            k_pw_axis<0, 1><<<nb, 256, lds(2), st>>>(ax, p.npair, b2, nullptr, 0, d.ldz, nullptr, zgs, 2 * d.nr * b,
                                                      ks);
             ps.stop();
             DMET_LAUNCH_CHECK("k_pw_axis");
         }
     }
-    return contract_f64(p.nspin, p.npair, (int)d.zrows_g, zg, eri_aa, eri_bb, eri_ab, st);
+    return contract_f64(p.nspin, p.npair, d.ldz, d.krows_p, zg, eri_aa, eri_bb, eri_ab, part, st);
 }
 
 }  // namespace dmet
