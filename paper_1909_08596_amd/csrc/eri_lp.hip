@@ -27,6 +27,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <type_traits>
 
 #include <vector>
 
@@ -293,42 +294,53 @@ __global__ void __launch_bounds__(512) k_contract_w8(int npair, int kgroups, con
     constexpr int TM = 2, TN = 2;
     constexpr int PA = G * BM, PB = G * BN;      // 16-byte chunks of one part of A / B per stage
     constexpr int STAGE = NS * (PA + PB);
-    static_assert(PB % 512 == 0 && (PA % 512 == 0 || PA == 256), "chunk split over 8 waves");
-    // loads per thread per stage (waves 4-7 stage no A when a part of A has 256 chunks)
-    constexpr int LOADS_HI = NS * ((PA + 511) / 512 + PB / 512), LOADS_LO = NS * (PA / 512 + PB / 512);
+    // every wave stages PA / 8 chunks of each part of A (with that many lanes)
+    // and PB / 8 of B, so all waves wait on the same load count
+    constexpr int CA = PA / 8, NLB = PB / 512;
+    static_assert(CA == 32 || CA == 64, "A chunks per wave");
+    static_assert(PB % 512 == 0, "B chunks per wave");
+    constexpr int LOADS = NS * (1 + NLB);        // load instructions per thread per stage
     extern __shared__ __align__(16) bf8 ring[];
     int mt, nt;
     const long logical = xcd_logical(blockIdx.x, nblocks);
     const int ntm = (npair + BM - 1) / BM, ntn = (npair + BN - 1) / BN;
     if (!w8_tile_of<MODE>(logical, ntm, ntn, mt, nt)) return;
     const int m0 = mt * BM, n0 = nt * BN;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: scalar registers
     const int wm0 = (wave >> 2) * 64, wn0 = (wave & 3) * 64;
-    const bool hi = wave * 64 < PA % 512 || PA % 512 == 0;
     const size_t plane = (size_t)kgroups * npair;
     const int nkt = kgroups / G;
-
-    auto issue = [&](int kt) {
+    // this lane's byte offset within its rows (fixed over stages) and the
+    // wave-uniform row pointers of the next stage to issue
+    const int fa = wave * CA;
+    const unsigned offa = (unsigned)min(m0 + fa % BM + (lane & (CA - 1)), npair - 1) * 16u;
+    unsigned offb[NLB];
+    const char* rowa[NS];
+    const char* rowb[NS][NLB];
+#pragma unroll
+    for (int h = 0; h < NLB; ++h) offb[h] = (unsigned)min(n0 + (h * 512 + wave * 64) % BN + lane, npair - 1) * 16u;
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        rowa[t] = (const char*)pa + (t * plane + (size_t)(fa / BM) * npair) * 16;
+#pragma unroll
+        for (int h = 0; h < NLB; ++h)
+            rowb[t][h] = (const char*)pb + (t * plane + (size_t)((h * 512 + wave * 64) / BN) * npair) * 16;
+    }
+    const size_t stage_bytes = (size_t)G * npair * 16;
+    auto issue = [&](int kt) {   // stages are issued in increasing order
         bf8* st = ring + (size_t)(kt % NBUF) * STAGE;
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
+            if (CA == 64 || lane < CA)
+                __builtin_amdgcn_global_load_lds((const void*)(rowa[t] + offa), DMET_LDS_PTR(st + t * PA + fa), 16,
+                                                 0, 0);
+            rowa[t] += stage_bytes;
 #pragma unroll
-            for (int f0 = 0; f0 < PA; f0 += 512) {
-                const int f = f0 + wave * 64;
-                if (f < PA) {
-                    const size_t ga = (size_t)kt * G + f / BM;
-                    const int xa = min(m0 + f % BM + lane, npair - 1);
-                    __builtin_amdgcn_global_load_lds((const void*)(pa + (t * plane + ga * npair + xa) * 8),
-                                                     DMET_LDS_PTR(st + t * PA + f), 16, 0, 0);
-                }
-            }
-#pragma unroll
-            for (int f0 = 0; f0 < PB; f0 += 512) {
-                const int f = f0 + wave * 64;
-                const size_t gb = (size_t)kt * G + f / BN;
-                const int xb = min(n0 + f % BN + lane, npair - 1);
-                __builtin_amdgcn_global_load_lds((const void*)(pb + (t * plane + gb * npair + xb) * 8),
-                                                 DMET_LDS_PTR(st + NS * PA + t * PB + f), 16, 0, 0);
+            for (int h = 0; h < NLB; ++h) {
+                __builtin_amdgcn_global_load_lds((const void*)(rowb[t][h] + offb[h]),
+                                                 DMET_LDS_PTR(st + NS * PA + t * PB + h * 512 + wave * 64), 16, 0, 0);
+                rowb[t][h] += stage_bytes;
             }
         }
     };
@@ -348,20 +360,13 @@ __global__ void __launch_bounds__(512) k_contract_w8(int npair, int kgroups, con
     for (int s2 = 0; s2 < NBUF - 1; ++s2)
         if (s2 < nkt) issue(s2);
     int since = 0;
-    for (int kt = 0; kt < nkt; ++kt) {
-        // stage kt has landed when only the loads of the younger stages in
-        // flight (at most NBUF - 2 of them) remain
-        const int younger = min(NBUF - 2, nkt - 1 - kt);
+    // one stage: wait (vmcnt immediate YOUNGER * LOADS: the loads of the
+    // younger stages in flight may stay outstanding), barrier, issue, multiply
+    auto stage = [&](int kt, auto younger_c) {
+        constexpr int YOUNGER = decltype(younger_c)::value;
+        constexpr int VM = YOUNGER * LOADS;
         __builtin_amdgcn_sched_barrier(0);
-        if (hi) {
-            if (younger >= 2) __builtin_amdgcn_s_waitcnt(0x0F70 | ((2 * LOADS_HI) & 15) | (((2 * LOADS_HI) >> 4) << 14));
-            else if (younger == 1) __builtin_amdgcn_s_waitcnt(0x0F70 | (LOADS_HI & 15) | ((LOADS_HI >> 4) << 14));
-            else __builtin_amdgcn_s_waitcnt(0x0F70);
-        } else {
-            if (younger >= 2) __builtin_amdgcn_s_waitcnt(0x0F70 | ((2 * LOADS_LO) & 15) | (((2 * LOADS_LO) >> 4) << 14));
-            else if (younger == 1) __builtin_amdgcn_s_waitcnt(0x0F70 | (LOADS_LO & 15) | ((LOADS_LO >> 4) << 14));
-            else __builtin_amdgcn_s_waitcnt(0x0F70);
-        }
+        __builtin_amdgcn_s_waitcnt(0x0F70 | (VM & 15) | ((VM >> 4) << 14));
         __builtin_amdgcn_s_barrier();
         __builtin_amdgcn_sched_barrier(0);
         if (kt + NBUF - 1 < nkt) issue(kt + NBUF - 1);
@@ -377,17 +382,12 @@ __global__ void __launch_bounds__(512) k_contract_w8(int npair, int kgroups, con
                 for (int j = 0; j < TN; ++j) b[t][j] = sB[t * PB + g * BN + wn0 + j * 32 + (lane & 31)];
             // parts of A outermost and both row tiles per part, so that four
             // independent accumulators separate two MFMAs on the same one (the
-            // order of the products per output element is unchanged); the A
-            // fragments of the next part are read before the current MFMAs
-            bf8 a[TM], an[TM];
-#pragma unroll
-            for (int i = 0; i < TM; ++i) a[i] = sA[(NS - 1) * PA + g * BM + wm0 + i * 32 + (lane & 31)];
+            // order of the products per output element is unchanged)
 #pragma unroll
             for (int ta = NS - 1; ta >= 0; --ta) {
-                if (ta > 0) {
+                bf8 a[TM];
 #pragma unroll
-                    for (int i = 0; i < TM; ++i) an[i] = sA[(ta - 1) * PA + g * BM + wm0 + i * 32 + (lane & 31)];
-                }
+                for (int i = 0; i < TM; ++i) a[i] = sA[ta * PA + g * BM + wm0 + i * 32 + (lane & 31)];
 #pragma unroll
                 for (int tb = NS - 1 - ta; tb >= 0; --tb)
 #pragma unroll
@@ -405,10 +405,6 @@ __global__ void __launch_bounds__(512) k_contract_w8(int npair, int kgroups, con
                             for (int j = 0; j < TN; ++j)
                                 acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[1][j], acc[i][j], 0, 0, 0);
                 }
-                if (ta > 0) {
-#pragma unroll
-                    for (int i = 0; i < TM; ++i) a[i] = an[i];
-                }
             }
             since += 16;
             if (since >= flush_k || (kt + 1 == nkt && ks + 2 >= G)) {
@@ -424,7 +420,17 @@ __global__ void __launch_bounds__(512) k_contract_w8(int npair, int kgroups, con
                 since = 0;
             }
         }
+    };
+    // steady state with NBUF - 2 younger stages in flight, then the tail
+    int kt = 0;
+    for (; kt + NBUF - 2 < nkt; ++kt) stage(kt, std::integral_constant<int, NBUF - 2>{});
+    if constexpr (NBUF >= 4) {
+        if (kt + 1 < nkt) {
+            stage(kt, std::integral_constant<int, 1>{});
+            ++kt;
+        }
     }
+    for (; kt < nkt; ++kt) stage(kt, std::integral_constant<int, 0>{});
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
