@@ -125,6 +125,25 @@ inline long tile_grid(int ntile) {
 // matrix edge are clamped to the last row: they only feed output rows /
 // columns that are not stored.
 #define DMET_LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
+// Word 3 of a raw buffer resource (32-bit dwords, no swizzle, range-checked)
+#define DMET_RSRC_WORD3 0x00020000
+
+// A pointer that is the same in every lane, moved to scalar registers.
+__device__ inline const void* wave_uniform(const void* p) {
+    const unsigned long long v = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return (const void*)(((unsigned long long)hi << 32) | lo);
+}
+
+// Direct load of this lane's 16 bytes at byte offset off of a row (the same
+// in every lane, nbytes long) into LDS at dst + 16 * lane.  The buffer form
+// bounds the load by the row and keeps the compiler's LDS waits exact.
+__device__ inline void lds_dma16(const void* row, unsigned nbytes, unsigned off, void* dst) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(wave_uniform(row)), (short)0, (int)nbytes, DMET_RSRC_WORD3),
+        DMET_LDS_PTR(dst), 16, (int)off, 0, 0, 0);
+}
 
 // Variant sized for two workgroups per CU: 16-deep stages (72 KB ring for the
 // three-way split), at most 256 registers per lane (B fragments of a stage are
@@ -248,6 +267,13 @@ k_contract_d2(int npair, int kgroups, const __bf16* __restrict__ pa, const __bf1
             }
 }
 
+// One scheduling section: nr LDS reads issued first, then nm MFMAs; nothing is
+// moved across its end
+#define DMET_SECTION(nr, nm)                                 \
+    __builtin_amdgcn_sched_group_barrier(0x100, nr, 0);      \
+    __builtin_amdgcn_sched_group_barrier(0x008, nm, 0);      \
+    __builtin_amdgcn_sched_barrier(0)
+
 // Tile order of k_contract_w8 (128 x 256 tiles): super-blocks of 8 x 4 tiles
 // (1024 x 1024 outputs), lower-triangular order of super-blocks for s8.  A
 // tile is kept for s8 if it holds any KL <= IJ.
@@ -282,10 +308,13 @@ inline long w8_grid(int mode, int npair) {
 
 // Variant with 128 x 256 output tiles: 8 waves as 2 x 4, wave tile 64 x 64
 // with FP64 flush registers as in k_contract_d2, one workgroup per CU and a
-// 4-stage ring (36 KB stages for the three-way split).  Against two 128 x 128
-// workgroups per CU it moves 25% fewer operand bytes per flop, and the two
-// column halves that share the A panel run in step by construction.  Waves
-// 0-3 stage A and B, waves 4-7 only B, so their vmcnt budgets differ.
+// ring of G-group stages in LDS (three-way split: two 72 KB stages of 32 rows;
+// two-way: three 48 KB stages).  Against two 128 x 128 workgroups per CU it
+// moves 25% fewer operand bytes per flop, and the two column halves that share
+// the A panel run in step by construction.  Operands are staged with buffer
+// loads straight into LDS: each buffer resource spans one row group of one
+// part, so the hardware range check bounds every load, and (unlike the FLAT
+// form) the compiler keeps exact lgkmcnt waits for the LDS reads behind them.
 template <int NS, int MODE, int G, int NBUF>
 __global__ void __launch_bounds__(512) k_contract_w8(int npair, int kgroups, const __bf16* __restrict__ pa,
                                                      const __bf16* __restrict__ pb, int flush_k, long nblocks,
@@ -333,13 +362,15 @@ __global__ void __launch_bounds__(512) k_contract_w8(int npair, int kgroups, con
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
             if (CA == 64 || lane < CA)
-                __builtin_amdgcn_global_load_lds((const void*)(rowa[t] + offa), DMET_LDS_PTR(st + t * PA + fa), 16,
-                                                 0, 0);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    __builtin_amdgcn_make_buffer_rsrc((void*)rowa[t], (short)0, npair * 16, DMET_RSRC_WORD3),
+                    DMET_LDS_PTR(st + t * PA + fa), 16, (int)offa, 0, 0, 0);
             rowa[t] += stage_bytes;
 #pragma unroll
             for (int h = 0; h < NLB; ++h) {
-                __builtin_amdgcn_global_load_lds((const void*)(rowb[t][h] + offb[h]),
-                                                 DMET_LDS_PTR(st + NS * PA + t * PB + h * 512 + wave * 64), 16, 0, 0);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    __builtin_amdgcn_make_buffer_rsrc((void*)rowb[t][h], (short)0, npair * 16, DMET_RSRC_WORD3),
+                    DMET_LDS_PTR(st + NS * PA + t * PB + h * 512 + wave * 64), 16, (int)offb[h], 0, 0, 0);
                 rowb[t][h] += stage_bytes;
             }
         }
@@ -372,6 +403,80 @@ __global__ void __launch_bounds__(512) k_contract_w8(int npair, int kgroups, con
         if (kt + NBUF - 1 < nkt) issue(kt + NBUF - 1);
         const bf8* sA = ring + (size_t)(kt % NBUF) * STAGE;
         const bf8* sB = sA + NS * PA;
+        if constexpr (NS == 3 && G == 4) {
+            // two k-steps, software-pipelined: every LDS read is issued four to
+            // twelve MFMAs ahead of its first use and at most ten fragments are
+            // live; the products of each step keep the order of the generic
+            // loop below (smallest first), so the sums are the same bits
+            const int g0 = lane >> 5, g1 = 2 + (lane >> 5);
+            auto rdA = [&](bf8 (&r)[2], int t, int g) {
+                r[0] = sA[t * PA + g * BM + wm0 + (lane & 31)];
+                r[1] = sA[t * PA + g * BM + wm0 + 32 + (lane & 31)];
+            };
+            auto rdB = [&](bf8 (&r)[2], int t, int g) {
+                r[0] = sB[t * PB + g * BN + wn0 + (lane & 31)];
+                r[1] = sB[t * PB + g * BN + wn0 + 32 + (lane & 31)];
+            };
+            auto mm = [&](const bf8 (&a)[2], const bf8 (&b)[2]) {
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+            };
+            auto flush = [&](bool last) {
+                since += 16;
+                if (since >= flush_k || last) {
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j)
+#pragma unroll
+                            for (int r = 0; r < 16; ++r) {
+                                acc64[i][j][r] += (double)acc[i][j][r];
+                                acc[i][j][r] = 0.f;
+                            }
+                    since = 0;
+                }
+            };
+            // parts of the first step (a, b) and of the second (c, d)
+            bf8 a2[2], a1[2], a0[2], b0[2], b1[2], b2[2];
+            bf8 c2[2], c1[2], c0[2], d0[2], d1[2], d2[2];
+            rdA(a2, 2, g0); rdB(b0, 0, g0);
+            DMET_SECTION(4, 0);
+            rdA(a1, 1, g0); rdB(b1, 1, g0);
+            DMET_SECTION(4, 0);
+            mm(a2, b0);
+            DMET_SECTION(0, 4);
+            rdA(a0, 0, g0); rdB(b2, 2, g0);
+            mm(a1, b1);
+            mm(a1, b0);
+            DMET_SECTION(4, 8);
+            rdA(c2, 2, g1);
+            mm(a0, b2);
+            DMET_SECTION(2, 4);
+            rdB(d0, 0, g1);
+            mm(a0, b1);
+            DMET_SECTION(2, 4);
+            rdA(c1, 1, g1);
+            mm(a0, b0);
+            DMET_SECTION(2, 4);
+            rdB(d1, 1, g1); rdA(c0, 0, g1);
+            DMET_SECTION(4, 0);
+            flush(false);
+            __builtin_amdgcn_sched_barrier(0);
+            mm(c2, d0);
+            DMET_SECTION(0, 4);
+            rdB(d2, 2, g1);
+            mm(c1, d1);
+            mm(c1, d0);
+            DMET_SECTION(2, 8);
+            mm(c0, d2);
+            mm(c0, d1);
+            mm(c0, d0);
+            DMET_SECTION(0, 12);
+            flush(kt + 1 == nkt);
+        } else {
 #pragma unroll
         for (int ks = 0; ks < G; ks += 2) {
             const int g = ks + (lane >> 5);
@@ -420,7 +525,11 @@ __global__ void __launch_bounds__(512) k_contract_w8(int npair, int kgroups, con
                 since = 0;
             }
         }
+        }
     };
+    // a kernel-argument load still in flight would make the first LDS wait of
+    // every stage a full one
+    __builtin_amdgcn_s_waitcnt(0xC07F);
     // steady state with NBUF - 2 younger stages in flight, then the tail
     int kt = 0;
     for (; kt + NBUF - 2 < nkt; ++kt) stage(kt, std::integral_constant<int, NBUF - 2>{});
@@ -1056,9 +1165,10 @@ k_contract_persist(const int* __restrict__ qstart, const int* __restrict__ qlen,
     extern __shared__ __align__(16) bf8 ring[];
     __shared__ int s_item;
     const int xcd = blockIdx.x % NXCD;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
     const int g = lane >> 5;
+    static_assert(BM % 64 == 0, "a wave's 64 chunks lie in one row group");
     for (;;) {
         __syncthreads();
         if (tid == 0) s_item = atomicAdd(&qctr[xcd], 1);
@@ -1079,10 +1189,9 @@ k_contract_persist(const int* __restrict__ qstart, const int* __restrict__ qlen,
                 const int t = first / PART, w = first % PART, gg = w / BM, row0 = w % BM;
                 const size_t grp = (size_t)kt * G + gg;
                 const int xa = min(m0 + row0 + lane, npair - 1), xb = min(n0 + row0 + lane, npair - 1);
-                __builtin_amdgcn_global_load_lds((const void*)(pa + (t * plane + grp * npair + xa) * 8),
-                                                 DMET_LDS_PTR(st + first), 16, 0, 0);
-                __builtin_amdgcn_global_load_lds((const void*)(pa + (t * plane + grp * npair + xb) * 8),
-                                                 DMET_LDS_PTR(st + NS * PART + first), 16, 0, 0);
+                const __bf16* row = pa + (t * plane + grp * npair) * 8;
+                lds_dma16(row, (unsigned)npair * 16u, (unsigned)xa * 16u, st + first);
+                lds_dma16(row, (unsigned)npair * 16u, (unsigned)xb * 16u, st + NS * PART + first);
             }
         };
 
@@ -1099,6 +1208,7 @@ k_contract_persist(const int* __restrict__ qstart, const int* __restrict__ qlen,
                 }
         for (int s2 = 0; s2 < NBUF - 1; ++s2)
             if (s2 < nkt) issue(s2);
+        __builtin_amdgcn_s_waitcnt(0xC07F);   // no scalar load in flight at the loop head
         int since = 0;
         for (int kt = 0; kt < nkt; ++kt) {
             // with NBUF = 3 the loads of one younger stage may stay in flight; every
@@ -1325,8 +1435,8 @@ static dmet_status eri_lp_run(const EriPlan& p, const void* lmunu, const double*
     }
     const int variant = contract_variant();
     if (variant == 3) {
-        // three-way split: 16-row stages, 4-deep ring; two-way: 32-row stages, 3-deep
-        constexpr int G = NS == 3 ? 2 : 4, NB = NS == 3 ? 4 : 3;
+        // 32-row stages; three-way split: 2-deep ring, two-way: 3-deep
+        constexpr int G = 4, NB = NS == 3 ? 2 : 3;
         auto kw0 = k_contract_w8<NS, 0, G, NB>;
         auto kw1 = k_contract_w8<NS, 1, G, NB>;
         constexpr size_t lds = w8_lds<NS, G, NB>();
