@@ -119,11 +119,12 @@ inline long tile_grid(int ntile) {
 }
 
 // Contraction on packed bf16 parts.  Operand tiles move by direct
-// global->LDS loads (global_load_lds_dwordx4: lane l of a wave writes its 16
-// bytes at the wave's LDS base + 16 l) into a ring of stages, so that the tiles
-// of the next stages are in flight while one is multiplied.  Rows past the
-// matrix edge are clamped to the last row: they only feed output rows /
-// columns that are not stored.
+// global->LDS loads (lane l of a wave writes its 16 bytes at the wave's LDS
+// base + 16 l; FLAT global_load_lds_dwordx4 or, where exact LDS waits matter,
+// buffer_load_dwordx4 ... lds) into a ring of stages, so that the tiles of the
+// next stages are in flight while one is multiplied.  Rows past the matrix
+// edge are clamped to the last row: they only feed output rows / columns that
+// are not stored.
 #define DMET_LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
 // Word 3 of a raw buffer resource (32-bit dwords, no swizzle, range-checked)
 #define DMET_RSRC_WORD3 0x00020000
@@ -572,44 +573,83 @@ constexpr size_t d2_lds() { return (size_t)3 * 2 * NS * 2 * 128 * 16; }
 // contraction index is padded to an even number (a zero group) so that a
 // stage always holds two groups (16 contraction indices).
 
+inline size_t pack_lds_bytes(int mb, int ngv) { return (size_t)mb * (8 * ngv + 1) * sizeof(float2); }
+
 // lmunu[q][k][L][mu][nu] -> P1[q][k][plane][part][nu/8][L*nao_p + mu][8]
 // With only_needed, blocks (q, k) that the k <-> q-k paired transform never
-// reads are skipped (their input is not touched).
+// reads are skipped (their input is not touched).  One workgroup takes `mb`
+// rows mu of one (q, k, L): the rows are one contiguous run of the input, read
+// with consecutive lanes on consecutive elements, and staged as float pairs in
+// LDS (8 ngv columns, row stride 8 ngv + 1); each thread then packs one
+// 8-column chunk of one row.  Padding rows (up to nao_p) and columns (up to
+// 8 ngv) are written as zeros.
+inline int pack_rows_per_block(int ngv) {
+    int mb = 32;
+    while (mb > 1 && pack_lds_bytes(mb, ngv) > 48 * 1024) mb /= 2;
+    return mb;
+}
+
 template <int NS, class TIn>
-__global__ void k_pack_lmunu(const TIn* __restrict__ lm, int nao, int nao_p, int naux, int ngv,
-                             __bf16* __restrict__ out, Mesh mesh, int only_needed) {
-    const int M1 = naux * nao_p;
-    const int row = blockIdx.x * blockDim.x + threadIdx.x;
-    const int g = blockIdx.y, qk = blockIdx.z;
-    if (row >= M1) return;
+__global__ void __launch_bounds__(256) k_pack_lmunu(const TIn* __restrict__ lm, int nao, int nao_p, int naux,
+                                                    int ngv, int mb, __bf16* __restrict__ out, Mesh mesh,
+                                                    int only_needed) {
+    extern __shared__ float2 tile[];   // [mb][8 ngv + 1]
+    const int W = 8 * ngv, ld = W + 1;
+    const int nmb = (nao_p + mb - 1) / mb;
+    const long b = blockIdx.x;
+    const int blk = (int)(b % nmb), L = (int)((b / nmb) % naux), qk = (int)(b / ((long)nmb * naux));
     if (only_needed && !kpair_needed(mesh, qk / mesh.nk, qk % mesh.nk)) return;
-    const int L = row / nao_p, mu = row % nao_p;
-    bf8 part[3][NS];
-    const TIn* src = lm + (((size_t)qk * naux + L) * nao + mu) * (size_t)nao * 2;
-#pragma unroll
-    for (int v = 0; v < 8; ++v) {
-        const int nu = 8 * g + v;
-        float re = 0.f, im = 0.f;
-        if (mu < nao && nu < nao) {
-            re = (float)src[2 * nu];
-            im = (float)src[2 * nu + 1];
+    const int mu0 = blk * mb;
+    const int rows = min(mb, nao_p - mu0);          // rows of this block (padding rows included)
+    const int live = max(0, min(rows, nao - mu0));  // rows that exist in the input
+    const TIn* src = lm + (((size_t)qk * naux + L) * nao + mu0) * (size_t)nao * 2;
+    // rows mu0 .. mu0+live-1 are contiguous in the input: live * nao complex
+    for (int e = threadIdx.x; e < live * nao; e += blockDim.x) {
+        const int r = e / nao, c = e % nao;
+        float2 v;
+        if constexpr (sizeof(TIn) == 8) {
+            const double2 d = reinterpret_cast<const double2*>(src)[e];
+            v = make_float2((float)d.x, (float)d.y);
+        } else {
+            v = reinterpret_cast<const float2*>(src)[e];
         }
-        const float pl[3] = {re, im, re + im};
-#pragma unroll
-        for (int p = 0; p < 3; ++p) {
-            __bf16 sp[NS];
-            split_bf16<NS>(pl[p], sp);
-#pragma unroll
-            for (int t = 0; t < NS; ++t) part[p][t][v] = sp[t];
-        }
+        tile[r * ld + c] = v;
     }
+    // zero padding columns of every row, and the padding rows
+    for (int e = threadIdx.x; e < rows * (W - nao); e += blockDim.x) {
+        const int r = e / (W - nao), c = nao + e % (W - nao);
+        tile[r * ld + c] = make_float2(0.f, 0.f);
+    }
+    for (int e = threadIdx.x; e < (rows - live) * nao; e += blockDim.x) {
+        const int r = live + e / nao, c = e % nao;
+        tile[r * ld + c] = make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    const int M1 = naux * nao_p;
     const size_t pt_stride = (size_t)ngv * M1;
     __bf16* o = out + (size_t)qk * 3 * NS * pt_stride * 8;
+    for (int item = threadIdx.x; item < rows * ngv; item += blockDim.x) {
+        const int r = item % rows, g = item / rows;   // consecutive threads: consecutive rows
+        bf8 part[3][NS];
 #pragma unroll
-    for (int p = 0; p < 3; ++p)
+        for (int v = 0; v < 8; ++v) {
+            const float2 x = tile[r * ld + 8 * g + v];
+            const float pl[3] = {x.x, x.y, x.x + x.y};
 #pragma unroll
-        for (int t = 0; t < NS; ++t)
-            *reinterpret_cast<bf8*>(o + (((size_t)(p * NS + t) * ngv + g) * M1 + row) * 8) = part[p][t];
+            for (int p = 0; p < 3; ++p) {
+                __bf16 sp[NS];
+                split_bf16<NS>(pl[p], sp);
+#pragma unroll
+                for (int t = 0; t < NS; ++t) part[p][t][v] = sp[t];
+            }
+        }
+        const size_t row = (size_t)L * nao_p + mu0 + r;
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int t = 0; t < NS; ++t)
+                *reinterpret_cast<bf8*>(o + (((size_t)(p * NS + t) * ngv + g) * M1 + row) * 8) = part[p][t];
+    }
 }
 
 // C^k[s][k][nu][j] -> P1c[k][plane][part][nu/8][s*neo + j][8]   (planes Cr, Ci, Cr + Ci)
@@ -1353,12 +1393,15 @@ static dmet_status xform_packed(const EriPlan& p, const void* lmunu, const doubl
     const char* nm = NS == 3 ? "pack_in_bf16x6" : "pack_in_bf16x3";
     {
         ProfScope ps(nm, st);
+        const int mb = pack_rows_per_block(d.ngv);
+        const long nblk = (long)nk * nk * p.naux * ((d.nao_p + mb - 1) / mb);
+        const size_t lds = pack_lds_bytes(mb, d.ngv);
         if (p.dtype == DMET_C128)
-            k_pack_lmunu<NS, double><<<dim3((d.M1 + 255) / 256, d.ngv, nk * nk), 256, 0, st>>>(
-                static_cast<const double*>(lmunu), p.nao, d.nao_p, p.naux, d.ngv, plm, p.mesh, 1);
+            k_pack_lmunu<NS, double><<<dim3((unsigned)nblk), 256, lds, st>>>(
+                static_cast<const double*>(lmunu), p.nao, d.nao_p, p.naux, d.ngv, mb, plm, p.mesh, 1);
         else
-            k_pack_lmunu<NS, float><<<dim3((d.M1 + 255) / 256, d.ngv, nk * nk), 256, 0, st>>>(
-                static_cast<const float*>(lmunu), p.nao, d.nao_p, p.naux, d.ngv, plm, p.mesh, 1);
+            k_pack_lmunu<NS, float><<<dim3((unsigned)nblk), 256, lds, st>>>(
+                static_cast<const float*>(lmunu), p.nao, d.nao_p, p.naux, d.ngv, mb, plm, p.mesh, 1);
         k_pack_c1<NS><<<dim3((d.NB + 255) / 256, d.ngv, nk), 256, 0, st>>>(ck, nk, p.nspin, p.nao, p.neo, d.ngv, pc1,
                                                                           0, d.NB);
         k_pack_c2<NS><<<dim3((p.neo + 255) / 256, d.ng2, p.nspin), 256, 0, st>>>(ck, nk, p.nao, d.nao_p, p.neo,
@@ -1752,12 +1795,15 @@ static dmet_status batch_enqueue(BatchPlan& bp, int variant, bool prof, hipStrea
     for (auto& G : bp.groups) {
         const int nk = G.mesh.nk;
         __bf16* plm = at<__bf16>(ws, G.off_plm);
+        const int mb = pack_rows_per_block(G.ngv);
+        const long nblk = (long)nk * nk * G.naux * ((G.nao_p + mb - 1) / mb);
+        const size_t lds = pack_lds_bytes(mb, G.ngv);
         if (G.dt == DMET_C128)
-            k_pack_lmunu<NS, double><<<dim3((G.M1 + 255) / 256, G.ngv, nk * nk), 256, 0, st>>>(
-                static_cast<const double*>(G.lm), G.nao, G.nao_p, G.naux, G.ngv, plm, G.mesh, 1);
+            k_pack_lmunu<NS, double><<<dim3((unsigned)nblk), 256, lds, st>>>(
+                static_cast<const double*>(G.lm), G.nao, G.nao_p, G.naux, G.ngv, mb, plm, G.mesh, 1);
         else
-            k_pack_lmunu<NS, float><<<dim3((G.M1 + 255) / 256, G.ngv, nk * nk), 256, 0, st>>>(
-                static_cast<const float*>(G.lm), G.nao, G.nao_p, G.naux, G.ngv, plm, G.mesh, 1);
+            k_pack_lmunu<NS, float><<<dim3((unsigned)nblk), 256, lds, st>>>(
+                static_cast<const float*>(G.lm), G.nao, G.nao_p, G.naux, G.ngv, mb, plm, G.mesh, 1);
         for (int f : G.members) {
             const BatchFrag& F = bp.fs[f];
             k_pack_c1<NS><<<dim3((F.neo + 255) / 256, G.ngv, nk), 256, 0, st>>>(
