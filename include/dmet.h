@@ -121,6 +121,11 @@ int dmet_version(void);
  * neo      out HOST [nspin]: nimp + number of kept bath orbitals.
  * workspace/ws_bytes: device scratch, at least dmet_build_bath_workspace().
  *
+ * An impurity that is the whole supercell (nimp = N_k*nao, e.g. one k-point
+ * with every orbital in the impurity) leaves no environment and so no bath:
+ * neo[s] = nimp, sv is zero and the bath columns of c_k are zero.  A
+ * non-empty environment with fewer orbitals than nval is DMET_E_ARG.
+ *
  * This call synchronises `stream` before returning (it reads back the
  * convergence status and the kept bath count).  Returns DMET_E_NOCONV if the
  * SVD needs more than 60 sweeps, DMET_E_NONFINITE for NaN/Inf in dm_k,

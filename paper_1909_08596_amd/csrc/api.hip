@@ -159,7 +159,7 @@ dmet_status dmet_build_bath(const dmet_lattice* lat, const void* dm_k, int nimp,
     if (s != DMET_OK) return s;
     const int nsup = lat->kmesh[0] * lat->kmesh[1] * lat->kmesh[2] * lat->nao;
     if (!dm_k || !c_k || !sv || !neo) return fail(DMET_E_ARG, "null array argument");
-    if (nimp < 1 || nimp >= nsup) return fail(DMET_E_ARG, "nimp must be in [1, N_k*nao)");
+    if (nimp < 1 || nimp > nsup) return fail(DMET_E_ARG, "nimp must be in [1, N_k*nao]");
     if (!imp_idx && nimp != lat->nao) return fail(DMET_E_ARG, "imp_idx == NULL requires nimp == nao");
     if (nval < 1 || nval > nimp) return fail(DMET_E_ARG, "nval must be in [1, nimp]");
     if (!val_idx && nval != nimp) return fail(DMET_E_ARG, "val_idx == NULL requires nval == nimp");

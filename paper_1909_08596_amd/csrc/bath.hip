@@ -343,13 +343,17 @@ dmet_status build_bath(const dmet_lattice* lat, const double2* dm_k, int nimp, c
             env.push_back(r);
         }
     if ((int)env.size() != p.nenv) return fail(DMET_E_ARG, "impurity list inconsistent");
-    if (p.nenv < nval) return fail(DMET_E_ARG, "fewer environment orbitals than SVD columns");
+    // an empty environment (the impurity is the whole supercell, e.g. one
+    // k-point with every orbital in the impurity) has no bath; a non-empty one
+    // must have at least as many orbitals as the SVD has columns
+    if (p.nenv > 0 && p.nenv < nval) return fail(DMET_E_ARG, "fewer environment orbitals than SVD columns");
 
     Carve cv(ws, ws_bytes);
     BathWs w = carve_bath(cv, p, c_ao_lo != nullptr);
     if (cv.bytes() > ws_bytes) return fail(DMET_E_WORKSPACE, "build_bath workspace too small");
 
-    DMET_HIP(hipMemcpyAsync(w.env, env.data(), sizeof(int) * env.size(), hipMemcpyHostToDevice, st));
+    if (!env.empty())
+        DMET_HIP(hipMemcpyAsync(w.env, env.data(), sizeof(int) * env.size(), hipMemcpyHostToDevice, st));
     DMET_HIP(hipMemcpyAsync(w.cols, cols.data(), sizeof(int) * nval, hipMemcpyHostToDevice, st));
     DMET_HIP(hipMemcpyAsync(w.imp, imp.data(), sizeof(int) * nimp, hipMemcpyHostToDevice, st));
     DMET_HIP(hipMemcpyAsync(w.envpos, envpos.data(), sizeof(int) * p.nsup, hipMemcpyHostToDevice, st));
@@ -360,18 +364,25 @@ dmet_status build_bath(const dmet_lattice* lat, const double2* dm_k, int nimp, c
     k_dm_real<<<dim3((nn + 255) / 256, p.mesh.nk, p.nspin), 256, 0, st>>>(p.mesh, p.nao, dm_k, w.dm_r,
                                                                           w.flags, w.scal);
     DMET_LAUNCH_CHECK("k_dm_real");
-    k_build_m<<<dim3((p.nenv + 255) / 256, nval, p.nspin), 256, 0, st>>>(
-        p.mesh, p.nao, p.nenv, nval, w.env, w.cols, w.dm_r, w.mt);
-    DMET_LAUNCH_CHECK("k_build_m");
-    const double tol = fmax(1e-15, sqrt((double)p.nenv) * 2.220446049250313e-16);
-    k_jacobi<<<p.nspin, 1024, 0, st>>>(p.nenv, nval, w.mt, 60, tol, w.flags);
-    DMET_LAUNCH_CHECK("k_jacobi");
-    const size_t shm = (size_t)nval * (sizeof(double) + sizeof(int));
-    k_svd_finalize<<<p.nspin, 1024, shm, st>>>(p.nenv, nval, w.mt, w.ub, sv, sv_tol, w.flags);
-    DMET_LAUNCH_CHECK("k_svd_finalize");
-    k_overlap<<<dim3((nval * nval + 3) / 4, p.nspin), 256, 0, st>>>(p.nenv, nval, w.ub, w.emat, w.flags,
-                                                                     w.scal + 1);
-    DMET_LAUNCH_CHECK("k_overlap");
+    if (p.nenv > 0) {
+        k_build_m<<<dim3((p.nenv + 255) / 256, nval, p.nspin), 256, 0, st>>>(
+            p.mesh, p.nao, p.nenv, nval, w.env, w.cols, w.dm_r, w.mt);
+        DMET_LAUNCH_CHECK("k_build_m");
+    }
+    if (p.nenv > 0) {
+        const double tol = fmax(1e-15, sqrt((double)p.nenv) * 2.220446049250313e-16);
+        k_jacobi<<<p.nspin, 1024, 0, st>>>(p.nenv, nval, w.mt, 60, tol, w.flags);
+        DMET_LAUNCH_CHECK("k_jacobi");
+        const size_t shm = (size_t)nval * (sizeof(double) + sizeof(int));
+        k_svd_finalize<<<p.nspin, 1024, shm, st>>>(p.nenv, nval, w.mt, w.ub, sv, sv_tol, w.flags);
+        DMET_LAUNCH_CHECK("k_svd_finalize");
+        k_overlap<<<dim3((nval * nval + 3) / 4, p.nspin), 256, 0, st>>>(p.nenv, nval, w.ub, w.emat, w.flags,
+                                                                         w.scal + 1);
+        DMET_LAUNCH_CHECK("k_overlap");
+    } else {
+        // no bath: the kept count (flags[4 + s]) stays 0, singular values are 0
+        if (nval > 0) fill_zero(sv, (size_t)p.nspin * nval * sizeof(double), st);
+    }
     k_assemble_cr<<<dim3((p.nsup + 255) / 256, p.ldc, p.nspin), 256, 0, st>>>(
         p.nsup, nimp, nval, p.ldc, p.nenv, w.imp, w.envpos, w.ub, w.emat, w.flags, w.cr);
     DMET_LAUNCH_CHECK("k_assemble_cr");
@@ -394,7 +405,7 @@ dmet_status build_bath(const dmet_lattice* lat, const double2* dm_k, int nimp, c
     if (flags[0] & FLAG_NOCONV) return fail(DMET_E_NOCONV, "Jacobi SVD did not converge in 60 sweeps");
     if (scal[1] > 1e-6) return fail(DMET_E_NOCONV, "bath vectors lost orthogonality (|S - I| > 1e-6)");
     for (int s = 0; s < p.nspin; ++s) {
-        if (flags[4 + s] == 0) return fail(DMET_E_RANK, "sv_tol removed every bath orbital");
+        if (flags[4 + s] == 0 && p.nenv > 0) return fail(DMET_E_RANK, "sv_tol removed every bath orbital");
         neo[s] = nimp + flags[4 + s];
     }
     return DMET_OK;
