@@ -151,6 +151,22 @@ def run_batched(args, dev):
     neos = [f["c_k"].shape[-1] for f in frags]
     forms = [args.precision] + [p for p in args.compare.split(",") if p and p != args.precision and p != "fp64"]
     out = {}
+    # plain FP64 path over the same batch (the per-fragment FP64 kernels): the
+    # reference for every form's speed-up and max error
+    ws = torch.empty(dmet.dmet_transform_eri_batched_workspace(frags, "fp64"), dtype=torch.uint8, device=dev)
+    dmet.dmet_transform_eri_batched(frags, "fp64", workspace=ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        dmet.dmet_transform_eri_batched(frags, "fp64", workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_64 = e0.elapsed_time(e1) / args.steps
+    ref64 = [f.pop("eri") for f in frags]
+    del ws
+    out["fp64"] = {"ms_batched": round(ms_64, 3), "TFLOP/s": round(wsum / (ms_64 * 1e-3) / 1e12, 3)}
+    print(f"[bench] batched fp64: {ms_64:.2f} ms", file=sys.stderr, flush=True)
     for prec in forms:
         ws = torch.empty(dmet.dmet_transform_eri_batched_workspace(frags, prec), dtype=torch.uint8, device=dev)
         for _ in range(max(1, args.warmup)):
@@ -166,6 +182,7 @@ def run_batched(args, dev):
         torch.cuda.synchronize()
         dmet.dmet_profile_enable(False)
         ms_b = e0.elapsed_time(e1) / args.steps
+        err64 = max(float((f["eri"] - r).abs().max()) for f, r in zip(frags, ref64))
         ref = [f["eri"].clone() for f in frags]
         # loop of single-fragment calls, same precision
         loop_ws = torch.empty(max(dmet.dmet_transform_eri_workspace(f["kmesh"], f["nao"], f["naux"], 1,
@@ -187,9 +204,10 @@ def run_batched(args, dev):
         same = all(torch.equal(a, o["aa"]) for a, o in zip(ref, outs))
         out[prec] = {"ms_batched": round(ms_b, 3), "ms_loop": round(ms_l, 3),
                      "speedup_batched_vs_loop": round(ms_l / ms_b, 3),
-                     "TFLOP/s": round(wsum / (ms_b * 1e-3) / 1e12, 3), "batched_equals_loop": bool(same)}
-        print(f"[bench] batched {prec}: {ms_b:.2f} ms vs loop {ms_l:.2f} ms; equal={same}", file=sys.stderr,
-              flush=True)
+                     "TFLOP/s": round(wsum / (ms_b * 1e-3) / 1e12, 3), "batched_equals_loop": bool(same),
+                     "speedup_vs_fp64": round(ms_64 / ms_b, 3), "max_abs_err_vs_fp64": err64}
+        print(f"[bench] batched {prec}: {ms_b:.2f} ms vs loop {ms_l:.2f} ms; equal={same}; "
+              f"{ms_64 / ms_b:.2f}x fp64, max err {err64:.2e}", file=sys.stderr, flush=True)
         del ws, loop_ws
     head = out[args.precision]
     line = {
