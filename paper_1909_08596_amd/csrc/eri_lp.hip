@@ -575,6 +575,10 @@ constexpr size_t d2_lds() { return (size_t)3 * 2 * NS * 2 * 128 * 16; }
 
 inline size_t pack_lds_bytes(int mb, int ngv) { return (size_t)mb * (8 * ngv + 1) * sizeof(float2); }
 
+// Stage 2 multiplies complex operands with four real products (4M) on two
+// planes (re, im) per operand: T and conj C are packed with P2 planes.
+constexpr int P2 = 2;
+
 // lmunu[q][k][L][mu][nu] -> P1[q][k][plane][part][nu/8][L*nao_p + mu][8]
 // With only_needed, blocks (q, k) that the k <-> q-k paired transform never
 // reads are skipped (their input is not touched).  One workgroup takes `mb`
@@ -689,14 +693,14 @@ __global__ void k_pack_c1(const double* __restrict__ ck, int nk, int nspin, int 
                 out + ((size_t)k * per_k + ((size_t)(p * NS + t) * ngv + g) * nb_total + col0 + col) * 8) = part[p][t];
 }
 
-// conj(C^k)[s][(k,mu)][i] -> P2c[s][plane][part][(k*nao_p + mu)/8][i][8]  (planes Cr, -Ci, Cr - Ci)
+// conj(C^k)[s][(k,mu)][i] -> P2c[s][plane][part][(k*nao_p + mu)/8][i][8]  (planes Cr, -Ci)
 template <int NS>
 __global__ void k_pack_c2(const double* __restrict__ ck, int nk, int nao, int nao_p, int neo, int ng2,
                           __bf16* __restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int g = blockIdx.y, s = blockIdx.z;
     if (i >= neo) return;
-    bf8 part[3][NS];
+    bf8 part[P2][NS];
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
         const int kk = 8 * g + v, k = kk / nao_p, mu = kk % nao_p;
@@ -706,29 +710,29 @@ __global__ void k_pack_c2(const double* __restrict__ ck, int nk, int nao, int na
             re = (float)c[0];
             im = (float)c[1];
         }
-        const float pl[3] = {re, -im, re - im};
+        const float pl[P2] = {re, -im};
 #pragma unroll
-        for (int p = 0; p < 3; ++p) {
+        for (int p = 0; p < P2; ++p) {
             __bf16 sp[NS];
             split_bf16<NS>(pl[p], sp);
 #pragma unroll
             for (int t = 0; t < NS; ++t) part[p][t][v] = sp[t];
         }
     }
-    const size_t per_s = (size_t)3 * NS * ng2 * neo;
+    const size_t per_s = (size_t)P2 * NS * ng2 * neo;
 #pragma unroll
-    for (int p = 0; p < 3; ++p)
+    for (int p = 0; p < P2; ++p)
 #pragma unroll
         for (int t = 0; t < NS; ++t)
             *reinterpret_cast<bf8*>(out + ((size_t)s * per_s + ((size_t)(p * NS + t) * ng2 + g) * neo + i) * 8) =
                 part[p][t];
 }
 
-// One stage of a packed operand (3 planes x NS parts x 2 groups x ROWS rows)
+// One stage of a stage-2 operand (P2 planes x NS parts x 2 groups x ROWS rows)
 // from two explicit groups g0, g1 (a zero group pads an odd count).
 template <int NS, int ROWS>
 __device__ inline void pk_issue_g(const __bf16* base, size_t pt_stride, int X, int x0, int g0, int g1, bf8* dst) {
-    constexpr int CH = 3 * NS * 2 * ROWS;
+    constexpr int CH = P2 * NS * 2 * ROWS;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int first = wave * 64; first < CH; first += 256) {
         const int pt = first / (2 * ROWS), g = (first / ROWS) % 2, row0 = first % ROWS;
@@ -789,6 +793,49 @@ __device__ inline void pk_mma3(const bf8* sA, const bf8* sB, int wm0, int wn0, f
     }
 }
 
+// 4M x NS-split products of one 16-deep stage on (re, im) planes:
+// acc[0] += Ar Br, acc[1] += Ai Bi, acc[2] += Ar Bi, acc[3] += Ai Br
+// (re = acc0 - acc1, im = acc2 + acc3).  The split products of each real
+// product run in the order of pk_mma3.
+template <int NS, int BM, int BN, int TM, int TN>
+__device__ inline void pk_mma4(const bf8* sA, const bf8* sB, int wm0, int wn0, f16v (&acc)[4][TM][TN]) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 5;
+    bf8 a[P2][TM][NS], b[P2][TN][NS];
+#pragma unroll
+    for (int p = 0; p < P2; ++p)
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+#pragma unroll
+            for (int i = 0; i < TM; ++i) a[p][i][t] = sA[((p * NS + t) * 2 + g) * BM + wm0 + i * 32 + (lane & 31)];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) b[p][j][t] = sB[((p * NS + t) * 2 + g) * BN + wn0 + j * 32 + (lane & 31)];
+        }
+    constexpr int PA[4] = {0, 1, 0, 1}, PB[4] = {0, 1, 1, 0};
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const bf8* x = a[PA[c]][i];
+                const bf8* y = b[PB[c]][j];
+                f16v d = acc[c][i][j];
+                if constexpr (NS == 2) {
+                    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[1], y[0], d, 0, 0, 0);
+                    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[0], y[1], d, 0, 0, 0);
+                } else {
+                    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[2], y[0], d, 0, 0, 0);
+                    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[1], y[1], d, 0, 0, 0);
+                    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[0], y[2], d, 0, 0, 0);
+                    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[1], y[0], d, 0, 0, 0);
+                    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[0], y[1], d, 0, 0, 0);
+                }
+                d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[0], y[0], d, 0, 0, 0);
+                acc[c][i][j] = d;
+            }
+}
+
 // Double-buffered K loop over `nst` stages of two groups each.
 template <int NS, int BM, int BN, int TM, int TN>
 __device__ inline void pk_loop3(const __bf16* pa, size_t pa_pt, int XA, int m0, const __bf16* pb, size_t pb_pt,
@@ -813,14 +860,15 @@ __device__ inline void pk_loop3(const __bf16* pa, size_t pa_pt, int XA, int m0, 
 // K loop of stage 2 under the k <-> q-k pairing: pass 1 over the groups of
 // all kept k (A = conj C, rows i; B = T, columns (L, j)), pass 2 over the
 // paired k with the operands swapped (A = T columns (L, i), B = conj C rows j),
-// which adds the transposed terms of the partners.  The 3M planes combine the
-// same way in both passes.  Odd group counts are padded with group zg (zero
-// in both operands).  Double-buffered stages of two groups.
+// which adds the transposed terms of the partners.  The 4M products on the
+// (re, im) planes give the plain complex product of the two operands in both
+// passes.  Odd group counts are padded with group zg (zero in both operands).
+// Double-buffered stages of two groups.
 template <int NS, int BM, int BN, int TM, int TN, class KOf>
 __device__ inline void pk_loop_paired(const __bf16* pc2, size_t cst, int neo, const __bf16* ptt, size_t tst, int N2,
                                       int L, int m0, int j0, int gpk, int zg, int npaired, int nself, KOf kof,
-                                      bf8* ring, int wm0, int wn0, f16v (&acc)[3][TM][TN]) {
-    constexpr int SA = 3 * NS * 2 * BM, SB = 3 * NS * 2 * BN;
+                                      bf8* ring, int wm0, int wn0, f16v (&acc)[4][TM][TN]) {
+    constexpr int SA = P2 * NS * 2 * BM, SB = P2 * NS * 2 * BN;
     const int n1 = (npaired + nself) * gpk, n2 = npaired * gpk;
     const int s1 = (n1 + 1) / 2, nst = s1 + (n2 + 1) / 2;
     // running position (no division per stage): pass, group j in the pass,
@@ -863,13 +911,13 @@ __device__ inline void pk_loop_paired(const __bf16* pc2, size_t cst, int neo, co
         __builtin_amdgcn_s_barrier();         // everyone's loads landed; stage st-1 fully read
         __builtin_amdgcn_sched_barrier(0);
         if (st + 1 < nst) issue(ring + (size_t)((st + 1) & 1) * (SA + SB));
-        pk_mma3<NS, BM, BN, TM, TN>(cur, cur + SA, wm0, wn0, acc);
+        pk_mma4<NS, BM, BN, TM, TN>(cur, cur + SA, wm0, wn0, acc);
     }
 }
 
 // Stage 1 (both spins at once): T[(L,mu)][(s,j)] for one (q, k) from packed
-// lmunu and packed C^{k-q}; 3M combination and split into bf16 parts in the
-// epilogue, written as stage 2's packed B operand
+// lmunu and packed C^{k-q}; 3M combination into (re, im) and split into bf16
+// parts in the epilogue, written as stage 2's packed B operand
 //   PT[s][plane][part][(k*nao_p + mu)/8][L*neo + j][8].
 // Lanes l and l+32 hold rows 0-3 and 4-7 of each 8-row group of a 32x32
 // result tile; one exchange gives each lane a full 8-row column chunk.
@@ -922,9 +970,9 @@ __global__ void __launch_bounds__(256) k_xf1_pk(Mesh mesh, int q, int naux, int 
 #pragma unroll
             for (int qq = 0; qq < 4; qq += 2) {
                 // rows of register groups qq (this lane: h == 0) and qq + 1 (h == 1)
-                float pl[3][8];
+                float pl[P2][8];
 #pragma unroll
-                for (int p3 = 0; p3 < 3; ++p3) {
+                for (int p3 = 0; p3 < P2; ++p3) {
                     float mine[4], send[4], recv[4];
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
@@ -932,8 +980,9 @@ __global__ void __launch_bounds__(256) k_xf1_pk(Mesh mesh, int q, int naux, int 
                                     p3v = acc[2][i][j][4 * qq + r];
                         const float p1b = acc[0][i][j][4 * (qq + 1) + r], p2b = acc[1][i][j][4 * (qq + 1) + r],
                                     p3b = acc[2][i][j][4 * (qq + 1) + r];
-                        const float va = p3 == 0 ? p1 - p2 : (p3 == 1 ? p3v - p1 - p2 : p3v - 2.f * p2);
-                        const float vb = p3 == 0 ? p1b - p2b : (p3 == 1 ? p3b - p1b - p2b : p3b - 2.f * p2b);
+                        // 3M: re = P1 - P2, im = P3 - P1 - P2
+                        const float va = p3 == 0 ? p1 - p2 : p3v - p1 - p2;
+                        const float vb = p3 == 0 ? p1b - p2b : p3b - p1b - p2b;
                         mine[r] = h == 0 ? va : vb;
                         send[r] = h == 0 ? vb : va;
                     }
@@ -950,9 +999,9 @@ __global__ void __launch_bounds__(256) k_xf1_pk(Mesh mesh, int q, int naux, int 
                     const int L = grp_row / nao_p, mu0 = grp_row % nao_p;
                     const size_t g2 = ((size_t)slot * nao_p + mu0) / 8;
                     const size_t x = (size_t)L * neo + jj;
-                    __bf16* base = pt + (size_t)s * 3 * NS * per_part * 8;
+                    __bf16* base = pt + (size_t)s * P2 * NS * per_part * 8;
 #pragma unroll
-                    for (int p3 = 0; p3 < 3; ++p3) {
+                    for (int p3 = 0; p3 < P2; ++p3) {
                         bf8 part[NS];
 #pragma unroll
                         for (int v = 0; v < 8; ++v) {
@@ -970,7 +1019,7 @@ __global__ void __launch_bounds__(256) k_xf1_pk(Mesh mesh, int q, int naux, int 
         }
 }
 
-// Stage 2 for one q and spin, i >= j only; 3M combination; Z rows (FP32):
+// Stage 2 for one q and spin, i >= j only; 4M products; Z rows (FP32):
 //   X[i][(L,j)] = sum_{kept k, mu} conj(C^k_{mu i}) T_k[mu][(L,j)]
 //               + sum_{paired k, mu} T_k[mu][(L,i)] conj(C^k_{mu j}),
 // the second sum being the transposed terms of the partners q-k (a symmetric
@@ -995,9 +1044,9 @@ __global__ void __launch_bounds__(256) k_xf2_pk(int naux, int neo, int ng2, int 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
     const int N2 = naux * neo;
-    f16v acc[3][TM][TN];
+    f16v acc[4][TM][TN];
 #pragma unroll
-    for (int p = 0; p < 3; ++p)
+    for (int p = 0; p < 4; ++p)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[p][0][0][r] = 0.f;
     pk_loop_paired<NS, BM, BN, TM, TN>(pc2, (size_t)ng2 * neo, neo, ptt, (size_t)ng2 * N2, N2, L, m0, j0, gpk, zg,
@@ -1009,8 +1058,7 @@ __global__ void __launch_bounds__(256) k_xf2_pk(int naux, int neo, int ng2, int 
         const int j = j0 + wn0 + (lane & 31);
         if (i >= neo || j >= neo || j > i) continue;
         const size_t pair = (size_t)i * (i + 1) / 2 + j;
-        const float p1 = acc[0][0][0][r], p2 = acc[1][0][0][r], p3 = acc[2][0][0][r];
-        const float xr = p1 - p2, xi = p3 - p1 - p2;
+        const float xr = acc[0][0][0][r] - acc[1][0][0][r], xi = acc[2][0][0][r] + acc[3][0][0][r];
         if (self_conj) {
             z[(zrow0 + L) * ldz + pair] = wq * xr;
         } else {
@@ -1095,9 +1143,9 @@ __global__ void __launch_bounds__(256) k_xf1_batched(Mesh mesh, int q, int naux,
             if (col < NB) cm = colmap[col];
 #pragma unroll
             for (int qq = 0; qq < 4; qq += 2) {
-                float pl[3][8];
+                float pl[P2][8];
 #pragma unroll
-                for (int p3 = 0; p3 < 3; ++p3) {
+                for (int p3 = 0; p3 < P2; ++p3) {
                     float mine[4], send[4], recv[4];
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
@@ -1105,8 +1153,9 @@ __global__ void __launch_bounds__(256) k_xf1_batched(Mesh mesh, int q, int naux,
                                     p3v = acc[2][i][j][4 * qq + r];
                         const float p1b = acc[0][i][j][4 * (qq + 1) + r], p2b = acc[1][i][j][4 * (qq + 1) + r],
                                     p3b = acc[2][i][j][4 * (qq + 1) + r];
-                        const float va = p3 == 0 ? p1 - p2 : (p3 == 1 ? p3v - p1 - p2 : p3v - 2.f * p2);
-                        const float vb = p3 == 0 ? p1b - p2b : (p3 == 1 ? p3b - p1b - p2b : p3b - 2.f * p2b);
+                        // 3M: re = P1 - P2, im = P3 - P1 - P2
+                        const float va = p3 == 0 ? p1 - p2 : p3v - p1 - p2;
+                        const float vb = p3 == 0 ? p1b - p2b : p3b - p1b - p2b;
                         mine[r] = h == 0 ? va : vb;
                         send[r] = h == 0 ? vb : va;
                     }
@@ -1126,7 +1175,7 @@ __global__ void __launch_bounds__(256) k_xf1_batched(Mesh mesh, int q, int naux,
                     const size_t g2 = ((size_t)slot * nao_p + mu0) / 8;
                     const size_t x = (size_t)L * fr.neo + cm.y;
 #pragma unroll
-                    for (int p3 = 0; p3 < 3; ++p3) {
+                    for (int p3 = 0; p3 < P2; ++p3) {
                         bf8 part[NS];
 #pragma unroll
                         for (int v = 0; v < 8; ++v) {
@@ -1161,9 +1210,9 @@ __global__ void __launch_bounds__(256) k_xf2_batched(int nitems, const BItem2* _
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
     const int N2 = naux * neo;
-    f16v acc[3][TM][TN];
+    f16v acc[4][TM][TN];
 #pragma unroll
-    for (int p = 0; p < 3; ++p)
+    for (int p = 0; p < 4; ++p)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[p][0][0][r] = 0.f;
     const short* kk = qs[item.slot].k;
@@ -1177,8 +1226,7 @@ __global__ void __launch_bounds__(256) k_xf2_batched(int nitems, const BItem2* _
         const int j = j0 + wn0 + (lane & 31);
         if (i >= neo || j >= neo || j > i) continue;
         const size_t pair = (size_t)i * (i + 1) / 2 + j;
-        const float p1 = acc[0][0][0][r], p2 = acc[1][0][0][r], p3 = acc[2][0][0][r];
-        const float xr = p1 - p2, xi = p3 - p1 - p2;
+        const float xr = acc[0][0][0][r] - acc[1][0][0][r], xi = acc[2][0][0][r] + acc[3][0][0][r];
         if (qb.self_conj) {
             fr.z[(qb.zrow0 + L) * ldz + pair] = qb.wq * xr;
         } else {
@@ -1321,7 +1369,7 @@ constexpr size_t persist_lds() { return (size_t)(BM == 128 ? 3 : 2) * 2 * NS * 2
 template <int NS>
 constexpr size_t xf1_lds() { return (size_t)2 * 3 * NS * 2 * (128 + 128) * 16; }
 template <int NS>
-constexpr size_t xf2_lds() { return (size_t)2 * 3 * NS * 2 * (64 + 64) * 16; }
+constexpr size_t xf2_lds() { return (size_t)2 * P2 * NS * 2 * (64 + 64) * 16; }
 
 // ------------------------------------------------------------------ driver
 // contraction kernel: k_contract_w8 (128 x 256 tiles, one workgroup per CU);
@@ -1357,11 +1405,11 @@ static PkDims pk_dims(const EriPlan& p) {
     d.M1 = p.naux * d.nao_p;
     d.NB = p.nspin * p.neo;
     d.N2 = (size_t)p.naux * p.neo;
-    const size_t pl = (size_t)3 * d.ns * 8;
+    const size_t pl = (size_t)3 * d.ns * 8, pl2 = (size_t)P2 * d.ns * 8;
     d.lm_elems = (size_t)p.mesh.nk * p.mesh.nk * pl * d.ngv * d.M1;
     d.c1_elems = (size_t)p.mesh.nk * pl * d.ngv * d.NB;
-    d.c2_elems = (size_t)p.nspin * pl * d.ng2 * p.neo;
-    d.t_elems = (size_t)p.nspin * pl * d.ng2 * d.N2;
+    d.c2_elems = (size_t)p.nspin * pl2 * d.ng2 * p.neo;
+    d.t_elems = (size_t)p.nspin * pl2 * d.ng2 * d.N2;
     return d;
 }
 
@@ -1409,7 +1457,7 @@ static dmet_status xform_packed(const EriPlan& p, const void* lmunu, const doubl
         // groups zg .. ng2-1 of T pad odd group counts in stage 2: make them zero
         // (stage 1 writes compact slots below zg only; conj C is zero there too)
         const size_t part = (size_t)d.ng2 * d.N2 * 8;
-        for (int sp = 0; sp < p.nspin * 3 * NS; ++sp)
+        for (int sp = 0; sp < p.nspin * P2 * NS; ++sp)
             fill_zero(ptt + (size_t)sp * part + (size_t)zg * d.N2 * 8, (size_t)(d.ng2 - zg) * d.N2 * 8 * sizeof(__bf16),
                       st);
         ps.stop();
@@ -1423,8 +1471,8 @@ static dmet_status xform_packed(const EriPlan& p, const void* lmunu, const doubl
     const char* n2 = NS == 3 ? "xform2_bf16x6" : "xform2_bf16x3";
     const size_t ldz = (size_t)p.npair;
     const int njt = (p.neo + 63) / 64, nit = (p.neo + 63) / 64;
-    const size_t t_spin = (size_t)3 * NS * d.ng2 * d.N2 * 8;
-    const size_t c2_spin = (size_t)3 * NS * d.ng2 * p.neo * 8;
+    const size_t t_spin = (size_t)P2 * NS * d.ng2 * d.N2 * 8;
+    const size_t c2_spin = (size_t)P2 * NS * d.ng2 * p.neo * 8;
     for (const QBlock& qb : p.qblocks) {
         const KSlots ks = kpair_slots(p.mesh, qb.q);
         ProfScope ps1(n1, st);
@@ -1732,15 +1780,15 @@ static void plan_batch(BatchPlan& bp) {
     bp.off_bq = off(sizeof(BQ) * std::max<size_t>(1, bp.h_bq.size()));
     bp.off_itemsc = off(sizeof(BItemC) * std::max(bp.h_itemsc[0].size(), bp.h_itemsc[1].size()) + 16);
     bp.off_q = off(sizeof(int) * 3 * NXCD);
-    const size_t pl = (size_t)3 * NS * 8;
+    const size_t pl = (size_t)3 * NS * 8, pl2 = (size_t)P2 * NS * 8;
     for (auto& G : bp.groups) {
         G.off_plm = off(sizeof(__bf16) * (size_t)G.mesh.nk * G.mesh.nk * pl * G.ngv * G.M1);
         G.off_pc1 = off(sizeof(__bf16) * (size_t)G.mesh.nk * pl * G.ngv * G.nbtot);
     }
     for (auto& F : bp.fs) {
         const BatchGroup& G = bp.groups[F.group];
-        F.off_pc2 = off(sizeof(__bf16) * pl * G.ng2 * F.neo);
-        F.off_ptt = off(sizeof(__bf16) * pl * G.ng2 * (size_t)G.naux * F.neo);
+        F.off_pc2 = off(sizeof(__bf16) * pl2 * G.ng2 * F.neo);
+        F.off_ptt = off(sizeof(__bf16) * pl2 * G.ng2 * (size_t)G.naux * F.neo);
         F.off_z = off(sizeof(float) * (size_t)F.zrows * F.npair);
         F.off_zp = off(sizeof(__bf16) * (size_t)NS * F.kgroups * 8 * F.npair);
     }
@@ -1817,7 +1865,7 @@ static dmet_status batch_enqueue(BatchPlan& bp, int variant, bool prof, hipStrea
                 const int zg = nk * (G.nao_p / 8);
                 const size_t n2 = (size_t)G.naux * F.neo, part = (size_t)G.ng2 * n2 * 8;
                 __bf16* ptt = at<__bf16>(ws, F.off_ptt);
-                for (int sp = 0; sp < 3 * NS; ++sp)
+                for (int sp = 0; sp < P2 * NS; ++sp)
                     fill_zero(ptt + (size_t)sp * part + (size_t)zg * n2 * 8,
                               (size_t)(G.ng2 - zg) * n2 * 8 * sizeof(__bf16), st);
             }
