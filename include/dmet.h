@@ -67,10 +67,12 @@ typedef enum {
 typedef enum {
     DMET_FP64 = 0,           /* complex GEMMs as 4 real FP64 MFMA products              */
     DMET_FP32_3M = 1,        /* complex GEMMs as 3 real FP32 products, FP32 accumulate   */
-    DMET_BF16X3_3M = 2,      /* 3M with each FP32 operand split into bf16 hi + lo and
-                                the products hi*hi + hi*lo + lo*hi, FP32 accumulate
+    DMET_BF16X3_3M = 2,      /* 3M (4M in the transform's second stage) with each FP32
+                                operand split into bf16 hi + lo and the products
+                                hi*hi + hi*lo + lo*hi, FP32 accumulate
                                 (about 2^-17 relative per operand)                   */
-    DMET_BF16X6_3M = 3       /* 3M with a three-way bf16 split hi + mid + lo and the six
+    DMET_BF16X6_3M = 3       /* 3M (4M in the transform's second stage) with a
+                                three-way bf16 split hi + mid + lo and the six
                                 products hh, hm, mh, hl, mm, lh, FP32 accumulate
                                 (about FP32 accuracy)                                */
 } dmet_precision;
