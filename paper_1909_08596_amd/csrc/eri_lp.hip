@@ -1,8 +1,10 @@
 // Split-BF16 forms of the embedding-ERI transformation (Alg. 1).
 //
-// Every complex GEMM runs as 3 real GEMMs (3M / Gauss): P1 = Ar Br,
-// P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi), Re = P1 - P2, Im = P3 - P1 - P2, with
-// each FP32 operand split into bf16 parts for v_mfma_f32_32x32x16_bf16:
+// Every complex GEMM of the transform runs as 4 real GEMMs (4M) on (re, im)
+// planes, Re = Ar Br - Ai Bi, Im = Ar Bi + Ai Br (against 3M on three planes
+// it moves a third fewer operand bytes, which bound these kernels, and has no
+// (re + im) cancellation), with each FP32 operand split into bf16 parts for
+// v_mfma_f32_32x32x16_bf16 (the precision names keep their 3M suffix):
 //   DMET_BF16X3_3M : x = hi + lo (hi = bf16(x), lo = bf16(x - hi)); each real
 //                    product formed as hi*hi + hi*lo + lo*hi with FP32
 //                    accumulation.  On the diagonal tiles of the contraction
@@ -13,7 +15,7 @@
 //                    whose order is at most 2^-16 (hh, hm, mh, hl, mm, lh):
 //                    ~2^-24 relative, FP32-level accuracy on the bf16 pipes.
 //
-// Intermediates are FP32: T (stage-1 output, three planes Tr, Ti, Tr + Ti) and
+// Intermediates are FP32: T (stage-1 output, two planes Tr, Ti) and
 // Z (real rows of the contraction), both stored as packed bf16 parts
 // [plane][part][k/8][x][8] so that one MFMA operand fragment (8 consecutive k
 // of one row) is one aligned 16-byte chunk moved straight from global memory
@@ -568,15 +570,16 @@ constexpr size_t d2_lds() { return (size_t)3 * 2 * NS * 2 * 128 * 16; }
 // ------------------------------------------------------------------ packed transform (bf16 forms)
 // Operand packing for the transform.  Every packed operand has the layout
 //   [plane][part][group][x][8]   (bf16; group = 8 consecutive contraction indices)
-// with planes (re, im, re + im) for the 3M products.  nao is padded to
+// with planes (re, im) for the 4M products.  nao is padded to
 // nao_p = 8 * ceil(nao / 8) (zero rows / columns) and the group count of each
 // contraction index is padded to an even number (a zero group) so that a
 // stage always holds two groups (16 contraction indices).
 
 inline size_t pack_lds_bytes(int mb, int ngv) { return (size_t)mb * (8 * ngv + 1) * sizeof(float2); }
 
-// Stage 2 multiplies complex operands with four real products (4M) on two
-// planes (re, im) per operand: T and conj C are packed with P2 planes.
+// Both transform stages multiply complex operands with four real products
+// (4M) on two planes (re, im) per operand: every packed transform operand has
+// P2 planes.
 constexpr int P2 = 2;
 
 // lmunu[q][k][L][mu][nu] -> P1[q][k][plane][part][nu/8][L*nao_p + mu][8]
@@ -631,16 +634,16 @@ __global__ void __launch_bounds__(256) k_pack_lmunu(const TIn* __restrict__ lm, 
     __syncthreads();
     const int M1 = naux * nao_p;
     const size_t pt_stride = (size_t)ngv * M1;
-    __bf16* o = out + (size_t)qk * 3 * NS * pt_stride * 8;
+    __bf16* o = out + (size_t)qk * P2 * NS * pt_stride * 8;
     for (int item = threadIdx.x; item < rows * ngv; item += blockDim.x) {
         const int r = item % rows, g = item / rows;   // consecutive threads: consecutive rows
-        bf8 part[3][NS];
+        bf8 part[P2][NS];
 #pragma unroll
         for (int v = 0; v < 8; ++v) {
             const float2 x = tile[r * ld + 8 * g + v];
-            const float pl[3] = {x.x, x.y, x.x + x.y};
+            const float pl[P2] = {x.x, x.y};
 #pragma unroll
-            for (int p = 0; p < 3; ++p) {
+            for (int p = 0; p < P2; ++p) {
                 __bf16 sp[NS];
                 split_bf16<NS>(pl[p], sp);
 #pragma unroll
@@ -649,14 +652,14 @@ __global__ void __launch_bounds__(256) k_pack_lmunu(const TIn* __restrict__ lm, 
         }
         const size_t row = (size_t)L * nao_p + mu0 + r;
 #pragma unroll
-        for (int p = 0; p < 3; ++p)
+        for (int p = 0; p < P2; ++p)
 #pragma unroll
             for (int t = 0; t < NS; ++t)
                 *reinterpret_cast<bf8*>(o + (((size_t)(p * NS + t) * ngv + g) * M1 + row) * 8) = part[p][t];
     }
 }
 
-// C^k[s][k][nu][j] -> P1c[k][plane][part][nu/8][s*neo + j][8]   (planes Cr, Ci, Cr + Ci)
+// C^k[s][k][nu][j] -> P1c[k][plane][part][nu/8][s*neo + j][8]   (planes Cr, Ci)
 template <int NS>
 __global__ void k_pack_c1(const double* __restrict__ ck, int nk, int nspin, int nao, int neo, int ngv,
                           __bf16* __restrict__ out, int col0, int nb_total) {
@@ -665,7 +668,7 @@ __global__ void k_pack_c1(const double* __restrict__ ck, int nk, int nspin, int 
     const int g = blockIdx.y, k = blockIdx.z;
     if (col >= nb) return;
     const int s = col / neo, j = col % neo;
-    bf8 part[3][NS];
+    bf8 part[P2][NS];
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
         const int nu = 8 * g + v;
@@ -675,18 +678,18 @@ __global__ void k_pack_c1(const double* __restrict__ ck, int nk, int nspin, int 
             re = (float)c[0];
             im = (float)c[1];
         }
-        const float pl[3] = {re, im, re + im};
+        const float pl[P2] = {re, im};
 #pragma unroll
-        for (int p = 0; p < 3; ++p) {
+        for (int p = 0; p < P2; ++p) {
             __bf16 sp[NS];
             split_bf16<NS>(pl[p], sp);
 #pragma unroll
             for (int t = 0; t < NS; ++t) part[p][t][v] = sp[t];
         }
     }
-    const size_t per_k = (size_t)3 * NS * ngv * nb_total;
+    const size_t per_k = (size_t)P2 * NS * ngv * nb_total;
 #pragma unroll
-    for (int p = 0; p < 3; ++p)
+    for (int p = 0; p < P2; ++p)
 #pragma unroll
         for (int t = 0; t < NS; ++t)
             *reinterpret_cast<bf8*>(
@@ -742,12 +745,12 @@ __device__ inline void pk_issue_g(const __bf16* base, size_t pt_stride, int X, i
     }
 }
 
-// One stage of a packed operand (3 planes x NS parts x 2 groups x ROWS rows)
+// One stage of a packed operand (P2 planes x NS parts x 2 groups x ROWS rows)
 // moved to LDS [plane*NS + part][group][row] by direct loads; rows clamped.
 template <int NS, int ROWS>
 __device__ inline void pk_issue(const __bf16* base, size_t pt_stride /*chunks per part*/, int X, int x0, int g0,
                                 bf8* dst) {
-    constexpr int CH = 3 * NS * 2 * ROWS;  // chunks in the stage
+    constexpr int CH = P2 * NS * 2 * ROWS;  // chunks in the stage
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int first = wave * 64; first < CH; first += 256) {
         const int pt = first / (2 * ROWS), g = (first / ROWS) % 2, row0 = first % ROWS;
@@ -757,46 +760,10 @@ __device__ inline void pk_issue(const __bf16* base, size_t pt_stride /*chunks pe
     }
 }
 
-// 3M x NS-split products of one 16-deep stage: acc[p][i][j] += A_p B_p
-template <int NS, int BM, int BN, int TM, int TN>
-__device__ inline void pk_mma3(const bf8* sA, const bf8* sB, int wm0, int wn0, f16v (&acc)[3][TM][TN]) {
-    const int lane = threadIdx.x & 63;
-    const int g = lane >> 5;
-#pragma unroll
-    for (int p = 0; p < 3; ++p) {
-        bf8 a[TM][NS], b[TN][NS];
-#pragma unroll
-        for (int t = 0; t < NS; ++t) {
-#pragma unroll
-            for (int i = 0; i < TM; ++i) a[i][t] = sA[((p * NS + t) * 2 + g) * BM + wm0 + i * 32 + (lane & 31)];
-#pragma unroll
-            for (int j = 0; j < TN; ++j) b[j][t] = sB[((p * NS + t) * 2 + g) * BN + wn0 + j * 32 + (lane & 31)];
-        }
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j) {
-                f16v c = acc[p][i][j];
-                if constexpr (NS == 2) {
-                    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][0], c, 0, 0, 0);
-                    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][1], c, 0, 0, 0);
-                } else {
-                    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][2], b[j][0], c, 0, 0, 0);
-                    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][1], c, 0, 0, 0);
-                    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][2], c, 0, 0, 0);
-                    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][0], c, 0, 0, 0);
-                    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][1], c, 0, 0, 0);
-                }
-                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][0], c, 0, 0, 0);
-                acc[p][i][j] = c;
-            }
-    }
-}
-
 // 4M x NS-split products of one 16-deep stage on (re, im) planes:
 // acc[0] += Ar Br, acc[1] += Ai Bi, acc[2] += Ar Bi, acc[3] += Ai Br
 // (re = acc0 - acc1, im = acc2 + acc3).  The split products of each real
-// product run in the order of pk_mma3.
+// product run smallest first: lo*hi terms, then mid*mid and hi*lo, ..., hi*hi.
 template <int NS, int BM, int BN, int TM, int TN>
 __device__ inline void pk_mma4(const bf8* sA, const bf8* sB, int wm0, int wn0, f16v (&acc)[4][TM][TN]) {
     const int lane = threadIdx.x & 63;
@@ -839,8 +806,8 @@ __device__ inline void pk_mma4(const bf8* sA, const bf8* sB, int wm0, int wn0, f
 // Double-buffered K loop over `nst` stages of two groups each.
 template <int NS, int BM, int BN, int TM, int TN>
 __device__ inline void pk_loop3(const __bf16* pa, size_t pa_pt, int XA, int m0, const __bf16* pb, size_t pb_pt,
-                                int XB, int n0, int nst, bf8* ring, int wm0, int wn0, f16v (&acc)[3][TM][TN]) {
-    constexpr int SA = 3 * NS * 2 * BM, SB = 3 * NS * 2 * BN;
+                                int XB, int n0, int nst, bf8* ring, int wm0, int wn0, f16v (&acc)[4][TM][TN]) {
+    constexpr int SA = P2 * NS * 2 * BM, SB = P2 * NS * 2 * BN;
     pk_issue<NS, BM>(pa, pa_pt, XA, m0, 0, ring);
     pk_issue<NS, BN>(pb, pb_pt, XB, n0, 0, ring + SA);
     for (int st = 0; st < nst; ++st) {
@@ -853,7 +820,7 @@ __device__ inline void pk_loop3(const __bf16* pa, size_t pa_pt, int XA, int m0, 
             pk_issue<NS, BM>(pa, pa_pt, XA, m0, 2 * (st + 1), nxt);
             pk_issue<NS, BN>(pb, pb_pt, XB, n0, 2 * (st + 1), nxt + SA);
         }
-        pk_mma3<NS, BM, BN, TM, TN>(cur, cur + SA, wm0, wn0, acc);
+        pk_mma4<NS, BM, BN, TM, TN>(cur, cur + SA, wm0, wn0, acc);
     }
 }
 
@@ -916,8 +883,8 @@ __device__ inline void pk_loop_paired(const __bf16* pc2, size_t cst, int neo, co
 }
 
 // Stage 1 (both spins at once): T[(L,mu)][(s,j)] for one (q, k) from packed
-// lmunu and packed C^{k-q}; 3M combination into (re, im) and split into bf16
-// parts in the epilogue, written as stage 2's packed B operand
+// lmunu and packed C^{k-q}; 4M products combined into (re, im) and split into
+// bf16 parts in the epilogue, written as stage 2's packed B operand
 //   PT[s][plane][part][(k*nao_p + mu)/8][L*neo + j][8].
 // Lanes l and l+32 hold rows 0-3 and 4-7 of each 8-row group of a 32x32
 // result tile; one exchange gives each lane a full 8-row column chunk.
@@ -945,11 +912,11 @@ __global__ void __launch_bounds__(256) k_xf1_pk(Mesh mesh, int q, int naux, int 
     const int kmq = mesh_sub(mesh, k, q);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
-    const __bf16* pa = plm + ((size_t)q * nk + k) * 3 * NS * (size_t)ngv * M1 * 8;
-    const __bf16* pb = pc1 + (size_t)kmq * 3 * NS * (size_t)ngv * NB * 8;
-    f16v acc[3][TM][TN];
+    const __bf16* pa = plm + ((size_t)q * nk + k) * P2 * NS * (size_t)ngv * M1 * 8;
+    const __bf16* pb = pc1 + (size_t)kmq * P2 * NS * (size_t)ngv * NB * 8;
+    f16v acc[4][TM][TN];
 #pragma unroll
-    for (int p = 0; p < 3; ++p)
+    for (int p = 0; p < 4; ++p)
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -976,13 +943,12 @@ __global__ void __launch_bounds__(256) k_xf1_pk(Mesh mesh, int q, int naux, int 
                     float mine[4], send[4], recv[4];
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const float p1 = acc[0][i][j][4 * qq + r], p2 = acc[1][i][j][4 * qq + r],
-                                    p3v = acc[2][i][j][4 * qq + r];
-                        const float p1b = acc[0][i][j][4 * (qq + 1) + r], p2b = acc[1][i][j][4 * (qq + 1) + r],
-                                    p3b = acc[2][i][j][4 * (qq + 1) + r];
-                        // 3M: re = P1 - P2, im = P3 - P1 - P2
-                        const float va = p3 == 0 ? p1 - p2 : p3v - p1 - p2;
-                        const float vb = p3 == 0 ? p1b - p2b : p3b - p1b - p2b;
+                        // 4M: re = Ar Br - Ai Bi, im = Ar Bi + Ai Br
+                        const int ra = 4 * qq + r, rb = 4 * (qq + 1) + r;
+                        const float va = p3 == 0 ? acc[0][i][j][ra] - acc[1][i][j][ra]
+                                                 : acc[2][i][j][ra] + acc[3][i][j][ra];
+                        const float vb = p3 == 0 ? acc[0][i][j][rb] - acc[1][i][j][rb]
+                                                 : acc[2][i][j][rb] + acc[3][i][j][rb];
                         mine[r] = h == 0 ? va : vb;
                         send[r] = h == 0 ? vb : va;
                     }
@@ -1120,11 +1086,11 @@ __global__ void __launch_bounds__(256) k_xf1_batched(Mesh mesh, int q, int naux,
     const int kmq = mesh_sub(mesh, k, q);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
-    const __bf16* pa = plm + ((size_t)q * nk + k) * 3 * NS * (size_t)ngv * M1 * 8;
-    const __bf16* pb = pc1 + (size_t)kmq * 3 * NS * (size_t)ngv * NB * 8;
-    f16v acc[3][TM][TN];
+    const __bf16* pa = plm + ((size_t)q * nk + k) * P2 * NS * (size_t)ngv * M1 * 8;
+    const __bf16* pb = pc1 + (size_t)kmq * P2 * NS * (size_t)ngv * NB * 8;
+    f16v acc[4][TM][TN];
 #pragma unroll
-    for (int p = 0; p < 3; ++p)
+    for (int p = 0; p < 4; ++p)
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -1149,13 +1115,12 @@ __global__ void __launch_bounds__(256) k_xf1_batched(Mesh mesh, int q, int naux,
                     float mine[4], send[4], recv[4];
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const float p1 = acc[0][i][j][4 * qq + r], p2 = acc[1][i][j][4 * qq + r],
-                                    p3v = acc[2][i][j][4 * qq + r];
-                        const float p1b = acc[0][i][j][4 * (qq + 1) + r], p2b = acc[1][i][j][4 * (qq + 1) + r],
-                                    p3b = acc[2][i][j][4 * (qq + 1) + r];
-                        // 3M: re = P1 - P2, im = P3 - P1 - P2
-                        const float va = p3 == 0 ? p1 - p2 : p3v - p1 - p2;
-                        const float vb = p3 == 0 ? p1b - p2b : p3b - p1b - p2b;
+                        // 4M: re = Ar Br - Ai Bi, im = Ar Bi + Ai Br
+                        const int ra = 4 * qq + r, rb = 4 * (qq + 1) + r;
+                        const float va = p3 == 0 ? acc[0][i][j][ra] - acc[1][i][j][ra]
+                                                 : acc[2][i][j][ra] + acc[3][i][j][ra];
+                        const float vb = p3 == 0 ? acc[0][i][j][rb] - acc[1][i][j][rb]
+                                                 : acc[2][i][j][rb] + acc[3][i][j][rb];
                         mine[r] = h == 0 ? va : vb;
                         send[r] = h == 0 ? vb : va;
                     }
@@ -1367,7 +1332,7 @@ template <int NS, int BM>
 constexpr size_t persist_lds() { return (size_t)(BM == 128 ? 3 : 2) * 2 * NS * 2 * BM * 16; }
 
 template <int NS>
-constexpr size_t xf1_lds() { return (size_t)2 * 3 * NS * 2 * (128 + 128) * 16; }
+constexpr size_t xf1_lds() { return (size_t)2 * P2 * NS * 2 * (128 + 128) * 16; }
 template <int NS>
 constexpr size_t xf2_lds() { return (size_t)2 * P2 * NS * 2 * (64 + 64) * 16; }
 
@@ -1405,9 +1370,9 @@ static PkDims pk_dims(const EriPlan& p) {
     d.M1 = p.naux * d.nao_p;
     d.NB = p.nspin * p.neo;
     d.N2 = (size_t)p.naux * p.neo;
-    const size_t pl = (size_t)3 * d.ns * 8, pl2 = (size_t)P2 * d.ns * 8;
-    d.lm_elems = (size_t)p.mesh.nk * p.mesh.nk * pl * d.ngv * d.M1;
-    d.c1_elems = (size_t)p.mesh.nk * pl * d.ngv * d.NB;
+    const size_t pl2 = (size_t)P2 * d.ns * 8;
+    d.lm_elems = (size_t)p.mesh.nk * p.mesh.nk * pl2 * d.ngv * d.M1;
+    d.c1_elems = (size_t)p.mesh.nk * pl2 * d.ngv * d.NB;
     d.c2_elems = (size_t)p.nspin * pl2 * d.ng2 * p.neo;
     d.t_elems = (size_t)p.nspin * pl2 * d.ng2 * d.N2;
     return d;
@@ -1780,10 +1745,10 @@ static void plan_batch(BatchPlan& bp) {
     bp.off_bq = off(sizeof(BQ) * std::max<size_t>(1, bp.h_bq.size()));
     bp.off_itemsc = off(sizeof(BItemC) * std::max(bp.h_itemsc[0].size(), bp.h_itemsc[1].size()) + 16);
     bp.off_q = off(sizeof(int) * 3 * NXCD);
-    const size_t pl = (size_t)3 * NS * 8, pl2 = (size_t)P2 * NS * 8;
+    const size_t pl2 = (size_t)P2 * NS * 8;
     for (auto& G : bp.groups) {
-        G.off_plm = off(sizeof(__bf16) * (size_t)G.mesh.nk * G.mesh.nk * pl * G.ngv * G.M1);
-        G.off_pc1 = off(sizeof(__bf16) * (size_t)G.mesh.nk * pl * G.ngv * G.nbtot);
+        G.off_plm = off(sizeof(__bf16) * (size_t)G.mesh.nk * G.mesh.nk * pl2 * G.ngv * G.M1);
+        G.off_pc1 = off(sizeof(__bf16) * (size_t)G.mesh.nk * pl2 * G.ngv * G.nbtot);
     }
     for (auto& F : bp.fs) {
         const BatchGroup& G = bp.groups[F.group];
