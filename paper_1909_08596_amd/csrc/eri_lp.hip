@@ -1201,6 +1201,118 @@ __global__ void __launch_bounds__(256) k_xf2_batched(int nitems, const BItem2* _
     }
 }
 
+// Stage 2 of small fragments with 32 x 32 tiles: the four waves of a
+// workgroup take the same (i, j) tile of four consecutive fitting functions
+// (item.L is the group of four), so the operand that does not depend on L
+// (conj C) is staged once for the four.  Against 64 x 64 tiles of one L it
+// pads a triangle of neo x neo pairs far less when neo is small.  The k <->
+// q-k passes, group walk and 4M products are those of pk_loop_paired.
+// LDS per stage: [conj C tile][T tile of L0] .. [T tile of L3], each
+// P2 x NS x 2 groups x 32 rows.
+constexpr int L4_ROWS = 32;
+
+template <int NS>
+constexpr size_t xf2_l4_lds() { return (size_t)2 * 5 * P2 * NS * 2 * L4_ROWS * 16; }
+
+// one 32-row tile operand (P2 x NS parts x groups g0, g1 x 32 rows) of a
+// stage, loaded by one wave: lanes 0-31 take group g0, lanes 32-63 group g1
+template <int NS>
+__device__ inline void l4_issue(const __bf16* base, size_t pt_stride, int X, int x0, int g0, int g1, bf8* dst) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 5, x = min(x0 + (lane & 31), X - 1);
+#pragma unroll
+    for (int pt = 0; pt < P2 * NS; ++pt) {
+        const __bf16* src = base + ((size_t)pt * pt_stride + (size_t)(g ? g1 : g0) * X + x) * 8;
+        __builtin_amdgcn_global_load_lds((const void*)src, DMET_LDS_PTR(dst + pt * 2 * L4_ROWS), 16, 0, 0);
+    }
+}
+
+template <int NS>
+__global__ void __launch_bounds__(256) k_xf2_batched_l4(int nitems, const BItem2* __restrict__ items,
+                                                        const BFrag* __restrict__ frags, const BQ* __restrict__ qs) {
+    constexpr int TCH = P2 * NS * 2 * L4_ROWS;      // chunks of one tile operand
+    constexpr int STAGE = 5 * TCH;
+    extern __shared__ __align__(16) bf8 ring[];
+    const long it_id = xcd_logical(blockIdx.x, gridDim.x);
+    if (it_id >= nitems) return;
+    const BItem2 item = items[it_id];
+    const BFrag fr = frags[item.slot];
+    const BQ& qb = qs[item.slot];
+    const int neo = fr.neo, naux = fr.naux;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int L = 4 * item.L + wave;
+    const int Lc = min(L, naux - 1);                 // a wave past naux stages a valid block, stores nothing
+    const int m0 = item.it * L4_ROWS, j0 = item.jt * L4_ROWS;
+    const int N2 = naux * neo;
+    const size_t cst = (size_t)fr.ng2 * neo, tst = (size_t)fr.ng2 * N2;
+    const int gpk = qb.gpk, zg = qb.zg;
+    const int n1 = (qb.npaired + qb.nself) * gpk, n2 = qb.npaired * gpk;
+    const int s1 = (n1 + 1) / 2, nst = s1 + (n2 + 1) / 2;
+    f16v acc[4][1][1];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[c][0][0][r] = 0.f;
+    // running group walk (as in pk_loop_paired)
+    int pass = 0, j = 0, slot = 0, gl = 0, cnt = 0;
+    auto next = [&](int& gc, int& gt) {
+        if (j < (pass ? n2 : n1)) {
+            gc = (int)qb.k[slot] * gpk + gl;
+            gt = j;
+            ++j;
+            if (++gl == gpk) {
+                gl = 0;
+                ++slot;
+            }
+        } else {
+            gc = gt = zg;
+        }
+    };
+    // wave w stages the T tile of its own L; wave 0 also the conj C tile
+    auto issue = [&](bf8* dst) {
+        if (pass == 0 && cnt == s1) {
+            pass = 1;
+            j = slot = gl = cnt = 0;
+        }
+        int gc0, gt0, gc1, gt1;
+        next(gc0, gt0);
+        next(gc1, gt1);
+        ++cnt;
+        const int xc = pass ? j0 : m0;                        // conj C rows
+        const int xt = Lc * neo + (pass ? m0 : j0);            // T columns of this wave's L
+        if (wave == 0) l4_issue<NS>(fr.pc2, cst, neo, xc, gc0, gc1, dst);
+        l4_issue<NS>(fr.ptt, tst, N2, xt, gt0, gt1, dst + (1 + wave) * TCH);
+    };
+    issue(ring);
+    for (int st = 0; st < nst; ++st) {
+        bf8* cur = ring + (size_t)(st & 1) * STAGE;
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // own loads of stage st landed
+        __builtin_amdgcn_s_barrier();         // everyone's loads landed; stage st-1 fully read
+        __builtin_amdgcn_sched_barrier(0);
+        if (st + 1 < nst) issue(ring + (size_t)((st + 1) & 1) * STAGE);
+        const bf8* sc = cur;                      // conj C tile
+        const bf8* stt = cur + (1 + wave) * TCH;  // T tile of this wave's L
+        if (st < s1) pk_mma4<NS, L4_ROWS, L4_ROWS, 1, 1>(sc, stt, 0, 0, acc);
+        else pk_mma4<NS, L4_ROWS, L4_ROWS, 1, 1>(stt, sc, 0, 0, acc);
+    }
+    if (L >= naux) return;
+    const size_t ldz = (size_t)fr.npair;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = m0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int jj = j0 + (lane & 31);
+        if (i >= neo || jj >= neo || jj > i) continue;
+        const size_t pair = (size_t)i * (i + 1) / 2 + jj;
+        const float xr = acc[0][0][0][r] - acc[1][0][0][r], xi = acc[2][0][0][r] + acc[3][0][0][r];
+        if (qb.self_conj) {
+            fr.z[(qb.zrow0 + L) * ldz + pair] = qb.wq * xr;
+        } else {
+            fr.z[(qb.zrow0 + 2 * (size_t)L) * ldz + pair] = qb.wq * xr;
+            fr.z[(qb.zrow0 + 2 * (size_t)L + 1) * ldz + pair] = qb.wq * xi;
+        }
+    }
+}
+
 // Persistent packed contraction over the tiles of all fragments.  Workgroup b
 // pops items from the queue of XCD b % 8 (items of one 8 x 8 super-block of one
 // fragment are in one queue, so tiles sharing panels run on one XCD).
@@ -1578,6 +1690,16 @@ struct BatchFrag {
     size_t off_pc2, off_ptt, off_z, off_zp;
 };
 
+// Fragments with at most this many embedding orbitals take the 32 x 32
+// four-L stage-2 tiles in the batched pipeline (DMET_XF2_SMALL_NEO overrides).
+// On 64 fragments with neo 21-199 all-32 x 32 was fastest (495 ms against 511
+// for all-64 x 64); a split at 128 was slower than either (532: two launches
+// per round, each with fewer workgroups).
+static int xf2_small_neo() {
+    const char* e = getenv("DMET_XF2_SMALL_NEO");
+    return e ? atoi(e) : 256;
+}
+
 struct BatchPlan {
     std::vector<dmet_fragment> frags;
     int prec = 0, ns = 0;
@@ -1587,7 +1709,8 @@ struct BatchPlan {
     std::vector<BatchFrag> fs;
     int rounds = 0;
     size_t off_bfrag = 0, off_items2 = 0, off_bq = 0, off_itemsc = 0, off_q = 0;
-    std::vector<int> items2_off, items2_cnt;
+    std::vector<int> items2_off, items2_cnt;     // 64 x 64 stage-2 items per round
+    std::vector<int> items2s_off, items2s_cnt;   // 32 x 32 four-L items (small fragments) per round
     std::vector<BFrag> h_bfrag;
     std::vector<int2> h_colmap;
     std::vector<BItem2> h_items2;
@@ -1672,6 +1795,9 @@ static void plan_batch(BatchPlan& bp) {
     bp.h_bq.assign((size_t)bp.rounds * nfrag, BQ{});
     bp.items2_off.assign(bp.rounds, 0);
     bp.items2_cnt.assign(bp.rounds, 0);
+    bp.items2s_off.assign(bp.rounds, 0);
+    bp.items2s_cnt.assign(bp.rounds, 0);
+    const int small_neo = xf2_small_neo();
     for (int r = 0; r < bp.rounds; ++r) {
         bp.items2_off[r] = (int)bp.h_items2.size();
         for (int f = 0; f < nfrag; ++f) {
@@ -1687,12 +1813,25 @@ static void plan_batch(BatchPlan& bp) {
             for (int sl = 0; sl < b.npaired + b.nself; ++sl) b.k[sl] = (short)kpair_slot_k(G.mesh, qb.q, sl);
             b.gpk = G.nao_p / 8;
             b.zg = G.mesh.nk * b.gpk;
+            if (F.neo <= small_neo) continue;
             const int nt = (F.neo + 63) / 64;
             for (int L = 0; L < G.naux; ++L)
                 for (int jt = 0; jt < nt; ++jt)
                     for (int it = jt; it < nt; ++it) bp.h_items2.push_back(BItem2{f, L, jt, it});
         }
         bp.items2_cnt[r] = (int)bp.h_items2.size() - bp.items2_off[r];
+        // small fragments: 32 x 32 tiles, four fitting functions per item
+        bp.items2s_off[r] = (int)bp.h_items2.size();
+        for (int f = 0; f < nfrag; ++f) {
+            const BatchFrag& F = bp.fs[f];
+            const BatchGroup& G = bp.groups[F.group];
+            if (r >= (int)G.qbs.size() || F.neo > small_neo) continue;
+            const int nt = (F.neo + L4_ROWS - 1) / L4_ROWS, nlg = (G.naux + 3) / 4;
+            for (int lg = 0; lg < nlg; ++lg)
+                for (int jt = 0; jt < nt; ++jt)
+                    for (int it = jt; it < nt; ++it) bp.h_items2.push_back(BItem2{f, lg, jt, it});
+        }
+        bp.items2s_cnt[r] = (int)bp.h_items2.size() - bp.items2s_off[r];
     }
     for (int v = 0; v < 2; ++v) {
         const int BM = v == 0 ? 128 : 64;
@@ -1777,6 +1916,8 @@ static dmet_status batch_prepare() {
                                  (int)xf1_lds<NS>()));
     DMET_HIP(hipFuncSetAttribute((const void*)k_xf2_batched<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)xf2_lds<NS>()));
+    DMET_HIP(hipFuncSetAttribute((const void*)k_xf2_batched_l4<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)xf2_l4_lds<NS>()));
     DMET_HIP(hipFuncSetAttribute((const void*)k_contract_persist<NS, 128>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)persist_lds<NS, 128>()));
     DMET_HIP(hipFuncSetAttribute((const void*)k_contract_persist<NS, 64>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1852,14 +1993,23 @@ static dmet_status batch_enqueue(BatchPlan& bp, int variant, bool prof, hipStrea
         }
         done(ps);
         DMET_LAUNCH_CHECK("batch xform1");
-        if (bp.items2_cnt[r] > 0) {
+        if (bp.items2_cnt[r] + bp.items2s_cnt[r] > 0) {
             ps = scope(NS == 3 ? "batch_xform2_bf16x6" : "batch_xform2_bf16x3");
-            const long nb = ((long)bp.items2_cnt[r] + NXCD - 1) / NXCD * NXCD;
-            k2<<<dim3((unsigned)nb), 256, xf2_lds<NS>(), st>>>(bp.items2_cnt[r],
-                                                              at<BItem2>(ws, bp.off_items2) + bp.items2_off[r], dfr,
-                                                              at<BQ>(ws, bp.off_bq) + (size_t)r * nfrag);
+            if (bp.items2_cnt[r] > 0) {
+                const long nb = ((long)bp.items2_cnt[r] + NXCD - 1) / NXCD * NXCD;
+                k2<<<dim3((unsigned)nb), 256, xf2_lds<NS>(), st>>>(bp.items2_cnt[r],
+                                                                  at<BItem2>(ws, bp.off_items2) + bp.items2_off[r],
+                                                                  dfr, at<BQ>(ws, bp.off_bq) + (size_t)r * nfrag);
+                DMET_LAUNCH_CHECK("batch xform2");
+            }
+            if (bp.items2s_cnt[r] > 0) {
+                const long nb = ((long)bp.items2s_cnt[r] + NXCD - 1) / NXCD * NXCD;
+                k_xf2_batched_l4<NS><<<dim3((unsigned)nb), 256, xf2_l4_lds<NS>(), st>>>(
+                    bp.items2s_cnt[r], at<BItem2>(ws, bp.off_items2) + bp.items2s_off[r], dfr,
+                    at<BQ>(ws, bp.off_bq) + (size_t)r * nfrag);
+                DMET_LAUNCH_CHECK("batch xform2 (32 x 32)");
+            }
             done(ps);
-            DMET_LAUNCH_CHECK("batch xform2");
         }
     }
     // 3. split Z into bf16 parts
