@@ -30,14 +30,19 @@ __device__ inline double ld<float>(const float* p, size_t i) { return (double)p[
 // A: lmunu[q][k] rows (L,mu), K = (nu, re/im) contiguous; B: real embedding
 // of C^{k-q}: B[(nu,c')][(j,c)] = [[Cr, Ci], [-Ci, Cr]][c'][c].
 // Output T[k][mu][L][(j,c)] (interleaved complex, row length 2 neo).
+// Both stages gather the next BK-deep slice of A and B into registers while
+// the MFMAs run on the current one, then store it into the other half of a
+// double-buffered LDS tile (one barrier per slice).
 template <int BM, int BN, int BK, class TIn>
 __global__ void __launch_bounds__(256) k_xform1_f64(Mesh mesh, int q, int nao, int naux, int neo,
                                                     const TIn* __restrict__ lmunu,
                                                     const double* __restrict__ ck,
                                                     double* __restrict__ tout) {
     using T = F64Tile<BM, BN, BK>;
-    __shared__ double As[BK * T::LDA];
-    __shared__ double Bs[BK * T::LDB];
+    constexpr int NA = BM * BK / 256, NB = BK * BN / 256;
+    static_assert(NA * 256 == BM * BK && NB * 256 == BK * BN, "slice per thread");
+    __shared__ double As[2][BK * T::LDA];
+    __shared__ double Bs[2][BK * T::LDB];
     const int k = blockIdx.z;
     const int kmq = mesh_sub(mesh, k, q);
     const int M = naux * nao, K = 2 * nao, N = 2 * neo;
@@ -47,14 +52,17 @@ __global__ void __launch_bounds__(256) k_xform1_f64(Mesh mesh, int q, int nao, i
     d4 acc[BM / 32][BN / 32];
     zero_acc<BM, BN>(acc);
     const int tid = threadIdx.x;
-    for (int k0 = 0; k0 < K; k0 += BK) {
-        for (int e = tid; e < BM * BK; e += 256) {
-            const int kk = e % BK, mm = e / BK;
+    double ra[NA], rb[NB];
+    auto gather = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int e = tid + u * 256, kk = e % BK, mm = e / BK;
             const int gm = m0 + mm, gk = k0 + kk;
-            As[kk * T::LDA + mm] = (gm < M && gk < K) ? ld(a_base, (size_t)gm * K + gk) : 0.0;
+            ra[u] = (gm < M && gk < K) ? ld(a_base, (size_t)gm * K + gk) : 0.0;
         }
-        for (int e = tid; e < BK * BN; e += 256) {
-            const int nn = e % BN, kk = e / BN;
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int e = tid + u * 256, nn = e % BN, kk = e / BN;
             const int gn = n0 + nn, gk = k0 + kk;
             double v = 0.0;
             if (gn < N && gk < K) {
@@ -62,10 +70,29 @@ __global__ void __launch_bounds__(256) k_xform1_f64(Mesh mesh, int q, int nao, i
                 const double cr = c_base[((size_t)nu * neo + j) * 2], ci = c_base[((size_t)nu * neo + j) * 2 + 1];
                 v = cp == 0 ? (c == 0 ? cr : ci) : (c == 0 ? -ci : cr);
             }
-            Bs[kk * T::LDB + nn] = v;
+            rb[u] = v;
         }
-        __syncthreads();
-        f64_mma<BM, BN, BK>(As, Bs, acc);
+    };
+    auto stash = [&](int b) {
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int e = tid + u * 256;
+            As[b][(e % BK) * T::LDA + e / BK] = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int e = tid + u * 256;
+            Bs[b][(e / BN) * T::LDB + e % BN] = rb[u];
+        }
+    };
+    const int nkt = (K + BK - 1) / BK;
+    gather(0);
+    stash(0);
+    __syncthreads();
+    for (int it = 0; it < nkt; ++it) {
+        if (it + 1 < nkt) gather((it + 1) * BK);
+        f64_mma<BM, BN, BK>(As[it & 1], Bs[it & 1], acc);
+        if (it + 1 < nkt) stash((it + 1) & 1);
         __syncthreads();
     }
     f64_visit<BM, BN, BK>(acc, [&](int r, int c, double v) {
@@ -87,8 +114,10 @@ __global__ void __launch_bounds__(256) k_xform2_f64(Mesh mesh, int nao, int naux
                                                     const double* __restrict__ tin, double* __restrict__ z,
                                                     size_t ldz) {
     using T = F64Tile<BM, BN, BK>;
-    __shared__ double As[BK * T::LDA];
-    __shared__ double Bs[BK * T::LDB];
+    constexpr int NA = BM * BK / 256, NB = BK * BN / 256;
+    static_assert(NA * 256 == BM * BK && NB * 256 == BK * BN, "slice per thread");
+    __shared__ double As[2][BK * T::LDA];
+    __shared__ double Bs[2][BK * T::LDB];
     const int N2 = 2 * neo;
     const int njt = (N2 + BN - 1) / BN;
     const int L = blockIdx.y / njt, jt = blockIdx.y % njt;
@@ -99,19 +128,22 @@ __global__ void __launch_bounds__(256) k_xform2_f64(Mesh mesh, int nao, int naux
     d4 acc[BM / 32][BN / 32];
     zero_acc<BM, BN>(acc);
     const int tid = threadIdx.x;
-    for (int k0 = 0; k0 < K; k0 += BK) {
-        for (int e = tid; e < BK * BM; e += 256) {
-            const int mm = e % BM, kk = e / BM;
+    double ra[NA], rb[NB];
+    auto gather = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int e = tid + u * 256, mm = e % BM, kk = e / BM;
             const int gm = m0 + mm, gk = k0 + kk;
             double v = 0.0;
             if (gm < neo && gk < K) {
                 const int kmu = gk >> 1, cp = gk & 1;
                 v = ck[((size_t)kmu * neo + gm) * 2 + cp];
             }
-            As[kk * T::LDA + mm] = v;
+            ra[u] = v;
         }
-        for (int e = tid; e < BK * BN; e += 256) {
-            const int nn = e % BN, kk = e / BN;
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int e = tid + u * 256, nn = e % BN, kk = e / BN;
             const int gn = n0 + nn, gk = k0 + kk;
             double v = 0.0;
             if (gn < N2 && gk < K) {
@@ -119,10 +151,29 @@ __global__ void __launch_bounds__(256) k_xform2_f64(Mesh mesh, int nao, int naux
                 const double* row = tin + ((size_t)kmu * naux + L) * N2 + 2 * j;
                 v = cp == 0 ? row[c] : (c == 0 ? row[1] : -row[0]);
             }
-            Bs[kk * T::LDB + nn] = v;
+            rb[u] = v;
         }
-        __syncthreads();
-        f64_mma<BM, BN, BK>(As, Bs, acc);
+    };
+    auto stash = [&](int b) {
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int e = tid + u * 256;
+            As[b][(e / BM) * T::LDA + e % BM] = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int e = tid + u * 256;
+            Bs[b][(e / BN) * T::LDB + e % BN] = rb[u];
+        }
+    };
+    const int nkt = (K + BK - 1) / BK;
+    gather(0);
+    stash(0);
+    __syncthreads();
+    for (int it = 0; it < nkt; ++it) {
+        if (it + 1 < nkt) gather((it + 1) * BK);
+        f64_mma<BM, BN, BK>(As[it & 1], Bs[it & 1], acc);
+        if (it + 1 < nkt) stash((it + 1) & 1);
         __syncthreads();
     }
     f64_visit<BM, BN, BK>(acc, [&](int r, int c, double v) {
@@ -300,8 +351,11 @@ __global__ void k_contract_f64_reduce(int npair, int nsplit, const double* __res
 }
 
 // ---------------------------------------------------------------- driver
-constexpr int X1_BM = 64, X1_BN = 64, X1_BK = 16;
-constexpr int X2_BM = 64, X2_BN = 64, X2_BK = 16;
+// stage 1: 128 x 128 tiles; stage 2: 64 x 64 (its i >= j triangle of neo x neo pairs per L pads
+// less, and the complex gather of T keeps registers high enough that larger tiles drop to one
+// wave per SIMD)
+constexpr int X1_BM = 128, X1_BN = 128, X1_BK = 8;
+constexpr int X2_BM = 64, X2_BN = 64, X2_BK = 8;
 
 // padded Z of the contraction: even row length, rows a multiple of 16
 static inline int f64_ldz(int npair) { return (npair + 1) / 2 * 2; }
