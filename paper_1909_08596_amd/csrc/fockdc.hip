@@ -56,37 +56,56 @@ __global__ void k_dc_j(int nrows, int npair, const double* __restrict__ z, const
 // K is symmetric, so k_dc_k forms only the 64 x 64 tiles with it >= jt.  Each
 // workgroup of k_dc_k reduces DK_PCW rows P into a partial tile of its own;
 // k_dc_final sums the partials in a fixed order (deterministic result).
+// Both GEMMs gather the next DBK-deep slice of their operands into registers
+// while the MFMAs run on the current one, into a double-buffered LDS tile.
 constexpr int DT = 64, DBK = 16;
+constexpr int DNE = DBK * DT / 256;              // slice elements per thread and operand
 constexpr int DK_PCW = 16;                       // rows P per k_dc_k workgroup
 constexpr size_t DW_CAP = size_t(1) << 30;       // bytes of W per chunk of rows P
 
 __global__ void __launch_bounds__(256) k_dc_w(long p0, int np, int neo, int npair, const double* __restrict__ z,
                                                const double* __restrict__ g, double* __restrict__ w) {
     using T = F64Tile<DT, DT, DBK>;
-    __shared__ double As[DBK * T::LDA];
-    __shared__ double Bs[DBK * T::LDB];
+    __shared__ double As[2][DBK * T::LDA];
+    __shared__ double Bs[2][DBK * T::LDB];
     const long M = (long)np * neo;
     const int n0 = blockIdx.x * DT;          // x fastest: tiles sharing A run together
     const long m0 = (long)blockIdx.y * DT;
     d4 acc[DT / 32][DT / 32];
     zero_acc<DT, DT>(acc);
     const int tid = threadIdx.x;
-    for (int k0 = 0; k0 < neo; k0 += DBK) {
-        for (int e = tid; e < DBK * DT; e += 256) {
-            const int kk = e % DBK, mm = e / DBK;
+    double ra[DNE], rb[DNE];
+    auto gather = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < DNE; ++u) {
+            const int e = tid + u * 256, kk = e % DBK, mm = e / DBK;
             const long m = m0 + mm;
             const int k = k0 + kk;
-            double v = 0.0;
-            if (m < M && k < neo) v = z[(p0 + m / neo) * npair + pidx((int)(m % neo), k)];
-            As[kk * T::LDA + mm] = v;
+            ra[u] = (m < M && k < neo) ? z[(p0 + m / neo) * npair + pidx((int)(m % neo), k)] : 0.0;
         }
-        for (int e = tid; e < DBK * DT; e += 256) {
-            const int nn = e % DT, kk = e / DT;
+#pragma unroll
+        for (int u = 0; u < DNE; ++u) {
+            const int e = tid + u * 256, nn = e % DT, kk = e / DT;
             const int k = k0 + kk, l = n0 + nn;
-            Bs[kk * T::LDB + nn] = (k < neo && l < neo) ? g[(size_t)k * neo + l] : 0.0;
+            rb[u] = (k < neo && l < neo) ? g[(size_t)k * neo + l] : 0.0;
         }
-        __syncthreads();
-        f64_mma<DT, DT, DBK>(As, Bs, acc);
+    };
+    auto stash = [&](int b) {
+#pragma unroll
+        for (int u = 0; u < DNE; ++u) {
+            const int e = tid + u * 256;
+            As[b][(e % DBK) * T::LDA + e / DBK] = ra[u];
+            Bs[b][(e / DT) * T::LDB + e % DT] = rb[u];
+        }
+    };
+    const int nkt = (neo + DBK - 1) / DBK;
+    gather(0);
+    stash(0);
+    __syncthreads();
+    for (int it = 0; it < nkt; ++it) {
+        if (it + 1 < nkt) gather((it + 1) * DBK);
+        f64_mma<DT, DT, DBK>(As[it & 1], Bs[it & 1], acc);
+        if (it + 1 < nkt) stash((it + 1) & 1);
         __syncthreads();
     }
     f64_visit<DT, DT, DBK>(acc, [&](int r, int c, double v) {
@@ -102,8 +121,8 @@ __global__ void __launch_bounds__(256) k_dc_k(long p0, int np, int neo, int npai
                                                const double* __restrict__ z, const double* __restrict__ w,
                                                double* __restrict__ part) {
     using T = F64Tile<DT, DT, DBK>;
-    __shared__ double As[DBK * T::LDA];
-    __shared__ double Bs[DBK * T::LDB];
+    __shared__ double As[2][DBK * T::LDA];
+    __shared__ double Bs[2][DBK * T::LDB];
     const int tri = blockIdx.x;
     int it = (int)((sqrt(8.0 * tri + 1.0) - 1.0) * 0.5);
     while (it * (it + 1) / 2 > tri) --it;
@@ -116,29 +135,47 @@ __global__ void __launch_bounds__(256) k_dc_k(long p0, int np, int neo, int npai
     d4 acc[DT / 32][DT / 32];
     zero_acc<DT, DT>(acc);
     const int tid = threadIdx.x;
-    for (int r0 = 0; r0 < R; r0 += DBK) {
-        for (int e = tid; e < DBK * DT; e += 256) {
-            const int kk = e % DBK, mm = e / DBK;
+    double ra[DNE], rb[DNE];
+    auto gather = [&](int r0) {
+#pragma unroll
+        for (int u = 0; u < DNE; ++u) {
+            const int e = tid + u * 256, kk = e % DBK, mm = e / DBK;
             const int r = r0 + kk, i = i0 + mm;
             double v = 0.0;
             if (r < R && i < neo) {
                 const int pl = pl0 + r / neo, l = r % neo;
                 v = w[((size_t)pl * neo + i) * neo + l];
             }
-            As[kk * T::LDA + mm] = v;
+            ra[u] = v;
         }
-        for (int e = tid; e < DBK * DT; e += 256) {
-            const int nn = e % DT, kk = e / DT;
+#pragma unroll
+        for (int u = 0; u < DNE; ++u) {
+            const int e = tid + u * 256, nn = e % DT, kk = e / DT;
             const int r = r0 + kk, j = j0 + nn;
             double v = 0.0;
             if (r < R && j < neo) {
                 const long P = p0 + pl0 + r / neo;
                 v = z[P * npair + pidx(r % neo, j)];
             }
-            Bs[kk * T::LDB + nn] = v;
+            rb[u] = v;
         }
-        __syncthreads();
-        f64_mma<DT, DT, DBK>(As, Bs, acc);
+    };
+    auto stash = [&](int b) {
+#pragma unroll
+        for (int u = 0; u < DNE; ++u) {
+            const int e = tid + u * 256;
+            As[b][(e % DBK) * T::LDA + e / DBK] = ra[u];
+            Bs[b][(e / DT) * T::LDB + e % DT] = rb[u];
+        }
+    };
+    const int nkt = (R + DBK - 1) / DBK;
+    gather(0);
+    stash(0);
+    __syncthreads();
+    for (int it = 0; it < nkt; ++it) {
+        if (it + 1 < nkt) gather((it + 1) * DBK);
+        f64_mma<DT, DT, DBK>(As[it & 1], Bs[it & 1], acc);
+        if (it + 1 < nkt) stash((it + 1) & 1);
         __syncthreads();
     }
     double* out = part + ((size_t)(split0 + blockIdx.y) * ntri + tri) * (DT * DT);
