@@ -60,61 +60,52 @@ __device__ inline int rr_player(int seat, int round, int n) {
     return seat == 0 ? 0 : 1 + (seat - 1 + round) % (n - 1);
 }
 
-// One workgroup per spin.  On exit the columns of mt are mutually orthogonal
-// (|a.b| <= tol |a||b|), flags[1 + s] holds the sweeps used.
-__global__ void __launch_bounds__(1024) k_jacobi(int m, int n, double* __restrict__ mt,
-                                                 int max_sweeps, double tol, int* flags) {
-    const int s = blockIdx.x;
-    double* a_base = mt + (size_t)s * n * m;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
-    const int np = n + (n & 1);  // even player count (a dummy column when n is odd)
-    __shared__ int rotations;
-    int sweep = 0;
-    bool converged = false;
-    for (; sweep < max_sweeps; ++sweep) {
-        if (threadIdx.x == 0) rotations = 0;
-        __syncthreads();
-        for (int round = 0; round < np - 1; ++round) {
-            for (int p = wave; p < np / 2; p += nwave) {
-                int ca = rr_player(p, round, np), cb = rr_player(np - 1 - p, round, np);
-                if (ca >= n || cb >= n) continue;
-                double* a = a_base + (size_t)ca * m;
-                double* b = a_base + (size_t)cb * m;
-                double al = 0.0, be = 0.0, ga = 0.0;
-                for (int i = lane; i < m; i += 64) {
-                    double x = a[i], y = b[i];
-                    al += x * x;
-                    be += y * y;
-                    ga += x * y;
-                }
-                al = wave_sum(al);
-                be = wave_sum(be);
-                ga = wave_sum(ga);
-                if (al == 0.0 || be == 0.0 || fabs(ga) <= tol * sqrt(al) * sqrt(be)) continue;
-                double zeta = (be - al) / (2.0 * ga);
-                double t;
-                if (fabs(zeta) > 1e150) t = 0.5 / zeta;
-                else t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-                for (int i = lane; i < m; i += 64) {
-                    double x = a[i], y = b[i];
-                    a[i] = c * x - sn * y;
-                    b[i] = sn * x + c * y;
-                }
-                if (lane == 0) atomicAdd(&rotations, 1);
-            }
-            __syncthreads();
-        }
-        if (rotations == 0) {
-            converged = true;
-            break;
-        }
-        __syncthreads();
+// One round of the cyclic round-robin ordering of the one-sided Jacobi SVD:
+// workgroup (p, s) orthogonalises column pair p of the round for spin s (the
+// pairs of a round are disjoint, so a round is one launch).  The three dot
+// products are reduced over the block in a fixed order; rot[s] counts the
+// rotations applied (a sweep with none has converged: |a.b| <= tol |a||b|
+// for every pair).
+__global__ void __launch_bounds__(256) k_jacobi_round(int m, int n, int np, int round,
+                                                      double* __restrict__ mt, double tol, int* rot) {
+    const int pr = blockIdx.x, s = blockIdx.y;
+    const int ca = rr_player(pr, round, np), cb = rr_player(np - 1 - pr, round, np);
+    if (ca >= n || cb >= n) return;   // the dummy column of an odd count (whole block)
+    double* a = mt + ((size_t)s * n + ca) * m;
+    double* b = mt + ((size_t)s * n + cb) * m;
+    double al = 0.0, be = 0.0, ga = 0.0;
+    for (int i = threadIdx.x; i < m; i += 256) {
+        const double x = a[i], y = b[i];
+        al += x * x;
+        be += y * y;
+        ga += x * y;
     }
-    if (threadIdx.x == 0) {
-        flags[2 + s] = sweep + 1;
-        if (!converged) atomicOr(flags, FLAG_NOCONV);
+    __shared__ double red[3][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    al = wave_sum(al);
+    be = wave_sum(be);
+    ga = wave_sum(ga);
+    if (lane == 0) {
+        red[0][wave] = al;
+        red[1][wave] = be;
+        red[2][wave] = ga;
     }
+    __syncthreads();
+    al = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    be = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    ga = (red[2][0] + red[2][1]) + (red[2][2] + red[2][3]);
+    if (al == 0.0 || be == 0.0 || fabs(ga) <= tol * sqrt(al) * sqrt(be)) return;   // same in every thread
+    const double zeta = (be - al) / (2.0 * ga);
+    double t;
+    if (fabs(zeta) > 1e150) t = 0.5 / zeta;
+    else t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+    for (int i = threadIdx.x; i < m; i += 256) {
+        const double x = a[i], y = b[i];
+        a[i] = c * x - sn * y;
+        b[i] = sn * x + c * y;
+    }
+    if (threadIdx.x == 0) atomicAdd(&rot[s], 1);
 }
 
 // sigma, descending order, normalised and sign-fixed left vectors.
@@ -264,7 +255,7 @@ struct BathPlan {
 
 struct BathWs {
     double* dm_r;
-    int* flags;        // [0] status bits, [2+s] sweeps, [4+s] kept bath
+    int* flags;        // [0] status bits, [4+s] kept bath, [8+s] rotations of the current sweep
     double* scal;      // [0] max |Im gamma^R|, [1] max |S - I|
     int* env;
     int* cols;
@@ -370,9 +361,25 @@ dmet_status build_bath(const dmet_lattice* lat, const double2* dm_k, int nimp, c
         DMET_LAUNCH_CHECK("k_build_m");
     }
     if (p.nenv > 0) {
+        // sweeps of np - 1 rounds until a sweep applies no rotation (the
+        // rotation counts of the sweep are read back, at most 60 sweeps)
         const double tol = fmax(1e-15, sqrt((double)p.nenv) * 2.220446049250313e-16);
-        k_jacobi<<<p.nspin, 1024, 0, st>>>(p.nenv, nval, w.mt, 60, tol, w.flags);
-        DMET_LAUNCH_CHECK("k_jacobi");
+        const int np = nval + (nval & 1);
+        int* rot = w.flags + 8;
+        bool converged = false;
+        for (int sweep = 0; sweep < 60 && !converged; ++sweep) {
+            fill_zero(rot, 2 * sizeof(int), st);
+            for (int round = 0; round < np - 1; ++round)
+                k_jacobi_round<<<dim3(np / 2, p.nspin), 256, 0, st>>>(p.nenv, nval, np, round, w.mt, tol, rot);
+            DMET_LAUNCH_CHECK("k_jacobi_round");
+            int h_rot[2] = {0, 0};
+            DMET_HIP(hipMemcpyAsync(h_rot, rot, sizeof(int) * p.nspin, hipMemcpyDeviceToHost, st));
+            DMET_HIP(hipStreamSynchronize(st));
+            converged = true;
+            for (int sp = 0; sp < p.nspin; ++sp)
+                if (h_rot[sp] != 0) converged = false;
+        }
+        if (!converged) return fail(DMET_E_NOCONV, "Jacobi SVD did not converge in 60 sweeps");
         const size_t shm = (size_t)nval * (sizeof(double) + sizeof(int));
         k_svd_finalize<<<p.nspin, 1024, shm, st>>>(p.nenv, nval, w.mt, w.ub, sv, sv_tol, w.flags);
         DMET_LAUNCH_CHECK("k_svd_finalize");
