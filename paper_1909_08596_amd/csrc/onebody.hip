@@ -6,56 +6,94 @@
 
 namespace dmet {
 
-constexpr int OB_T = 32;   // output tile (i, j)
-constexpr int OB_C = 16;   // mu chunk staged in LDS
+// Each workgroup owns a 64 x 32 tile (i, j) of one spin's output and walks k and mu chunks of 32:
+//   T[mu][j] = sum_nu X^k[mu][nu] C^k[nu][j]   (nu in slices of 16 staged through LDS, the next
+//                                              slice prefetched into registers during the current)
+//   out[i][j] += sum_mu conj(C^k[mu][i]) T[mu][j]
+constexpr int OB_TI = 64, OB_TJ = 32, OB_MC = 32, OB_NC = 16;
 
 __global__ void __launch_bounds__(256) k_onebody(Mesh mesh, int nao, int neo, const double2* __restrict__ ck,
                                                  const double2* __restrict__ op, double* __restrict__ out,
                                                  double* __restrict__ max_imag) {
     const int s = blockIdx.z;
-    const int i0 = blockIdx.y * OB_T, j0 = blockIdx.x * OB_T;
-    __shared__ double2 t_sh[OB_C][OB_T];   // T[mu][j] = sum_nu X[mu][nu] C[nu][j]
-    __shared__ double2 c_sh[OB_C][OB_T];   // C[mu][i]
+    const int i0 = blockIdx.y * OB_TI, j0 = blockIdx.x * OB_TJ;
+    __shared__ double2 xs[2][OB_MC][OB_NC];   // X[mu][nu] slice
+    __shared__ double2 cs[2][OB_NC][OB_TJ];   // C[nu][j] slice
+    __shared__ double2 ts[OB_MC][OB_TJ];      // T[mu][j] of the current mu chunk
     const int tid = threadIdx.x;
-    const int ti = tid / 8, tj = tid % 8;  // each thread: i = i0+ti, j = j0+tj+8*r
-    double re[4] = {0, 0, 0, 0}, im[4] = {0, 0, 0, 0};
-    for (int k = 0; k < mesh.nk; ++k) {
-        const double2* c = ck + ((size_t)s * mesh.nk + k) * nao * neo;
+    const int tj = tid % OB_TJ, tm = tid / OB_TJ;     // T: mu = tm + 8 m, m < 4
+    const int oi = tid % OB_TI, og = tid / OB_TI;     // out: i = oi, j = 8 og + r, r < 8
+    const int nmc = (nao + OB_MC - 1) / OB_MC, nnc = (nao + OB_NC - 1) / OB_NC;
+    const int total = mesh.nk * nmc * nnc;
+    double2 rx[2], rc[2];
+    auto gather = [&](int it) {
+        const int nc = it % nnc, mc = (it / nnc) % nmc, k = it / (nnc * nmc);
         const double2* x = op + ((size_t)s * mesh.nk + k) * nao * nao;
-        for (int m0 = 0; m0 < nao; m0 += OB_C) {
-            __syncthreads();
-            for (int e = tid; e < OB_C * OB_T; e += 256) {
-                const int mu = m0 + e / OB_T, jj = e % OB_T;
-                double2 tv = make_double2(0.0, 0.0), cv = make_double2(0.0, 0.0);
-                if (mu < nao) {
-                    if (j0 + jj < neo) {
-                        for (int nu = 0; nu < nao; ++nu) {
-                            const double2 a = x[(size_t)mu * nao + nu];
-                            const double2 b = c[(size_t)nu * neo + j0 + jj];
-                            tv.x += a.x * b.x - a.y * b.y;
-                            tv.y += a.x * b.y + a.y * b.x;
-                        }
-                    }
-                    if (i0 + jj < neo) cv = c[(size_t)mu * neo + i0 + jj];
-                }
-                t_sh[e / OB_T][jj] = tv;
-                c_sh[e / OB_T][jj] = cv;
+        const double2* c = ck + ((size_t)s * mesh.nk + k) * nao * neo;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int e = tid + 256 * u;
+            const int xm = mc * OB_MC + e / OB_NC, xn = nc * OB_NC + e % OB_NC;
+            rx[u] = (xm < nao && xn < nao) ? x[(size_t)xm * nao + xn] : make_double2(0.0, 0.0);
+            const int cn = nc * OB_NC + e / OB_TJ, cj = j0 + e % OB_TJ;
+            rc[u] = (cn < nao && cj < neo) ? c[(size_t)cn * neo + cj] : make_double2(0.0, 0.0);
+        }
+    };
+    auto stash = [&](int b) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int e = tid + 256 * u;
+            xs[b][e / OB_NC][e % OB_NC] = rx[u];
+            cs[b][e / OB_TJ][e % OB_TJ] = rc[u];
+        }
+    };
+    double2 tacc[4] = {};
+    double re[8] = {}, im[8] = {};
+    gather(0);
+    stash(0);
+    __syncthreads();
+    for (int it = 0; it < total; ++it) {
+        const int b = it & 1;
+        if (it + 1 < total) gather(it + 1);
+#pragma unroll
+        for (int n = 0; n < OB_NC; ++n) {
+            const double2 cv = cs[b][n][tj];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const double2 xv = xs[b][tm + 8 * m][n];
+                tacc[m].x += xv.x * cv.x - xv.y * cv.y;
+                tacc[m].y += xv.x * cv.y + xv.y * cv.x;
+            }
+        }
+        if (it % nnc == nnc - 1) {      // T of this mu chunk is complete
+            const int mc = (it / nnc) % nmc, k = it / (nnc * nmc);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                ts[tm + 8 * m][tj] = tacc[m];
+                tacc[m] = make_double2(0.0, 0.0);
             }
             __syncthreads();
-            for (int mm = 0; mm < OB_C; ++mm) {
-                const double2 a = c_sh[mm][ti];          // conj taken below
-                for (int r = 0; r < 4; ++r) {
-                    const double2 b = t_sh[mm][tj + 8 * r];
-                    re[r] += a.x * b.x + a.y * b.y;
-                    im[r] += a.x * b.y - a.y * b.x;
+            const double2* c = ck + ((size_t)s * mesh.nk + k) * nao * neo;
+            const int mlen = min(OB_MC, nao - mc * OB_MC);
+            const bool iok = i0 + oi < neo;
+            for (int mm = 0; mm < mlen; ++mm) {
+                const double2 a = iok ? c[(size_t)(mc * OB_MC + mm) * neo + i0 + oi] : make_double2(0.0, 0.0);
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const double2 t = ts[mm][8 * og + r];
+                    re[r] += a.x * t.x + a.y * t.y;      // conj(a) * t
+                    im[r] += a.x * t.y - a.y * t.x;
                 }
             }
         }
+        if (it + 1 < total) stash(b ^ 1);
+        __syncthreads();
     }
     double mi = 0.0;
-    const int i = i0 + ti;
-    for (int r = 0; r < 4; ++r) {
-        const int j = j0 + tj + 8 * r;
+    const int i = i0 + oi;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int j = j0 + 8 * og + r;
         if (i < neo && j < neo) {
             out[((size_t)s * neo + i) * neo + j] = re[r] / mesh.nk;
             mi = fmax(mi, fabs(im[r] / mesh.nk));
@@ -90,8 +128,8 @@ dmet_status transform_1e(const dmet_lattice* lat, int neo, const double2* ck, co
                          double* out, double* max_imag, hipStream_t st) {
     Mesh mesh = make_mesh(lat->kmesh);
     if (max_imag) fill_zero(max_imag, sizeof(double), st);
-    const int nt = (neo + OB_T - 1) / OB_T;
-    k_onebody<<<dim3(nt, nt, lat->nspin), 256, 0, st>>>(mesh, lat->nao, neo, ck, op, out, max_imag);
+    const int ntj = (neo + OB_TJ - 1) / OB_TJ, nti = (neo + OB_TI - 1) / OB_TI;
+    k_onebody<<<dim3(ntj, nti, lat->nspin), 256, 0, st>>>(mesh, lat->nao, neo, ck, op, out, max_imag);
     DMET_LAUNCH_CHECK("k_onebody");
     return DMET_OK;
 }
