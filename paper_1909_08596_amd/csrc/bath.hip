@@ -108,6 +108,98 @@ __global__ void __launch_bounds__(256) k_jacobi_round(int m, int n, int np, int 
     if (threadIdx.x == 0) atomicAdd(&rot[s], 1);
 }
 
+// Block form of the same sweep: the columns are grouped in blocks of JB and
+// a round-robin round pairs the blocks.  Workgroup (p, s) stages the 2 JB
+// columns of its block pair in LDS and applies one cyclic sweep over every
+// pair among them (2 JB - 1 inner rounds of JB disjoint pairs, one wave per
+// pair, dot products reduced over the wave in a fixed order).  An outer sweep
+// (nbp - 1 launches) therefore visits every column pair at least once, and a
+// sweep with no rotation has converged exactly as in the per-pair form.
+// Columns of a missing block (odd block count) or past n take no part.
+constexpr int JB = 4;
+constexpr int JB_MAXM = 2400;   // rows that fit: 2 JB m doubles of LDS
+
+__global__ void __launch_bounds__(64 * JB) k_jacobi_block(int m, int n, int nbp, int round,
+                                                          double* __restrict__ mt, double tol, int* rot) {
+    extern __shared__ double colsh[];   // [2 JB][m]
+    const int pr = blockIdx.x, s = blockIdx.y;
+    const int nb = (n + JB - 1) / JB;
+    const int ba = rr_player(pr, round, nbp), bb = rr_player(nbp - 1 - pr, round, nbp);
+    auto colof = [&](int e) {   // column of slot e, or n if it takes no part
+        const int b = e < JB ? ba : bb;
+        const int c = b * JB + (e % JB);
+        return (b < nb && c < n) ? c : n;
+    };
+    // JB_RU rows of every column per thread are loaded before any is stored,
+    // so that one memory latency covers the whole stage at m <= 64 JB JB_RU
+    constexpr int JB_RU = 5;
+    for (int i0 = threadIdx.x; i0 < m; i0 += 64 * JB * JB_RU) {
+        double v[JB_RU][2 * JB];
+#pragma unroll
+        for (int u = 0; u < JB_RU; ++u) {
+            const int i = i0 + u * 64 * JB;
+#pragma unroll
+            for (int e = 0; e < 2 * JB; ++e) {
+                const int c = colof(e);
+                v[u][e] = (c < n && i < m) ? mt[((size_t)s * n + c) * m + i] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < JB_RU; ++u) {
+            const int i = i0 + u * 64 * JB;
+#pragma unroll
+            for (int e = 0; e < 2 * JB; ++e)
+                if (i < m) colsh[(size_t)e * m + i] = v[u][e];
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int nrot = 0;
+    for (int ir = 0; ir < 2 * JB - 1; ++ir) {
+        const int ea = rr_player(wave, ir, 2 * JB), eb = rr_player(2 * JB - 1 - wave, ir, 2 * JB);
+        if (colof(ea) < n && colof(eb) < n) {
+            double* a = colsh + (size_t)ea * m;
+            double* b = colsh + (size_t)eb * m;
+            double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll 4
+            for (int i = lane; i < m; i += 64) {
+                const double x = a[i], y = b[i];
+                al += x * x;
+                be += y * y;
+                ga += x * y;
+            }
+            for (int off = 32; off > 0; off >>= 1) {   // the three reductions interleaved
+                al += __shfl_xor(al, off, 64);
+                be += __shfl_xor(be, off, 64);
+                ga += __shfl_xor(ga, off, 64);
+            }
+            if (!(al == 0.0 || be == 0.0 || fabs(ga) <= tol * sqrt(al) * sqrt(be))) {   // wave-uniform
+                const double zeta = (be - al) / (2.0 * ga);
+                double t;
+                if (fabs(zeta) > 1e150) t = 0.5 / zeta;
+                else t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+#pragma unroll 4
+                for (int i = lane; i < m; i += 64) {
+                    const double x = a[i], y = b[i];
+                    a[i] = c * x - sn * y;
+                    b[i] = sn * x + c * y;
+                }
+                ++nrot;
+            }
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < m; i += 64 * JB) {
+#pragma unroll
+        for (int e = 0; e < 2 * JB; ++e) {
+            const int c = colof(e);
+            if (c < n) mt[((size_t)s * n + c) * m + i] = colsh[(size_t)e * m + i];
+        }
+    }
+    if (lane == 0 && nrot) atomicAdd(&rot[s], nrot);
+}
+
 // sigma, descending order, normalised and sign-fixed left vectors.
 // One workgroup per spin.  ub[s][b][r] = u_b, sv[s][b] = sigma_b, and
 // flags[4 + s] = number of kept bath vectors (sigma > sv_tol, or all).
@@ -365,13 +457,27 @@ dmet_status build_bath(const dmet_lattice* lat, const double2* dm_k, int nimp, c
         // rotation counts of the sweep are read back, at most 60 sweeps)
         const double tol = fmax(1e-15, sqrt((double)p.nenv) * 2.220446049250313e-16);
         const int np = nval + (nval & 1);
+        // block form when the 2 JB columns of a block pair fit in LDS
+        const bool blocked = p.nenv <= JB_MAXM;
+        const int nb = (nval + JB - 1) / JB, nbp = nb + (nb & 1);
+        const size_t lds = (size_t)2 * JB * p.nenv * sizeof(double);
+        if (blocked)
+            DMET_HIP(hipFuncSetAttribute((const void*)k_jacobi_block, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)lds));
         int* rot = w.flags + 8;
         bool converged = false;
         for (int sweep = 0; sweep < 60 && !converged; ++sweep) {
             fill_zero(rot, 2 * sizeof(int), st);
-            for (int round = 0; round < np - 1; ++round)
-                k_jacobi_round<<<dim3(np / 2, p.nspin), 256, 0, st>>>(p.nenv, nval, np, round, w.mt, tol, rot);
-            DMET_LAUNCH_CHECK("k_jacobi_round");
+            if (blocked) {
+                for (int round = 0; round < nbp - 1; ++round)
+                    k_jacobi_block<<<dim3(nbp / 2, p.nspin), 64 * JB, lds, st>>>(p.nenv, nval, nbp, round, w.mt,
+                                                                                  tol, rot);
+                DMET_LAUNCH_CHECK("k_jacobi_block");
+            } else {
+                for (int round = 0; round < np - 1; ++round)
+                    k_jacobi_round<<<dim3(np / 2, p.nspin), 256, 0, st>>>(p.nenv, nval, np, round, w.mt, tol, rot);
+                DMET_LAUNCH_CHECK("k_jacobi_round");
+            }
             int h_rot[2] = {0, 0};
             DMET_HIP(hipMemcpyAsync(h_rot, rot, sizeof(int) * p.nspin, hipMemcpyDeviceToHost, st));
             DMET_HIP(hipStreamSynchronize(st));
