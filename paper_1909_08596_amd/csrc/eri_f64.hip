@@ -32,7 +32,10 @@ __device__ inline double ld<float>(const float* p, size_t i) { return (double)p[
 // Output T[k][mu][L][(j,c)] (interleaved complex, row length 2 neo).
 // Both stages gather the next BK-deep slice of A and B into registers while
 // the MFMAs run on the current one, then store it into the other half of a
-// double-buffered LDS tile (one barrier per slice).
+// double-buffered LDS tile (one barrier per slice).  The gathers load from
+// clamped, always valid addresses with no condition, so that no load is waited
+// for before the MFMAs; the real embedding of the complex values and the zero
+// padding are applied when the slice is stored.
 template <int BM, int BN, int BK, class TIn>
 __global__ void __launch_bounds__(256) k_xform1_f64(Mesh mesh, int q, int nao, int naux, int neo,
                                                     const TIn* __restrict__ lmunu,
@@ -52,47 +55,48 @@ __global__ void __launch_bounds__(256) k_xform1_f64(Mesh mesh, int q, int nao, i
     d4 acc[BM / 32][BN / 32];
     zero_acc<BM, BN>(acc);
     const int tid = threadIdx.x;
-    double ra[NA], rb[NB];
-    auto gather = [&](int k0) {
+    const double2* c2 = reinterpret_cast<const double2*>(c_base);
+    double ra[NA];
+    double2 rb[NB];
+    auto gather = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < NA; ++u) {
             const int e = tid + u * 256, kk = e % BK, mm = e / BK;
-            const int gm = m0 + mm, gk = k0 + kk;
-            ra[u] = (gm < M && gk < K) ? ld(a_base, (size_t)gm * K + gk) : 0.0;
+            const int gm = min(m0 + mm, M - 1), gk = min(k0 + kk, K - 1);
+            ra[u] = ld(a_base, (size_t)gm * K + gk);
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int e = tid + u * 256, nn = e % BN, kk = e / BN;
+            const int nu = min(k0 + kk, K - 1) >> 1, j = min(n0 + nn, N - 1) >> 1;
+            rb[u] = c2[(size_t)nu * neo + j];
+        }
+    };
+    auto stash = [&](int k0, int b) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int e = tid + u * 256, kk = e % BK, mm = e / BK;
+            const bool ok = m0 + mm < M && k0 + kk < K;
+            As[b][kk * T::LDA + mm] = ok ? ra[u] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
             const int e = tid + u * 256, nn = e % BN, kk = e / BN;
             const int gn = n0 + nn, gk = k0 + kk;
-            double v = 0.0;
-            if (gn < N && gk < K) {
-                const int nu = gk >> 1, cp = gk & 1, j = gn >> 1, c = gn & 1;
-                const double cr = c_base[((size_t)nu * neo + j) * 2], ci = c_base[((size_t)nu * neo + j) * 2 + 1];
-                v = cp == 0 ? (c == 0 ? cr : ci) : (c == 0 ? -ci : cr);
-            }
-            rb[u] = v;
-        }
-    };
-    auto stash = [&](int b) {
-#pragma unroll
-        for (int u = 0; u < NA; ++u) {
-            const int e = tid + u * 256;
-            As[b][(e % BK) * T::LDA + e / BK] = ra[u];
-        }
-#pragma unroll
-        for (int u = 0; u < NB; ++u) {
-            const int e = tid + u * 256;
-            Bs[b][(e / BN) * T::LDB + e % BN] = rb[u];
+            const int cp = gk & 1, c = gn & 1;
+            const double cr = rb[u].x, ci = rb[u].y;
+            const double v = cp == 0 ? (c == 0 ? cr : ci) : (c == 0 ? -ci : cr);
+            Bs[b][kk * T::LDB + nn] = (gn < N && gk < K) ? v : 0.0;
         }
     };
     const int nkt = (K + BK - 1) / BK;
     gather(0);
-    stash(0);
+    stash(0, 0);
     __syncthreads();
     for (int it = 0; it < nkt; ++it) {
         if (it + 1 < nkt) gather((it + 1) * BK);
         f64_mma<BM, BN, BK>(As[it & 1], Bs[it & 1], acc);
-        if (it + 1 < nkt) stash((it + 1) & 1);
+        if (it + 1 < nkt) stash((it + 1) * BK, (it + 1) & 1);
         __syncthreads();
     }
     f64_visit<BM, BN, BK>(acc, [&](int r, int c, double v) {
@@ -128,52 +132,47 @@ __global__ void __launch_bounds__(256) k_xform2_f64(Mesh mesh, int nao, int naux
     d4 acc[BM / 32][BN / 32];
     zero_acc<BM, BN>(acc);
     const int tid = threadIdx.x;
-    double ra[NA], rb[NB];
-    auto gather = [&](int k0) {
+    const double2* t2 = reinterpret_cast<const double2*>(tin);
+    double ra[NA];
+    double2 rb[NB];
+    auto gather = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < NA; ++u) {
             const int e = tid + u * 256, mm = e % BM, kk = e / BM;
-            const int gm = m0 + mm, gk = k0 + kk;
-            double v = 0.0;
-            if (gm < neo && gk < K) {
-                const int kmu = gk >> 1, cp = gk & 1;
-                v = ck[((size_t)kmu * neo + gm) * 2 + cp];
-            }
-            ra[u] = v;
+            const int gm = min(m0 + mm, neo - 1), gk = min(k0 + kk, K - 1);
+            ra[u] = ck[((size_t)(gk >> 1) * neo + gm) * 2 + (gk & 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int e = tid + u * 256, nn = e % BN, kk = e / BN;
+            const int kmu = min(k0 + kk, K - 1) >> 1, j = min(n0 + nn, N2 - 1) >> 1;
+            rb[u] = t2[((size_t)kmu * naux + L) * neo + j];
+        }
+    };
+    auto stash = [&](int k0, int b) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int e = tid + u * 256, mm = e % BM, kk = e / BM;
+            As[b][kk * T::LDA + mm] = (m0 + mm < neo && k0 + kk < K) ? ra[u] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
             const int e = tid + u * 256, nn = e % BN, kk = e / BN;
             const int gn = n0 + nn, gk = k0 + kk;
-            double v = 0.0;
-            if (gn < N2 && gk < K) {
-                const int kmu = gk >> 1, cp = gk & 1, j = gn >> 1, c = gn & 1;
-                const double* row = tin + ((size_t)kmu * naux + L) * N2 + 2 * j;
-                v = cp == 0 ? row[c] : (c == 0 ? row[1] : -row[0]);
-            }
-            rb[u] = v;
-        }
-    };
-    auto stash = [&](int b) {
-#pragma unroll
-        for (int u = 0; u < NA; ++u) {
-            const int e = tid + u * 256;
-            As[b][(e / BM) * T::LDA + e % BM] = ra[u];
-        }
-#pragma unroll
-        for (int u = 0; u < NB; ++u) {
-            const int e = tid + u * 256;
-            Bs[b][(e / BN) * T::LDB + e % BN] = rb[u];
+            const int cp = gk & 1, c = gn & 1;
+            const double tr = rb[u].x, ti = rb[u].y;
+            const double v = cp == 0 ? (c == 0 ? tr : ti) : (c == 0 ? ti : -tr);
+            Bs[b][kk * T::LDB + nn] = (gn < N2 && gk < K) ? v : 0.0;
         }
     };
     const int nkt = (K + BK - 1) / BK;
     gather(0);
-    stash(0);
+    stash(0, 0);
     __syncthreads();
     for (int it = 0; it < nkt; ++it) {
         if (it + 1 < nkt) gather((it + 1) * BK);
         f64_mma<BM, BN, BK>(As[it & 1], Bs[it & 1], acc);
-        if (it + 1 < nkt) stash((it + 1) & 1);
+        if (it + 1 < nkt) stash((it + 1) * BK, (it + 1) & 1);
         __syncthreads();
     }
     f64_visit<BM, BN, BK>(acc, [&](int r, int c, double v) {
