@@ -39,13 +39,22 @@ __global__ void k_dc_v(int nrows, int neo, int npair, const double* __restrict__
     if (lane == 0) v[P] += scale * acc;
 }
 
-// J[ij] = sum_P Z[P][ij] v[P] for pair columns (one thread per pair, loop over P)
+// J[ij] = sum_P Z[P][ij] v[P] for pair columns (one thread per pair, loop over P
+// in order; eight rows' loads in flight per thread)
 __global__ void k_dc_j(int nrows, int npair, const double* __restrict__ z, const double* __restrict__ v,
                        double* __restrict__ jp) {
     const int kl = blockIdx.x * blockDim.x + threadIdx.x;
     if (kl >= npair) return;
     double acc = 0.0;
-    for (int P = 0; P < nrows; ++P) acc += z[(size_t)P * npair + kl] * v[P];
+    int P = 0;
+    for (; P + 8 <= nrows; P += 8) {
+        double zv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) zv[u] = z[(size_t)(P + u) * npair + kl];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += zv[u] * v[P + u];
+    }
+    for (; P < nrows; ++P) acc += z[(size_t)P * npair + kl] * v[P];
     jp[kl] = acc;
 }
 
@@ -58,6 +67,9 @@ __global__ void k_dc_j(int nrows, int npair, const double* __restrict__ z, const
 // k_dc_final sums the partials in a fixed order (deterministic result).
 // Both GEMMs gather the next DBK-deep slice of their operands into registers
 // while the MFMAs run on the current one, into a double-buffered LDS tile.
+// The gathers load from clamped, always valid indices with no condition (the
+// zero padding is applied when the slice is stored), and the row-dependent
+// parts of the addresses are computed once per workgroup.
 constexpr int DT = 64, DBK = 16;
 constexpr int DNE = DBK * DT / 256;              // slice elements per thread and operand
 constexpr int DK_PCW = 16;                       // rows P per k_dc_k workgroup
@@ -75,37 +87,43 @@ __global__ void __launch_bounds__(256) k_dc_w(long p0, int np, int neo, int npai
     zero_acc<DT, DT>(acc);
     const int tid = threadIdx.x;
     double ra[DNE], rb[DNE];
-    auto gather = [&](int k0) {
+    const double* zrow[DNE];   // row P of Z for this thread's A rows m (clamped)
+    int irow[DNE];             // i = m mod neo
+#pragma unroll
+    for (int u = 0; u < DNE; ++u) {
+        const long m = std::min(m0 + (tid + u * 256) / DBK, M - 1);
+        zrow[u] = z + (p0 + m / neo) * npair;
+        irow[u] = (int)(m % neo);
+    }
+    auto gather = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < DNE; ++u) {
-            const int e = tid + u * 256, kk = e % DBK, mm = e / DBK;
-            const long m = m0 + mm;
-            const int k = k0 + kk;
-            ra[u] = (m < M && k < neo) ? z[(p0 + m / neo) * npair + pidx((int)(m % neo), k)] : 0.0;
+            const int kk = (tid + u * 256) % DBK;
+            ra[u] = zrow[u][pidx(irow[u], min(k0 + kk, neo - 1))];
         }
 #pragma unroll
         for (int u = 0; u < DNE; ++u) {
             const int e = tid + u * 256, nn = e % DT, kk = e / DT;
-            const int k = k0 + kk, l = n0 + nn;
-            rb[u] = (k < neo && l < neo) ? g[(size_t)k * neo + l] : 0.0;
+            rb[u] = g[(size_t)min(k0 + kk, neo - 1) * neo + min(n0 + nn, neo - 1)];
         }
     };
-    auto stash = [&](int b) {
+    auto stash = [&](int k0, int b) __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < DNE; ++u) {
             const int e = tid + u * 256;
-            As[b][(e % DBK) * T::LDA + e / DBK] = ra[u];
-            Bs[b][(e / DT) * T::LDB + e % DT] = rb[u];
+            const int ka = k0 + e % DBK, kb = k0 + e / DT;
+            As[b][(e % DBK) * T::LDA + e / DBK] = (m0 + e / DBK < M && ka < neo) ? ra[u] : 0.0;
+            Bs[b][(e / DT) * T::LDB + e % DT] = (kb < neo && n0 + e % DT < neo) ? rb[u] : 0.0;
         }
     };
     const int nkt = (neo + DBK - 1) / DBK;
     gather(0);
-    stash(0);
+    stash(0, 0);
     __syncthreads();
     for (int it = 0; it < nkt; ++it) {
         if (it + 1 < nkt) gather((it + 1) * DBK);
         f64_mma<DT, DT, DBK>(As[it & 1], Bs[it & 1], acc);
-        if (it + 1 < nkt) stash((it + 1) & 1);
+        if (it + 1 < nkt) stash((it + 1) * DBK, (it + 1) & 1);
         __syncthreads();
     }
     f64_visit<DT, DT, DBK>(acc, [&](int r, int c, double v) {
@@ -136,46 +154,54 @@ __global__ void __launch_bounds__(256) k_dc_k(long p0, int np, int neo, int npai
     zero_acc<DT, DT>(acc);
     const int tid = threadIdx.x;
     double ra[DNE], rb[DNE];
-    auto gather = [&](int r0) {
+    const float rneo = 1.0f / (float)neo;
+    // (r / neo, r mod neo) for 0 <= r < 2^24: float quotient, corrected by one step
+    auto divmod = [&](int r, int& q, int& l) __attribute__((always_inline)) {
+        q = (int)((float)r * rneo);
+        l = r - q * neo;
+        if (l < 0) {
+            --q;
+            l += neo;
+        } else if (l >= neo) {
+            ++q;
+            l -= neo;
+        }
+    };
+    const double* wrow = w + ((size_t)pl0 * neo) * neo;
+    const double* zrow = z + (p0 + pl0) * npair;
+    auto gather = [&](int r0) __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < DNE; ++u) {
             const int e = tid + u * 256, kk = e % DBK, mm = e / DBK;
-            const int r = r0 + kk, i = i0 + mm;
-            double v = 0.0;
-            if (r < R && i < neo) {
-                const int pl = pl0 + r / neo, l = r % neo;
-                v = w[((size_t)pl * neo + i) * neo + l];
-            }
-            ra[u] = v;
+            int pl, l;
+            divmod(min(r0 + kk, R - 1), pl, l);
+            ra[u] = wrow[((size_t)pl * neo + min(i0 + mm, neo - 1)) * neo + l];
         }
 #pragma unroll
         for (int u = 0; u < DNE; ++u) {
             const int e = tid + u * 256, nn = e % DT, kk = e / DT;
-            const int r = r0 + kk, j = j0 + nn;
-            double v = 0.0;
-            if (r < R && j < neo) {
-                const long P = p0 + pl0 + r / neo;
-                v = z[P * npair + pidx(r % neo, j)];
-            }
-            rb[u] = v;
+            int pl, l;
+            divmod(min(r0 + kk, R - 1), pl, l);
+            rb[u] = zrow[(size_t)pl * npair + pidx(l, min(j0 + nn, neo - 1))];
         }
     };
-    auto stash = [&](int b) {
+    auto stash = [&](int r0, int b) __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < DNE; ++u) {
             const int e = tid + u * 256;
-            As[b][(e % DBK) * T::LDA + e / DBK] = ra[u];
-            Bs[b][(e / DT) * T::LDB + e % DT] = rb[u];
+            const int ra_r = r0 + e % DBK, rb_r = r0 + e / DT;
+            As[b][(e % DBK) * T::LDA + e / DBK] = (ra_r < R && i0 + e / DBK < neo) ? ra[u] : 0.0;
+            Bs[b][(e / DT) * T::LDB + e % DT] = (rb_r < R && j0 + e % DT < neo) ? rb[u] : 0.0;
         }
     };
     const int nkt = (R + DBK - 1) / DBK;
     gather(0);
-    stash(0);
+    stash(0, 0);
     __syncthreads();
     for (int it = 0; it < nkt; ++it) {
         if (it + 1 < nkt) gather((it + 1) * DBK);
         f64_mma<DT, DT, DBK>(As[it & 1], Bs[it & 1], acc);
-        if (it + 1 < nkt) stash((it + 1) & 1);
+        if (it + 1 < nkt) stash((it + 1) * DBK, (it + 1) & 1);
         __syncthreads();
     }
     double* out = part + ((size_t)(split0 + blockIdx.y) * ntri + tri) * (DT * DT);
