@@ -261,6 +261,9 @@ __global__ void __launch_bounds__(256) k_f32_xf2(int naux, int neo, int neo_p, i
         for (int r = 0; r < 16; ++r) acc[p][0][0][r] = 0.f;
     const int spk = nao_p / BK;                               // stages per k slot
     const int s1 = (ks.npaired + ks.nself) * spk, nst = s1 + ks.npaired * spk;
+    __shared__ short ksh[KP_MAX];   // the slot -> k table in LDS (no memory round trip per stage)
+    for (int t = threadIdx.x; t < ks.npaired + ks.nself; t += blockDim.x) ksh[t] = ks.k[t];
+    __syncthreads();
     const size_t cst = (size_t)K2 * neo_p, tst = (size_t)K2 * N2p;
     // running position: pass, stage within the pass, its slot and row offset
     int pass = 0, sp = 0, slot = 0, roff = 0;
@@ -269,7 +272,7 @@ __global__ void __launch_bounds__(256) k_f32_xf2(int naux, int neo, int neo_p, i
             pass = 1;
             sp = slot = roff = 0;
         }
-        const int kc = ks.k[slot] * nao_p + roff, kt_ = sp * BK;   // rows of conj C and of T
+        const int kc = ksh[slot] * nao_p + roff, kt_ = sp * BK;   // rows of conj C and of T
         // B columns past L's own neo_p would belong to L+1 (or are clamped at
         // the end of T): they only reach outputs that are dropped
         if (!pass) {

@@ -1010,13 +1010,17 @@ __global__ void __launch_bounds__(256) k_xf2_pk(int naux, int neo, int ng2, int 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
     const int N2 = naux * neo;
+    // the slot -> k table in LDS: read there, a lookup per stage costs no memory round trip
+    __shared__ short ksh[KP_MAX];
+    for (int t = threadIdx.x; t < ks.npaired + ks.nself; t += blockDim.x) ksh[t] = ks.k[t];
+    __syncthreads();
     f16v acc[4][TM][TN];
 #pragma unroll
     for (int p = 0; p < 4; ++p)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[p][0][0][r] = 0.f;
     pk_loop_paired<NS, BM, BN, TM, TN>(pc2, (size_t)ng2 * neo, neo, ptt, (size_t)ng2 * N2, N2, L, m0, j0, gpk, zg,
-                                       ks.npaired, ks.nself, [&](int sl) { return (int)ks.k[sl]; }, ring, wm0, wn0,
+                                       ks.npaired, ks.nself, [&](int sl) { return (int)ksh[sl]; }, ring, wm0, wn0,
                                        acc);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -1180,9 +1184,11 @@ __global__ void __launch_bounds__(256) k_xf2_batched(int nitems, const BItem2* _
     for (int p = 0; p < 4; ++p)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[p][0][0][r] = 0.f;
-    const short* kk = qs[item.slot].k;
+    __shared__ short ksh[KP_MAX];   // the slot -> k table, staged once
+    for (int t = threadIdx.x; t < qb.npaired + qb.nself; t += blockDim.x) ksh[t] = qb.k[t];
+    __syncthreads();
     pk_loop_paired<NS, BM, BN, TM, TN>(fr.pc2, (size_t)fr.ng2 * neo, neo, fr.ptt, (size_t)fr.ng2 * N2, N2, L, m0, j0,
-                                       qb.gpk, qb.zg, qb.npaired, qb.nself, [&](int sl) { return (int)kk[sl]; },
+                                       qb.gpk, qb.zg, qb.npaired, qb.nself, [&](int sl) { return (int)ksh[sl]; },
                                        ring, wm0, wn0, acc);
     const size_t ldz = (size_t)fr.npair;
 #pragma unroll
@@ -1248,6 +1254,9 @@ __global__ void __launch_bounds__(256) k_xf2_batched_l4(int nitems, const BItem2
     const int gpk = qb.gpk, zg = qb.zg;
     const int n1 = (qb.npaired + qb.nself) * gpk, n2 = qb.npaired * gpk;
     const int s1 = (n1 + 1) / 2, nst = s1 + (n2 + 1) / 2;
+    __shared__ short ksh[KP_MAX];   // the slot -> k table, staged once
+    for (int t = threadIdx.x; t < qb.npaired + qb.nself; t += blockDim.x) ksh[t] = qb.k[t];
+    __syncthreads();
     f16v acc[4][1][1];
 #pragma unroll
     for (int c = 0; c < 4; ++c)
@@ -1257,7 +1266,7 @@ __global__ void __launch_bounds__(256) k_xf2_batched_l4(int nitems, const BItem2
     int pass = 0, j = 0, slot = 0, gl = 0, cnt = 0;
     auto next = [&](int& gc, int& gt) {
         if (j < (pass ? n2 : n1)) {
-            gc = (int)qb.k[slot] * gpk + gl;
+            gc = (int)ksh[slot] * gpk + gl;
             gt = j;
             ++j;
             if (++gl == gpk) {
