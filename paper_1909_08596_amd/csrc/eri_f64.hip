@@ -354,7 +354,7 @@ __global__ void k_contract_f64_reduce(int npair, int nsplit, const double* __res
 // less, and the complex gather of T keeps registers high enough that larger tiles drop to one
 // wave per SIMD)
 constexpr int X1_BM = 128, X1_BN = 128, X1_BK = 8;
-constexpr int X2_BM = 64, X2_BN = 64, X2_BK = 8;
+constexpr int X2_BM = 64, X2_BN = 64, X2_BK = 16;
 
 // padded Z of the contraction: even row length, rows a multiple of 16
 static inline int f64_ldz(int npair) { return (npair + 1) / 2 * 2; }
