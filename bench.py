@@ -40,7 +40,10 @@ def work_counts(wl):
 
 
 def kernel_flops(wl, name):
-    """Algorithmic flops of ONE launch of the named kernel."""
+    """Algorithmic flops of ONE launch of the named kernel: stage 1 of Alg. 1 for one q over all k
+    (8 real flops per complex MAC), stage 2 for one q and spin over the i >= j half, and the
+    packed contraction of one spin block (two flops per MAC over IJ >= KL, or the full alpha-beta
+    square)."""
     nk, nao, naux, neo = wl.nk, wl.nao, wl.naux, wl.neo
     npair = neo * (neo + 1) // 2
     if name.startswith("xform1"):
@@ -317,7 +320,7 @@ def main():
                     help="only run a plain device-to-device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.copy_calib_gib > 0:

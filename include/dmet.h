@@ -61,7 +61,7 @@ typedef enum {
     DMET_E_RANK = 4,         /* sv_tol removed every bath orbital                    */
     DMET_E_NONFINITE = 5,    /* NaN/Inf in an input                                  */
     DMET_E_WORKSPACE = 6,    /* workspace missing or smaller than the query          */
-    DMET_E_UNSUPPORTED = 7   /* valid request outside what this build implements    */
+    DMET_E_UNSUPPORTED = 7   /* valid request outside what this library implements  */
 } dmet_status;
 
 typedef enum {

@@ -1,0 +1,57 @@
+"""Host-side checks of the benchmark (no GPU): the one-GPU guard and the work
+counts behind `value` and `roofline.achieved`, the latter against flops
+counted by walking the loops of Alg. 1 and of the packed contraction on a
+small workload."""
+import itertools
+import os
+import subprocess
+import sys
+
+import bench
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout
+
+
+def _walk_counts(nk, nao, naux, neo, nspin):
+    """Flops by enumeration: every (q, k, L) block of Alg. 1 multiplies C^dagger (neo x nao) by the
+    nao x nao block and the result by C (nao x neo); the contraction adds one product per kept
+    (IJ, KL) and row."""
+    wt = 0
+    for _q, _k, _l in itertools.product(range(nk), range(nk), range(naux)):
+        wt += 8 * (neo * nao * nao + neo * nao * neo)
+    wt *= nspin
+    npair = neo * (neo + 1) // 2
+    rows = nk * naux
+    tri = sum(1 for ij in range(npair) for kl in range(ij + 1))
+    wc = nspin * rows * 2 * tri
+    if nspin == 2:
+        wc += rows * 2 * npair * npair
+    return wt, wc
+
+
+def test_work_counts_match_enumeration():
+    for nspin in (1, 2):
+        wl = synth.Workload("w", (2, 1, 1), 5, 3, 5, 5, nspin, 1.5, 1)
+        wt, wc = bench.work_counts(wl)
+        ref_t, ref_c = _walk_counts(wl.nk, wl.nao, wl.naux, wl.neo, nspin)
+        assert wt == ref_t and wc == ref_c
+
+
+def test_kernel_flops_sum_to_the_work():
+    # the per-launch counts of stage 2 (i >= j half) and of the contractions add up to W_C and to
+    # the stage-2 share of W_T as the library launches them (one stage-2 launch per q and spin)
+    wl = synth.Workload("w", (2, 2, 1), 6, 4, 6, 6, 2, 1.5, 1)
+    npair = wl.neo * (wl.neo + 1) // 2
+    s8, s4 = bench.kernel_flops(wl, "contract_s8_x"), bench.kernel_flops(wl, "contract_s4_x")
+    _, wc = bench.work_counts(wl)
+    assert 2 * s8 + s4 == wc
+    x2 = bench.kernel_flops(wl, "xform2_x")
+    assert x2 == 8.0 * wl.nk * wl.naux * wl.nao * npair
