@@ -254,27 +254,39 @@ __global__ void __launch_bounds__(1024) k_svd_finalize(int m, int n, const doubl
 }
 
 // ---------------------------------------------------------------- step a3
-// Loewdin: S = U^T U over the kept bath vectors; E = S - I.
+// Loewdin: S = U^T U over the kept bath vectors; E = S - I.  One wave per
+// pair i >= j (written to both triangles, the same bits); the largest |E| of
+// the workgroup's four waves goes to emax in one atomic.
 __global__ void k_overlap(int m, int n, const double* __restrict__ ub, double* __restrict__ e_out,
                           const int* flags, double* __restrict__ emax) {
     const int s = blockIdx.y;
     const int nb = flags[4 + s];
-    const int lane = threadIdx.x & 63;
-    const int pair = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (pair >= n * n) return;
-    const int i = pair / n, j = pair % n;
-    double acc = 0.0;
-    if (i < nb && j < nb) {
-        const double* a = ub + ((size_t)s * n + i) * m;
-        const double* b = ub + ((size_t)s * n + j) * m;
-        for (int r = lane; r < m; r += 64) acc += a[r] * b[r];
-        acc = wave_sum(acc);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long pair = (long)blockIdx.x * (blockDim.x >> 6) + wave;
+    const long npair = (long)n * (n + 1) / 2;
+    double e = 0.0;
+    if (pair < npair) {
+        int i = (int)((sqrt(8.0 * (double)pair + 1.0) - 1.0) * 0.5);
+        while ((long)i * (i + 1) / 2 > pair) --i;
+        while ((long)(i + 1) * (i + 2) / 2 <= pair) ++i;
+        const int j = (int)(pair - (long)i * (i + 1) / 2);
+        double acc = 0.0;
+        if (i < nb && j < nb) {
+            const double* a = ub + ((size_t)s * n + i) * m;
+            const double* b = ub + ((size_t)s * n + j) * m;
+            for (int r = lane; r < m; r += 64) acc += a[r] * b[r];
+            acc = wave_sum(acc);
+        }
+        e = (i < nb && j < nb) ? acc - (i == j) : 0.0;
+        if (lane == 0) {
+            e_out[((size_t)s * n + i) * n + j] = e;
+            e_out[((size_t)s * n + j) * n + i] = e;
+        }
     }
-    const double e = (i < nb && j < nb) ? acc - (i == j) : 0.0;
-    if (lane == 0) {
-        e_out[((size_t)s * n + i) * n + j] = e;
-        atomic_max_nonneg(emax, fabs(e));
-    }
+    __shared__ double wmax[4];
+    if (lane == 0) wmax[wave] = fabs(e);
+    __syncthreads();
+    if (threadIdx.x == 0) atomic_max_nonneg(emax, fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3])));
 }
 
 // C <- C S^{-1/2} with S = I + E, |E| ~ 1e-15:  S^{-1/2} = I - E/2 + O(E^2).
@@ -489,8 +501,8 @@ dmet_status build_bath(const dmet_lattice* lat, const double2* dm_k, int nimp, c
         const size_t shm = (size_t)nval * (sizeof(double) + sizeof(int));
         k_svd_finalize<<<p.nspin, 1024, shm, st>>>(p.nenv, nval, w.mt, w.ub, sv, sv_tol, w.flags);
         DMET_LAUNCH_CHECK("k_svd_finalize");
-        k_overlap<<<dim3((nval * nval + 3) / 4, p.nspin), 256, 0, st>>>(p.nenv, nval, w.ub, w.emat, w.flags,
-                                                                         w.scal + 1);
+        const int ovl_blocks = (nval * (nval + 1) / 2 + 3) / 4;
+        k_overlap<<<dim3(ovl_blocks, p.nspin), 256, 0, st>>>(p.nenv, nval, w.ub, w.emat, w.flags, w.scal + 1);
         DMET_LAUNCH_CHECK("k_overlap");
     } else {
         // no bath: the kept count (flags[4 + s]) stays 0, singular values are 0
