@@ -41,13 +41,13 @@ def work_counts(wl):
 
 def kernel_flops(wl, name):
     """Algorithmic flops of ONE launch of the named kernel: stage 1 of Alg. 1 for one q over all k
-    (8 real flops per complex MAC), stage 2 for one q and spin over the i >= j half, and the
+    and both spins (8 real flops per complex MAC), stage 2 for one q and spin over the i >= j half, and the
     packed contraction of one spin block (two flops per MAC over IJ >= KL, or the full alpha-beta
     square)."""
     nk, nao, naux, neo = wl.nk, wl.nao, wl.naux, wl.neo
     npair = neo * (neo + 1) // 2
     if name.startswith("xform1"):
-        return 8.0 * nk * naux * nao * nao * neo
+        return 8.0 * nk * naux * nao * nao * neo * wl.nspin
     if name.startswith("xform2"):
         return 8.0 * nk * naux * nao * neo * (neo + 1) / 2
     if name.startswith("contract_s8"):

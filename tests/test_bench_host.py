@@ -55,3 +55,10 @@ def test_kernel_flops_sum_to_the_work():
     assert 2 * s8 + s4 == wc
     x2 = bench.kernel_flops(wl, "xform2_x")
     assert x2 == 8.0 * wl.nk * wl.naux * wl.nao * npair
+    # one stage-1 launch per q covers both spins: N_k launches make the stage-1 share of W_T
+    wt, _ = bench.work_counts(wl)
+    x1 = bench.kernel_flops(wl, "xform1_x")
+    assert wl.nk * x1 == 8.0 * wl.nk ** 2 * wl.naux * wl.nao ** 2 * wl.neo * wl.nspin
+    # stage 2 over the full ij square (twice the i >= j count less the diagonal share), every q and spin
+    full2 = 2 * x2 * wl.neo / (wl.neo + 1)
+    assert abs(wl.nk * x1 + wl.nspin * wl.nk * full2 - wt) <= 1e-12 * wt
