@@ -440,10 +440,12 @@ def main():
     z = dmet.dmet_transform_eri_df(wl.kmesh, wl.nao, wl.naux, lm_d, ck, args.precision, workspace=ws_df)
     ev2[1].record()
     ft = dmet.dmet_fock_dc(z, f_eo, g_eo)
+    e_mf = dmet.dmet_energy_mf(ft, f_eo, g_eo)
     ev2[2].record()
     torch.cuda.synchronize()
     t_df, t_dc = ev2[0].elapsed_time(ev2[1]), ev2[1].elapsed_time(ev2[2])
-    print(f"[bench] DF output {t_df:.2f} ms, double-counting Fock {t_dc:.2f} ms", file=sys.stderr, flush=True)
+    print(f"[bench] DF output {t_df:.2f} ms, double-counting Fock and mean-field energy {t_dc:.2f} ms "
+          f"(E_mf = {float(e_mf.cpu()):.10f})", file=sys.stderr, flush=True)
     del z, ws_df, ft
 
     wt, wc = work_counts(wl)

@@ -10,6 +10,8 @@
  *   dmet_transform_1e    Eq. "fock transform"
  *   dmet_energy_1e       one-body energy of the embedding Hamiltonian, Eq. "emb Ham"
  *   dmet_transform_eri   Alg. 1 (GDF embedding ERI), Eq. "density fitting"
+ *   dmet_fock_dc         Eq. "fock double counting" (F~ from the density-fitting factors)
+ *   dmet_energy_mf       mean-field (Hartree-Fock form) energy of the embedding Hamiltonian
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -255,6 +257,21 @@ dmet_status dmet_fock_dc_workspace(int nspin, int neo, int nrows, size_t* bytes)
 dmet_status dmet_fock_dc(int nspin, int neo, int nrows, const double* z, const double* f_eo,
                          const double* dm_eo, double* f_tilde, void* workspace, size_t ws_bytes,
                          hipStream_t stream);
+
+/* Mean-field energy of the embedding Hamiltonian whose one-body part is F~
+ * (Eq. "fock double counting") and whose two-body part is the embedding ERIs,
+ * with the Hartree-Fock expression at the embedding density (the paper
+ * evaluates every DMET mean-field energy with the Hartree-Fock form, Sec. 2.2):
+ *   E = sum_ij F~_ij gamma_ji + 1/2 sum (ij|kl)[gamma_ji gamma_lk - 1/2 gamma_jk gamma_li],
+ * computed as 1/2 sum_ij (F~ + F^EO)_ij gamma_ji, which is the same because
+ * F^EO = F~ + J - K/2 at that density.  Per-spin inputs as dmet_fock_dc:
+ * nspin = 1: gamma = 2 dm_eo, E = sum_ij (F~ + F)_ij dm_ji;
+ * nspin = 2: E = 1/2 sum_s sum_ij (F~_s + F_s)_ij dm_s,ji.
+ * f_tilde, f_eo, dm_eo: [nspin][neo][neo] float64 DEVICE; e: out DEVICE [1]
+ * float64.  Returns DMET_E_ARG for nspin not 1 or 2, neo < 1 or a NULL
+ * pointer.  Asynchronous. */
+dmet_status dmet_energy_mf(int nspin, int neo, const double* f_tilde, const double* f_eo,
+                           const double* dm_eo, double* e, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Batched embedding ERIs (Alg. 1 for many fragments in one submission).

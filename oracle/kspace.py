@@ -410,3 +410,31 @@ def fock_double_counting(f_eo, dm_eo, eri):
     ka = np.einsum("iklj,kl->ij", aa, ga)
     kb = np.einsum("iklj,kl->ij", bb, gb)
     return np.stack([f_eo[0] - (ja - ka), f_eo[1] - (jb - kb)])
+
+
+def energy_mf(f_tilde, dm_eo, eri):
+    """Mean-field energy of the embedding Hamiltonian (one-body part F~ of Eq.
+    ``fock double counting``, two-body part the embedding ERIs), evaluated
+    with the Hartree-Fock expression at the embedding density (Sec. 2.2: DMET
+    energies use the Hartree-Fock form of the mean-field energy).
+
+    Restricted: gamma = 2 dm_eo[0] (spin-summed),
+        E = sum_ij F~_ij gamma_ji + 1/2 sum_ijkl (ij|kl) [gamma_ji gamma_lk - 1/2 gamma_jk gamma_li].
+    Unrestricted (eri = (aa, bb, ab)), per-spin densities g_a, g_b:
+        E = sum_s sum_ij F~_s,ij g_s,ji
+          + 1/2 sum_{s,t} sum (ij|kl)_st g_s,ji g_t,lk - 1/2 sum_s sum (ij|kl)_ss g_s,jk g_s,li.
+    """
+    f_tilde = np.asarray(f_tilde)
+    if f_tilde.shape[0] == 1:
+        g = 2.0 * dm_eo[0]
+        one = np.einsum("ij,ji->", f_tilde[0], g)
+        coul = np.einsum("ijkl,ji,lk->", eri, g, g)
+        exch = np.einsum("ijkl,jk,li->", eri, g, g)
+        return float(one + 0.5 * coul - 0.25 * exch)
+    aa, bb, ab = eri
+    ga, gb = dm_eo[0], dm_eo[1]
+    one = np.einsum("ij,ji->", f_tilde[0], ga) + np.einsum("ij,ji->", f_tilde[1], gb)
+    coul = (np.einsum("ijkl,ji,lk->", aa, ga, ga) + np.einsum("ijkl,ji,lk->", bb, gb, gb)
+            + 2.0 * np.einsum("ijkl,ji,lk->", ab, ga, gb))
+    exch = np.einsum("ijkl,jk,li->", aa, ga, ga) + np.einsum("ijkl,jk,li->", bb, gb, gb)
+    return float(one + 0.5 * coul - 0.5 * exch)

@@ -192,6 +192,15 @@ dmet_status dmet_energy_1e(int nspin, int neo, const double* h_eo, const double*
 }
 
 // FP64 and FP32-3M have kernels of their own; the split-BF16 forms share one
+dmet_status dmet_energy_mf(int nspin, int neo, const double* f_tilde, const double* f_eo, const double* dm_eo,
+                           double* e, hipStream_t stream) {
+    g_last_error.clear();
+    if (nspin != 1 && nspin != 2) return fail(DMET_E_ARG, "nspin must be 1 or 2");
+    if (neo < 1) return fail(DMET_E_ARG, "neo must be positive");
+    if (!f_tilde || !f_eo || !dm_eo || !e) return fail(DMET_E_ARG, "null array argument");
+    return energy_mf(nspin, neo, f_tilde, f_eo, dm_eo, e, stream);
+}
+
 static size_t eri_workspace(const EriPlan& p) {
     if (p.prec == DMET_FP64) return eri_f64_workspace(p);
     if (p.prec == DMET_FP32_3M) return eri_f32_workspace(p);

@@ -118,5 +118,7 @@ dmet_status build_bath(const dmet_lattice* lat, const double2* dm_k, int nimp, c
 dmet_status transform_1e(const dmet_lattice* lat, int neo, const double2* ck, const double2* op,
                          double* out, double* max_imag, hipStream_t st);
 dmet_status energy_1e(int nspin, int neo, const double* h, const double* g, double* e1, hipStream_t st);
+dmet_status energy_mf(int nspin, int neo, const double* f_tilde, const double* f_eo, const double* dm_eo,
+                      double* e, hipStream_t st);
 
 }  // namespace dmet

@@ -295,4 +295,36 @@ dmet_status fock_dc(int nspin, int neo, int nrows, const double* z, const double
     return DMET_OK;
 }
 
+// Mean-field energy of the embedding Hamiltonian with the Hartree-Fock
+// expression: since F^EO = F~ + J - K/2 at the same density, the one- and
+// two-body terms combine into E = 1/2 sum_s sum_ij (F~_s + F_s)_ij gamma_s,ji
+// with the spin-summed gamma (restricted: gamma = 2 g, so E = sum (F~ + F) g;
+// unrestricted: per-spin g and the factor 1/2).  One workgroup, fixed order.
+__global__ void __launch_bounds__(1024) k_energy_mf(int nspin, int neo, const double* __restrict__ ft,
+                                                    const double* __restrict__ f, const double* __restrict__ g,
+                                                    double* __restrict__ e) {
+    __shared__ double part[16];
+    double acc = 0.0;
+    const size_t per = (size_t)neo * neo;
+    for (size_t x = threadIdx.x; x < (size_t)nspin * per; x += blockDim.x) {
+        const size_t sp = x / per, ij = x % per, i = ij / neo, j = ij % neo;
+        acc += (ft[x] + f[x]) * g[sp * per + j * neo + i];
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += part[w];
+        e[0] = (nspin == 1 ? 1.0 : 0.5) * t;
+    }
+}
+
+dmet_status energy_mf(int nspin, int neo, const double* f_tilde, const double* f_eo, const double* dm_eo,
+                      double* e, hipStream_t st) {
+    k_energy_mf<<<1, 1024, 0, st>>>(nspin, neo, f_tilde, f_eo, dm_eo, e);
+    DMET_LAUNCH_CHECK("k_energy_mf");
+    return DMET_OK;
+}
+
 }  // namespace dmet

@@ -27,7 +27,7 @@ EXPORTS = ("dmet_last_error", "dmet_version", "dmet_build_bath_workspace", "dmet
            "dmet_transform_1e", "dmet_energy_1e", "dmet_transform_eri_workspace", "dmet_transform_eri",
            "dmet_transform_eri_batched_workspace", "dmet_transform_eri_batched",
            "dmet_transform_eri_df", "dmet_transform_eri_fftdf_workspace", "dmet_transform_eri_fftdf",
-           "dmet_fock_dc_workspace", "dmet_fock_dc",
+           "dmet_fock_dc_workspace", "dmet_fock_dc", "dmet_energy_mf",
            "dmet_profile_enable", "dmet_profile_reset", "dmet_profile_report")
 DMET_BATCH_GRAPH, DMET_BATCH_AUTOTUNE = 1, 2
 
@@ -99,6 +99,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dmet_transform_eri_fftdf.argtypes = [lp, gp, i, vp, i, vp, vp, vp, vp, vp, sz, vp]
     lib.dmet_fock_dc_workspace.argtypes = [i, i, i, ctypes.POINTER(sz)]
     lib.dmet_fock_dc.argtypes = [i, i, i, vp, vp, vp, vp, vp, sz, vp]
+    lib.dmet_energy_mf.argtypes = [i, i, vp, vp, vp, vp, vp]
     lib.dmet_profile_enable.argtypes = [i]
     lib.dmet_profile_reset.argtypes = []
     lib.dmet_profile_report.argtypes = [ctypes.c_char_p, sz]
@@ -307,6 +308,19 @@ def dmet_fock_dc(z: torch.Tensor, f_eo: torch.Tensor, dm_eo: torch.Tensor, strea
     _check(lib.dmet_fock_dc(nspin, neo, nrows, _ptr(z), _ptr(f_eo), _ptr(dm_eo), _ptr(out), _ptr(ws), ws.numel(),
                             _stream(stream)))
     return out
+
+
+def dmet_energy_mf(f_tilde: torch.Tensor, f_eo: torch.Tensor, dm_eo: torch.Tensor, stream=None) -> torch.Tensor:
+    """Mean-field (Hartree-Fock form) energy of the embedding Hamiltonian with
+    one-body part F~ (float64 device tensors [nspin][neo][neo]); device [1]."""
+    lib = load()
+    _dev(f_tilde, torch.float64, "f_tilde")
+    _dev(f_eo, torch.float64, "f_eo")
+    _dev(dm_eo, torch.float64, "dm_eo")
+    e = torch.empty(1, dtype=torch.float64, device=f_eo.device)
+    _check(lib.dmet_energy_mf(f_eo.shape[0], f_eo.shape[1], _ptr(f_tilde), _ptr(f_eo), _ptr(dm_eo), _ptr(e),
+                              _stream(stream)))
+    return e
 
 
 def _fragments(frags, precision):

@@ -87,6 +87,14 @@ def test_onebody_argument_validation(lib):
     assert lib.dmet_energy_1e(3, 4, None, None, None, None) == 1
 
 
+def test_energy_mf_argument_validation(lib):
+    fake = ctypes.c_void_p(16)
+    assert lib.dmet_energy_mf(3, 4, fake, fake, fake, fake, None) == 1
+    assert lib.dmet_energy_mf(1, 0, fake, fake, fake, fake, None) == 1
+    assert lib.dmet_energy_mf(2, 4, fake, None, fake, fake, None) == 1
+    assert b"null" in lib.dmet_last_error()
+
+
 def test_fftdf_argument_validation(lib):
     """The plane-wave entry points check the grid against naux and the cell on
     the host (no GPU call)."""

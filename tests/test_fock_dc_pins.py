@@ -83,3 +83,50 @@ def test_double_counting_planted_mistakes():
     bad2 = f_eo[0] - (j - 0.5 * np.einsum("ijkl,kl->ij", eri, g))
     for bad in (bad1, bad2):
         assert np.abs(bad - ref[0]).max() > 1e-4
+
+
+def _hf_energy(hsup, b, kmesh, dens):
+    """Hartree-Fock energy of the BvK supercell at per-spin densities `dens`
+    (restricted: one per-spin density, spin-summed 2 g)."""
+    if len(dens) == 1:
+        g = 2.0 * dens[0]
+        j, k = sc.coulomb_exchange(b, kmesh, g)
+        return float(np.sum(hsup * g) + 0.5 * np.sum((j - 0.5 * k) * g))
+    j, _ = sc.coulomb_exchange(b, kmesh, dens[0] + dens[1])
+    e = 0.0
+    for g in dens:
+        k = sc.coulomb_exchange(b, kmesh, g)[1]
+        e += float(np.sum(hsup * g) + 0.5 * np.sum((j - k) * g))
+    return e
+
+
+@pytest.mark.parametrize("nspin", [1, 2])
+def test_mean_field_energy_splits_the_lattice_energy(nspin):
+    """Mean-field energy of the embedding Hamiltonian (F~ plus embedding ERIs,
+    Hartree-Fock expression) plus the Hartree-Fock energy of the core density
+    equals the Hartree-Fock energy of the whole supercell: the core-embedding
+    interaction sits in F~, the embedding-embedding one in the ERIs."""
+    wl = synth.Workload("emf", (3, 2, 1), 5, 14, 5, 5, nspin, 1.5, 321 + nspin)
+    lat, lm, b, hsup, gs, fk = _hf_lattice(wl)
+    bath = ok.build_bath(lat.dm_k, wl.kmesh, wl.nao)
+    ck = bath["c_k"]
+    f_eo, _ = ok.transform_1e(ck, fk)
+    g_eo, _ = ok.transform_1e(ck, lat.dm_k)
+    if nspin == 1:
+        eri = ok.alg1_eri(lm, ck[0], wl.kmesh)[0]
+    else:
+        eri = tuple(ok.alg1_eri(lm, ck[a], wl.kmesh, None if c is None else ck[c])[0]
+                    for a, c in ((0, None), (1, None), (0, 1)))
+    ft = ok.fock_double_counting(f_eo, g_eo, eri)
+    e_emb = ok.energy_mf(ft, g_eo, eri)
+    cs = [bath["c_r"][s].reshape(-1, bath["neo"][s]) for s in range(nspin)]
+    core = [gs[s] - cs[s] @ cs[s].T @ gs[s] @ cs[s] @ cs[s].T for s in range(nspin)]
+    e_tot = _hf_energy(hsup, b, wl.kmesh, gs)
+    e_core = _hf_energy(hsup, b, wl.kmesh, core)
+    assert abs(e_emb + e_core - e_tot) < 1e-10 * max(1.0, abs(e_tot))
+    # a dropped 1/2 on exchange, or F^EO in place of F~, breaks the split
+    if nspin == 1:
+        g = 2.0 * g_eo[0]
+        wrong = e_emb - 0.25 * np.einsum("ijkl,jk,li->", eri, g, g)
+        assert abs(wrong + e_core - e_tot) > 1e-6
+    assert abs(ok.energy_mf(f_eo, g_eo, eri) + e_core - e_tot) > 1e-6

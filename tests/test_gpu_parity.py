@@ -273,12 +273,17 @@ def test_fock_dc_parity(dmet, nspin):
     ck_d = to_dev(ck)
     fe, _ = dmet.dmet_transform_1e(wl.kmesh, wl.nao, ck_d, to_dev(fk))
     ge, _ = dmet.dmet_transform_1e(wl.kmesh, wl.nao, ck_d, to_dev(lat.dm_k))
+    e_ref = ok.energy_mf(ref, g_eo, eri)
     for prec, tol in (("fp64", 1e-10), ("bf16x6", 1e-5)):
         z = dmet.dmet_transform_eri_df(wl.kmesh, wl.nao, wl.naux, to_dev(lm), ck_d, prec)
-        ft = dmet.dmet_fock_dc(z, fe, ge).cpu().numpy()
+        ft_d = dmet.dmet_fock_dc(z, fe, ge)
+        ft = ft_d.cpu().numpy()
         err = np.abs(ft - ref).max()
-        print(f"fock_dc nspin={nspin} {prec}: {err:.3e}")
+        # mean-field energy of the embedding Hamiltonian from the GPU F~ and F^EO
+        e = float(dmet.dmet_energy_mf(ft_d, fe, ge).cpu())
+        print(f"fock_dc nspin={nspin} {prec}: {err:.3e}; E_mf {e:.12f} vs {e_ref:.12f}")
         assert err < tol, (prec, err)
+        assert abs(e - e_ref) < tol * max(1.0, abs(e_ref)), (prec, e, e_ref)
 
 
 def test_fock_dc_chunked_against_torch(dmet):
