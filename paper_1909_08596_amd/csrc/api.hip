@@ -140,7 +140,7 @@ extern "C" {
 
 const char* dmet_last_error(void) { return g_last_error.c_str(); }
 
-int dmet_version(void) { return 100; }
+int dmet_version(void) { return 200; }   // 0.2.0: dmet_energy_mf added
 
 dmet_status dmet_build_bath_workspace(const dmet_lattice* lat, int nimp, int nval, size_t* bytes) {
     dmet_status s = check_lattice(lat);
