@@ -108,6 +108,31 @@ __global__ void __launch_bounds__(256) k_jacobi_round(int m, int n, int np, int 
     if (threadIdx.x == 0) atomicAdd(&rot[s], 1);
 }
 
+// Wave sum through DPP lane moves (row shifts, then row broadcasts into the
+// last lane; the GCN cross-lane reduction sequence), read back from lane 63
+// so every lane holds the same total.  A double moves as two 32-bit halves.
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ inline double dpp_mov(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, ROW_MASK, BANK_MASK, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, BANK_MASK, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ inline double wave_sum_dpp(double x) {
+    double v = x + dpp_mov<0x111, 0xf, 0xf>(x);     // row_shr:1
+    v += dpp_mov<0x112, 0xf, 0xf>(x);               // row_shr:2
+    v += dpp_mov<0x113, 0xf, 0xf>(x);               // row_shr:3: lane i holds x[i-3..i] within its row
+    v += dpp_mov<0x114, 0xf, 0xe>(v);               // row_shr:4 into banks 1-3
+    v += dpp_mov<0x118, 0xf, 0xc>(v);               // row_shr:8 into banks 2-3: lane 15 of a row has the row sum
+    v += dpp_mov<0x142, 0xa, 0xf>(v);               // row_bcast:15 into rows 1 and 3
+    v += dpp_mov<0x143, 0xc, 0xf>(v);               // row_bcast:31 into rows 2 and 3: lane 63 has the total
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Block form of the same sweep: the columns are grouped in blocks of JB and
 // a round-robin round pairs the blocks.  Workgroup (p, s) stages the 2 JB
 // columns of its block pair in LDS and applies one cyclic sweep over every
@@ -168,11 +193,9 @@ __global__ void __launch_bounds__(64 * JB) k_jacobi_block(int m, int n, int nbp,
                 be += y * y;
                 ga += x * y;
             }
-            for (int off = 32; off > 0; off >>= 1) {   // the three reductions interleaved
-                al += __shfl_xor(al, off, 64);
-                be += __shfl_xor(be, off, 64);
-                ga += __shfl_xor(ga, off, 64);
-            }
+            al = wave_sum_dpp(al);
+            be = wave_sum_dpp(be);
+            ga = wave_sum_dpp(ga);
             if (!(al == 0.0 || be == 0.0 || fabs(ga) <= tol * sqrt(al) * sqrt(be))) {   // wave-uniform
                 const double zeta = (be - al) / (2.0 * ga);
                 double t;
