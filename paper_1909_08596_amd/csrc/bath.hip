@@ -146,7 +146,8 @@ constexpr int JB_MAXM = 2400;   // rows that fit: 2 JB m doubles of LDS
 
 __global__ void __launch_bounds__(64 * JB) k_jacobi_block(int m, int n, int nbp, int round,
                                                           double* __restrict__ mt, double tol, int* rot) {
-    extern __shared__ double colsh[];   // [2 JB][m]
+    extern __shared__ __align__(16) double colsh[];   // [2 JB][mp], rows m..mp-1 zero
+    const int mp = m + (m & 1);                        // even stride: rows move in pairs
     const int pr = blockIdx.x, s = blockIdx.y;
     const int nb = (n + JB - 1) / JB;
     const int ba = rr_player(pr, round, nbp), bb = rr_player(nbp - 1 - pr, round, nbp);
@@ -158,7 +159,7 @@ __global__ void __launch_bounds__(64 * JB) k_jacobi_block(int m, int n, int nbp,
     // JB_RU rows of every column per thread are loaded before any is stored,
     // so that one memory latency covers the whole stage at m <= 64 JB JB_RU
     constexpr int JB_RU = 5;
-    for (int i0 = threadIdx.x; i0 < m; i0 += 64 * JB * JB_RU) {
+    for (int i0 = threadIdx.x; i0 < mp; i0 += 64 * JB * JB_RU) {
         double v[JB_RU][2 * JB];
 #pragma unroll
         for (int u = 0; u < JB_RU; ++u) {
@@ -174,7 +175,7 @@ __global__ void __launch_bounds__(64 * JB) k_jacobi_block(int m, int n, int nbp,
             const int i = i0 + u * 64 * JB;
 #pragma unroll
             for (int e = 0; e < 2 * JB; ++e)
-                if (i < m) colsh[(size_t)e * m + i] = v[u][e];
+                if (i < mp) colsh[(size_t)e * mp + i] = v[u][e];
         }
     }
     __syncthreads();
@@ -183,15 +184,16 @@ __global__ void __launch_bounds__(64 * JB) k_jacobi_block(int m, int n, int nbp,
     for (int ir = 0; ir < 2 * JB - 1; ++ir) {
         const int ea = rr_player(wave, ir, 2 * JB), eb = rr_player(2 * JB - 1 - wave, ir, 2 * JB);
         if (colof(ea) < n && colof(eb) < n) {
-            double* a = colsh + (size_t)ea * m;
-            double* b = colsh + (size_t)eb * m;
+            double2* a = reinterpret_cast<double2*>(colsh + (size_t)ea * mp);
+            double2* b = reinterpret_cast<double2*>(colsh + (size_t)eb * mp);
+            const int mh = mp / 2;
             double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll 4
-            for (int i = lane; i < m; i += 64) {
-                const double x = a[i], y = b[i];
-                al += x * x;
-                be += y * y;
-                ga += x * y;
+            for (int i = lane; i < mh; i += 64) {
+                const double2 x = a[i], y = b[i];
+                al += x.x * x.x + x.y * x.y;
+                be += y.x * y.x + y.y * y.y;
+                ga += x.x * y.x + x.y * y.y;
             }
             al = wave_sum_dpp(al);
             be = wave_sum_dpp(be);
@@ -203,10 +205,10 @@ __global__ void __launch_bounds__(64 * JB) k_jacobi_block(int m, int n, int nbp,
                 else t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                 const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
 #pragma unroll 4
-                for (int i = lane; i < m; i += 64) {
-                    const double x = a[i], y = b[i];
-                    a[i] = c * x - sn * y;
-                    b[i] = sn * x + c * y;
+                for (int i = lane; i < mh; i += 64) {
+                    const double2 x = a[i], y = b[i];
+                    a[i] = make_double2(c * x.x - sn * y.x, c * x.y - sn * y.y);
+                    b[i] = make_double2(sn * x.x + c * y.x, sn * x.y + c * y.y);
                 }
                 ++nrot;
             }
@@ -217,7 +219,7 @@ __global__ void __launch_bounds__(64 * JB) k_jacobi_block(int m, int n, int nbp,
 #pragma unroll
         for (int e = 0; e < 2 * JB; ++e) {
             const int c = colof(e);
-            if (c < n) mt[((size_t)s * n + c) * m + i] = colsh[(size_t)e * m + i];
+            if (c < n) mt[((size_t)s * n + c) * m + i] = colsh[(size_t)e * mp + i];
         }
     }
     if (lane == 0 && nrot) atomicAdd(&rot[s], nrot);
@@ -495,7 +497,7 @@ dmet_status build_bath(const dmet_lattice* lat, const double2* dm_k, int nimp, c
         // block form when the 2 JB columns of a block pair fit in LDS
         const bool blocked = p.nenv <= JB_MAXM;
         const int nb = (nval + JB - 1) / JB, nbp = nb + (nb & 1);
-        const size_t lds = (size_t)2 * JB * p.nenv * sizeof(double);
+        const size_t lds = (size_t)2 * JB * (p.nenv + (p.nenv & 1)) * sizeof(double);
         if (blocked)
             DMET_HIP(hipFuncSetAttribute((const void*)k_jacobi_block, hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)lds));
