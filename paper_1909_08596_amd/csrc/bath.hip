@@ -135,11 +135,11 @@ __device__ inline double wave_sum_dpp(double x) {
 
 // Block form of the same sweep: the columns are grouped in blocks of JB and
 // a round-robin round pairs the blocks.  Workgroup (p, s) stages the 2 JB
-// columns of its block pair in LDS and applies one cyclic sweep over every
-// pair among them (2 JB - 1 inner rounds of JB disjoint pairs, one wave per
-// pair, dot products reduced over the wave in a fixed order).  An outer sweep
-// (nbp - 1 launches) therefore visits every column pair at least once, and a
-// sweep with no rotation has converged exactly as in the per-pair form.
+// columns of its block pair in LDS and rotates every pair across the two
+// blocks (one wave per pair, dot products reduced over the wave in a fixed
+// order); pairs inside a block are rotated in the sweep's first round.  An
+// outer sweep (nbp - 1 launches) therefore visits every column pair once, and
+// a sweep with no rotation has converged exactly as in the per-pair form.
 // Columns of a missing block (odd block count) or past n take no part.
 constexpr int JB = 4;
 constexpr int JB_MAXM = 2400;   // rows that fit: 2 JB m doubles of LDS
@@ -181,8 +181,21 @@ __global__ void __launch_bounds__(64 * JB) k_jacobi_block(int m, int n, int nbp,
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int nrot = 0;
-    for (int ir = 0; ir < 2 * JB - 1; ++ir) {
-        const int ea = rr_player(wave, ir, 2 * JB), eb = rr_player(2 * JB - 1 - wave, ir, 2 * JB);
+    // pairs across the two blocks: JB rounds of JB disjoint pairs (wave w takes
+    // slot w of the first block and slot (w + r) mod JB of the second); pairs
+    // inside a block only in the sweep's first round (every block plays in
+    // every round), JB - 1 rounds with JB / 2 waves per block
+    const int nintra = round == 0 ? JB - 1 : 0;
+    for (int ir = 0; ir < nintra + JB; ++ir) {
+        int ea, eb;
+        if (ir < nintra) {
+            const int base = wave < JB / 2 ? 0 : JB, w = wave % (JB / 2);
+            ea = base + rr_player(w, ir, JB);
+            eb = base + rr_player(JB - 1 - w, ir, JB);
+        } else {
+            ea = wave;
+            eb = JB + (wave + ir - nintra) % JB;
+        }
         if (colof(ea) < n && colof(eb) < n) {
             double2* a = reinterpret_cast<double2*>(colsh + (size_t)ea * mp);
             double2* b = reinterpret_cast<double2*>(colsh + (size_t)eb * mp);
