@@ -324,6 +324,10 @@ static dmet_status check_batch(int nfrag, const dmet_fragment* frags, dmet_preci
         const dmet_fragment& d = frags[f];
         dmet_status s = check_eri_args(&d.lat, d.neo, prec, d.dtype);
         if (s != DMET_OK) return fail(s, "fragment " + std::to_string(f) + ": " + dmet_last_error());
+        const long nk = (long)d.lat.kmesh[0] * d.lat.kmesh[1] * d.lat.kmesh[2];
+        if ((prec == DMET_BF16X3_3M || prec == DMET_BF16X6_3M) && nk > KP_MAX)
+            return fail(DMET_E_UNSUPPORTED, "fragment " + std::to_string(f) +
+                                                ": the split-bf16 batched transform supports at most 256 k-points");
         if (d.lat.nspin != 1) return fail(DMET_E_ARG, "fragment " + std::to_string(f) + ": nspin must be 1");
         if ((prec == DMET_BF16X3_3M || prec == DMET_BF16X6_3M) &&
             d.lat.kmesh[0] * d.lat.kmesh[1] * d.lat.kmesh[2] > 256)
