@@ -611,16 +611,27 @@ __global__ void __launch_bounds__(256) k_pack_lmunu(const TIn* __restrict__ lm, 
     const int live = max(0, min(rows, nao - mu0));  // rows that exist in the input
     const TIn* src = lm + (((size_t)qk * naux + L) * nao + mu0) * (size_t)nao * 2;
     // rows mu0 .. mu0+live-1 are contiguous in the input: live * nao complex
-    for (int e = threadIdx.x; e < live * nao; e += blockDim.x) {
-        const int r = e / nao, c = e % nao;
-        float2 v;
-        if constexpr (sizeof(TIn) == 8) {
-            const double2 d = reinterpret_cast<const double2*>(src)[e];
-            v = make_float2((float)d.x, (float)d.y);
-        } else {
-            v = reinterpret_cast<const float2*>(src)[e];
+    // PU elements per thread are loaded (clamped, unconditional) before any is
+    // stored, so that several loads per thread are in flight
+    constexpr int PU = 8;
+    const int nel = live * nao;
+    for (int e0 = threadIdx.x; e0 < nel; e0 += PU * blockDim.x) {
+        float2 v[PU];
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
+            const int e = min(e0 + u * (int)blockDim.x, nel - 1);
+            if constexpr (sizeof(TIn) == 8) {
+                const double2 d = reinterpret_cast<const double2*>(src)[e];
+                v[u] = make_float2((float)d.x, (float)d.y);
+            } else {
+                v[u] = reinterpret_cast<const float2*>(src)[e];
+            }
         }
-        tile[r * ld + c] = v;
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
+            const int e = e0 + u * (int)blockDim.x;
+            if (e < nel) tile[(e / nao) * ld + e % nao] = v[u];
+        }
     }
     // zero padding columns of every row, and the padding rows
     for (int e = threadIdx.x; e < rows * (W - nao); e += blockDim.x) {
