@@ -32,40 +32,49 @@ __device__ inline long xcd_map(long b, long n) {
 inline int pad4(int n) { return (n + 3) / 4 * 4; }
 
 // ------------------------------------------------------------------ packing
-// lmunu[qk][L][mu][nu] -> PL[qk][plane][nu (nao_p)][L*nao_p + mu]; 32 rows x 8 nu
-// per workgroup through LDS so both the read and the write are coalesced.
-// Blocks (q, k) that the k <-> q-k paired transform does not read are skipped.
+// lmunu[qk][L][mu][nu] -> PL[qk][plane][nu (nao_p)][L*nao_p + mu]; 32 rows x 32 nu
+// per workgroup through LDS: each thread reads 4 consecutive nu of one row (16-byte
+// complex loads, all issued before the LDS stores) and writes 4 consecutive rows
+// of one nu and plane as one 16-byte store.  Blocks (q, k) that the k <-> q-k
+// paired transform does not read are skipped.
 template <class TIn>
 __global__ void __launch_bounds__(256) k_f32_pack_lmunu(const TIn* __restrict__ lm, int nao, int nao_p, int naux,
                                                         float* __restrict__ out, Mesh mesh) {
-    __shared__ float sh[3][8][33];
+    __shared__ float sh[3][32][33];
     const int M1 = naux * nao_p;
-    const int row0 = blockIdx.x * 32, nu0 = blockIdx.y * 8, qk = blockIdx.z;
+    const int row0 = blockIdx.x * 32, nu0 = blockIdx.y * 32, qk = blockIdx.z;
     if (!kpair_needed(mesh, qk / mesh.nk, qk % mesh.nk)) return;
     const int t = threadIdx.x;
     {
-        const int r = t / 8, v = t % 8, row = row0 + r, nu = nu0 + v;
-        float re = 0.f, im = 0.f;
-        if (row < M1) {
-            const int L = row / nao_p, mu = row % nao_p;
-            if (mu < nao && nu < nao) {
-                const TIn* src = lm + ((((size_t)qk * naux + L) * nao + mu) * nao + nu) * 2;
-                re = (float)src[0];
-                im = (float)src[1];
-            }
+        const int r = t / 8, v0 = (t % 8) * 4, row = row0 + r;
+        const int L = min(row, M1 - 1) / nao_p, mu = min(row, M1 - 1) % nao_p;
+        const bool rok = row < M1 && mu < nao;
+        const TIn* src = lm + (((size_t)qk * naux + L) * nao + min(mu, nao - 1)) * (size_t)nao * 2;
+        float re[4], im[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int nu = min(nu0 + v0 + u, nao - 1);
+            re[u] = (float)src[2 * nu];
+            im[u] = (float)src[2 * nu + 1];
         }
-        sh[0][v][r] = re;
-        sh[1][v][r] = im;
-        sh[2][v][r] = re + im;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool ok = rok && nu0 + v0 + u < nao;
+            const float a = ok ? re[u] : 0.f, b = ok ? im[u] : 0.f;
+            sh[0][v0 + u][r] = a;
+            sh[1][v0 + u][r] = b;
+            sh[2][v0 + u][r] = a + b;
+        }
     }
     __syncthreads();
-    const int v = t / 32, r = t % 32, row = row0 + r, nu = nu0 + v;
+    const int v = t / 8, r0 = (t % 8) * 4, nu = nu0 + v, row = row0 + r0;
     if (row < M1 && nu < nao_p) {
         const size_t plane = (size_t)nao_p * M1;
         float* o = out + (size_t)qk * 3 * plane + (size_t)nu * M1 + row;
-        o[0] = sh[0][v][r];
-        o[plane] = sh[1][v][r];
-        o[2 * plane] = sh[2][v][r];
+#pragma unroll
+        for (int pl = 0; pl < 3; ++pl)
+            *reinterpret_cast<float4*>(o + pl * plane) =
+                make_float4(sh[pl][v][r0], sh[pl][v][r0 + 1], sh[pl][v][r0 + 2], sh[pl][v][r0 + 3]);
     }
 }
 
@@ -513,10 +522,10 @@ dmet_status eri_f32(const EriPlan& p, const void* lmunu, const double* ck, doubl
     {
         ProfScope ps("pack_in_f32", st);
         if (p.dtype == DMET_C128)
-            k_f32_pack_lmunu<double><<<dim3((d.M1 + 31) / 32, d.nao_p / 8, nk * nk), 256, 0, st>>>(
+            k_f32_pack_lmunu<double><<<dim3((d.M1 + 31) / 32, (d.nao_p + 31) / 32, nk * nk), 256, 0, st>>>(
                 static_cast<const double*>(lmunu), p.nao, d.nao_p, p.naux, plm, p.mesh);
         else
-            k_f32_pack_lmunu<float><<<dim3((d.M1 + 31) / 32, d.nao_p / 8, nk * nk), 256, 0, st>>>(
+            k_f32_pack_lmunu<float><<<dim3((d.M1 + 31) / 32, (d.nao_p + 31) / 32, nk * nk), 256, 0, st>>>(
                 static_cast<const float*>(lmunu), p.nao, d.nao_p, p.naux, plm, p.mesh);
         k_f32_pack_c1<<<dim3((d.NBp + 255) / 256, d.nao_p, nk), 256, 0, st>>>(ck, nk, p.nspin, p.nao, d.nao_p, p.neo,
                                                                             d.neo_p, pc1);
