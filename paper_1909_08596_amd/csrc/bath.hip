@@ -141,9 +141,11 @@ __device__ inline double wave_sum_dpp(double x) {
 // outer sweep (nbp - 1 launches) therefore visits every column pair once, and
 // a sweep with no rotation has converged exactly as in the per-pair form.
 // Columns of a missing block (odd block count) or past n take no part.
-constexpr int JB = 4;
-constexpr int JB_MAXM = 2400;   // rows that fit: 2 JB m doubles of LDS
+// JB = 8 (eight waves) when 16 columns fit in LDS, else JB = 4.
+constexpr int JB_LDS = 150 * 1024;
+constexpr int jb_maxm(int jb) { return JB_LDS / (2 * jb * 8) / 2 * 2; }   // rows that fit: 2 JB mp doubles
 
+template <int JB>
 __global__ void __launch_bounds__(64 * JB) k_jacobi_block(int m, int n, int nbp, int round,
                                                           double* __restrict__ mt, double tol, int* rot) {
     extern __shared__ __align__(16) double colsh[];   // [2 JB][mp], rows m..mp-1 zero
@@ -158,7 +160,7 @@ __global__ void __launch_bounds__(64 * JB) k_jacobi_block(int m, int n, int nbp,
     };
     // JB_RU rows of every column per thread are loaded before any is stored,
     // so that one memory latency covers the whole stage at m <= 64 JB JB_RU
-    constexpr int JB_RU = 5;
+    constexpr int JB_RU = JB == 4 ? 5 : 3;
     for (int i0 = threadIdx.x; i0 < mp; i0 += 64 * JB * JB_RU) {
         double v[JB_RU][2 * JB];
 #pragma unroll
@@ -508,20 +510,26 @@ dmet_status build_bath(const dmet_lattice* lat, const double2* dm_k, int nimp, c
         const double tol = fmax(1e-15, sqrt((double)p.nenv) * 2.220446049250313e-16);
         const int np = nval + (nval & 1);
         // block form when the 2 JB columns of a block pair fit in LDS
-        const bool blocked = p.nenv <= JB_MAXM;
+        const int mp = p.nenv + (p.nenv & 1);
+        const int JB = mp <= jb_maxm(8) ? 8 : 4;
+        const bool blocked = mp <= jb_maxm(4);
         const int nb = (nval + JB - 1) / JB, nbp = nb + (nb & 1);
-        const size_t lds = (size_t)2 * JB * (p.nenv + (p.nenv & 1)) * sizeof(double);
-        if (blocked)
-            DMET_HIP(hipFuncSetAttribute((const void*)k_jacobi_block, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)lds));
+        const size_t lds = (size_t)2 * JB * mp * sizeof(double);
+        const void* kblk = JB == 8 ? (const void*)k_jacobi_block<8> : (const void*)k_jacobi_block<4>;
+        if (blocked) DMET_HIP(hipFuncSetAttribute(kblk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         int* rot = w.flags + 8;
         bool converged = false;
         for (int sweep = 0; sweep < 60 && !converged; ++sweep) {
             fill_zero(rot, 2 * sizeof(int), st);
             if (blocked) {
-                for (int round = 0; round < nbp - 1; ++round)
-                    k_jacobi_block<<<dim3(nbp / 2, p.nspin), 64 * JB, lds, st>>>(p.nenv, nval, nbp, round, w.mt,
-                                                                                  tol, rot);
+                for (int round = 0; round < nbp - 1; ++round) {
+                    if (JB == 8)
+                        k_jacobi_block<8><<<dim3(nbp / 2, p.nspin), 512, lds, st>>>(p.nenv, nval, nbp, round, w.mt,
+                                                                                    tol, rot);
+                    else
+                        k_jacobi_block<4><<<dim3(nbp / 2, p.nspin), 256, lds, st>>>(p.nenv, nval, nbp, round, w.mt,
+                                                                                    tol, rot);
+                }
                 DMET_LAUNCH_CHECK("k_jacobi_block");
             } else {
                 for (int round = 0; round < np - 1; ++round)

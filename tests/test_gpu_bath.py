@@ -2,8 +2,10 @@
 the shapes that select each form of the Jacobi SVD:
 
 * one column block (3 SVD columns, the partner block missing);
-* the NiO-like shape (1050 x 150 per spin, two spins), the block form at the
-  size the benchmark runs;
+* the NiO-like shape (1050 x 150 per spin, two spins), the block form with
+  8-column blocks at the size the benchmark runs;
+* the Si-like shape (1352 x 52), too many rows for 8-column blocks in LDS,
+  which takes 4-column blocks;
 * more environment rows than the block form stages in LDS (2520 x 40 on a
   4x4x4 mesh), which takes the per-pair form.
 
@@ -25,6 +27,7 @@ SHAPES = {
     # name: (kmesh, nao, nspin, seed)
     "one_block": ((2, 1, 1), 3, 1, 41),
     "nio": ((2, 2, 2), 150, 2, 1003),
+    "si": ((3, 3, 3), 52, 1, 1002),
     "many_rows": ((4, 4, 4), 40, 1, 77),
 }
 
