@@ -95,3 +95,27 @@ def test_fullsize_sampled_parity(dmet, name):
             assert np.all(got ** 2 <= np.outer(da, db) * (1 + 1e-9) + 1e-14)
         del out
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("name", ["nio", "bn33"])
+def test_fullsize_onebody_parity(dmet, name):
+    """One-body operators h, F, gamma and E1 at the benchmark's sizes (NiO: nao 150 over
+    ragged 64-row chunks, neo 300 over ragged output tiles; BN 3x3: 36 k-points) against
+    the oracle, on the oracle's C^k."""
+    wl = synth.BN33 if name == "bn33" else synth.CONFIGS[name]
+    imp, val = synth.bn33_impurity() if name == "bn33" else (None, None)
+    lat = synth.make_lattice(wl)
+    bath = ok.build_bath(lat.dm_k, wl.kmesh, wl.nao, imp_idx=imp, val_idx=val)
+    ck = bath["c_k"]
+    ck_d = to_dev(ck)
+    outs = {}
+    for nm, op in (("h", lat.h_k), ("f", lat.f_k), ("g", lat.dm_k)):
+        x, mi = dmet.dmet_transform_1e(wl.kmesh, wl.nao, ck_d, to_dev(op))
+        ref, _ = ok.transform_1e(ck, op)
+        err = np.abs(x.cpu().numpy() - ref).max()
+        print(f"{name} one-body {nm}: max err {err:.3e}, max |Im| {float(mi.cpu()):.3e}", flush=True)
+        assert err < 1e-12 * max(1.0, np.abs(ref).max())
+        assert float(mi.cpu()) < 1e-12
+        outs[nm] = (x, ref)
+    e1 = float(dmet.dmet_energy_1e(outs["h"][0], outs["g"][0]).cpu())
+    assert abs(e1 - ok.energy_1e(outs["h"][1], outs["g"][1])) < 1e-10 * max(1.0, abs(e1))
