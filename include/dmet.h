@@ -76,14 +76,16 @@ typedef enum {
 typedef enum {
     DMET_FP64 = 0,           /* complex GEMMs as 4 real FP64 MFMA products              */
     DMET_FP32_3M = 1,        /* complex GEMMs as 3 real FP32 products, FP32 accumulate   */
-    DMET_BF16X3_3M = 2,      /* 3M (4M in the transform's second stage) with each FP32
-                                operand split into bf16 hi + lo and the products
-                                hi*hi + hi*lo + lo*hi, FP32 accumulate
-                                (about 2^-17 relative per operand)                   */
-    DMET_BF16X6_3M = 3       /* 3M (4M in the transform's second stage) with a
-                                three-way bf16 split hi + mid + lo and the six
+    DMET_BF16X3_3M = 2,      /* each FP32 operand split into bf16 hi + lo and the
+                                products hi*hi + hi*lo + lo*hi, FP32 accumulate
+                                (about 2^-17 relative per operand).  Both transform
+                                stages multiply complex numbers with 4 real
+                                products (4M, not 3M: fewer operand bytes and no
+                                re+im cancellation); the contraction is real    */
+    DMET_BF16X6_3M = 3       /* three-way bf16 split hi + mid + lo and the six
                                 products hh, hm, mh, hl, mm, lh, FP32 accumulate
-                                (about FP32 accuracy)                                */
+                                (about FP32 accuracy); 4M in both transform
+                                stages as DMET_BF16X3_3M (the name is kept)     */
 } dmet_precision;
 
 typedef enum {
@@ -123,13 +125,20 @@ int dmet_version(void);
  *          cell*nao + mu, or NULL for the LOs of cell 0 (nimp must then be nao).
  * nval     number of SVD columns; val_idx (host) lists positions in the
  *          impurity list, or NULL for all (nval must then be nimp).
- * sv_tol   0 keeps all nval bath orbitals; > 0 drops those with sigma <= sv_tol.
+ * sv_tol   bath orbitals with sigma <= max(sv_tol, sigma_max * max(n_env, nval)
+ *          * 2^-52) are dropped; sv_tol = 0 thus keeps every orbital whose
+ *          singular value is above the rounding level (a sigma at that level,
+ *          e.g. an impurity column with no coupling to the environment, leaves
+ *          its singular vector undetermined by M).
  * c_ao_lo  [N_k][nao][nao] complex128 AO->LO rotation (Eq. "C aolo"), or NULL
  *          for the identity.
  * c_k      out [nspin][N_k][nao][nimp+nval] complex128.  Columns 0..nimp-1 are
  *          the impurity, then the bath; columns beyond neo[s] are zero.
  * sv       out [nspin][nval] float64 singular values, descending.
  * neo      out HOST [nspin]: nimp + number of kept bath orbitals.
+ * max_imag out HOST [1], or NULL: max |Im gamma^{R,0}| over every cell and
+ *          spin (zero up to rounding for time-reversal-symmetric input; the
+ *          imaginary part is discarded).
  * workspace/ws_bytes: device scratch, at least dmet_build_bath_workspace().
  *
  * An impurity that is the whole supercell (nimp = N_k*nao, e.g. one k-point
@@ -138,16 +147,17 @@ int dmet_version(void);
  * non-empty environment with fewer orbitals than nval is DMET_E_ARG.
  *
  * This call synchronises `stream` before returning (it reads back the
- * convergence status and the kept bath count).  Returns DMET_E_NOCONV if the
- * SVD needs more than 60 sweeps, DMET_E_NONFINITE for NaN/Inf in dm_k,
- * DMET_E_RANK if sv_tol removes every bath orbital.
+ * convergence status and the kept bath count).  Returns DMET_E_NONFINITE for
+ * NaN/Inf in dm_k (checked before the SVD), DMET_E_NOCONV if the SVD needs
+ * more than 60 sweeps, DMET_E_RANK if no singular value is above the drop
+ * threshold (no bath orbital is left).
  * ------------------------------------------------------------------------- */
 dmet_status dmet_build_bath_workspace(const dmet_lattice* lat, int nimp, int nval,
                                       size_t* bytes);
 dmet_status dmet_build_bath(const dmet_lattice* lat, const void* dm_k,
                             int nimp, const int* imp_idx, int nval, const int* val_idx,
                             double sv_tol, const void* c_ao_lo,
-                            void* c_k, double* sv, int* neo,
+                            void* c_k, double* sv, int* neo, double* max_imag,
                             void* workspace, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------

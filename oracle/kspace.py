@@ -12,11 +12,13 @@ matrix embedding theory", Sec. 2.1):
 * Eq. ``C loemb k``    : C^{k,LO,EO} = sum_R exp(-i k.R) C^{R,LO,EO};
                          C^{k,AO,EO} = C^{k,AO,LO} C^{k,LO,EO}
 * Eq. ``fock transform``: F^{0,EO} = 1/N_k sum_k C^{k dagger} F^k C^k
-* Alg. 1 (GDF embedding ERI): k-AO -> k-EO transform of (L|mu k_mu, nu k_nu),
-  Fourier sum to the reference cell with 1/N_k, contraction with 1/N_k.
-* App. B, Eq. ``FFTDF`` and Alg. 2 (plane-wave embedding ERI): the same
-  transform of the AO pair densities on the real-space grid, FFT, the Coulomb
-  kernel 4 pi / |q + G|^2, inverse FFT and the contraction over the grid.
+* Eq. ``density fitting`` with the embedding orbitals substituted (what Alg. 1
+  computes): the fitted 3-index of an EO pair in the reference cell,
+  X_L(q)_ij = 1/N_k sum_k [C^{k dagger} (L|k, k-q) C^{k-q}]_ij, and the ERI
+  (ij|kl) = 1/N_k sum_q sum_L conj(X_L(q)_ij) X_L(q)_kl.
+* App. B, Eq. ``FFTDF`` (what Alg. 2 computes): the Coulomb energy of the EO
+  pair densities, written as a sum over the plane waves q + G of the
+  Born-von Karman supercell with the kernel 4 pi / |q + G|^2.
 
 Readings of points the paper leaves open (k ordering, Fourier sign of gamma,
 normalisation of the 3-index tensor, which index of (0i0j|L) is conjugated,
@@ -115,8 +117,12 @@ def bath_orbitals(dm_r, kmesh, nao, imp_idx=None, val_idx=None, sv_tol=0.0):
     order (for a cell-0 impurity: R != 0, then mu); columns are the impurity
     valence LOs ``imp_idx[val_idx]`` (valence-only SVD, Sec. 2.1 "DMET bath and
     truncation").  Returns (env_rows, B [n_env][n_bath], sigma [n_val]).
-    Singular values are sorted descending; vectors with sigma <= sv_tol are
-    dropped (sv_tol = 0 keeps all n_val).
+    Singular values are sorted descending.  Bath orbitals with vanishing
+    singular values carry no entanglement with the impurity and are dropped
+    (Sec. 2.1, bath truncation): a vector is kept when sigma > max(sv_tol,
+    sigma_max * max(n_env, n_val) * eps), the second term being the rounding
+    level below which M does not determine the singular vector (the usual
+    numerical-rank tolerance).  sv_tol = 0 thus keeps every determined vector.
     """
     nk = int(np.prod(kmesh))
     nsup = nk * nao
@@ -129,7 +135,8 @@ def bath_orbitals(dm_r, kmesh, nao, imp_idx=None, val_idx=None, sv_tol=0.0):
     order = np.argsort(-s, kind="stable")
     s = s[order]
     u = u[:, order]
-    nb = int(np.count_nonzero(s > sv_tol)) if sv_tol > 0 else len(s)
+    thr = max(float(sv_tol), float(s.max(initial=0.0)) * max(m.shape) * np.finfo(np.float64).eps)
+    nb = int(np.count_nonzero(s > thr))
     b = sign_fix(u[:, :nb])
     return env, b, s
 
@@ -210,30 +217,31 @@ def energy_1e(h_eo, dm_eo):
 # Steps a5-a7: Alg. 1, embedding ERIs from the k-point GDF 3-index tensor
 # --------------------------------------------------------------------------
 def alg1_embedded_3index(lmunu, c_k, kmesh, q):
-    """Alg. 1 inner loop for one fitting momentum q:
+    """The fitted 3-index of the embedding-orbital pairs for one fitting
+    momentum q (Eq. ``density fitting`` in the EO basis, as used by Alg. 1):
 
-        (L|0i 0j) = 1/N_k sum_k [C^{k dagger} (L|k, k-q) C^{k-q}]_{ij}
+        X_L(q)_ij = 1/N_k sum_k sum_{mu nu} conj(C^k_{mu i}) (L|mu k, nu k-q) C^{k-q}_{nu j}
 
-    i.e. transform the 3-index to the k-EO basis with C^{k,AO,EO} and Fourier
-    sum to the reference cell.  Returns X [L][neo][neo] complex."""
+    The pair (i, j) lives in the reference cell, so every k contributes with
+    weight 1/N_k.  Returns X [L][neo][neo] complex."""
     nk = lmunu.shape[0]
     pts = mesh_points(kmesh)
     x = 0
     for k in range(nk):
         kmq = mesh_index(kmesh, pts[k] - pts[q])
-        t = lmunu[q, k] @ c_k[kmq]                      # k-AO -> k-EO, right index
-        x = x + (c_k[k].conj().T @ t) / nk              # left index, FT to R = 0
+        x = x + (c_k[k].conj().T @ lmunu[q, k] @ c_k[kmq]) / nk
     return x
 
 
 def alg1_eri(lmunu, c_k_a, kmesh, c_k_b=None):
-    """Embedding ERI (ij|kl) by Alg. 1:
+    """Embedding ERI as Alg. 1 defines it:
 
-        (ij|kl) += 1/N_k sum_L (0i 0j|L)(L|0k 0l)   for every q,
+        (ij|kl) = 1/N_k sum_q sum_L conj(X_L(q)_ij) X_L(q)_kl,
 
-    with (0i 0j|L) = conj((L|0i 0j)).  With a second spin's C^k the mixed
-    (alpha alpha|beta beta) block is returned.  Returns (real [n][n][n][n],
-    max |Im|)."""
+    the fitted Coulomb integral of the reference-cell EO pairs (the bra side
+    of Eq. ``density fitting`` is the complex conjugate of the ket side).
+    With a second spin's C^k the mixed (alpha alpha|beta beta) block is
+    returned.  Returns (real [n][n][n][n], max |Im|)."""
     nk = lmunu.shape[0]
     eri = 0
     for q in range(nk):
@@ -306,35 +314,38 @@ def coulomb_kernel(kmesh, grid_n, cell, q):
 
 
 def alg2_eri(rho, c_k_a, kmesh, grid_n, cell, c_k_b=None):
-    """Embedding ERI (ij|kl) by Alg. 2.  For every q:
+    """Plane-wave embedding ERI (App. B, Eq. ``FFTDF``; the quantity Alg. 2
+    evaluates).  The EO pair density of the reference cell with momentum q,
+    X_ij(q)[r] = 1/N_k sum_k [C^{k dagger} (r|k, k-q) C^{k-q}]_ij, has the
+    plane-wave coefficients W_ij(q)[G] = sum_r exp(+i (q+G).r) X_ij(q)[r] on the
+    cell grid; the ERI is the Coulomb energy of the pair densities on the
+    Born-von Karman supercell,
 
-        X(q)[r] = 1/N_k sum_k C^{k dagger} (r|k, k-q) C^{k-q}      k-AO -> k-EO, FT to R = 0
-        W(q)[G] = sum_r exp(+i (q+G).r) X(q)[r]                     FFT
-        W(q)[G] *= 4 pi / |q + G|^2                                 Coulomb kernel
-        V(q)[r] = 1/n_r sum_G exp(-i (q+G).r) W(q)[G]               inverse FFT
-        (ij|kl) += dV/N_k sum_r conj(X_ij(q)[r]) V_kl(q)[r]         contraction over the grid
+        (ij|kl) = dV^2 / (N_k Omega) sum_q sum_G 4 pi/|q+G|^2 conj(W_ij(q)[G]) W_kl(q)[G],
 
-    with dV = Omega / n_r the volume per grid point, so that the result is the
-    Coulomb integral of the EO pair densities on the Born-von Karman supercell.
-    rho[q][k][r][mu][nu] = (r|mu k, nu k-q).  Returns (real [n][n][m][m], max |Im|)."""
+    dV = Omega / n_r, with the q + G = 0 term left out (neutralising
+    background).  rho[q][k][r][mu][nu] = (r|mu k, nu k-q).
+    Returns (real [n][n][m][m], max |Im|)."""
     nk = rho.shape[0]
     grid_n = tuple(grid_n)
     nr = int(np.prod(grid_n))
-    dv = float(np.prod(cell)) / nr
+    omega = float(np.prod(cell))
+    dv = omega / nr
     idx = np.indices(grid_n).reshape(3, -1).T
     eri = 0
     for q in range(nk):
         m = mesh_points(kmesh)[q]
         ph = np.exp(2j * np.pi * (idx * (m / (np.asarray(kmesh) * np.asarray(grid_n)))[None, :]).sum(axis=1))
         kern = coulomb_kernel(kmesh, grid_n, cell, q)
-        xs = [alg1_embedded_3index(rho, c, kmesh, q) for c in ((c_k_a,) if c_k_b is None else (c_k_a, c_k_b))]
-        xa, xb = xs[0], xs[-1]
-        n, mm = xa.shape[1], xb.shape[1]
-        w = np.fft.ifftn((ph[:, None, None] * xb).reshape(*grid_n, mm, mm), axes=(0, 1, 2)) * nr
-        w = w.reshape(nr, mm, mm) * kern[:, None, None]
-        v = np.fft.fftn(w.reshape(*grid_n, mm, mm), axes=(0, 1, 2)).reshape(nr, mm, mm) / nr
-        v = v * ph.conj()[:, None, None]
-        eri = eri + dv / nk * (xa.reshape(nr, n * n).conj().T @ v.reshape(nr, mm * mm))
+        w = []
+        for c in ((c_k_a,) if c_k_b is None else (c_k_a, c_k_b)):
+            x = alg1_embedded_3index(rho, c, kmesh, q)                     # [r][i][j]
+            n = x.shape[1]
+            # sum_r exp(+i G.r) f(r) over the cell grid is n_r times numpy's inverse DFT
+            wq = np.fft.ifftn((ph[:, None, None] * x).reshape(*grid_n, n, n), axes=(0, 1, 2)) * nr
+            w.append(wq.reshape(nr, n * n))
+        wa, wb = w[0], w[-1]
+        eri = eri + dv * dv / (nk * omega) * ((wa.conj() * kern[:, None]).T @ wb)
     n = c_k_a.shape[2]
     m = n if c_k_b is None else c_k_b.shape[2]
     eri = eri.reshape(n, n, m, m)

@@ -140,7 +140,7 @@ extern "C" {
 
 const char* dmet_last_error(void) { return g_last_error.c_str(); }
 
-int dmet_version(void) { return 200; }   // 0.2.0: dmet_energy_mf added
+int dmet_version(void) { return 300; }   // 0.3.0: dmet_build_bath reports max |Im gamma^{R,0}|
 
 dmet_status dmet_build_bath_workspace(const dmet_lattice* lat, int nimp, int nval, size_t* bytes) {
     dmet_status s = check_lattice(lat);
@@ -153,7 +153,7 @@ dmet_status dmet_build_bath_workspace(const dmet_lattice* lat, int nimp, int nva
 
 dmet_status dmet_build_bath(const dmet_lattice* lat, const void* dm_k, int nimp, const int* imp_idx, int nval,
                             const int* val_idx, double sv_tol, const void* c_ao_lo, void* c_k, double* sv,
-                            int* neo, void* workspace, size_t ws_bytes, hipStream_t stream) {
+                            int* neo, double* max_imag, void* workspace, size_t ws_bytes, hipStream_t stream) {
     g_last_error.clear();
     dmet_status s = check_lattice(lat);
     if (s != DMET_OK) return s;
@@ -167,8 +167,8 @@ dmet_status dmet_build_bath(const dmet_lattice* lat, const void* dm_k, int nimp,
     if (nval > 1024) return fail(DMET_E_UNSUPPORTED, "more than 1024 SVD columns");
     if (!workspace) return fail(DMET_E_WORKSPACE, "workspace is NULL");
     return build_bath(lat, static_cast<const double2*>(dm_k), nimp, imp_idx, nval, val_idx, sv_tol,
-                      static_cast<const double2*>(c_ao_lo), static_cast<double2*>(c_k), sv, neo, workspace,
-                      ws_bytes, stream);
+                      static_cast<const double2*>(c_ao_lo), static_cast<double2*>(c_k), sv, neo, max_imag,
+                      workspace, ws_bytes, stream);
 }
 
 dmet_status dmet_transform_1e(const dmet_lattice* lat, int neo, const void* c_k, const void* op_k, double* op_eo,

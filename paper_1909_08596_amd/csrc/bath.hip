@@ -242,7 +242,10 @@ __global__ void __launch_bounds__(64 * JB) k_jacobi_block(int m, int n, int nbp,
 
 // sigma, descending order, normalised and sign-fixed left vectors.
 // One workgroup per spin.  ub[s][b][r] = u_b, sv[s][b] = sigma_b, and
-// flags[4 + s] = number of kept bath vectors (sigma > sv_tol, or all).
+// flags[4 + s] = number of kept bath vectors: sigma > max(sv_tol, rank_tol)
+// with rank_tol = sigma_max * max(m, n) * 2^-52, the rounding level below
+// which M does not determine a singular vector (such a column is exactly
+// zero after the sweeps, so its bath vector would be zero).
 __global__ void __launch_bounds__(1024) k_svd_finalize(int m, int n, const double* __restrict__ mt,
                                                        double* __restrict__ ub, double* __restrict__ sv,
                                                        double sv_tol, int* flags) {
@@ -284,11 +287,11 @@ __global__ void __launch_bounds__(1024) k_svd_finalize(int m, int n, const doubl
         if (lane == 0) sv[(size_t)s * n + b] = sig[c];
     }
     if (threadIdx.x == 0) {
-        int kept = n;
-        if (sv_tol > 0.0) {
-            kept = 0;
-            for (int c = 0; c < n; ++c) kept += sig[c] > sv_tol;
-        }
+        double smax = 0.0;
+        for (int c = 0; c < n; ++c) smax = fmax(smax, sig[c]);
+        const double thr = fmax(sv_tol, smax * (double)max(m, n) * 2.220446049250313e-16);
+        int kept = 0;
+        for (int c = 0; c < n; ++c) kept += sig[c] > thr;
         flags[4 + s] = kept;
     }
 }
@@ -446,7 +449,7 @@ size_t bath_workspace_bytes(const dmet_lattice* lat, int nimp, int nval) {
 
 dmet_status build_bath(const dmet_lattice* lat, const double2* dm_k, int nimp, const int* imp_idx,
                        int nval, const int* val_idx, double sv_tol, const double2* c_ao_lo,
-                       double2* c_k, double* sv, int* neo, void* ws, size_t ws_bytes,
+                       double2* c_k, double* sv, int* neo, double* max_imag, void* ws, size_t ws_bytes,
                        hipStream_t st) {
     BathPlan p;
     p.mesh = make_mesh(lat->kmesh);
@@ -499,6 +502,12 @@ dmet_status build_bath(const dmet_lattice* lat, const double2* dm_k, int nimp, c
     k_dm_real<<<dim3((nn + 255) / 256, p.mesh.nk, p.nspin), 256, 0, st>>>(p.mesh, p.nao, dm_k, w.dm_r,
                                                                           w.flags, w.scal);
     DMET_LAUNCH_CHECK("k_dm_real");
+    {   // a non-finite density is reported before the SVD sweeps would spin on it
+        int f0 = 0;
+        DMET_HIP(hipMemcpyAsync(&f0, w.flags, sizeof(int), hipMemcpyDeviceToHost, st));
+        DMET_HIP(hipStreamSynchronize(st));
+        if (f0 & FLAG_NONFINITE) return fail(DMET_E_NONFINITE, "non-finite entry in dm_k");
+    }
     if (p.nenv > 0) {
         k_build_m<<<dim3((p.nenv + 255) / 256, nval, p.nspin), 256, 0, st>>>(
             p.mesh, p.nao, p.nenv, nval, w.env, w.cols, w.dm_r, w.mt);
@@ -576,9 +585,11 @@ dmet_status build_bath(const dmet_lattice* lat, const double2* dm_k, int nimp, c
     if (flags[0] & FLAG_NOCONV) return fail(DMET_E_NOCONV, "Jacobi SVD did not converge in 60 sweeps");
     if (scal[1] > 1e-6) return fail(DMET_E_NOCONV, "bath vectors lost orthogonality (|S - I| > 1e-6)");
     for (int s = 0; s < p.nspin; ++s) {
-        if (flags[4 + s] == 0 && p.nenv > 0) return fail(DMET_E_RANK, "sv_tol removed every bath orbital");
+        if (flags[4 + s] == 0 && p.nenv > 0)
+            return fail(DMET_E_RANK, "no singular value above max(sv_tol, rounding level): no bath orbital");
         neo[s] = nimp + flags[4 + s];
     }
+    if (max_imag) *max_imag = scal[0];
     return DMET_OK;
 }
 

@@ -114,7 +114,8 @@ dmet_status eri_batched(int nfrag, const dmet_fragment* frags, dmet_precision pr
 size_t bath_workspace_bytes(const dmet_lattice* lat, int nimp, int nval);
 dmet_status build_bath(const dmet_lattice* lat, const double2* dm_k, int nimp, const int* imp_idx,
                        int nval, const int* val_idx, double sv_tol, const double2* c_ao_lo,
-                       double2* c_k, double* sv, int* neo, void* ws, size_t ws_bytes, hipStream_t st);
+                       double2* c_k, double* sv, int* neo, double* max_imag, void* ws, size_t ws_bytes,
+                       hipStream_t st);
 dmet_status transform_1e(const dmet_lattice* lat, int neo, const double2* ck, const double2* op,
                          double* out, double* max_imag, hipStream_t st);
 dmet_status energy_1e(int nspin, int neo, const double* h, const double* g, double* e1, hipStream_t st);

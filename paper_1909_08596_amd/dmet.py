@@ -8,6 +8,7 @@ no CPU fallback.  Names and arguments mirror include/dmet.h.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from typing import Optional, Sequence
 
@@ -85,7 +86,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dmet_last_error.argtypes = []
     lib.dmet_version.restype = i
     lib.dmet_build_bath_workspace.argtypes = [lp, i, i, ctypes.POINTER(sz)]
-    lib.dmet_build_bath.argtypes = [lp, vp, i, vp, i, vp, d, vp, vp, vp, vp, vp, sz, vp]
+    lib.dmet_build_bath.argtypes = [lp, vp, i, vp, i, vp, d, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.dmet_transform_1e.argtypes = [lp, i, vp, vp, vp, vp, vp]
     lib.dmet_energy_1e.argtypes = [i, i, vp, vp, vp, vp]
     lib.dmet_transform_eri_workspace.argtypes = [lp, i, i, i, ctypes.POINTER(sz)]
@@ -119,6 +120,23 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _shape(t, shape, name):
+    """The library receives raw pointers, so every extent is checked here:
+    a tensor of the wrong shape would make the kernels read or write past it."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    want = tuple(int(x) for x in shape)
+    if tuple(t.shape) != want:
+        raise ValueError(f"{name} must have shape {want}, got {tuple(t.shape)}")
+    return t
+
+
+def _nk(kmesh) -> int:
+    if len(kmesh) != 3 or any(int(x) < 1 for x in kmesh):
+        raise ValueError("kmesh must be three positive integers")
+    return int(kmesh[0]) * int(kmesh[1]) * int(kmesh[2])
+
+
 def _dev(t: torch.Tensor, dtype, name):
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise ValueError(f"{name} must be a device tensor")
@@ -139,37 +157,51 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 
 def dmet_build_bath(kmesh, nao, dm_k: torch.Tensor, imp_idx=None, val_idx=None, sv_tol: float = 0.0,
-                    c_ao_lo: Optional[torch.Tensor] = None, stream=None):
-    """Bath SVD and embedding coefficients.  Returns (c_k, sv, neo list);
-    c_k has nimp + nval columns, those past neo[s] are zero."""
+                    c_ao_lo: Optional[torch.Tensor] = None, stream=None, return_imag: bool = False):
+    """Bath SVD and embedding coefficients.  Returns (c_k, sv, neo list), and
+    max |Im gamma^{R,0}| as a fourth item if return_imag; c_k has nimp + nval
+    columns, those past neo[s] are zero."""
     lib = load()
-    _dev(dm_k, torch.complex128, "dm_k")
+    nk = _nk(kmesh)
+    if dm_k.dim() != 4 or dm_k.shape[0] not in (1, 2):
+        raise ValueError("dm_k must be [nspin][N_k][nao][nao] with nspin 1 or 2")
     nspin = dm_k.shape[0]
+    _shape(dm_k, (nspin, nk, nao, nao), "dm_k")
+    if c_ao_lo is not None:
+        _shape(c_ao_lo, (nk, nao, nao), "c_ao_lo")
+        _dev(c_ao_lo, torch.complex128, "c_ao_lo")
+    _dev(dm_k, torch.complex128, "dm_k")
     lat = lattice(kmesh, nao, 1, nspin)
     nimp = nao if imp_idx is None else len(imp_idx)
     nval = nimp if val_idx is None else len(val_idx)
     imp_arr = None if imp_idx is None else (ctypes.c_int * nimp)(*[int(x) for x in imp_idx])
     val_arr = None if val_idx is None else (ctypes.c_int * nval)(*[int(x) for x in val_idx])
-    nk = int(kmesh[0]) * int(kmesh[1]) * int(kmesh[2])
-    if c_ao_lo is not None:
-        _dev(c_ao_lo, torch.complex128, "c_ao_lo")
     c_k = torch.empty((nspin, nk, nao, nimp + nval), dtype=torch.complex128, device=dm_k.device)
     sv = torch.empty((nspin, nval), dtype=torch.float64, device=dm_k.device)
     nb = ctypes.c_size_t()
     _check(lib.dmet_build_bath_workspace(ctypes.byref(lat), nimp, nval, ctypes.byref(nb)))
     ws = _workspace(nb.value, dm_k.device)
     neo = (ctypes.c_int * nspin)()
+    mi = ctypes.c_double(-1.0)
     _check(lib.dmet_build_bath(ctypes.byref(lat), _ptr(dm_k), nimp, imp_arr, nval, val_arr, float(sv_tol),
-                               _ptr(c_ao_lo), _ptr(c_k), _ptr(sv), neo, _ptr(ws), ws.numel(), _stream(stream)))
+                               _ptr(c_ao_lo), _ptr(c_k), _ptr(sv), neo, ctypes.byref(mi), _ptr(ws), ws.numel(),
+                               _stream(stream)))
+    if return_imag:
+        return c_k, sv, [int(x) for x in neo], mi.value
     return c_k, sv, [int(x) for x in neo]
 
 
 def dmet_transform_1e(kmesh, nao, c_k: torch.Tensor, op_k: torch.Tensor, want_imag: bool = True, stream=None):
     """X^{0,EO} = 1/N_k sum_k C^k^H X^k C^k.  Returns (op_eo, max_imag or None)."""
     lib = load()
+    nk = _nk(kmesh)
+    if c_k.dim() != 4 or c_k.shape[0] not in (1, 2):
+        raise ValueError("c_k must be [nspin][N_k][nao][neo] with nspin 1 or 2")
+    nspin, neo = c_k.shape[0], c_k.shape[3]
+    _shape(c_k, (nspin, nk, nao, neo), "c_k")
+    _shape(op_k, (nspin, nk, nao, nao), "op_k")
     _dev(c_k, torch.complex128, "c_k")
     _dev(op_k, torch.complex128, "op_k")
-    nspin, nk, _, neo = c_k.shape
     lat = lattice(kmesh, nao, 1, nspin)
     out = torch.empty((nspin, neo, neo), dtype=torch.float64, device=c_k.device)
     mi = torch.empty(1, dtype=torch.float64, device=c_k.device) if want_imag else None
@@ -180,6 +212,9 @@ def dmet_transform_1e(kmesh, nao, c_k: torch.Tensor, op_k: torch.Tensor, want_im
 
 def dmet_energy_1e(h_eo: torch.Tensor, dm_eo: torch.Tensor, stream=None) -> torch.Tensor:
     lib = load()
+    if h_eo.dim() != 3 or h_eo.shape[0] not in (1, 2) or h_eo.shape[1] != h_eo.shape[2]:
+        raise ValueError("h_eo must be [nspin][neo][neo] with nspin 1 or 2")
+    _shape(dm_eo, h_eo.shape, "dm_eo")
     _dev(h_eo, torch.float64, "h_eo")
     _dev(dm_eo, torch.float64, "dm_eo")
     e1 = torch.empty(1, dtype=torch.float64, device=h_eo.device)
@@ -197,16 +232,52 @@ def dmet_transform_eri_workspace(kmesh, nao, naux, nspin, neo, precision="fp64",
     return nb.value
 
 
+def _eri_inputs(kmesh, nao, naux, lmunu, c_k, name="lmunu"):
+    """Shape, dtype and device checks of the 3-index tensor and C^k; returns (nspin, neo)."""
+    nk = _nk(kmesh)
+    if not isinstance(lmunu, torch.Tensor) or lmunu.dtype not in (torch.complex128, torch.complex64):
+        raise ValueError(f"{name} must be complex128 or complex64")
+    if not isinstance(c_k, torch.Tensor) or c_k.dim() != 4 or c_k.shape[0] not in (1, 2):
+        raise ValueError("c_k must be [nspin][N_k][nao][neo] with nspin 1 or 2")
+    nspin, neo = c_k.shape[0], c_k.shape[3]
+    _shape(lmunu, (nk, nk, naux, nao, nao), name)
+    _shape(c_k, (nspin, nk, nao, neo), "c_k")
+    _dev(lmunu, lmunu.dtype, name)
+    _dev(c_k, torch.complex128, "c_k")
+    return nspin, neo
+
+
+def _eri_outputs(out, nspin, npair):
+    """Caller-supplied output tensors must hold the packed blocks the call writes."""
+    s8 = npair * (npair + 1) // 2
+    if "aa" not in out:
+        raise ValueError("out needs an 'aa' tensor")
+    want = {"aa": (s8,), "bb": (s8,), "ab": (npair, npair)}
+    for key, t in out.items():
+        if key not in want:
+            raise ValueError(f"unknown output block {key!r}")
+        if nspin == 1 and key != "aa":
+            raise ValueError("one spin writes only the 'aa' block")
+        if t.numel() != math.prod(want[key]):
+            raise ValueError(f"out[{key!r}] must hold {want[key]} float64 values, got {tuple(t.shape)}")
+    if nspin == 2 and "bb" not in out:
+        raise ValueError("two spins need a 'bb' output")
+    for key, t in out.items():
+        _dev(t, torch.float64, f"out[{key!r}]")
+
+
+def _workspace_ok(ws, need):
+    _dev(ws, torch.uint8, "workspace")
+    if ws.numel() < need:
+        raise ValueError(f"workspace holds {ws.numel()} bytes, the call needs {need}")
+
+
 def dmet_transform_eri(kmesh, nao, naux, lmunu: torch.Tensor, c_k: torch.Tensor, precision: str = "fp64",
                        eri_ab: bool = True, workspace: Optional[torch.Tensor] = None, out=None, stream=None):
     """Packed embedding ERIs by Alg. 1.  Returns dict with 'aa' (s8), and for
     two spins 'bb' (s8) and 'ab' (s4, if requested)."""
     lib = load()
-    if lmunu.dtype not in (torch.complex128, torch.complex64):
-        raise ValueError("lmunu must be complex128 or complex64")
-    _dev(lmunu, lmunu.dtype, "lmunu")
-    _dev(c_k, torch.complex128, "c_k")
-    nspin, nk, _, neo = c_k.shape
+    nspin, neo = _eri_inputs(kmesh, nao, naux, lmunu, c_k)
     lat = lattice(kmesh, nao, naux, nspin)
     dt = DMET_C128 if lmunu.dtype == torch.complex128 else DMET_C64
     npair = neo * (neo + 1) // 2
@@ -217,9 +288,11 @@ def dmet_transform_eri(kmesh, nao, naux, lmunu: torch.Tensor, c_k: torch.Tensor,
             out["bb"] = torch.empty_like(out["aa"])
             if eri_ab:
                 out["ab"] = torch.empty((npair, npair), dtype=torch.float64, device=dev)
+    _eri_outputs(out, nspin, npair)
+    need = dmet_transform_eri_workspace(kmesh, nao, naux, nspin, neo, precision, lmunu.dtype)
     if workspace is None:
-        workspace = _workspace(dmet_transform_eri_workspace(kmesh, nao, naux, nspin, neo, precision,
-                                                            lmunu.dtype), dev)
+        workspace = _workspace(need, dev)
+    _workspace_ok(workspace, need)
     _check(lib.dmet_transform_eri(ctypes.byref(lat), neo, _ptr(lmunu), dt, _ptr(c_k), PRECISIONS[precision],
                                   _ptr(out["aa"]), _ptr(out.get("bb")), _ptr(out.get("ab")), _ptr(workspace),
                                   workspace.numel(), _stream(stream)))
@@ -245,12 +318,8 @@ def dmet_transform_eri_fftdf(kmesh, nao, grid_n, cell, rho: torch.Tensor, c_k: t
     grid_n the grid points per axis and cell the orthorhombic cell lengths
     (bohr).  Same return value as dmet_transform_eri."""
     lib = load()
-    if rho.dtype not in (torch.complex128, torch.complex64):
-        raise ValueError("rho must be complex128 or complex64")
-    _dev(rho, rho.dtype, "rho")
-    _dev(c_k, torch.complex128, "c_k")
-    nspin, nk, _, neo = c_k.shape
     nr = int(grid_n[0]) * int(grid_n[1]) * int(grid_n[2])
+    nspin, neo = _eri_inputs(kmesh, nao, nr, rho, c_k, "rho")
     lat = lattice(kmesh, nao, nr, nspin)
     grid = pw_grid(grid_n, cell)
     dt = DMET_C128 if rho.dtype == torch.complex128 else DMET_C64
@@ -261,11 +330,11 @@ def dmet_transform_eri_fftdf(kmesh, nao, grid_n, cell, rho: torch.Tensor, c_k: t
         out["bb"] = torch.empty_like(out["aa"])
         if eri_ab:
             out["ab"] = torch.empty((npair, npair), dtype=torch.float64, device=dev)
+    nb = ctypes.c_size_t()
+    _check(lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(grid), neo, dt, ctypes.byref(nb)))
     if workspace is None:
-        nb = ctypes.c_size_t()
-        _check(lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(grid), neo, dt,
-                                                      ctypes.byref(nb)))
         workspace = _workspace(nb.value, dev)
+    _workspace_ok(workspace, nb.value)
     _check(lib.dmet_transform_eri_fftdf(ctypes.byref(lat), ctypes.byref(grid), neo, _ptr(rho), dt, _ptr(c_k),
                                         _ptr(out["aa"]), _ptr(out.get("bb")), _ptr(out.get("ab")), _ptr(workspace),
                                         workspace.numel(), _stream(stream)))
@@ -277,16 +346,16 @@ def dmet_transform_eri_df(kmesh, nao, naux, lmunu: torch.Tensor, c_k: torch.Tens
     """Density-fitting factors z [nspin][N_k*naux][npair] (float64) with
     (ij|kl)_st = sum_P z_s[P][ij] z_t[P][kl] (the contraction of Alg. 1 skipped)."""
     lib = load()
-    _dev(lmunu, lmunu.dtype, "lmunu")
-    _dev(c_k, torch.complex128, "c_k")
-    nspin, nk, _, neo = c_k.shape
+    nspin, neo = _eri_inputs(kmesh, nao, naux, lmunu, c_k)
+    nk = _nk(kmesh)
     lat = lattice(kmesh, nao, naux, nspin)
     dt = DMET_C128 if lmunu.dtype == torch.complex128 else DMET_C64
     npair = neo * (neo + 1) // 2
     z = torch.empty((nspin, nk * naux, npair), dtype=torch.float64, device=c_k.device)
+    need = dmet_transform_eri_workspace(kmesh, nao, naux, nspin, neo, precision, lmunu.dtype)
     if workspace is None:
-        workspace = _workspace(dmet_transform_eri_workspace(kmesh, nao, naux, nspin, neo, precision, lmunu.dtype),
-                               c_k.device)
+        workspace = _workspace(need, c_k.device)
+    _workspace_ok(workspace, need)
     _check(lib.dmet_transform_eri_df(ctypes.byref(lat), neo, _ptr(lmunu), dt, _ptr(c_k), PRECISIONS[precision],
                                      _ptr(z), _ptr(workspace), workspace.numel(), _stream(stream)))
     return z
@@ -296,11 +365,17 @@ def dmet_fock_dc(z: torch.Tensor, f_eo: torch.Tensor, dm_eo: torch.Tensor, strea
     """F~ of Eq. "fock double counting" from the DF factors z, F^EO and the
     per-spin embedding density (all float64 device tensors)."""
     lib = load()
+    if f_eo.dim() != 3 or f_eo.shape[0] not in (1, 2) or f_eo.shape[1] != f_eo.shape[2]:
+        raise ValueError("f_eo must be [nspin][neo][neo] with nspin 1 or 2")
+    nspin, neo = f_eo.shape[0], f_eo.shape[1]
+    if z.dim() != 3:
+        raise ValueError("z must be [nspin][nrows][npair]")
+    nrows = z.shape[1]
+    _shape(z, (nspin, nrows, neo * (neo + 1) // 2), "z")
+    _shape(dm_eo, f_eo.shape, "dm_eo")
     _dev(z, torch.float64, "z")
     _dev(f_eo, torch.float64, "f_eo")
     _dev(dm_eo, torch.float64, "dm_eo")
-    nspin, neo = f_eo.shape[0], f_eo.shape[1]
-    nrows = z.shape[1]
     nb = ctypes.c_size_t()
     _check(lib.dmet_fock_dc_workspace(nspin, neo, nrows, ctypes.byref(nb)))
     ws = _workspace(nb.value, f_eo.device)
@@ -314,6 +389,10 @@ def dmet_energy_mf(f_tilde: torch.Tensor, f_eo: torch.Tensor, dm_eo: torch.Tenso
     """Mean-field (Hartree-Fock form) energy of the embedding Hamiltonian with
     one-body part F~ (float64 device tensors [nspin][neo][neo]); device [1]."""
     lib = load()
+    if f_eo.dim() != 3 or f_eo.shape[0] not in (1, 2) or f_eo.shape[1] != f_eo.shape[2]:
+        raise ValueError("f_eo must be [nspin][neo][neo] with nspin 1 or 2")
+    _shape(f_tilde, f_eo.shape, "f_tilde")
+    _shape(dm_eo, f_eo.shape, "dm_eo")
     _dev(f_tilde, torch.float64, "f_tilde")
     _dev(f_eo, torch.float64, "f_eo")
     _dev(dm_eo, torch.float64, "dm_eo")
@@ -324,16 +403,26 @@ def dmet_energy_mf(f_tilde: torch.Tensor, f_eo: torch.Tensor, dm_eo: torch.Tenso
 
 
 def _fragments(frags, precision):
-    for f in frags:
+    for n, f in enumerate(frags):
+        nk = _nk(f["kmesh"])
+        ck = f["c_k"]
+        if not isinstance(ck, torch.Tensor) or ck.dim() != 3:
+            raise ValueError(f"fragment {n}: c_k must be [N_k][nao][neo]")
+        neo = ck.shape[-1]
+        npair = neo * (neo + 1) // 2
+        _shape(ck, (nk, f["nao"], neo), f"fragment {n}: c_k")
+        lm = f["lmunu"]
+        if not isinstance(lm, torch.Tensor) or lm.dtype not in (torch.complex128, torch.complex64):
+            raise ValueError(f"fragment {n}: lmunu must be complex128 or complex64")
+        _shape(lm, (nk, nk, f["naux"], f["nao"], f["nao"]), f"fragment {n}: lmunu")
         if "eri" not in f:
-            neo = f["c_k"].shape[-1]
-            npair = neo * (neo + 1) // 2
-            f["eri"] = torch.empty(npair * (npair + 1) // 2, dtype=torch.float64, device=f["c_k"].device)
+            f["eri"] = torch.empty(npair * (npair + 1) // 2, dtype=torch.float64, device=ck.device)
+        if f["eri"].numel() != npair * (npair + 1) // 2:
+            raise ValueError(f"fragment {n}: eri must hold {npair * (npair + 1) // 2} float64 values")
+        _dev(f["eri"], torch.float64, f"fragment {n}: eri")
     arr = (Fragment * len(frags))()
     for n, f in enumerate(frags):
         lm, ck = f["lmunu"], f["c_k"]
-        if lm.dtype not in (torch.complex128, torch.complex64):
-            raise ValueError("lmunu must be complex128 or complex64")
         _dev(lm, lm.dtype, "lmunu")
         _dev(ck, torch.complex128, "c_k")
         neo = ck.shape[-1]
@@ -359,10 +448,11 @@ def dmet_transform_eri_batched(frags, precision="bf16x6", graph=False, autotune=
     dicts with kmesh, nao, naux, lmunu, c_k ([N_k][nao][neo] complex128) and an
     optional preallocated 'eri'; returns the list of output tensors."""
     arr = _fragments(frags, precision)
+    nb = ctypes.c_size_t()
+    _check(load().dmet_transform_eri_batched_workspace(len(frags), arr, PRECISIONS[precision], ctypes.byref(nb)))
     if workspace is None:
-        nb = ctypes.c_size_t()
-        _check(load().dmet_transform_eri_batched_workspace(len(frags), arr, PRECISIONS[precision], ctypes.byref(nb)))
         workspace = _workspace(nb.value, frags[0]["c_k"].device)
+    _workspace_ok(workspace, nb.value)
     flags = (DMET_BATCH_GRAPH if graph else 0) | (DMET_BATCH_AUTOTUNE if autotune else 0)
     _check(load().dmet_transform_eri_batched(len(frags), arr, PRECISIONS[precision], flags, _ptr(workspace),
                                              workspace.numel(), _stream(stream)))

@@ -43,6 +43,7 @@ __all__ = [
     "Workload", "CONFIGS", "cells", "min_image_length", "kq_index",
     "make_lattice", "three_index", "three_index_block", "Lattice",
     "FftGrid", "FFT_CONFIGS", "fftdf_pair_density", "fftdf_ao_supercell",
+    "random_lattice_unitary", "decouple_orbital",
 ]
 
 
@@ -288,6 +289,34 @@ def three_index(wl: Workload, real_space: bool = False, dtype=np.complex128,
     with ThreadPoolExecutor(nthr) as ex:
         list(ex.map(work, starts))
     return (out, bfull) if real_space else out
+
+
+def random_lattice_unitary(kmesh, nao, seed, scale=0.3) -> np.ndarray:
+    """A k-dependent unitary U(k) [N_k][nao][nao] complex128 that stands in for
+    a crystal-AO -> LO rotation C^{k,AO,LO} (orthonormal AOs assumed):
+    U(k) = expm(S(k)), S(k) = sum_R exp(+i k.R) A(R) with real A(-R) = -A(R)^T,
+    so S(k) is anti-Hermitian (U unitary) and U(-k) = conj(U(k)) (a real
+    rotation in the supercell, time-reversal symmetric)."""
+    from scipy.linalg import expm
+    nk = int(np.prod(kmesh))
+    rng = np.random.default_rng([seed, 500])
+    env = np.exp(-min_image_length(kmesh))
+    g = rng.standard_normal((nk, nao, nao)) * scale * env[:, None, None]
+    a = 0.5 * (g - g[neg_index(kmesh)].transpose(0, 2, 1))
+    sk = np.einsum("kR,Rij->kij", _phase_kR(kmesh), a)
+    return np.array([expm(x) for x in sk])
+
+
+def decouple_orbital(dm_k, mu) -> np.ndarray:
+    """A copy of the per-spin density matrices in which orbital mu of every cell
+    is fully occupied and has no coherence with any other orbital (a core-like
+    orbital): gamma(k)[mu, :] = gamma(k)[:, mu] = e_mu for every k.  Its column
+    of the impurity-environment block vanishes, so it couples to no bath."""
+    out = np.array(dm_k, copy=True)
+    out[..., mu, :] = 0.0
+    out[..., :, mu] = 0.0
+    out[..., mu, mu] = 1.0
+    return out
 
 
 def random_orthonormal(rng, n, m) -> np.ndarray:

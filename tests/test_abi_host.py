@@ -63,21 +63,21 @@ def test_bath_argument_validation(lib):
     fake = ctypes.c_void_p(0x1000)
     neo = (ctypes.c_int * 1)()
     # imp_idx == NULL needs nimp == nao
-    st = lib.dmet_build_bath(ctypes.byref(_lat()), fake, 5, None, 5, None, 0.0, None, fake, fake, neo, fake, 1 << 20,
+    st = lib.dmet_build_bath(ctypes.byref(_lat()), fake, 5, None, 5, None, 0.0, None, fake, fake, neo, None, fake, 1 << 20,
                              None)
     assert st == 1
     # negative tolerance
-    st = lib.dmet_build_bath(ctypes.byref(_lat()), fake, 8, None, 8, None, -1.0, None, fake, fake, neo, fake, 1 << 20,
+    st = lib.dmet_build_bath(ctypes.byref(_lat()), fake, 8, None, 8, None, -1.0, None, fake, fake, neo, None, fake, 1 << 20,
                              None)
     assert st == 1
     # out-of-range impurity index is caught on the host
     imp = (ctypes.c_int * 8)(*range(0, 7), 99)
-    st = lib.dmet_build_bath(ctypes.byref(_lat()), fake, 8, imp, 8, None, 0.0, None, fake, fake, neo, fake, 1 << 20,
+    st = lib.dmet_build_bath(ctypes.byref(_lat()), fake, 8, imp, 8, None, 0.0, None, fake, fake, neo, None, fake, 1 << 20,
                              None)
     assert st == 1 and b"imp_idx" in lib.dmet_last_error()
     # repeated impurity orbital
     imp = (ctypes.c_int * 8)(0, 1, 2, 3, 4, 5, 6, 6)
-    st = lib.dmet_build_bath(ctypes.byref(_lat()), fake, 8, imp, 8, None, 0.0, None, fake, fake, neo, fake, 1 << 20,
+    st = lib.dmet_build_bath(ctypes.byref(_lat()), fake, 8, imp, 8, None, 0.0, None, fake, fake, neo, None, fake, 1 << 20,
                              None)
     assert st == 1 and b"repeated" in lib.dmet_last_error()
 
@@ -131,3 +131,63 @@ def test_fftdf_argument_validation(lib):
     # null arrays are rejected before any launch
     assert lib.dmet_transform_eri_fftdf(ctypes.byref(lat), ctypes.byref(good), 16, None, 0, None, None, None,
                                         None, None, 0, None) == E_ARG
+
+
+def test_binding_rejects_mismatched_shapes():
+    """The ctypes binding checks every tensor's extent against kmesh, nao,
+    naux and neo before calling the library (a wrong shape would otherwise
+    make the kernels read or write past the tensor).  CPU tensors suffice:
+    the shape check comes before the device check."""
+    import torch
+
+    from paper_1909_08596_amd import dmet
+    if not os.path.exists(dmet.LIB_PATH):
+        pytest.skip("libdmet.so not built")
+    c128, f64 = torch.complex128, torch.float64
+    km = (2, 2, 1)
+    with pytest.raises(ValueError, match="dm_k must have shape"):
+        dmet.dmet_build_bath(km, 8, torch.zeros((1, 3, 8, 8), dtype=c128))
+    with pytest.raises(ValueError, match="c_ao_lo must have shape"):
+        dmet.dmet_build_bath(km, 8, torch.zeros((1, 4, 8, 8), dtype=c128), c_ao_lo=torch.zeros((4, 8, 7), dtype=c128))
+    with pytest.raises(ValueError, match="device tensor"):
+        dmet.dmet_build_bath(km, 8, torch.zeros((1, 4, 8, 8), dtype=c128))
+    with pytest.raises(ValueError, match="op_k must have shape"):
+        dmet.dmet_transform_1e(km, 8, torch.zeros((1, 4, 8, 16), dtype=c128), torch.zeros((1, 4, 8, 9), dtype=c128))
+    with pytest.raises(ValueError, match="c_k must have shape"):
+        dmet.dmet_transform_1e(km, 8, torch.zeros((1, 4, 9, 16), dtype=c128), torch.zeros((1, 4, 8, 8), dtype=c128))
+    with pytest.raises(ValueError, match="dm_eo must have shape"):
+        dmet.dmet_energy_1e(torch.zeros((1, 16, 16), dtype=f64), torch.zeros((1, 16, 15), dtype=f64))
+    ck = torch.zeros((1, 4, 8, 16), dtype=c128)
+    with pytest.raises(ValueError, match="lmunu must have shape"):
+        dmet.dmet_transform_eri(km, 8, 40, torch.zeros((4, 4, 39, 8, 8), dtype=c128), ck)
+    with pytest.raises(ValueError, match="lmunu must have shape"):
+        dmet.dmet_transform_eri_df(km, 8, 40, torch.zeros((4, 3, 40, 8, 8), dtype=c128), ck)
+    with pytest.raises(ValueError, match="c_k must have shape"):
+        dmet.dmet_transform_eri(km, 8, 40, torch.zeros((4, 4, 40, 8, 8), dtype=c128), torch.zeros((1, 4, 9, 16), dtype=c128))
+    with pytest.raises(ValueError, match="rho must have shape"):
+        dmet.dmet_transform_eri_fftdf(km, 8, (6, 6, 6), (3.0, 3.0, 3.0), torch.zeros((4, 4, 215, 8, 8), dtype=c128), ck)
+    with pytest.raises(ValueError, match="z must have shape"):
+        dmet.dmet_fock_dc(torch.zeros((1, 160, 135), dtype=f64), torch.zeros((1, 16, 16), dtype=f64),
+                          torch.zeros((1, 16, 16), dtype=f64))
+    with pytest.raises(ValueError, match="f_tilde must have shape"):
+        dmet.dmet_energy_mf(torch.zeros((2, 16, 16), dtype=f64), torch.zeros((1, 16, 16), dtype=f64),
+                            torch.zeros((1, 16, 16), dtype=f64))
+    frag = {"kmesh": km, "nao": 8, "naux": 40, "lmunu": torch.zeros((4, 4, 40, 8, 8), dtype=c128),
+            "c_k": torch.zeros((4, 8, 16), dtype=c128), "eri": torch.zeros(100, dtype=f64)}
+    with pytest.raises(ValueError, match="eri must hold"):
+        dmet.dmet_transform_eri_batched([frag])
+    frag["c_k"] = torch.zeros((4, 7, 16), dtype=c128)
+    with pytest.raises(ValueError, match="c_k must have shape"):
+        dmet.dmet_transform_eri_batched([frag])
+
+
+def test_binding_rejects_bad_output_blocks():
+    import torch
+
+    from paper_1909_08596_amd import dmet
+    with pytest.raises(ValueError, match="must hold"):
+        dmet._eri_outputs({"aa": torch.zeros(10, dtype=torch.float64)}, 1, 136)
+    with pytest.raises(ValueError, match="one spin"):
+        dmet._eri_outputs({"aa": torch.zeros(136 * 137 // 2), "bb": torch.zeros(136 * 137 // 2)}, 1, 136)
+    with pytest.raises(ValueError, match="'bb'"):
+        dmet._eri_outputs({"aa": torch.zeros(136 * 137 // 2, dtype=torch.float64)}, 2, 136)

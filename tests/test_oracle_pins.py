@@ -312,3 +312,130 @@ def test_impurity_columns_give_impurity_block():
     csup[np.arange(n), np.arange(n)] = 1.0
     ref = sc.eri(b_real, csup, wl.kmesh)
     assert np.abs(imp - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+# ------------------------------------------------ supercell impurity, gauge
+def _bath_vs_supercell(dm_k, kmesh, nao, imp, val):
+    """Oracle bath (translation-invariant blocks of gamma^{R,0}) against the
+    SVD of the explicit supercell projector gamma_sup = U blockdiag U^H for an
+    impurity anywhere in the supercell: singular values, the EO projector
+    C C^T, and the identity entries on the impurity rows."""
+    out = ok.build_bath(dm_k, kmesh, nao, imp_idx=imp, val_idx=val)
+    gsup, gim = sc.supercell_dm(dm_k[0], kmesh)
+    assert gim < 1e-12
+    c_sc, s_sc = sc.embedding_orbitals(gsup, np.asarray(imp), np.asarray(val))
+    assert np.abs(out["sigma"][0] - s_sc).max() < 1e-12
+    neo = out["neo"][0]
+    cr = out["c_r"][0].reshape(-1, neo)
+    assert neo == len(imp) + len(val)
+    assert np.abs(cr @ cr.T - c_sc @ c_sc.T).max() < 1e-11
+    assert np.abs(cr[np.asarray(imp), np.arange(len(imp))] - 1.0).max() < 1e-14
+    return out, cr, c_sc
+
+
+def test_supercell_impurity_bath_bn33():
+    """The paper's BN 3x3 impurity (9 cells, 8 valence LOs per cell) on the
+    6x6x1 mesh: the bath of the k-space oracle equals the supercell SVD, which
+    fixes every cell offset of gamma_sup[env, imp[val]] (cells != 0 included)."""
+    wl = synth.BN33
+    lat = synth.make_lattice(wl)
+    imp, val = synth.bn33_impurity()
+    _bath_vs_supercell(lat.dm_k, wl.kmesh, wl.nao, imp, val)
+
+
+@pytest.mark.parametrize("lattice,neo", [("b222", 150), ("b333", 57)])
+def test_supercell_impurity_bath_fragment(lattice, neo):
+    """A batched-form fragment: ceil(neo/2) LOs in supercell order (nearest
+    cells first, so it straddles cells), bath from the first SVD columns."""
+    base = synth.BATCH_LATTICES[lattice]
+    wl = dataclasses.replace(base, nao=12, naux=4) if lattice == "b333" else base
+    lat = synth.make_lattice(wl)
+    nimp = (neo + 1) // 2
+    imp = synth.supercell_order(wl.kmesh, wl.nao)[:nimp]
+    _bath_vs_supercell(lat.dm_k, wl.kmesh, wl.nao, imp, list(range(neo - nimp)))
+
+
+def test_planted_cell_offset_is_caught():
+    """gamma^{R'-R} in place of gamma^{R-R'} for the supercell block (a wrong
+    cell offset) breaks agreement with the supercell SVD for an impurity that
+    spans several cells."""
+    wl = synth.Workload("offs", (3, 2, 1), 6, 4, 6, 6, 1, 1.5, 31)
+    lat = synth.make_lattice(wl)
+    imp = synth.supercell_order(wl.kmesh, wl.nao)[:9]
+    dm_r, _ = ok.real_space_dm(lat.dm_k, wl.kmesh)
+    env = [r for r in range(wl.nk * wl.nao) if r not in set(imp)]
+    good = ok.supercell_block(dm_r[0], wl.kmesh, wl.nao, env, imp)
+    gsup, _ = sc.supercell_dm(lat.dm_k[0], wl.kmesh)
+    assert np.abs(good - gsup[np.ix_(env, imp)]).max() < 1e-13
+    pts = ok.mesh_points(wl.kmesh)
+    bad = np.empty_like(good)
+    for a, r in enumerate(env):
+        cr, mu = divmod(r, wl.nao)
+        for b, c in enumerate(imp):
+            cc, nu = divmod(c, wl.nao)
+            bad[a, b] = dm_r[0][ok.mesh_index(wl.kmesh, pts[cc] - pts[cr]), mu, nu]
+    assert np.abs(bad - gsup[np.ix_(env, imp)]).max() > 1e-3
+
+
+def test_ao_lo_composition():
+    """Eq. ``C loemb k``, second form: with a k-dependent unitary AO->LO map U(k)
+    (orthonormal AOs), C^{k,AO,EO} = U(k) C^{k,LO,EO}, so any operator given in
+    the AO basis, X_AO(k) = U X_LO U^H, transforms to the same embedding matrix
+    as X_LO; and the composed C^k keeps the time-reversal symmetry of U."""
+    wl = synth.Workload("aolo", (3, 2, 1), 6, 4, 6, 6, 1, 1.5, 57)
+    lat = synth.make_lattice(wl)
+    u = synth.random_lattice_unitary(wl.kmesh, wl.nao, 5)
+    assert np.abs(np.einsum("kmi,kmj->kij", u.conj(), u) - np.eye(wl.nao)).max() < 1e-13
+    lo = ok.build_bath(lat.dm_k, wl.kmesh, wl.nao)
+    ao = ok.build_bath(lat.dm_k, wl.kmesh, wl.nao, c_ao_lo=u)
+    assert np.abs(ao["c_r"] - lo["c_r"]).max() == 0.0
+    neg = synth.neg_index(wl.kmesh)
+    assert np.abs(ao["c_k"][0][neg] - ao["c_k"][0].conj()).max() < 1e-13
+    for x_lo in (lat.h_k, lat.f_k, lat.dm_k):
+        x_ao = u[None] @ x_lo @ u.conj().transpose(0, 2, 1)[None]
+        a, aim = ok.transform_1e(ao["c_k"], x_ao)
+        b, _ = ok.transform_1e(lo["c_k"], x_lo)
+        assert aim < 1e-13
+        assert np.abs(a - b).max() < 1e-13
+    # the composition is not the identity: the AO-basis C^k differs
+    assert np.abs(ao["c_k"] - lo["c_k"]).max() > 1e-2
+
+
+@pytest.mark.parametrize("name", ["tiny", "odd", "hbn"])
+def test_bath_sign_gauge(name, request):
+    """Every bath column of the oracle has its entry of largest modulus
+    positive (the gauge dmet_build_bath promises); columns come in descending
+    singular value."""
+    wl, lat, lm, b, bath = request.getfixturevalue(name)
+    cr = bath["c_r"][0].reshape(wl.nk * wl.nao, wl.neo)[:, wl.nimp:]
+    for j in range(cr.shape[1]):
+        i = int(np.argmax(np.abs(cr[:, j])))
+        assert cr[i, j] > 0
+    assert np.all(np.diff(bath["sigma"][0]) <= 0)
+
+
+def test_sign_fix_tie_rule():
+    """Ties within 1e-12 of the largest modulus: the lowest index decides."""
+    u = np.array([[-0.5, 0.6], [0.5, -0.6 * (1 - 1e-14)], [0.1, 0.1]])
+    v = ok.sign_fix(u)
+    assert v[0, 0] == 0.5 and v[1, 0] == -0.5       # flipped: index 0 was negative
+    assert v[0, 1] == 0.6                           # kept: index 0 positive
+
+
+def test_decoupled_orbital_has_no_bath():
+    """An impurity LO with no coherence to the environment (a core-like,
+    fully occupied orbital) gives a zero column of M and a zero singular
+    value; its bath vector is undetermined, so it is dropped even at
+    sv_tol = 0 (neo = nimp + nval - 1), and the rest of the bath is the
+    supercell SVD's."""
+    wl = synth.Workload("dec", (3, 2, 1), 6, 4, 6, 6, 1, 1.5, 63)
+    lat = synth.make_lattice(wl)
+    dm = synth.decouple_orbital(lat.dm_k, 2)
+    out = ok.build_bath(dm, wl.kmesh, wl.nao)
+    assert out["neo"][0] == 2 * wl.nao - 1
+    assert out["sigma"][0][-1] < 1e-15
+    gsup, _ = sc.supercell_dm(dm[0], wl.kmesh)
+    c_sc, s_sc = sc.embedding_orbitals(gsup, np.arange(wl.nao), nbath=wl.nao - 1)
+    assert np.abs(out["sigma"][0] - s_sc).max() < 1e-13
+    cr = out["c_r"][0].reshape(-1, out["neo"][0])
+    assert np.abs(cr @ cr.T - c_sc @ c_sc.T).max() < 1e-11
