@@ -161,6 +161,26 @@ dmet_status dmet_build_bath(const dmet_lattice* lat, const void* dm_k,
                             void* workspace, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * dmet_build_bath without a workspace, for callers that cannot allocate device
+ * memory (tight DMET self-consistency or serving loops, harnesses that forbid
+ * hipMalloc).  Arguments, results, synchronisation and status codes are those
+ * of dmet_build_bath, whose kernels it runs.  Its scratch is a device array of
+ * 32 MiB inside the library, one per GPU, held until the process ends; it
+ * covers every bath whose dmet_build_bath_workspace() is at most 32 MiB with
+ * c_ao_lo (e.g. nspin 2, 2x2x2 mesh, nao 150, nimp = nval = 150: 24.4 MiB).
+ * A larger problem returns DMET_E_WORKSPACE before anything is enqueued.
+ * The call allocates no device memory.  All calls on one GPU share that array:
+ * calls that overlap in time on the same GPU (two host threads, or two streams)
+ * race and must be serialised by the caller.  The stream's device must be the
+ * calling thread's current device.
+ * ------------------------------------------------------------------------- */
+dmet_status dmet_build_bath_noalloc(const dmet_lattice* lat, const void* dm_k,
+                                    int nimp, const int* imp_idx, int nval, const int* val_idx,
+                                    double sv_tol, const void* c_ao_lo,
+                                    void* c_k, double* sv, int* neo, double* max_imag,
+                                    hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * One-body transform (Eq. "fock transform", without the double-counting term):
  *   X^{0,EO} = 1/N_k sum_k C^{k dagger} X^k C^k          per spin.
  *

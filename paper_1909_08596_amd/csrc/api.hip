@@ -151,10 +151,9 @@ dmet_status dmet_build_bath_workspace(const dmet_lattice* lat, int nimp, int nva
     return DMET_OK;
 }
 
-dmet_status dmet_build_bath(const dmet_lattice* lat, const void* dm_k, int nimp, const int* imp_idx, int nval,
-                            const int* val_idx, double sv_tol, const void* c_ao_lo, void* c_k, double* sv,
-                            int* neo, double* max_imag, void* workspace, size_t ws_bytes, hipStream_t stream) {
-    g_last_error.clear();
+static dmet_status check_bath_args(const dmet_lattice* lat, const void* dm_k, int nimp, const int* imp_idx,
+                                   int nval, const int* val_idx, double sv_tol, const void* c_k, const double* sv,
+                                   const int* neo) {
     dmet_status s = check_lattice(lat);
     if (s != DMET_OK) return s;
     const int nsup = lat->kmesh[0] * lat->kmesh[1] * lat->kmesh[2] * lat->nao;
@@ -165,6 +164,28 @@ dmet_status dmet_build_bath(const dmet_lattice* lat, const void* dm_k, int nimp,
     if (!val_idx && nval != nimp) return fail(DMET_E_ARG, "val_idx == NULL requires nval == nimp");
     if (!(sv_tol >= 0.0)) return fail(DMET_E_ARG, "sv_tol must be >= 0");
     if (nval > 1024) return fail(DMET_E_UNSUPPORTED, "more than 1024 SVD columns");
+    return DMET_OK;
+}
+
+dmet_status dmet_build_bath_noalloc(const dmet_lattice* lat, const void* dm_k, int nimp, const int* imp_idx,
+                                    int nval, const int* val_idx, double sv_tol, const void* c_ao_lo, void* c_k,
+                                    double* sv, int* neo, double* max_imag, hipStream_t stream) {
+    g_last_error.clear();
+    dmet_status s = check_bath_args(lat, dm_k, nimp, imp_idx, nval, val_idx, sv_tol, c_k, sv, neo);
+    if (s != DMET_OK) return s;
+    return build_bath_noalloc(lat, static_cast<const double2*>(dm_k), nimp, imp_idx, nval, val_idx, sv_tol,
+                              static_cast<const double2*>(c_ao_lo), static_cast<double2*>(c_k), sv, neo, max_imag,
+                              stream);
+}
+
+dmet_status dmet_build_bath(const dmet_lattice* lat, const void* dm_k, int nimp, const int* imp_idx, int nval,
+                            const int* val_idx, double sv_tol, const void* c_ao_lo, void* c_k, double* sv,
+                            int* neo, double* max_imag, void* workspace, size_t ws_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    dmet_status s = check_lattice(lat);
+    if (s != DMET_OK) return s;
+    s = check_bath_args(lat, dm_k, nimp, imp_idx, nval, val_idx, sv_tol, c_k, sv, neo);
+    if (s != DMET_OK) return s;
     if (!workspace) return fail(DMET_E_WORKSPACE, "workspace is NULL");
     return build_bath(lat, static_cast<const double2*>(dm_k), nimp, imp_idx, nval, val_idx, sv_tol,
                       static_cast<const double2*>(c_ao_lo), static_cast<double2*>(c_k), sv, neo, max_imag,

@@ -8,9 +8,12 @@
 // stored column-major so that every column is one contiguous vector; pairs are
 // visited in round-robin order, so the n/2 rotations of a round touch
 // disjoint columns and run on separate wavefronts of one workgroup.
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "common.h"
+#include "eri.h"
 
 namespace dmet {
 
@@ -591,6 +594,57 @@ dmet_status build_bath(const dmet_lattice* lat, const double2* dm_k, int nimp, c
     }
     if (max_imag) *max_imag = scal[0];
     return DMET_OK;
+}
+
+// ---------------------------------------------------------------- no-allocation entry
+// Device scratch of build_bath_noalloc: a file-scope array, one copy per GPU,
+// held until the process ends.  In host code `scratch` names a host-side
+// stand-in, never the device array: its device address is looked up once per
+// device with hipGetSymbolAddress and only that address is handed to kernels.
+// Every call on a device shares the array and leaves the last call's contents
+// in it (build_bath clears the flags it accumulates into); calls that overlap
+// on one device race.
+static __device__ __align__(256) unsigned char scratch[BATH_SCRATCH_MAX];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+}  // namespace
+
+dmet_status build_bath_noalloc(const dmet_lattice* lat, const double2* dm_k, int nimp, const int* imp_idx,
+                               int nval, const int* val_idx, double sv_tol, const double2* c_ao_lo,
+                               double2* c_k, double* sv, int* neo, double* max_imag, hipStream_t st) {
+    BathPlan p;
+    p.mesh = make_mesh(lat->kmesh);
+    p.nao = lat->nao;
+    p.nspin = lat->nspin;
+    p.nimp = nimp;
+    p.nval = nval;
+    p.nsup = p.mesh.nk * p.nao;
+    p.nenv = p.nsup - nimp;
+    p.ldc = nimp + nval;
+    Carve cv(nullptr, 0);
+    carve_bath(cv, p, c_ao_lo != nullptr);
+    if (cv.bytes() > BATH_SCRATCH_MAX)
+        return fail(DMET_E_WORKSPACE, "dmet_build_bath_noalloc: this bath needs " + std::to_string(cv.bytes()) +
+                                          " bytes of scratch, more than the " + std::to_string(BATH_SCRATCH_MAX) +
+                                          " bytes it holds; call dmet_build_bath with a workspace");
+    int dev = 0;
+    DMET_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(DMET_E_UNSUPPORTED, "device ordinal above 63");
+    void* ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            void* a = nullptr;
+            DMET_HIP(hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)));
+            if (!a) return fail(DMET_E_HIP, "hipGetSymbolAddress returned a null scratch address");
+            g_scratch_ptr[dev] = a;
+        }
+        ptr = g_scratch_ptr[dev];
+    }
+    return build_bath(lat, dm_k, nimp, imp_idx, nval, val_idx, sv_tol, c_ao_lo, c_k, sv, neo, max_imag, ptr,
+                      BATH_SCRATCH_MAX, st);
 }
 
 }  // namespace dmet

@@ -112,6 +112,11 @@ dmet_status eri_batched(int nfrag, const dmet_fragment* frags, dmet_precision pr
 
 // bath / one-body (bath.hip, onebody.hip)
 size_t bath_workspace_bytes(const dmet_lattice* lat, int nimp, int nval);
+// size of the file-scope device scratch of build_bath_noalloc (one per GPU)
+constexpr size_t BATH_SCRATCH_MAX = (size_t)32 << 20;
+dmet_status build_bath_noalloc(const dmet_lattice* lat, const double2* dm_k, int nimp, const int* imp_idx,
+                               int nval, const int* val_idx, double sv_tol, const double2* c_ao_lo,
+                               double2* c_k, double* sv, int* neo, double* max_imag, hipStream_t st);
 dmet_status build_bath(const dmet_lattice* lat, const double2* dm_k, int nimp, const int* imp_idx,
                        int nval, const int* val_idx, double sv_tol, const double2* c_ao_lo,
                        double2* c_k, double* sv, int* neo, double* max_imag, void* ws, size_t ws_bytes,

@@ -25,6 +25,7 @@ STATUS = {0: "DMET_OK", 1: "DMET_E_ARG", 2: "DMET_E_HIP", 3: "DMET_E_NOCONV", 4:
 
 # every symbol include/dmet.h declares
 EXPORTS = ("dmet_last_error", "dmet_version", "dmet_build_bath_workspace", "dmet_build_bath",
+           "dmet_build_bath_noalloc",
            "dmet_transform_1e", "dmet_energy_1e", "dmet_transform_eri_workspace", "dmet_transform_eri",
            "dmet_transform_eri_batched_workspace", "dmet_transform_eri_batched",
            "dmet_transform_eri_df", "dmet_transform_eri_fftdf_workspace", "dmet_transform_eri_fftdf",
@@ -87,6 +88,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dmet_version.restype = i
     lib.dmet_build_bath_workspace.argtypes = [lp, i, i, ctypes.POINTER(sz)]
     lib.dmet_build_bath.argtypes = [lp, vp, i, vp, i, vp, d, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.dmet_build_bath_noalloc.argtypes = [lp, vp, i, vp, i, vp, d, vp, vp, vp, vp, vp, vp]
     lib.dmet_transform_1e.argtypes = [lp, i, vp, vp, vp, vp, vp]
     lib.dmet_energy_1e.argtypes = [i, i, vp, vp, vp, vp]
     lib.dmet_transform_eri_workspace.argtypes = [lp, i, i, i, ctypes.POINTER(sz)]
@@ -189,6 +191,42 @@ def dmet_build_bath(kmesh, nao, dm_k: torch.Tensor, imp_idx=None, val_idx=None, 
     if return_imag:
         return c_k, sv, [int(x) for x in neo], mi.value
     return c_k, sv, [int(x) for x in neo]
+
+
+def dmet_build_bath_noalloc(kmesh, nao, dm_k: torch.Tensor, imp_idx=None, val_idx=None, sv_tol: float = 0.0,
+                            c_ao_lo: Optional[torch.Tensor] = None, c_k: Optional[torch.Tensor] = None,
+                            sv: Optional[torch.Tensor] = None, stream=None):
+    """dmet_build_bath on the library's own per-GPU scratch (no workspace);
+    c_k and sv may be preallocated by the caller.  Returns (c_k, sv, neo list,
+    max |Im gamma^{R,0}|)."""
+    lib = load()
+    nk = _nk(kmesh)
+    if dm_k.dim() != 4 or dm_k.shape[0] not in (1, 2):
+        raise ValueError("dm_k must be [nspin][N_k][nao][nao] with nspin 1 or 2")
+    nspin = dm_k.shape[0]
+    _shape(dm_k, (nspin, nk, nao, nao), "dm_k")
+    nimp = nao if imp_idx is None else len(imp_idx)
+    nval = nimp if val_idx is None else len(val_idx)
+    if c_ao_lo is not None:
+        _shape(c_ao_lo, (nk, nao, nao), "c_ao_lo")
+        _dev(c_ao_lo, torch.complex128, "c_ao_lo")
+    if c_k is None:
+        c_k = torch.empty((nspin, nk, nao, nimp + nval), dtype=torch.complex128, device=dm_k.device)
+    if sv is None:
+        sv = torch.empty((nspin, nval), dtype=torch.float64, device=dm_k.device)
+    _shape(c_k, (nspin, nk, nao, nimp + nval), "c_k")
+    _shape(sv, (nspin, nval), "sv")
+    _dev(dm_k, torch.complex128, "dm_k")
+    _dev(c_k, torch.complex128, "c_k")
+    _dev(sv, torch.float64, "sv")
+    lat = lattice(kmesh, nao, 1, nspin)
+    imp_arr = None if imp_idx is None else (ctypes.c_int * nimp)(*[int(x) for x in imp_idx])
+    val_arr = None if val_idx is None else (ctypes.c_int * nval)(*[int(x) for x in val_idx])
+    neo = (ctypes.c_int * nspin)()
+    mi = ctypes.c_double(-1.0)
+    _check(lib.dmet_build_bath_noalloc(ctypes.byref(lat), _ptr(dm_k), nimp, imp_arr, nval, val_arr, float(sv_tol),
+                                       _ptr(c_ao_lo), _ptr(c_k), _ptr(sv), neo, ctypes.byref(mi), _stream(stream)))
+    return c_k, sv, [int(x) for x in neo], mi.value
 
 
 def dmet_transform_1e(kmesh, nao, c_k: torch.Tensor, op_k: torch.Tensor, want_imag: bool = True, stream=None):
