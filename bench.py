@@ -28,7 +28,14 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 METRIC = "embedding-ERI build s + TFLOP/s, split-BF16/FP32 vs FP64 at ≤1e-6 max err"
-PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}   # dense MFMA TFLOP/s (MI355X spec)
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0, "bf16x6_i8": 2500.0}   # dense MFMA TFLOP/s
+PEAK_I8 = 5000.0   # dense int8 MFMA TOP/s (MI355X spec): the peak of the int8 contraction kernels
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "bf16x6": "bf16x6", "bf16x6_i8": "bf16x6+int8x3"}
+
+
+def kernel_peak(prec, name):
+    """Dense MFMA peak of the dtype the named kernel multiplies in."""
+    return PEAK_I8 if name.endswith("_i8") else PEAK[prec]
 
 
 def work_counts(wl):
@@ -57,7 +64,7 @@ def kernel_flops(wl, name):
     return None
 
 
-MFMA_PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}   # executed products per algorithmic one
+MFMA_PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6, "bf16x6_i8": 6}   # executed per algorithmic product
 
 
 def traffic_bytes(kernel, workload):
@@ -95,29 +102,59 @@ def host_info():
     return model, mem
 
 
-def cpu_baseline(wl, lat, lm, n_l, n_rows, imp_idx=None, val_idx=None):
-    """Time the FP64 oracle on a bounded sample of the same workload:
-    Alg. 1's transform for q = 0 over the first n_l fitting functions, then
-    the contraction of that block for n_rows output pair rows."""
+def cpu_baseline(wl, lat, lm, n_l, n_rows, imp_idx=None, val_idx=None, w_flop=None):
+    """Time the FP64 oracle on a bounded sample of the same workload, phase by
+    phase, and extrapolate its time for the whole workload:
+
+    * bath (Eqs. bath R SVD, C loemb R/k) and the one-body transforms of h and
+      gamma: timed in full;
+    * transform (the embedded 3-index of Alg. 1): q = 0 for the first n_l
+      fitting functions over every k, scaled by N_k q-points, naux / n_l and
+      the spins;
+    * contraction: that block's contribution to n_rows output pair rows (the
+      oracle forms the full square over all neo^2 pairs in complex
+      arithmetic), scaled by neo^2 / n_rows, naux / n_l, N_k and the spin
+      blocks (aa, or aa, bb and ab).
+
+    ``value`` = W / t_oracle(extrapolated) on the same useful-work convention W
+    as the GPU's value; the sample's own executed rate is reported too."""
     from threadpoolctl import threadpool_info
     from oracle import kspace as ok
+    t0 = time.perf_counter()
     bath = ok.build_bath(lat.dm_k, wl.kmesh, wl.nao, imp_idx=imp_idx, val_idx=val_idx)
+    t1 = time.perf_counter()
+    ok.transform_1e(bath["c_k"], lat.h_k)
+    ok.transform_1e(bath["c_k"], lat.dm_k)
+    t2 = time.perf_counter()
     ck = bath["c_k"][0]
     sub = lm[:, :, :n_l]
-    t0 = time.perf_counter()
+    t3 = time.perf_counter()
     x = ok.alg1_embedded_3index(sub, ck, wl.kmesh, 0)
+    t4 = time.perf_counter()
     xm = x.reshape(n_l, -1)
     e = (xm[:, :n_rows].conj().T @ xm) / wl.nk
-    t1 = time.perf_counter()
-    n = wl.neo
-    flops = 8.0 * wl.nk * n_l * (wl.nao * wl.nao * n + wl.nao * n * n) + 8.0 * n_l * n_rows * n * n
-    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    t5 = time.perf_counter()
     del e
-    return {"value": flops / (t1 - t0) / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"oracle Alg. 1 transform of q=0 for {n_l} of {wl.naux} fitting functions over all "
-                      f"{wl.nk} k, plus the contraction of that block for {n_rows} of {n * n} pair rows "
-                      f"(spin alpha); {flops:.3e} flop in {t1 - t0:.2f} s",
-            "seconds": t1 - t0}
+    n = wl.neo
+    nblocks = 3 if wl.nspin == 2 else 1
+    t_tr = (t4 - t3) * wl.nk * (wl.naux / n_l) * wl.nspin
+    t_co = (t5 - t4) * (n * n / n_rows) * (wl.naux / n_l) * wl.nk * nblocks
+    t_all = (t1 - t0) + (t2 - t1) + t_tr + t_co
+    flops = 8.0 * wl.nk * n_l * (wl.nao * wl.nao * n + wl.nao * n * n) + 8.0 * n_l * n_rows * n * n
+    info = threadpool_info()
+    threads = max([p.get("num_threads", 1) for p in info] or [1])
+    blas = ", ".join(sorted({f"{p.get('internal_api')} {p.get('version')}" for p in info if p.get("user_api") == "blas"}))
+    out = {"unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"oracle (numpy FP64, {blas}, {threads} threads): bath and one-body timed in full; Alg. 1 "
+                     f"transform of q=0 for {n_l} of {wl.naux} fitting functions over all {wl.nk} k, and that "
+                     f"block's contraction for {n_rows} of {n * n} pair rows (spin alpha); whole-workload time "
+                     f"extrapolated from these ({t_all:.0f} s)",
+           "seconds": t5 - t0, "extrapolated_s": round(t_all, 1),
+           "phases_s": {"bath": round(t1 - t0, 3), "onebody": round(t2 - t1, 3),
+                        "transform_extrapolated": round(t_tr, 1), "contraction_extrapolated": round(t_co, 1)},
+           "sample_rate_TFLOPs": round(flops / ((t5 - t3)) / 1e12, 4), "blas": blas}
+    out["value"] = (w_flop / t_all / 1e12) if w_flop else out["sample_rate_TFLOPs"]
+    return out
 
 
 def run_batched(args, dev):
@@ -216,7 +253,7 @@ def run_batched(args, dev):
     line = {
         "metric": METRIC, "value": head["TFLOP/s"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": head["ms_batched"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": {"bf16x3": "bf16x3", "bf16x6": "bf16x6", "fp32": "f32"}[args.precision],
+        "vs_baseline": None, "dtype": DTYPE[args.precision],
         "data": "synthetic",
         "config": {"workload": f"batched: {len(frags)} fragments, neo {min(neos)}-{max(neos)} (mean "
                                f"{sum(neos) / len(neos):.0f}), k-meshes 2x2x2 / 3x3x3, nao 52, naux 400, "
@@ -308,7 +345,7 @@ def main():
     ap.add_argument("--config", default="nio",
                     help="synthetic workload (tiny, hbn, si, nio, bn33 = the paper's timed BN 3x3x1 shape, batched, "
                          "fft_si = plane-wave density fitting)")
-    ap.add_argument("--precision", default="bf16x6", choices=["fp64", "fp32", "bf16x3", "bf16x6"],
+    ap.add_argument("--precision", default="bf16x6", choices=["fp64", "fp32", "bf16x3", "bf16x6", "bf16x6_i8"],
                     help="form whose throughput is `value` (bf16x6: the fastest form within 1e-6 Ha)")
     ap.add_argument("--compare", default="fp64,fp32,bf16x3",
                     help="comma list of other precisions to time and compare against fp64 ('' for none)")
@@ -465,15 +502,17 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
         "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None if paper_s is None else round(paper_s / (ms * 1e-3), 1),
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "bf16x6": "bf16x6"}[args.precision],
+        "dtype": DTYPE[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{wl.name}: k-mesh {'x'.join(map(str, wl.kmesh))}, nao {wl.nao}, naux {wl.naux}, "
                                f"neo {wl.neo}, nspin {wl.nspin}, 3-index {'complex128' if lm.dtype == np.complex128 else 'complex64'}",
                    "precision": args.precision, "W_flop": wt + wc, "W_T": wt, "W_C": wc},
-        "roofline": {"bound": "mfma", "kernel": dname, "achieved": round(achieved, 3), "peak": PEAK[args.precision],
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK[args.precision], 4),
+        "roofline": {"bound": "mfma", "kernel": dname, "achieved": round(achieved, 3),
+                     "peak": kernel_peak(args.precision, dname),
+                     "unit": "TFLOP/s", "frac": round(achieved / kernel_peak(args.precision, dname), 4),
                      "traffic": traffic_bytes(dname, wl.name),
-                     "mfma_util": round(achieved * MFMA_PRODUCTS[args.precision] / PEAK[args.precision], 4),
+                     "mfma_util": round(achieved * MFMA_PRODUCTS[args.precision] / kernel_peak(args.precision, dname),
+                                        4),
                      "launch_ms": round(avg_ms, 4), "flop_per_launch": kf},
         "eri_build_ms": round(eri_ms, 3),
         "kernels_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in prof.items()},
@@ -498,7 +537,8 @@ def main():
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         n_l = args.cpu_sample_l or max(1, wl.naux // 2)
         line["cpu_baseline"] = cpu_baseline(wl, lat, lm, min(n_l, wl.naux),
-                                            min(args.cpu_sample_rows, wl.neo * wl.neo), imp_idx, val_idx)
+                                            min(args.cpu_sample_rows, wl.neo * wl.neo), imp_idx, val_idx,
+                                            w_flop=wt + wc)
         model, mem = host_info()
         line["cpu_baseline"]["host"] = {"model": model, "os_cpu_count": os.cpu_count(), "ram_gb": mem}
     print(json.dumps(line), flush=True)

@@ -82,10 +82,19 @@ typedef enum {
                                 stages multiply complex numbers with 4 real
                                 products (4M, not 3M: fewer operand bytes and no
                                 re+im cancellation); the contraction is real    */
-    DMET_BF16X6_3M = 3       /* three-way bf16 split hi + mid + lo and the six
+    DMET_BF16X6_3M = 3,      /* three-way bf16 split hi + mid + lo and the six
                                 products hh, hm, mh, hl, mm, lh, FP32 accumulate
                                 (about FP32 accuracy); 4M in both transform
                                 stages as DMET_BF16X3_3M (the name is kept)     */
+    DMET_BF16X6_I8 = 4       /* transform as DMET_BF16X6_3M; the contraction on
+                                int8 MFMA: every pair column of the real rows Z
+                                gets a power-of-two scale and three signed
+                                digits (fixed point, ~2^-23 of the column's
+                                largest entry), the six digit products of
+                                level <= 2 summed exactly in int32 and combined
+                                in FP64.  At most N_k*naux = 44032 rows
+                                (DMET_E_UNSUPPORTED above); the batched entry
+                                point runs it per fragment                     */
 } dmet_precision;
 
 typedef enum {

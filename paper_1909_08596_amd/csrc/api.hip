@@ -123,7 +123,8 @@ static dmet_status check_eri_args(const dmet_lattice* lat, int neo, dmet_precisi
     if (s != DMET_OK) return s;
     if (lat->naux < 1) return fail(DMET_E_ARG, "naux must be positive");
     if (neo < 1 || neo > 2048) return fail(DMET_E_ARG, "neo must be in [1, 2048]");
-    if (prec != DMET_FP64 && prec != DMET_FP32_3M && prec != DMET_BF16X3_3M && prec != DMET_BF16X6_3M)
+    if (prec != DMET_FP64 && prec != DMET_FP32_3M && prec != DMET_BF16X3_3M && prec != DMET_BF16X6_3M &&
+        prec != DMET_BF16X6_I8)
         return fail(DMET_E_ARG, "unknown precision");
     if (dtype != DMET_C128 && dtype != DMET_C64) return fail(DMET_E_ARG, "unknown dtype");
     const double zbytes = (double)lat->kmesh[0] * lat->kmesh[1] * lat->kmesh[2] * lat->naux *

@@ -567,6 +567,242 @@ template <int NS>
 constexpr size_t d2_lds() { return (size_t)3 * 2 * NS * 2 * 128 * 16; }
 
 
+// ------------------------------------------------------------------ int8 fixed-point contraction
+// DMET_BF16X6_I8: the contraction (ij|kl) = sum_r Z[r][ij] Z[r][kl] on the int8
+// matrix cores.  Each column x of Z (one EO pair) gets a power-of-two scale
+// 2^e_x >= max_r |Z[r][x]| and its entries y = Z / 2^e_x in [-1, 1] are written
+// exactly in three signed digits (a fixed-point split in the manner of the
+// Ozaki scheme):
+//   y = d0 / 127 + d1 / (127 * 254) + d2 / (127 * 254^2) + rho,
+//   |d_t| <= 127,  |rho| <= 1 / (2 * 127 * 254^2)  (about 2^-23),
+// d0 = rint(127 y) and d_{t+1} = rint(254 * residual): a residual of at most
+// one half times 254 stays within [-127, 127], so every digit fits int8 (with
+// base 256 a residual of +1/2 would need +128).  The products of digit pairs
+// are exact in int32, summed per level l = t + u in its own accumulator:
+//   L0 = d0.d0,  L1 = d0.d1 + d1.d0,  L2 = d0.d2 + d1.d1 + d2.d0,
+// and (ij|kl) = 2^(e_ij + e_kl) / 127^2 * (L0 + (L1 + L2 / 254) / 254) in FP64.
+// Level 3 and 4 products (below 2^-24 of the largest) are dropped.  The int32
+// sums are exact while 3 * K * 127^2 < 2^31, i.e. for K <= I8_KMAX rows.  The
+// operands move as the bf16 ones do: 16-byte chunks = 16 consecutive rows of
+// one column of one digit plane, one MFMA fragment of v_mfma_i32_32x32x32_i8.
+typedef int i4v __attribute__((ext_vector_type(4)));
+typedef int i16v __attribute__((ext_vector_type(16)));
+constexpr int I8_KMAX = 44032;
+constexpr int I8_EBAD = 1 << 20;   // exponent marking a column with a non-finite entry
+
+// cmax[x] = max_r |Z[r][x]| as float bits (non-negative floats order as
+// unsigned integers); a NaN or infinity raises it to at least 0x7f800000.
+__global__ void k_colmax(const float* __restrict__ z, size_t ldz, int krows, int ncol, int rows_per,
+                         unsigned* __restrict__ cmax) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= ncol) return;
+    const int r0 = blockIdx.y * rows_per, r1 = min(krows, r0 + rows_per);
+    unsigned m = 0u;
+    for (int r = r0; r < r1; ++r) {
+        const float v = z[(size_t)r * ldz + x];
+        const unsigned b = __float_as_uint(fabsf(v));
+        m = max(m, isfinite(v) ? b : 0x7fc00000u);
+    }
+    atomicMax(cmax + x, m);
+}
+
+// Digit planes P[t][g][x][16] (int8) of Z[16 g + v][x] / 2^e_x, and ex[x] = e_x
+// (I8_EBAD for a non-finite column).  Rows at or past krows are zero.
+__global__ void k_pack_i8(const float* __restrict__ z, size_t ldz, int krows, int ncol, int kg16,
+                          const unsigned* __restrict__ cmax, int* __restrict__ ex, i4v* __restrict__ out) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = blockIdx.y;
+    if (x >= ncol) return;
+    const unsigned cb = cmax[x];
+    int e = 0;
+    if (cb >= 0x7f800000u) e = I8_EBAD;
+    else if (cb != 0u) frexpf(__uint_as_float(cb), &e);   // cmax = m 2^e, m in [0.5, 1): cmax < 2^e
+    if (g == 0) ex[x] = e;
+    const double sc = e == I8_EBAD ? 0.0 : ldexp(127.0, -e);
+    union {
+        signed char c[16];
+        i4v v;
+    } d[3];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int k = 16 * g + v;
+        double r = k < krows ? (double)z[(size_t)k * ldz + x] * sc : 0.0;   // |r| < 127, exact
+        const double d0 = rint(r);
+        r = (r - d0) * 254.0;
+        const double d1 = rint(r);
+        r = (r - d1) * 254.0;
+        const double d2 = rint(r);
+        d[0].c[v] = (signed char)(int)d0;
+        d[1].c[v] = (signed char)(int)d1;
+        d[2].c[v] = (signed char)(int)d2;
+    }
+    const size_t plane = (size_t)kg16 * ncol;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) out[(size_t)t * plane + (size_t)g * ncol + x] = d[t].v;
+}
+
+// 128 x 256 output tiles, 8 waves as 2 x 4, wave tile 64 x 64 (2 x 2 blocks of
+// 32 x 32), a 2-deep ring of 64-row stages (4 chunk groups of 16 rows; 72 KB
+// per stage for three digit planes) moved by buffer loads straight into LDS,
+// as in k_contract_w8; per 32-row k-step 24 MFMAs into three int32
+// accumulator sets (levels 0, 1, 2).  No partial flush: the sums are exact.
+template <int MODE>
+__global__ void __launch_bounds__(512) k_contract_i8(int npair, int kgroups, const i4v* __restrict__ pa,
+                                                     const i4v* __restrict__ pb, const int* __restrict__ exa,
+                                                     const int* __restrict__ exb, long nblocks,
+                                                     double* __restrict__ out) {
+    constexpr int NS = 3, G = 4, NBUF = 2;
+    constexpr int BM = 128, BN = 256;
+    constexpr int TM = 2, TN = 2;
+    constexpr int PA = G * BM, PB = G * BN;      // 16-byte chunks of one plane of A / B per stage
+    constexpr int STAGE = NS * (PA + PB);
+    constexpr int CA = PA / 8, NLB = PB / 512;
+    constexpr int LOADS = NS * (1 + NLB);
+    extern __shared__ __align__(16) i4v ring_i8[];
+    int mt, nt;
+    const long logical = xcd_logical(blockIdx.x, nblocks);
+    const int ntm = (npair + BM - 1) / BM, ntn = (npair + BN - 1) / BN;
+    if (!w8_tile_of<MODE>(logical, ntm, ntn, mt, nt)) return;
+    const int m0 = mt * BM, n0 = nt * BN;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wm0 = (wave >> 2) * 64, wn0 = (wave & 3) * 64;
+    const size_t plane = (size_t)kgroups * npair;
+    const int nkt = kgroups / G;
+    const int fa = wave * CA;
+    const unsigned offa = (unsigned)min(m0 + fa % BM + (lane & (CA - 1)), npair - 1) * 16u;
+    unsigned offb[NLB];
+    const char* rowa[NS];
+    const char* rowb[NS][NLB];
+#pragma unroll
+    for (int h = 0; h < NLB; ++h) offb[h] = (unsigned)min(n0 + (h * 512 + wave * 64) % BN + lane, npair - 1) * 16u;
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        rowa[t] = (const char*)pa + (t * plane + (size_t)(fa / BM) * npair) * 16;
+#pragma unroll
+        for (int h = 0; h < NLB; ++h)
+            rowb[t][h] = (const char*)pb + (t * plane + (size_t)((h * 512 + wave * 64) / BN) * npair) * 16;
+    }
+    const size_t stage_bytes = (size_t)G * npair * 16;
+    auto issue = [&](int kt) {
+        i4v* st = ring_i8 + (size_t)(kt % NBUF) * STAGE;
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            if (CA == 64 || lane < CA)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    __builtin_amdgcn_make_buffer_rsrc((void*)rowa[t], (short)0, npair * 16, DMET_RSRC_WORD3),
+                    DMET_LDS_PTR(st + t * PA + fa), 16, (int)offa, 0, 0, 0);
+            rowa[t] += stage_bytes;
+#pragma unroll
+            for (int h = 0; h < NLB; ++h) {
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    __builtin_amdgcn_make_buffer_rsrc((void*)rowb[t][h], (short)0, npair * 16, DMET_RSRC_WORD3),
+                    DMET_LDS_PTR(st + NS * PA + t * PB + h * 512 + wave * 64), 16, (int)offb[h], 0, 0, 0);
+                rowb[t][h] += stage_bytes;
+            }
+        }
+    };
+
+    i16v acc0[TM][TN], acc1[TM][TN], acc2[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                acc0[i][j][r] = 0;
+                acc1[i][j][r] = 0;
+                acc2[i][j][r] = 0;
+            }
+    if (nkt > 0) issue(0);
+    auto stage = [&](int kt, auto younger_c) {
+        constexpr int YOUNGER = decltype(younger_c)::value;
+        constexpr int VM = YOUNGER * LOADS;
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(0x0F70 | (VM & 15) | ((VM >> 4) << 14));
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_sched_barrier(0);
+        if (kt + NBUF - 1 < nkt) issue(kt + NBUF - 1);
+        const i4v* sA = ring_i8 + (size_t)(kt % NBUF) * STAGE;
+        const i4v* sB = sA + NS * PA;
+        // two k-steps of 32 rows, software-pipelined as in k_contract_w8
+        const int g0 = lane >> 5, g1 = 2 + (lane >> 5);
+        auto rdA = [&](i4v (&r)[2], int t, int g) {
+            r[0] = sA[t * PA + g * BM + wm0 + (lane & 31)];
+            r[1] = sA[t * PA + g * BM + wm0 + 32 + (lane & 31)];
+        };
+        auto rdB = [&](i4v (&r)[2], int t, int g) {
+            r[0] = sB[t * PB + g * BN + wn0 + (lane & 31)];
+            r[1] = sB[t * PB + g * BN + wn0 + 32 + (lane & 31)];
+        };
+        auto mm = [&](i16v (&acc)[TM][TN], const i4v (&a)[2], const i4v (&b)[2]) {
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i][j], 0, 0, 0);
+        };
+        i4v a2[2], a1[2], a0[2], b0[2], b1[2], b2[2];
+        i4v c2[2], c1[2], c0[2], d0[2], d1[2], d2[2];
+        rdA(a2, 2, g0); rdB(b0, 0, g0);
+        DMET_SECTION(4, 0);
+        rdA(a1, 1, g0); rdB(b1, 1, g0);
+        DMET_SECTION(4, 0);
+        mm(acc2, a2, b0);
+        DMET_SECTION(0, 4);
+        rdA(a0, 0, g0); rdB(b2, 2, g0);
+        mm(acc2, a1, b1);
+        mm(acc1, a1, b0);
+        DMET_SECTION(4, 8);
+        rdA(c2, 2, g1);
+        mm(acc2, a0, b2);
+        DMET_SECTION(2, 4);
+        rdB(d0, 0, g1);
+        mm(acc1, a0, b1);
+        DMET_SECTION(2, 4);
+        rdA(c1, 1, g1);
+        mm(acc0, a0, b0);
+        DMET_SECTION(2, 4);
+        rdB(d1, 1, g1); rdA(c0, 0, g1);
+        DMET_SECTION(4, 0);
+        mm(acc2, c2, d0);
+        DMET_SECTION(0, 4);
+        rdB(d2, 2, g1);
+        mm(acc2, c1, d1);
+        mm(acc1, c1, d0);
+        DMET_SECTION(2, 8);
+        mm(acc2, c0, d2);
+        mm(acc1, c0, d1);
+        mm(acc0, c0, d0);
+        DMET_SECTION(0, 12);
+    };
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    int kt = 0;
+    for (; kt + NBUF - 2 < nkt; ++kt) stage(kt, std::integral_constant<int, NBUF - 2>{});
+    for (; kt < nkt; ++kt) stage(kt, std::integral_constant<int, 0>{});
+    constexpr double inv_b = 1.0 / 254.0, inv_b0sq = 1.0 / (127.0 * 127.0);
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+        const int KL = n0 + wn0 + j * 32 + (lane & 31);
+        const int eb = exb[min(KL, npair - 1)];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int IJ = m0 + wm0 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                if (IJ >= npair || KL >= npair) continue;
+                if (MODE == 0 && KL > IJ) continue;
+                const int ea = exa[IJ];
+                double v = (double)acc0[i][j][r] + ((double)acc1[i][j][r] + (double)acc2[i][j][r] * inv_b) * inv_b;
+                v = (ea == I8_EBAD || eb == I8_EBAD) ? __builtin_nan("") : ldexp(v * inv_b0sq, ea + eb);
+                if constexpr (MODE == 0) out[(size_t)IJ * (IJ + 1) / 2 + KL] = v;
+                else out[(size_t)IJ * npair + KL] = v;
+            }
+    }
+}
+
+constexpr size_t i8_lds() { return (size_t)2 * 3 * 4 * (128 + 256) * 16; }
+
 // ------------------------------------------------------------------ packed transform (bf16 forms)
 // Operand packing for the transform.  Every packed operand has the layout
 //   [plane][part][group][x][8]   (bf16; group = 8 consecutive contraction indices)
@@ -1485,6 +1721,10 @@ static size_t packed_elems(const EriPlan& p) {
     return (size_t)ns * kgroups_of(p.zrows) * 8 * p.npair;
 }
 
+// int8 digit planes: groups of 16 rows, a multiple of the 4 groups of a stage
+static int kgroups16_of(int krows) { return (krows + 63) / 64 * 4; }
+static size_t i8_chunks(const EriPlan& p) { return (size_t)3 * kgroups16_of(p.zrows) * p.npair; }
+
 // padded sizes of the packed transform operands
 struct PkDims {
     int ns, nao_p, ngv, ng2, M1, NB;
@@ -1494,7 +1734,7 @@ struct PkDims {
 
 static PkDims pk_dims(const EriPlan& p) {
     PkDims d;
-    d.ns = p.prec == DMET_BF16X6_3M ? 3 : 2;
+    d.ns = p.prec == DMET_BF16X3_3M ? 2 : 3;
     d.nao_p = (p.nao + 7) / 8 * 8;
     d.ngv = (d.nao_p / 8 + 1) / 2 * 2;
     // groups of (k, mu) plus at least one zero group (index nk * nao_p / 8), even
@@ -1518,7 +1758,13 @@ size_t eri_lp_workspace(const EriPlan& p) {
     cv.take<__bf16>(d.c2_elems);
     cv.take<__bf16>(d.t_elems);
     cv.take<float>((size_t)p.nspin * p.zrows * p.npair);              // Z per spin
-    cv.take<__bf16>((size_t)p.nspin * packed_elems(p));               // split parts of Z
+    if (p.prec == DMET_BF16X6_I8) {
+        cv.take<i4v>((size_t)p.nspin * i8_chunks(p));                 // int8 digit planes of Z
+        cv.take<unsigned>((size_t)p.nspin * p.npair);                 // column max
+        cv.take<int>((size_t)p.nspin * p.npair);                      // column exponents
+    } else {
+        cv.take<__bf16>((size_t)p.nspin * packed_elems(p));           // split parts of Z
+    }
     return cv.bytes();
 }
 
@@ -1672,9 +1918,62 @@ static dmet_status eri_lp_run(const EriPlan& p, const void* lmunu, const double*
     return DMET_OK;
 }
 
+// DMET_BF16X6_I8: the BF16X6 transform, then the int8 fixed-point contraction
+static dmet_status eri_i8_run(const EriPlan& p, const void* lmunu, const double* ck, double* eri_aa,
+                              double* eri_bb, double* eri_ab, float* z, i4v* zp, unsigned* cmax, int* ex, Carve& cv,
+                              hipStream_t st, double* df_out) {
+    const size_t ldz = (size_t)p.npair;
+    dmet_status xs = xform_packed<3>(p, lmunu, ck, z, cv, st);
+    if (xs != DMET_OK) return xs;
+    if (df_out) {
+        const size_t n = (size_t)p.nspin * p.zrows * p.npair;
+        k_f32_to_f64<<<1024, 256, 0, st>>>(z, df_out, n);
+        DMET_LAUNCH_CHECK("k_f32_to_f64");
+        return DMET_OK;
+    }
+    const int kg = kgroups16_of(p.zrows);
+    const size_t per_spin = (size_t)3 * kg * p.npair;
+    fill_zero(cmax, (size_t)p.nspin * p.npair * sizeof(unsigned), st);
+    const int rows_per = 256;
+    for (int s = 0; s < p.nspin; ++s) {
+        ProfScope ps("pack_i8", st);
+        const float* zs = z + (size_t)s * p.zrows * ldz;
+        k_colmax<<<dim3((p.npair + 255) / 256, (p.zrows + rows_per - 1) / rows_per), 256, 0, st>>>(
+            zs, ldz, p.zrows, p.npair, rows_per, cmax + (size_t)s * p.npair);
+        k_pack_i8<<<dim3((p.npair + 255) / 256, kg), 256, 0, st>>>(zs, ldz, p.zrows, p.npair, kg,
+                                                                     cmax + (size_t)s * p.npair,
+                                                                     ex + (size_t)s * p.npair, zp + s * per_spin);
+        ps.stop();
+        DMET_LAUNCH_CHECK("k_pack_i8");
+    }
+    constexpr size_t lds = i8_lds();
+    static_assert(lds <= 160 * 1024, "LDS per workgroup");
+    DMET_HIP(hipFuncSetAttribute((const void*)k_contract_i8<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    DMET_HIP(hipFuncSetAttribute((const void*)k_contract_i8<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    for (int s = 0; s < p.nspin; ++s) {
+        const long nb = w8_grid(0, p.npair);
+        ProfScope ps("contract_s8_i8", st);
+        k_contract_i8<0><<<dim3((unsigned)nb), 512, lds, st>>>(p.npair, kg, zp + s * per_spin, zp + s * per_spin,
+                                                               ex + (size_t)s * p.npair, ex + (size_t)s * p.npair, nb,
+                                                               s == 0 ? eri_aa : eri_bb);
+        ps.stop();
+        DMET_LAUNCH_CHECK("contract_s8_i8");
+    }
+    if (p.nspin == 2 && eri_ab) {
+        const long nb = w8_grid(1, p.npair);
+        ProfScope ps("contract_s4_i8", st);
+        k_contract_i8<1><<<dim3((unsigned)nb), 512, lds, st>>>(p.npair, kg, zp, zp + per_spin, ex, ex + p.npair, nb,
+                                                               eri_ab);
+        ps.stop();
+        DMET_LAUNCH_CHECK("contract_s4_i8");
+    }
+    return DMET_OK;
+}
+
 dmet_status eri_lp(const EriPlan& p, const void* lmunu, const double* ck, double* eri_aa, double* eri_bb,
                    double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st, double* df_out) {
-    if (p.prec != DMET_BF16X3_3M && p.prec != DMET_BF16X6_3M) return fail(DMET_E_ARG, "eri_lp: split-bf16 forms only");
+    if (p.prec != DMET_BF16X3_3M && p.prec != DMET_BF16X6_3M && p.prec != DMET_BF16X6_I8)
+        return fail(DMET_E_ARG, "eri_lp: split-bf16 forms only");
     if (eri_lp_workspace(p) > ws_bytes) return fail(DMET_E_WORKSPACE, "transform_eri workspace too small");
     // layout: [packed transform operands] [Z] [split parts of Z]
     Carve cv(ws, ws_bytes);
@@ -1685,6 +1984,15 @@ dmet_status eri_lp(const EriPlan& p, const void* lmunu, const double* ck, double
     cv.take<__bf16>(d.c2_elems);
     cv.take<__bf16>(d.t_elems);
     float* z = cv.take<float>((size_t)p.nspin * p.zrows * p.npair);
+    if (p.prec == DMET_BF16X6_I8) {
+        if (p.zrows > I8_KMAX && !df_out)
+            return fail(DMET_E_UNSUPPORTED, "the int8 contraction holds exact sums for at most 44032 rows "
+                                            "(N_k * naux); use DMET_BF16X6_3M");
+        i4v* zp8 = cv.take<i4v>((size_t)p.nspin * i8_chunks(p));
+        unsigned* cmax = cv.take<unsigned>((size_t)p.nspin * p.npair);
+        int* ex = cv.take<int>((size_t)p.nspin * p.npair);
+        return eri_i8_run(p, lmunu, ck, eri_aa, eri_bb, eri_ab, z, zp8, cmax, ex, pre, st, df_out);
+    }
     __bf16* zp = cv.take<__bf16>((size_t)p.nspin * packed_elems(p));
     if (p.prec == DMET_BF16X3_3M) return eri_lp_run<2>(p, lmunu, ck, eri_aa, eri_bb, eri_ab, z, zp, pre, st, df_out);
     return eri_lp_run<3>(p, lmunu, ck, eri_aa, eri_bb, eri_ab, z, zp, pre, st, df_out);
@@ -2101,13 +2409,14 @@ static dmet_status batch_upload(BatchPlan& bp, int variant, hipStream_t st) {
 }
 
 size_t batch_workspace(int nfrag, const dmet_fragment* frags, dmet_precision prec) {
-    if (prec == DMET_FP64 || prec == DMET_FP32_3M) {
+    if (prec == DMET_FP64 || prec == DMET_FP32_3M || prec == DMET_BF16X6_I8) {
         size_t mx = 256;
         for (int f = 0; f < nfrag; ++f) {
             dmet_lattice lat = frags[f].lat;
             lat.nspin = 1;
             EriPlan p = make_eri_plan(&lat, frags[f].neo, prec, frags[f].dtype);
-            mx = std::max(mx, prec == DMET_FP64 ? eri_f64_workspace(p) : eri_f32_workspace(p));
+            mx = std::max(mx, prec == DMET_FP64 ? eri_f64_workspace(p)
+                                                : (prec == DMET_FP32_3M ? eri_f32_workspace(p) : eri_lp_workspace(p)));
         }
         return mx;
     }
@@ -2155,16 +2464,19 @@ static void tune_store(const std::string& key, int v, float ms128, float ms64) {
 
 dmet_status eri_batched(int nfrag, const dmet_fragment* frags, dmet_precision prec, unsigned flags, void* ws,
                         size_t ws_bytes, hipStream_t st) {
-    if (prec == DMET_FP64 || prec == DMET_FP32_3M) {
+    if (prec == DMET_FP64 || prec == DMET_FP32_3M || prec == DMET_BF16X6_I8) {
         for (int f = 0; f < nfrag; ++f) {
             dmet_lattice lat = frags[f].lat;
             lat.nspin = 1;
             EriPlan p = make_eri_plan(&lat, frags[f].neo, prec, frags[f].dtype);
+            const double* ckf = static_cast<const double*>(frags[f].c_k);
             dmet_status s = prec == DMET_FP64
-                                ? eri_f64(p, frags[f].lmunu, static_cast<const double*>(frags[f].c_k), frags[f].eri,
-                                          nullptr, nullptr, ws, ws_bytes, st)
-                                : eri_f32(p, frags[f].lmunu, static_cast<const double*>(frags[f].c_k), frags[f].eri,
-                                          nullptr, nullptr, ws, ws_bytes, st);
+                                ? eri_f64(p, frags[f].lmunu, ckf, frags[f].eri, nullptr, nullptr, ws, ws_bytes, st)
+                                : (prec == DMET_FP32_3M
+                                       ? eri_f32(p, frags[f].lmunu, ckf, frags[f].eri, nullptr, nullptr, ws, ws_bytes,
+                                                 st)
+                                       : eri_lp(p, frags[f].lmunu, ckf, frags[f].eri, nullptr, nullptr, ws, ws_bytes,
+                                                st));
             if (s != DMET_OK) return s;
         }
         return DMET_OK;

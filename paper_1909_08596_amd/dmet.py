@@ -17,9 +17,10 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdmet.so")
 
-DMET_FP64, DMET_FP32_3M, DMET_BF16X3_3M, DMET_BF16X6_3M = 0, 1, 2, 3
+DMET_FP64, DMET_FP32_3M, DMET_BF16X3_3M, DMET_BF16X6_3M, DMET_BF16X6_I8 = 0, 1, 2, 3, 4
 DMET_C128, DMET_C64 = 0, 1
-PRECISIONS = {"fp64": DMET_FP64, "fp32": DMET_FP32_3M, "bf16x3": DMET_BF16X3_3M, "bf16x6": DMET_BF16X6_3M}
+PRECISIONS = {"fp64": DMET_FP64, "fp32": DMET_FP32_3M, "bf16x3": DMET_BF16X3_3M, "bf16x6": DMET_BF16X6_3M,
+              "bf16x6_i8": DMET_BF16X6_I8}
 STATUS = {0: "DMET_OK", 1: "DMET_E_ARG", 2: "DMET_E_HIP", 3: "DMET_E_NOCONV", 4: "DMET_E_RANK",
           5: "DMET_E_NONFINITE", 6: "DMET_E_WORKSPACE", 7: "DMET_E_UNSUPPORTED"}
 

@@ -191,3 +191,17 @@ def test_binding_rejects_bad_output_blocks():
         dmet._eri_outputs({"aa": torch.zeros(136 * 137 // 2), "bb": torch.zeros(136 * 137 // 2)}, 1, 136)
     with pytest.raises(ValueError, match="'bb'"):
         dmet._eri_outputs({"aa": torch.zeros(136 * 137 // 2, dtype=torch.float64)}, 2, 136)
+
+
+def test_int8_contraction_row_limit(lib):
+    """The int8 contraction keeps exact int32 sums for at most 44032 rows
+    (3 * K * 127^2 < 2^31); a larger N_k * naux is refused on the host."""
+    from paper_1909_08596_amd import dmet
+    fake = ctypes.c_void_p(0x1000)
+    lat = _lat(kmesh=(4, 4, 4), nao=4, naux=700)           # 44800 rows
+    st = lib.dmet_transform_eri(ctypes.byref(lat), 4, fake, 0, fake, dmet.DMET_BF16X6_I8, fake, None, None, fake,
+                                1 << 60, None)
+    assert st == 7 and b"44032" in lib.dmet_last_error()
+    nb = ctypes.c_size_t()
+    lat = _lat(kmesh=(4, 4, 4), nao=4, naux=688)           # 44032 rows: accepted
+    assert lib.dmet_transform_eri_workspace(ctypes.byref(lat), 4, dmet.DMET_BF16X6_I8, 0, ctypes.byref(nb)) == 0

@@ -18,7 +18,7 @@ from tests.gpu_common import to_dev
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": None, "fp32": 1e-6, "bf16x6": 1e-6, "bf16x3": 1e-5}
+TOL = {"fp64": None, "fp32": 1e-6, "bf16x6": 1e-6, "bf16x3": 1e-5, "bf16x6_i8": 1e-6}
 
 SHAPES = {
     # name: (kmesh, nao, naux, neo, nspin, seed)
@@ -48,7 +48,7 @@ def _inputs(name):
     return kmesh, nao, naux, neo, lm, c_k
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6", "bf16x3", "bf16x6_i8"])
 @pytest.mark.parametrize("name", list(SHAPES))
 def test_degenerate_shapes(dmet, name, prec):
     kmesh, nao, naux, neo, lm, c_k = _inputs(name)

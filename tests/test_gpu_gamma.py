@@ -59,7 +59,7 @@ def test_gamma_bath_is_the_impurity(dmet, inputs):
     assert abs(e1 - ok.energy_1e(rh, rg)) < 1e-10
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6", "bf16x6_i8"])
 def test_gamma_eri_is_molecular_df(dmet, inputs, prec):
     lat, lm, bl = inputs
     rng = np.random.default_rng(7)

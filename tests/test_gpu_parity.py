@@ -131,7 +131,7 @@ def test_end_to_end_gauge_free(dmet):
 LP_TOL = 1e-6
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x6"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x6", "bf16x6_i8"])
 @pytest.mark.parametrize("key", ["tiny", "odd", "hbn"])
 def test_eri_reduced_precision(dmet, key, prec):
     wl, lat, lm, bath = case(**CASES[key])
@@ -143,7 +143,7 @@ def test_eri_reduced_precision(dmet, key, prec):
     assert err < LP_TOL
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x6"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x6", "bf16x6_i8"])
 def test_eri_reduced_precision_uhf(dmet, prec):
     wl, lat, lm, bath = case("uodd", kmesh=(3, 2, 1), nao=6, naux=17, nspin=2, seed=19)
     ck = bath["c_k"]
@@ -194,7 +194,7 @@ def _small_batch():
     return frags
 
 
-@pytest.mark.parametrize("prec", ["bf16x6", "bf16x3", "fp32"])
+@pytest.mark.parametrize("prec", ["bf16x6", "bf16x3", "fp32", "bf16x6_i8"])
 def test_batched_matches_single_and_oracle(dmet, prec):
     frags = _small_batch()
     dev_lm = {}
@@ -321,7 +321,7 @@ def test_fock_dc_chunked_against_torch(dmet):
     assert err < 1e-11 * scale
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x6"])
+@pytest.mark.parametrize("prec", ["fp64", "bf16x6", "bf16x6_i8"])
 def test_non_interacting_bath_impurity_eri(dmet, prec):
     """Impurity-only ERIs (non-interacting bath, Sec. 2.1) equal the impurity
     block of the oracle's full embedding ERIs, for both spins and the ab block."""
