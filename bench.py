@@ -345,9 +345,9 @@ def main():
     ap.add_argument("--config", default="nio",
                     help="synthetic workload (tiny, hbn, si, nio, bn33 = the paper's timed BN 3x3x1 shape, batched, "
                          "fft_si = plane-wave density fitting)")
-    ap.add_argument("--precision", default="bf16x6", choices=["fp64", "fp32", "bf16x3", "bf16x6", "bf16x6_i8"],
-                    help="form whose throughput is `value` (bf16x6: the fastest form within 1e-6 Ha)")
-    ap.add_argument("--compare", default="fp64,fp32,bf16x3",
+    ap.add_argument("--precision", default="bf16x6_i8", choices=["fp64", "fp32", "bf16x3", "bf16x6", "bf16x6_i8"],
+                    help="form whose throughput is `value` (bf16x6_i8: the fastest form within 1e-6 Ha)")
+    ap.add_argument("--compare", default="fp64,fp32,bf16x6,bf16x3",
                     help="comma list of other precisions to time and compare against fp64 ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-l", type=int, default=0, help="fitting functions in the CPU sample (0: naux/2)")

@@ -243,17 +243,49 @@ def alg1_eri(lmunu, c_k_a, kmesh, c_k_b=None):
     With a second spin's C^k the mixed (alpha alpha|beta beta) block is
     returned.  Returns (real [n][n][n][n], max |Im|)."""
     nk = lmunu.shape[0]
-    eri = 0
+    n = c_k_a.shape[2]
+    m = n if c_k_b is None else c_k_b.shape[2]
+    eri = np.zeros((n * n, m * m), dtype=np.complex128)
     for q in range(nk):
         xa = alg1_embedded_3index(lmunu, c_k_a, kmesh, q)
         xb = xa if c_k_b is None else alg1_embedded_3index(lmunu, c_k_b, kmesh, q)
-        naux, n = xa.shape[0], xa.shape[1]
-        m = xb.shape[1]
-        eri = eri + (xa.reshape(naux, n * n).conj().T @ xb.reshape(naux, m * m)) / nk
-    n = c_k_a.shape[2]
-    m = n if c_k_b is None else c_k_b.shape[2]
+        naux = xa.shape[0]
+        eri += (xa.reshape(naux, n * n).conj().T @ xb.reshape(naux, m * m)) / nk
     eri = eri.reshape(n, n, m, m)
     return eri.real.copy(), float(np.abs(eri.imag).max())
+
+
+def alg1_embedded_all(lmunu, c_k, kmesh):
+    """X_L(q) of ``alg1_embedded_3index`` for every q (a list over q)."""
+    return [alg1_embedded_3index(lmunu, c_k, kmesh, q) for q in range(lmunu.shape[0])]
+
+
+def alg1_eri_block(xa, rows, cols, xb=None):
+    """Entries of the Alg. 1 contraction for listed output pairs only:
+    E[p, r] = (i_p j_p | k_r l_r) = 1/N_k sum_q sum_L conj(X_L(q)_{i_p j_p}) X_L(q)_{k_r l_r},
+    from the embedded 3-index tensors of every q (``alg1_embedded_all``; xb
+    those of the second spin for the mixed block).  Returns (real [len(rows)]
+    [len(cols)], max |Im|).  The same sum as ``alg1_eri``, restricted to the
+    requested entries so that it runs where the full tensor does not fit."""
+    xb = xa if xb is None else xb
+    nk = len(xa)
+    ra = (np.array([p[0] for p in rows]), np.array([p[1] for p in rows]))
+    cb = (np.array([p[0] for p in cols]), np.array([p[1] for p in cols]))
+    out = np.zeros((len(rows), len(cols)), dtype=np.complex128)
+    for q in range(nk):
+        out += xa[q][:, ra[0], ra[1]].conj().T @ xb[q][:, cb[0], cb[1]] / nk
+    return out.real.copy(), float(np.abs(out.imag).max(initial=0.0))
+
+
+def alg1_eri_diag(xa, pairs):
+    """The diagonal (ij|ij) of the Alg. 1 contraction for the listed pairs:
+    1/N_k sum_q sum_L |X_L(q)_ij|^2 (real by construction)."""
+    nk = len(xa)
+    i, j = np.array([p[0] for p in pairs]), np.array([p[1] for p in pairs])
+    out = np.zeros(len(pairs))
+    for q in range(nk):
+        out += (np.abs(xa[q][:, i, j]) ** 2).sum(axis=0) / nk
+    return out
 
 
 def alg1_eri_columns(lmunu, c_k_a, kmesh, pairs_a, c_k_b=None, pairs_b=None):

@@ -439,3 +439,28 @@ def test_decoupled_orbital_has_no_bath():
     assert np.abs(out["sigma"][0] - s_sc).max() < 1e-13
     cr = out["c_r"][0].reshape(-1, out["neo"][0])
     assert np.abs(cr @ cr.T - c_sc @ c_sc.T).max() < 1e-11
+
+
+def test_eri_block_and_diag_forms():
+    """The restricted forms of the contraction (listed rows / columns, the
+    diagonal) reproduce the corresponding entries of the full alg1_eri tensor,
+    for a same-spin and a mixed-spin block."""
+    wl = synth.Workload("blk", (3, 2, 1), 6, 16, 6, 6, 2, 1.5, 93)
+    lat = synth.make_lattice(wl)
+    lm = synth.three_index(wl)
+    bath = ok.build_bath(lat.dm_k, wl.kmesh, wl.nao)
+    ck = bath["c_k"]
+    xa = ok.alg1_embedded_all(lm, ck[0], wl.kmesh)
+    xb = ok.alg1_embedded_all(lm, ck[1], wl.kmesh)
+    tri = list(zip(*np.tril_indices(wl.neo)))
+    rng = np.random.default_rng(1)
+    rows = [tri[int(x)] for x in rng.choice(len(tri), 9, replace=False)]
+    for b, full_args in ((None, (lm, ck[0], wl.kmesh)), (xb, (lm, ck[0], wl.kmesh, ck[1]))):
+        full, _ = ok.alg1_eri(*full_args)
+        got, im = ok.alg1_eri_block(xa, rows, tri, b)
+        ref = np.array([[full[i, j, k, l] for (k, l) in tri] for (i, j) in rows])
+        assert im < 1e-12
+        assert np.abs(got - ref).max() < 1e-13 * np.abs(full).max()
+    full, _ = ok.alg1_eri(lm, ck[0], wl.kmesh)
+    d = ok.alg1_eri_diag(xa, tri)
+    assert np.abs(d - np.array([full[i, j, i, j] for (i, j) in tri])).max() < 1e-13 * np.abs(full).max()
