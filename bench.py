@@ -83,6 +83,58 @@ def traffic_bytes(kernel, workload):
     return e["fetch_bytes"] + e["write_bytes"]
 
 
+def coulomb_exchange_energies(out, g_eo, chunk=1 << 27):
+    """E_J = 1/2 sum (ij|kl) g_ji g_lk and E_K = 1/2 sum (ij|kl) g_jk g_li per
+    spin block, from the packed outputs of one form (device tensors; g_eo
+    [nspin][neo][neo] float64, symmetric).  The s8 block is summed over its
+    stored triangle with the multiplicity of each element's symmetry images;
+    the alpha-beta block (s4) has a Coulomb term only.  Measurement helper of
+    the benchmark, not part of the library."""
+    import torch
+    neo = g_eo.shape[-1]
+    npair = neo * (neo + 1) // 2
+    dev = g_eo.device
+    tri_i, tri_j = torch.tril_indices(neo, neo, device=dev)
+
+    def pair_weight(g):        # g~[IJ] = g_ij (2 - delta_ij): sum over (i,j) and (j,i)
+        return g[tri_i, tri_j] * torch.where(tri_i == tri_j, 1.0, 2.0).to(g.dtype)
+
+    def k_weight(ga, gb, i, j, k, l):
+        # sum over the index orders of the two pairs of gb_{bc} ga_{da}, each
+        # distinct ordering once
+        t = ga[l, i] * gb[j, k]
+        t = t + torch.where(i != j, ga[l, j] * gb[i, k], torch.zeros_like(t))
+        t = t + torch.where(k != l, ga[k, i] * gb[j, l], torch.zeros_like(t))
+        t = t + torch.where((i != j) & (k != l), ga[k, j] * gb[i, l], torch.zeros_like(t))
+        return t
+
+    res = {}
+    for key, e in out.items():
+        sa, sb = {"aa": (0, 0), "bb": (1, 1), "ab": (0, 1)}[key]
+        ga, gb = g_eo[sa], g_eo[sb]
+        wa, wb = pair_weight(ga), pair_weight(gb)
+        ej = torch.zeros((), dtype=torch.float64, device=dev)
+        ek = torch.zeros((), dtype=torch.float64, device=dev)
+        flat = e.reshape(-1)
+        for s0 in range(0, flat.numel(), chunk):
+            idx = torch.arange(s0, min(flat.numel(), s0 + chunk), device=dev, dtype=torch.int64)
+            v = flat[s0:s0 + idx.numel()]
+            if key == "ab":
+                IJ, KL = idx // npair, idx % npair
+                ej += (v * wa[IJ] * wb[KL]).sum()
+                continue
+            IJ = ((torch.sqrt(8.0 * idx.double() + 1.0) - 1.0) / 2.0).floor().long()
+            IJ = IJ - (IJ * (IJ + 1) // 2 > idx).long()
+            IJ = IJ + ((IJ + 1) * (IJ + 2) // 2 <= idx).long()
+            KL = idx - IJ * (IJ + 1) // 2
+            mult = torch.where(IJ == KL, 1.0, 2.0).double()
+            ej += (v * mult * wa[IJ] * wa[KL]).sum()
+            i, j, k, l = tri_i[IJ], tri_j[IJ], tri_i[KL], tri_j[KL]
+            ek += (v * mult * k_weight(ga, ga, i, j, k, l)).sum()
+        res[key] = {"E_J": 0.5 * float(ej)} if key == "ab" else {"E_J": 0.5 * float(ej), "E_K": 0.5 * float(ek)}
+    return res
+
+
 def host_info():
     model = ""
     try:
@@ -455,13 +507,25 @@ def main():
         return ms, wall, prof, out, eri_ms
 
     forms = [args.precision] + [p for p in args.compare.split(",") if p and p != args.precision]
-    results = {}
-    for prec in forms:
+    # FP64 first (when compared), so that each other form is checked against it
+    # as soon as it has run and only the FP64 output is kept
+    order = (["fp64"] if "fp64" in forms else []) + [p for p in forms if p != "fp64"]
+    results, checks = {}, {}
+    for prec in order:
         print(f"[bench] timing {prec}: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
         ms, wall, prof, out, eri_ms = run_form(prec, args.steps, args.warmup, keep=len(forms) > 1)
+        if out is not None:
+            chk = {"E": coulomb_exchange_energies(out, g_eo)}
+            if prec != "fp64" and "fp64" in results:
+                ref = results["fp64"][3]
+                chk["max_abs_err_vs_fp64"] = {k: float((out[k] - ref[k]).abs().max()) for k in out}
+            checks[prec] = chk
+            if prec != "fp64":
+                out = None
+                torch.cuda.empty_cache()
         results[prec] = (ms, wall, prof, out, eri_ms)
-        print(f"[bench] {prec}: {ms:.2f} ms/step ({eri_ms:.2f} ms ERI build); kernels {prof}", file=sys.stderr,
-              flush=True)
+        print(f"[bench] {prec}: {ms:.2f} ms/step ({eri_ms:.2f} ms ERI build); kernels {prof}; "
+              f"{checks.get(prec, {})}", file=sys.stderr, flush=True)
 
     # next rows: density-fitting output (contraction skipped) and the
     # double-counting-corrected Fock matrix from it, timed once each
@@ -521,15 +585,20 @@ def main():
         "h2d_s": round(t_h2d, 2), "h2d_GBps": round(lm.nbytes / 1e9 / t_h2d, 2),
     }
     if len(forms) > 1:
-        ref = results["fp64"][3] if "fp64" in results else None
         cmp = {}
+        e64 = checks.get("fp64", {}).get("E")
         for prec in forms:
             msp = results[prec][0]
             entry = {"ms_per_step": round(msp, 3), "eri_build_ms": round(results[prec][4], 3),
                      "TFLOP/s": round((wt + wc) / (msp * 1e-3) / 1e12, 3)}
-            if ref is not None and prec != "fp64":
-                out = results[prec][3]
-                entry["max_abs_err_vs_fp64"] = {k: float((out[k] - ref[k]).abs().max()) for k in out}
+            chk = checks.get(prec, {})
+            if "E" in chk:
+                entry["E_J_E_K"] = chk["E"]
+                if e64 is not None and prec != "fp64":
+                    entry["E_err_vs_fp64"] = {k: {n: abs(v - e64[k][n]) for n, v in d.items()}
+                                              for k, d in chk["E"].items()}
+            if "max_abs_err_vs_fp64" in chk:
+                entry["max_abs_err_vs_fp64"] = chk["max_abs_err_vs_fp64"]
                 entry["speedup_vs_fp64"] = round(results["fp64"][0] / msp, 3)
             cmp[prec] = entry
         line["forms"] = cmp

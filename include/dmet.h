@@ -46,9 +46,7 @@
  * entry point aborts or throws across the ABI.
  *
  * Tuning (environment, read at each call; results do not depend on them beyond
- * rounding order): DMET_CONTRACT=2 selects the split-bf16 contraction with two
- * 128 x 128 workgroups per CU instead of one 128 x 256 workgroup;
- * DMET_XF2_SMALL_NEO=n sets the largest fragment neo that the batched form
+ * rounding order): DMET_XF2_SMALL_NEO=n sets the largest fragment neo that the batched form
  * transforms with 32 x 32 stage-2 tiles (default 256); DMET_TUNE_CACHE names
  * the file of the batched autotuner's choices.
  */

@@ -148,128 +148,6 @@ __device__ inline void lds_dma16(const void* row, unsigned nbytes, unsigned off,
         DMET_LDS_PTR(dst), 16, (int)off, 0, 0, 0);
 }
 
-// Variant sized for two workgroups per CU: 16-deep stages (72 KB ring for the
-// three-way split), at most 256 registers per lane (B fragments of a stage are
-// held, A fragments are loaded one part at a time), so two independent
-// workgroups interleave their waits on each CU.
-template <int NS, int MODE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
-k_contract_d2(int npair, int kgroups, const __bf16* __restrict__ pa, const __bf16* __restrict__ pb, int flush_k,
-              long nblocks, double* __restrict__ out) {
-    constexpr int BM = 128, BN = 128, G = 2, NBUF = 3;
-    constexpr int TM = 2, TN = 2;
-    constexpr int PART = G * BM;
-    constexpr int STAGE = 2 * NS * PART;
-    constexpr int LOADS = 2 * NS * (PART / 256);
-    extern __shared__ __align__(16) bf8 ring[];
-    int mt, nt;
-    const long logical = xcd_logical(blockIdx.x, nblocks);
-    const int ntile = (npair + BM - 1) / BM;
-    if (!tile_of<MODE>(logical, ntile, mt, nt)) return;
-    const int m0 = mt * BM, n0 = nt * BN;
-    const bool diag = mt == nt;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
-    const size_t plane = (size_t)kgroups * npair;
-    const int nkt = kgroups / G;
-
-    auto issue = [&](int kt) {
-        bf8* st = ring + (size_t)(kt % NBUF) * STAGE;
-#pragma unroll
-        for (int t = 0; t < NS; ++t)
-#pragma unroll
-            for (int c = 0; c < PART / 256; ++c) {
-                const int first = wave * 64 + 256 * c;
-                const int g = first / BM, row0 = first % BM;
-                const size_t gg = (size_t)kt * G + g;
-                const int xa = min(m0 + row0 + lane, npair - 1), xb = min(n0 + row0 + lane, npair - 1);
-                __builtin_amdgcn_global_load_lds((const void*)(pa + (t * plane + gg * npair + xa) * 8),
-                                                 DMET_LDS_PTR(st + t * PART + first), 16, 0, 0);
-                __builtin_amdgcn_global_load_lds((const void*)(pb + (t * plane + gg * npair + xb) * 8),
-                                                 DMET_LDS_PTR(st + (NS + t) * PART + first), 16, 0, 0);
-            }
-    };
-
-    f16v acc[TM][TN];
-    double acc64[TM][TN][16];
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                acc[i][j][r] = 0.f;
-                acc64[i][j][r] = 0.0;
-            }
-#pragma unroll
-    for (int s2 = 0; s2 < NBUF - 1; ++s2)
-        if (s2 < nkt) issue(s2);
-    int since = 0;
-    const int g = lane >> 5;
-    for (int kt = 0; kt < nkt; ++kt) {
-        const int younger = min(NBUF - 2, nkt - 1 - kt);
-        if (younger >= 1) __builtin_amdgcn_s_waitcnt(0x0F70 | (LOADS & 15) | ((LOADS >> 4) << 14));
-        else __builtin_amdgcn_s_waitcnt(0x0F70);
-        __builtin_amdgcn_s_barrier();
-        __builtin_amdgcn_sched_barrier(0);
-        if (kt + NBUF - 1 < nkt) issue(kt + NBUF - 1);
-        const bf8* sA = ring + (size_t)(kt % NBUF) * STAGE;
-        const bf8* sB = sA + NS * PART;
-        bf8 b[NS][TN];
-#pragma unroll
-        for (int t = 0; t < NS; ++t)
-#pragma unroll
-            for (int j = 0; j < TN; ++j) b[t][j] = sB[t * PART + g * BN + wn0 + j * 32 + (lane & 31)];
-#pragma unroll
-        for (int i = 0; i < TM; ++i) {
-#pragma unroll
-            for (int ta = NS - 1; ta >= 0; --ta) {
-                const bf8 a = sA[ta * PART + g * BM + wm0 + i * 32 + (lane & 31)];
-                // products a_ta * b_tb with ta + tb <= NS - 1 (plus lo*lo on diagonal tiles for NS = 2)
-#pragma unroll
-                for (int tb = NS - 1 - ta; tb >= 0; --tb)
-#pragma unroll
-                    for (int j = 0; j < TN; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[tb][j], acc[i][j], 0, 0, 0);
-                if constexpr (NS == 2) {
-                    if (ta == 1 && diag)
-#pragma unroll
-                        for (int j = 0; j < TN; ++j)
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[1][j], acc[i][j], 0, 0, 0);
-                }
-            }
-        }
-        since += 8 * G;
-        if (since >= flush_k || kt + 1 == nkt) {
-#pragma unroll
-            for (int i = 0; i < TM; ++i)
-#pragma unroll
-                for (int j = 0; j < TN; ++j)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        acc64[i][j][r] += (double)acc[i][j][r];
-                        acc[i][j][r] = 0.f;
-                    }
-            since = 0;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int IJ = m0 + wm0 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const int KL = n0 + wn0 + j * 32 + (lane & 31);
-                if (IJ >= npair || KL >= npair) continue;
-                if constexpr (MODE == 0) {
-                    if (KL <= IJ) out[(size_t)IJ * (IJ + 1) / 2 + KL] = acc64[i][j][r];
-                } else {
-                    out[(size_t)IJ * npair + KL] = acc64[i][j][r];
-                }
-            }
-}
-
 // One scheduling section: nr LDS reads issued first, then nm MFMAs; nothing is
 // moved across its end
 #define DMET_SECTION(nr, nm)                                 \
@@ -309,12 +187,12 @@ inline long w8_grid(int mode, int npair) {
     return (n + NXCD - 1) / NXCD * NXCD;
 }
 
-// Variant with 128 x 256 output tiles: 8 waves as 2 x 4, wave tile 64 x 64
-// with FP64 flush registers as in k_contract_d2, one workgroup per CU and a
-// ring of G-group stages in LDS (three-way split: two 72 KB stages of 32 rows;
-// two-way: three 48 KB stages).  Against two 128 x 128 workgroups per CU it
-// moves 25% fewer operand bytes per flop, and the two column halves that share
-// the A panel run in step by construction.  Operands are staged with buffer
+// 128 x 256 output tiles: 8 waves as 2 x 4, wave tile 64 x 64 (FP32 MFMA
+// partials flushed into FP64 registers every flush_k rows), one workgroup per
+// CU and a ring of G-group stages in LDS (three-way split: two 72 KB stages of
+// 32 rows; two-way: three 48 KB stages).  Against two 128 x 128 workgroups per
+// CU it moves 25% fewer operand bytes per flop, and the two column halves that
+// share the A panel run in step by construction.  Operands are staged with buffer
 // loads straight into LDS: each buffer resource spans one row group of one
 // part, so the hardware range check bounds every load, and (unlike the FLAT
 // form) the compiler keeps exact lgkmcnt waits for the LDS reads behind them.
@@ -563,8 +441,6 @@ __global__ void __launch_bounds__(512) k_contract_w8(int npair, int kgroups, con
 template <int NS, int G, int NBUF>
 constexpr size_t w8_lds() { return (size_t)NBUF * NS * G * (128 + 256) * 16; }
 
-template <int NS>
-constexpr size_t d2_lds() { return (size_t)3 * 2 * NS * 2 * 128 * 16; }
 
 
 // ------------------------------------------------------------------ int8 fixed-point contraction
@@ -1705,13 +1581,6 @@ template <int NS>
 constexpr size_t xf2_lds() { return (size_t)2 * P2 * NS * 2 * (64 + 64) * 16; }
 
 // ------------------------------------------------------------------ driver
-// contraction kernel: k_contract_w8 (128 x 256 tiles, one workgroup per CU);
-// DMET_CONTRACT=2 selects k_contract_d2 (128 x 128, two workgroups per CU)
-static int contract_variant() {
-    const char* e = getenv("DMET_CONTRACT");
-    return e && e[0] == '2' ? 2 : 3;
-}
-
 constexpr int FLUSH_K = 256;
 
 static int kgroups_of(int krows) { return (krows + 31) / 32 * 4; }
@@ -1867,51 +1736,26 @@ static dmet_status eri_lp_run(const EriPlan& p, const void* lmunu, const double*
         ps.stop();
         DMET_LAUNCH_CHECK("k_pack_parts");
     }
-    const int variant = contract_variant();
-    if (variant == 3) {
-        // 32-row stages; three-way split: 2-deep ring, two-way: 3-deep
-        constexpr int G = 4, NB = NS == 3 ? 2 : 3;
-        auto kw0 = k_contract_w8<NS, 0, G, NB>;
-        auto kw1 = k_contract_w8<NS, 1, G, NB>;
-        constexpr size_t lds = w8_lds<NS, G, NB>();
-        static_assert(lds <= 160 * 1024, "LDS per workgroup");
-        DMET_HIP(hipFuncSetAttribute((const void*)kw0, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        DMET_HIP(hipFuncSetAttribute((const void*)kw1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        for (int s = 0; s < p.nspin; ++s) {
-            const long nb = w8_grid(0, p.npair);
-            ProfScope ps(n3, st);
-            kw0<<<dim3((unsigned)nb), 512, lds, st>>>(p.npair, kg, zp + s * per_spin, zp + s * per_spin, FLUSH_K, nb,
-                                                      s == 0 ? eri_aa : eri_bb);
-            ps.stop();
-            DMET_LAUNCH_CHECK(n3);
-        }
-        if (p.nspin == 2 && eri_ab) {
-            const long nb = w8_grid(1, p.npair);
-            ProfScope ps(n4, st);
-            kw1<<<dim3((unsigned)nb), 512, lds, st>>>(p.npair, kg, zp, zp + per_spin, FLUSH_K, nb, eri_ab);
-            ps.stop();
-            DMET_LAUNCH_CHECK(n4);
-        }
-        return DMET_OK;
-    }
-    const int ntile = (p.npair + 127) / 128;
-    auto kd0 = k_contract_d2<NS, 0>;
-    auto kd1 = k_contract_d2<NS, 1>;
-    const size_t lds = d2_lds<NS>();
-    DMET_HIP(hipFuncSetAttribute((const void*)kd0, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    DMET_HIP(hipFuncSetAttribute((const void*)kd1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    // 32-row stages; three-way split: 2-deep ring, two-way: 3-deep
+    constexpr int G = 4, NB = NS == 3 ? 2 : 3;
+    auto kw0 = k_contract_w8<NS, 0, G, NB>;
+    auto kw1 = k_contract_w8<NS, 1, G, NB>;
+    constexpr size_t lds = w8_lds<NS, G, NB>();
+    static_assert(lds <= 160 * 1024, "LDS per workgroup");
+    DMET_HIP(hipFuncSetAttribute((const void*)kw0, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    DMET_HIP(hipFuncSetAttribute((const void*)kw1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     for (int s = 0; s < p.nspin; ++s) {
-        const long nb = tile_grid<0>(ntile);
+        const long nb = w8_grid(0, p.npair);
         ProfScope ps(n3, st);
-        kd0<<<dim3((unsigned)nb), 256, lds, st>>>(p.npair, kg, zp + s * per_spin, zp + s * per_spin, FLUSH_K, nb,
+        kw0<<<dim3((unsigned)nb), 512, lds, st>>>(p.npair, kg, zp + s * per_spin, zp + s * per_spin, FLUSH_K, nb,
                                                   s == 0 ? eri_aa : eri_bb);
         ps.stop();
         DMET_LAUNCH_CHECK(n3);
     }
     if (p.nspin == 2 && eri_ab) {
-        const long nb = tile_grid<1>(ntile);
+        const long nb = w8_grid(1, p.npair);
         ProfScope ps(n4, st);
-        kd1<<<dim3((unsigned)nb), 256, lds, st>>>(p.npair, kg, zp, zp + per_spin, FLUSH_K, nb, eri_ab);
+        kw1<<<dim3((unsigned)nb), 512, lds, st>>>(p.npair, kg, zp, zp + per_spin, FLUSH_K, nb, eri_ab);
         ps.stop();
         DMET_LAUNCH_CHECK(n4);
     }
@@ -2072,6 +1916,9 @@ static std::string batch_key(int nfrag, const dmet_fragment* f, int prec, bool w
         snprintf(buf, sizeof(buf), "#%p,%zu", ws, wsb);
         k += buf;
     }
+    // the stage-2 tile choice is part of a plan
+    snprintf(buf, sizeof(buf), "~%d", xf2_small_neo());
+    k += buf;
     return k;
 }
 

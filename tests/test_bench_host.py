@@ -62,3 +62,31 @@ def test_kernel_flops_sum_to_the_work():
     # stage 2 over the full ij square (twice the i >= j count less the diagonal share), every q and spin
     full2 = 2 * x2 * wl.neo / (wl.neo + 1)
     assert abs(wl.nk * x1 + wl.nspin * wl.nk * full2 - wt) <= 1e-12 * wt
+
+
+def test_coulomb_exchange_energies_match_einsum():
+    """The benchmark's E_J / E_K from packed s8 / s4 blocks equal the plain
+    einsum definitions on the unpacked oracle tensors (UHF, 3x2x1 mesh)."""
+    import numpy as np
+    import torch
+
+    import bench
+    import synth
+    from oracle import kspace as ok
+    wl = synth.Workload("ej", (3, 2, 1), 5, 12, 5, 5, 2, 1.5, 17)
+    lat = synth.make_lattice(wl)
+    lm = synth.three_index(wl)
+    bath = ok.build_bath(lat.dm_k, wl.kmesh, wl.nao)
+    ck = bath["c_k"]
+    g, _ = ok.transform_1e(ck, lat.dm_k)
+    full = {"aa": ok.alg1_eri(lm, ck[0], wl.kmesh)[0], "bb": ok.alg1_eri(lm, ck[1], wl.kmesh)[0],
+            "ab": ok.alg1_eri(lm, ck[0], wl.kmesh, ck[1])[0]}
+    packed = {"aa": torch.from_numpy(ok.pack_s8(full["aa"])), "bb": torch.from_numpy(ok.pack_s8(full["bb"])),
+              "ab": torch.from_numpy(ok.pack_s4(full["ab"]))}
+    got = bench.coulomb_exchange_energies(packed, torch.from_numpy(g), chunk=37)
+    for key, (sa, sb) in {"aa": (0, 0), "bb": (1, 1), "ab": (0, 1)}.items():
+        ej = 0.5 * np.einsum("ijkl,ji,lk->", full[key], g[sa], g[sb])
+        assert abs(got[key]["E_J"] - ej) < 1e-12 * max(1.0, abs(ej))
+        if key != "ab":
+            ek = 0.5 * np.einsum("ijkl,jk,li->", full[key], g[sa], g[sa])
+            assert abs(got[key]["E_K"] - ek) < 1e-12 * max(1.0, abs(ek))

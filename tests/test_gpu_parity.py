@@ -386,3 +386,27 @@ def test_paired_transform_reads_half_the_input(dmet, key, prec):
     bat = dmet.dmet_transform_eri_batched(spec, prec)[0]
     torch.cuda.synchronize()
     assert torch.equal(ref, bat)
+
+
+@pytest.mark.parametrize("prec", ["bf16x6", "bf16x3"])
+def test_batched_64x64_stage2_tiles(dmet, prec, monkeypatch):
+    """DMET_XF2_SMALL_NEO=0 sends every fragment through the 64 x 64 one-L
+    stage-2 tiles (k_xf2_batched, the path of fragments above 256 orbitals):
+    same bits as the single-fragment call and within the bound of the oracle."""
+    monkeypatch.setenv("DMET_XF2_SMALL_NEO", "0")
+    frags = _small_batch()
+    dev_lm = {}
+    specs = []
+    for wl, lm, ck in frags:
+        if id(lm) not in dev_lm:
+            dev_lm[id(lm)] = to_dev(lm.astype(np.complex64))
+        specs.append({"kmesh": wl.kmesh, "nao": wl.nao, "naux": wl.naux, "lmunu": dev_lm[id(lm)],
+                      "c_k": to_dev(np.ascontiguousarray(ck))})
+    outs = [o.clone() for o in dmet.dmet_transform_eri_batched(specs, prec)]
+    torch.cuda.synchronize()
+    for (wl, lm, ck), spec, got in zip(frags, specs, outs):
+        single = dmet.dmet_transform_eri(wl.kmesh, wl.nao, wl.naux, spec["lmunu"], spec["c_k"][None], prec)["aa"]
+        assert torch.equal(single, got)
+        ref, _ = ok.alg1_eri(lm.astype(np.complex64).astype(np.complex128), ck, wl.kmesh)
+        err = np.abs(got.cpu().numpy() - ok.pack_s8(ref)).max()
+        assert err < (1e-5 if prec == "bf16x3" else LP_TOL), err
