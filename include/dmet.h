@@ -227,7 +227,9 @@ dmet_status dmet_energy_1e(int nspin, int neo, const double* h_eo, const double*
  * eri_ab   out s4 [npair][npair] float64 (alpha-beta) -- optional when
  *          nspin == 2, must be NULL when nspin == 1.
  * workspace/ws_bytes: device scratch, at least dmet_transform_eri_workspace().
- * Asynchronous.
+ * Asynchronous.  The device inputs are not checked for NaN or infinity (that
+ * would need a synchronisation); a non-finite entry that the transform reads
+ * makes the ERIs it reaches NaN in every form (never finite values).
  * ------------------------------------------------------------------------- */
 dmet_status dmet_transform_eri_workspace(const dmet_lattice* lat, int neo,
                                          dmet_precision prec, dmet_dtype dtype,

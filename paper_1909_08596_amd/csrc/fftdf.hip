@@ -7,7 +7,8 @@
 // rows are Fourier transformed over the grid with the phase of q,
 //   W(G) = sum_r exp(+i (q+G).r) X(r),
 // one axis at a time (a separable 3-D DFT; each output sums the n_d points of
-// its line with a twiddle table held in LDS), and scaled by
+// its line, the phases read from a table of the L = N_d n_d roots of unity of
+// the supercell axis held in LDS), and scaled by
 // dV sqrt(4 pi / (Omega |q+G|^2)) into two real rows (Re W, Im W) per G.  The
 // FP64 contraction of those rows gives the ERIs.
 #include <math.h>
@@ -22,7 +23,7 @@
 namespace dmet {
 namespace {
 
-constexpr int PW_MAXN = 64;      // grid points per axis (twiddle table nd^2 in LDS)
+constexpr int PW_MAXL = 8192;    // N_d n_d roots of unity per supercell axis (128 KB of LDS)
 
 struct PwAxis {
     int n[3];          // grid
@@ -57,15 +58,13 @@ __global__ void __launch_bounds__(256) k_pw_axis(PwAxis ax, int npair, const dou
                                                  const double* __restrict__ zin, size_t zrow0, size_t ldz,
                                                  double2* __restrict__ cout, double* __restrict__ zout, size_t zg0,
                                                  PwScale ks) {
-    extern __shared__ double2 tw[];   // [g][t], nd^2 entries
+    extern __shared__ double2 tw[];   // tw[j] = exp(2 pi i j / L), L = N_d n_d entries
     const int nd = ax.n[ax.axis];
-    const long L = (long)ax.nmesh * nd;
-    for (int e = threadIdx.x; e < nd * nd; e += blockDim.x) {
-        const int g = e / nd, t = e % nd;
-        const long num = (((long)ax.nmesh * g + ax.m) * t) % L;   // exact reduction of (q+G).r
+    const int L = ax.nmesh * nd;
+    for (int j = threadIdx.x; j < L; j += blockDim.x) {
         double s, c;
-        sincospi(2.0 * (double)num / (double)L, &s, &c);
-        tw[e] = make_double2(c, s);
+        sincospi(2.0 * (double)j / (double)L, &s, &c);
+        tw[j] = make_double2(c, s);
     }
     __syncthreads();
     const long n12 = (long)ax.n[1] * ax.n[2];
@@ -78,9 +77,14 @@ __global__ void __launch_bounds__(256) k_pw_axis(PwAxis ax, int npair, const dou
         int x[3] = {(int)(r / n12), (int)((r / ax.n[2]) % ax.n[1]), (int)(r % ax.n[2])};
         const int g = x[ax.axis];
         const long base = r - (long)g * stride;
-        const double2* w = tw + g * nd;
+        // the phase of point t is (N g + m) t mod L, advanced exactly in integers
+        const int step = (ax.nmesh * g + ax.m) % L;
+        int ph = 0;
         double re = 0.0, im = 0.0;
         for (int t = 0; t < nd; ++t) {
+            const double2 w = tw[ph];
+            ph += step;
+            ph -= ph >= L ? L : 0;
             const long rt = base + (long)t * stride;
             double vr, vi;
             if (IN == 0) {
@@ -94,8 +98,8 @@ __global__ void __launch_bounds__(256) k_pw_axis(PwAxis ax, int npair, const dou
                 vr = zin[(zrow0 + 2 * rt) * ldz + p];
                 vi = zin[(zrow0 + 2 * rt + 1) * ldz + p];
             }
-            re += w[t].x * vr - w[t].y * vi;
-            im += w[t].x * vi + w[t].y * vr;
+            re += w.x * vr - w.y * vi;
+            im += w.x * vi + w.y * vr;
         }
         if (OUT == 0) {
             cout[r * npair + p] = make_double2(re, im);
@@ -152,7 +156,8 @@ dmet_status fftdf_eri(const EriPlan& p, const dmet_pw_grid* grid, const void* rh
     double* part = cv.take<double>(d.part);
     if (cv.bytes() > ws_bytes) return fail(DMET_E_WORKSPACE, "fftdf workspace too small");
     for (int a = 0; a < 3; ++a)
-        if (grid->n[a] > PW_MAXN) return fail(DMET_E_UNSUPPORTED, "fftdf: at most 64 grid points per axis");
+        if ((long)grid->n[a] * p.mesh.n[a] > PW_MAXL)
+            return fail(DMET_E_UNSUPPORTED, "fftdf: at most 8192 supercell grid points per axis (N_d n_d)");
     // embedded pair densities on the grid, real rows per q block (Alg. 1 transform)
     dmet_status s = eri_f64(p, rho, ck, nullptr, nullptr, nullptr, ews, d.eri_ws, st, zr);
     if (s != DMET_OK) return s;
@@ -164,6 +169,13 @@ dmet_status fftdf_eri(const EriPlan& p, const dmet_pw_grid* grid, const void* rh
     }
     ks.omega = grid->cell[0] * grid->cell[1] * grid->cell[2];
     ks.dv = ks.omega / (double)d.nr;
+    {   // root tables above 64 KB of LDS need the larger dynamic allocation
+        int lmax = 0;
+        for (int a = 0; a < 3; ++a) lmax = std::max(lmax, grid->n[a] * p.mesh.n[a] * (int)sizeof(double2));
+        const void* ks4[4] = {(const void*)k_pw_axis<1, 0>, (const void*)k_pw_axis<2, 0>, (const void*)k_pw_axis<0, 0>,
+                              (const void*)k_pw_axis<0, 1>};
+        for (const void* kf : ks4) DMET_HIP(hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, lmax));
+    }
     const long total = (long)d.nr * p.npair;
     const unsigned nb = (unsigned)std::min<long>((total + 255) / 256, 65535L * 4);
     for (int sp = 0; sp < p.nspin; ++sp) {
@@ -180,7 +192,7 @@ dmet_status fftdf_eri(const EriPlan& p, const dmet_pw_grid* grid, const void* rh
             PwAxis ax;
             for (int a = 0; a < 3; ++a) ax.n[a] = grid->n[a];
             ProfScope ps("fftdf_dft", st);
-            auto lds = [&](int a) { return (size_t)grid->n[a] * grid->n[a] * sizeof(double2); };
+            auto lds = [&](int a) { return (size_t)grid->n[a] * p.mesh.n[a] * sizeof(double2); };
             ax.axis = 0;
             ax.nmesh = p.mesh.n[0];
             ax.m = m[0];

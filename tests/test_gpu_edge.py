@@ -64,3 +64,19 @@ def test_degenerate_shapes(dmet, name, prec):
         tol = TOL[prec] if TOL[prec] is not None else 1e-10 * np.abs(ref).max()
         print(f"{name} {prec} {key} npair {neo * (neo + 1) // 2} max abs err {err:.3e}")
         assert err < tol, (key, err)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6", "bf16x3", "bf16x6_i8"])
+def test_nonfinite_input_gives_nan_output(dmet, prec):
+    """The ERI entry points are asynchronous and report no input check: a NaN
+    in a block of the 3-index tensor that the transform reads must come out as
+    NaN ERIs (never as finite numbers), in every form; clean input stays finite."""
+    kmesh, nao, naux, neo, lm, c_k = _inputs("odd_mesh")
+    lm = lm.copy()
+    lm[0, 0, 0, 0, 0] = np.nan                  # (q = 0, k = 0) is read by every form
+    out = dmet.dmet_transform_eri(kmesh, nao, naux, to_dev(lm), to_dev(c_k), prec)
+    torch.cuda.synchronize()
+    assert bool(torch.isnan(out["aa"]).any()), prec
+    clean = dmet.dmet_transform_eri(kmesh, nao, naux, to_dev(_inputs("odd_mesh")[4]), to_dev(c_k), prec)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(clean["aa"]).all()), prec

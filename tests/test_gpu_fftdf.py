@@ -64,3 +64,17 @@ def test_fftdf_parity_fullsize(dmet):
     err = np.abs(got - refp).max()
     print(f"fft_si fftdf max err {err:.3e} (max {np.abs(refp).max():.3f}, im {im:.1e})")
     assert err < 1e-10 * np.abs(refp).max()
+
+
+def test_fftdf_long_axis(dmet):
+    """More than 64 grid points along an axis (72 in a 20 bohr cell, two
+    k-points along it: 144 roots of unity per supercell axis), the limit of the
+    earlier square twiddle table; odd short axes."""
+    wl = synth.Workload("fft_long", (2, 1, 1), 3, 72 * 3 * 5, 3, 3, 1, 1.5, 1014)
+    g = synth.FftGrid((72, 3, 5), (20.0, 2.2, 2.6))
+    rho, ck, out = _run(dmet, wl, g)
+    ref, im = ok.alg2_eri(rho, ck[0], wl.kmesh, g.n, g.cell)
+    refp = ok.pack_s8(ref)
+    err = np.abs(out["aa"].cpu().numpy() - refp).max()
+    print(f"fft_long fftdf max err {err:.3e} (max {np.abs(refp).max():.3f})")
+    assert err < 1e-10 * np.abs(refp).max()

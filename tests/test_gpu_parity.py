@@ -274,7 +274,7 @@ def test_fock_dc_parity(dmet, nspin):
     fe, _ = dmet.dmet_transform_1e(wl.kmesh, wl.nao, ck_d, to_dev(fk))
     ge, _ = dmet.dmet_transform_1e(wl.kmesh, wl.nao, ck_d, to_dev(lat.dm_k))
     e_ref = ok.energy_mf(ref, g_eo, eri)
-    for prec, tol in (("fp64", 1e-10), ("bf16x6", 1e-5)):
+    for prec, tol in (("fp64", 1e-10), ("bf16x6", 1e-6), ("bf16x6_i8", 1e-6)):
         z = dmet.dmet_transform_eri_df(wl.kmesh, wl.nao, wl.naux, to_dev(lm), ck_d, prec)
         ft_d = dmet.dmet_fock_dc(z, fe, ge)
         ft = ft_d.cpu().numpy()
