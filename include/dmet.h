@@ -91,8 +91,7 @@ typedef enum {
                                 largest entry), the six digit products of
                                 level <= 2 summed exactly in int32 and combined
                                 in FP64.  At most N_k*naux = 44032 rows
-                                (DMET_E_UNSUPPORTED above); the batched entry
-                                point runs it per fragment                     */
+                                (DMET_E_UNSUPPORTED above)                     */
 } dmet_precision;
 
 typedef enum {
@@ -332,9 +331,11 @@ dmet_status dmet_energy_mf(int nspin, int neo, const double* f_tilde, const doub
  *
  * frags    host array of nfrag descriptors; lat.nspin must be 1; fragments
  *          that share lmunu must share lat and dtype.
- * prec     DMET_BF16X3_3M or DMET_BF16X6_3M run the batched pipeline above;
- *          DMET_FP64 and DMET_FP32_3M run the single-fragment path for each
- *          fragment in turn (same results as dmet_transform_eri).
+ * prec     DMET_BF16X3_3M, DMET_BF16X6_3M or DMET_BF16X6_I8 run the batched
+ *          pipeline above (the last with the int8 contraction, at most 44032
+ *          rows N_k*naux per fragment); DMET_FP64 and DMET_FP32_3M run the
+ *          single-fragment path for each fragment in turn (same results as
+ *          dmet_transform_eri).
  * flags    DMET_BATCH_GRAPH: capture the whole submission into a hipGraph on the
  *            first call with a given batch (descriptors, precision, workspace)
  *            and replay it on later calls (inputs may change, pointers may not);

@@ -347,13 +347,14 @@ static dmet_status check_batch(int nfrag, const dmet_fragment* frags, dmet_preci
         dmet_status s = check_eri_args(&d.lat, d.neo, prec, d.dtype);
         if (s != DMET_OK) return fail(s, "fragment " + std::to_string(f) + ": " + dmet_last_error());
         const long nk = (long)d.lat.kmesh[0] * d.lat.kmesh[1] * d.lat.kmesh[2];
-        if ((prec == DMET_BF16X3_3M || prec == DMET_BF16X6_3M) && nk > KP_MAX)
+        const bool split = prec == DMET_BF16X3_3M || prec == DMET_BF16X6_3M || prec == DMET_BF16X6_I8;
+        if (split && nk > KP_MAX)
             return fail(DMET_E_UNSUPPORTED, "fragment " + std::to_string(f) +
                                                 ": the split-bf16 batched transform supports at most 256 k-points");
         if (d.lat.nspin != 1) return fail(DMET_E_ARG, "fragment " + std::to_string(f) + ": nspin must be 1");
-        if ((prec == DMET_BF16X3_3M || prec == DMET_BF16X6_3M) &&
-            d.lat.kmesh[0] * d.lat.kmesh[1] * d.lat.kmesh[2] > 256)
-            return fail(DMET_E_UNSUPPORTED, "fragment " + std::to_string(f) + ": at most 256 k-points");
+        if (prec == DMET_BF16X6_I8 && nk * (long)d.lat.naux > 44032)
+            return fail(DMET_E_UNSUPPORTED, "fragment " + std::to_string(f) +
+                                                ": the int8 contraction holds exact sums for at most 44032 rows");
         if (!d.lmunu || !d.c_k || !d.eri) return fail(DMET_E_ARG, "fragment " + std::to_string(f) + ": null pointer");
         for (int g = 0; g < f; ++g)
             if (frags[g].lmunu == d.lmunu &&

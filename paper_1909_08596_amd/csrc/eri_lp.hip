@@ -1170,6 +1170,10 @@ struct BFrag {
     const __bf16* zp;    // packed parts of Z [part][kgroups][npair][8]
     double* eri;         // s8 output
     int neo, naux, ng2, npair, zrows, kgroups;
+    const i4v* zp8;      // int8 digit planes of Z [digit][kg16][npair] (int8 contraction)
+    unsigned* cmax;      // column max of Z (float bits)
+    int* ex;             // column exponents
+    int kg16;            // 16-row groups of the digit planes
 };
 
 // Per (round, fragment) q-block of the stage-2 items, with the kept k of the
@@ -1575,6 +1579,113 @@ k_contract_persist(const int* __restrict__ qstart, const int* __restrict__ qlen,
 template <int NS, int BM>
 constexpr size_t persist_lds() { return (size_t)(BM == 128 ? 3 : 2) * 2 * NS * 2 * BM * 16; }
 
+// Persistent int8 contraction over the tiles of all fragments (the int8 form of
+// k_contract_persist): 128 x 128 tiles, four waves of 64 x 64, 32-row stages
+// of three digit planes in a 3-deep ring (two workgroups per CU), three int32
+// accumulator sets, the FP64 combination with the column exponents at the end.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_contract_persist_i8(const int* __restrict__ qstart, const int* __restrict__ qlen, int* __restrict__ qctr,
+                      const BItemC* __restrict__ items, const BFrag* __restrict__ frags) {
+    constexpr int NS = 3, BM = 128, BN = 128, G = 2, NBUF = 3;
+    constexpr int TM = 2, TN = 2;
+    constexpr int PART = G * BM;
+    constexpr int STAGE = 2 * NS * PART;
+    extern __shared__ __align__(16) i4v ring_p8[];
+    __shared__ int s_item;
+    const int xcd = blockIdx.x % NXCD;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
+    const int g = lane >> 5;
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) s_item = atomicAdd(&qctr[xcd], 1);
+        __syncthreads();
+        const int idx = s_item;
+        if (idx >= qlen[xcd]) break;
+        const BItemC item = items[qstart[xcd] + idx];
+        const BFrag fr = frags[item.slot];
+        const int npair = fr.npair, nkt = fr.kg16 / G;
+        const int m0 = item.mt * BM, n0 = item.nt * BN;
+        const size_t plane = (size_t)fr.kg16 * npair;
+        const i4v* pa = fr.zp8;
+
+        auto issue = [&](int kt) {
+            i4v* st = ring_p8 + (size_t)(kt % NBUF) * STAGE;
+            for (int first = wave * 64; first < NS * PART; first += 256) {
+                const int t = first / PART, w = first % PART, gg = w / BM, row0 = w % BM;
+                const size_t grp = (size_t)kt * G + gg;
+                const int xa = min(m0 + row0 + lane, npair - 1), xb = min(n0 + row0 + lane, npair - 1);
+                const i4v* row = pa + t * plane + grp * npair;
+                lds_dma16(row, (unsigned)npair * 16u, (unsigned)xa * 16u, st + first);
+                lds_dma16(row, (unsigned)npair * 16u, (unsigned)xb * 16u, st + NS * PART + first);
+            }
+        };
+
+        i16v acc[3][TM][TN];
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) acc[l][i][j][r] = 0;
+        for (int s2 = 0; s2 < NBUF - 1; ++s2)
+            if (s2 < nkt) issue(s2);
+        __builtin_amdgcn_s_waitcnt(0xC07F);   // no scalar load in flight at the loop head
+        for (int kt = 0; kt < nkt; ++kt) {
+            // the loads of one younger stage may stay in flight; every wave issues
+            // the same number of loads per stage
+            constexpr int LOADS = 2 * NS * (PART / 256);
+            if (kt + 1 < nkt) __builtin_amdgcn_s_waitcnt(0x0F70 | (LOADS & 15) | ((LOADS >> 4) << 14));
+            else __builtin_amdgcn_s_waitcnt(0x0F70);
+            __builtin_amdgcn_s_barrier();
+            __builtin_amdgcn_sched_barrier(0);
+            if (kt + NBUF - 1 < nkt) issue(kt + NBUF - 1);
+            const i4v* sA = ring_p8 + (size_t)(kt % NBUF) * STAGE;
+            const i4v* sB = sA + NS * PART;
+            i4v b[NS][TN];
+#pragma unroll
+            for (int t = 0; t < NS; ++t)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) b[t][j] = sB[t * PART + g * BN + wn0 + j * 32 + (lane & 31)];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+#pragma unroll
+                for (int ta = NS - 1; ta >= 0; --ta) {
+                    const i4v a = sA[ta * PART + g * BM + wm0 + i * 32 + (lane & 31)];
+#pragma unroll
+                    for (int tb = NS - 1 - ta; tb >= 0; --tb)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j)
+                            acc[ta + tb][i][j] =
+                                __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b[tb][j], acc[ta + tb][i][j], 0, 0, 0);
+                }
+            }
+        }
+        constexpr double inv_b = 1.0 / 254.0, inv_b0sq = 1.0 / (127.0 * 127.0);
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int KL = n0 + wn0 + j * 32 + (lane & 31);
+            const int eb = fr.ex[min(KL, npair - 1)];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int IJ = m0 + wm0 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    if (IJ >= npair || KL > IJ) continue;
+                    const int ea = fr.ex[IJ];
+                    double v = (double)acc[0][i][j][r] +
+                               ((double)acc[1][i][j][r] + (double)acc[2][i][j][r] * inv_b) * inv_b;
+                    v = (ea == I8_EBAD || eb == I8_EBAD) ? __builtin_nan("") : ldexp(v * inv_b0sq, ea + eb);
+                    fr.eri[(size_t)IJ * (IJ + 1) / 2 + KL] = v;
+                }
+        }
+    }
+}
+
+constexpr size_t persist_i8_lds() { return (size_t)3 * 2 * 3 * 2 * 128 * 16; }
+
 template <int NS>
 constexpr size_t xf1_lds() { return (size_t)2 * P2 * NS * 2 * (128 + 128) * 16; }
 template <int NS>
@@ -1858,8 +1969,8 @@ struct BatchGroup {
 };
 
 struct BatchFrag {
-    int group, neo, npair, zrows, kgroups, col0;
-    size_t off_pc2, off_ptt, off_z, off_zp;
+    int group, neo, npair, zrows, kgroups, col0, kg16 = 0;
+    size_t off_pc2, off_ptt, off_z, off_zp, off_ex = 0, cmax_idx = 0;
 };
 
 // Fragments with at most this many embedding orbitals take the 32 x 32
@@ -1880,7 +1991,7 @@ struct BatchPlan {
     std::vector<BatchGroup> groups;
     std::vector<BatchFrag> fs;
     int rounds = 0;
-    size_t off_bfrag = 0, off_items2 = 0, off_bq = 0, off_itemsc = 0, off_q = 0;
+    size_t off_bfrag = 0, off_items2 = 0, off_bq = 0, off_itemsc = 0, off_q = 0, off_cmax = 0, ncmax = 0;
     std::vector<int> items2_off, items2_cnt;     // 64 x 64 stage-2 items per round
     std::vector<int> items2s_off, items2s_cnt;   // 32 x 32 four-L items (small fragments) per round
     std::vector<BFrag> h_bfrag;
@@ -1925,7 +2036,8 @@ static std::string batch_key(int nfrag, const dmet_fragment* f, int prec, bool w
 // Build groups, per-fragment dims, workspace offsets and the work lists.
 static void plan_batch(BatchPlan& bp) {
     const int nfrag = (int)bp.frags.size();
-    bp.ns = bp.prec == DMET_BF16X6_3M ? 3 : 2;
+    bp.ns = bp.prec == DMET_BF16X3_3M ? 2 : 3;
+    const bool i8 = bp.prec == DMET_BF16X6_I8;
     const int NS = bp.ns;
     // groups by lmunu pointer
     for (int f = 0; f < nfrag; ++f) {
@@ -1958,6 +2070,7 @@ static void plan_batch(BatchPlan& bp) {
         F.npair = d.neo * (d.neo + 1) / 2;
         F.zrows = G.mesh.nk * G.naux;
         F.kgroups = (F.zrows + 31) / 32 * 4;
+        F.kg16 = (F.zrows + 31) / 32 * 2;      // 32-row stages of two 16-row groups
         F.col0 = G.nbtot;
         G.nbtot += d.neo;
         G.members.push_back(f);
@@ -2069,7 +2182,21 @@ static void plan_batch(BatchPlan& bp) {
         F.off_pc2 = off(sizeof(__bf16) * pl2 * G.ng2 * F.neo);
         F.off_ptt = off(sizeof(__bf16) * pl2 * G.ng2 * (size_t)G.naux * F.neo);
         F.off_z = off(sizeof(float) * (size_t)F.zrows * F.npair);
-        F.off_zp = off(sizeof(__bf16) * (size_t)NS * F.kgroups * 8 * F.npair);
+        if (i8) {
+            F.off_zp = off(sizeof(i4v) * (size_t)3 * F.kg16 * F.npair);
+            F.off_ex = off(sizeof(int) * (size_t)F.npair);
+        } else {
+            F.off_zp = off(sizeof(__bf16) * (size_t)NS * F.kgroups * 8 * F.npair);
+        }
+    }
+    if (i8) {   // column maxima of every fragment in one region (one fill per call)
+        size_t n = 0;
+        for (auto& F : bp.fs) {
+            F.cmax_idx = n;
+            n += F.npair;
+        }
+        bp.off_cmax = off(sizeof(unsigned) * std::max<size_t>(1, n));
+        bp.ncmax = n;
     }
     bp.bytes = (cur + 255) & ~size_t(255);
 }
@@ -2097,6 +2224,8 @@ static dmet_status batch_prepare() {
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)persist_lds<NS, 128>()));
     DMET_HIP(hipFuncSetAttribute((const void*)k_contract_persist<NS, 64>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)persist_lds<NS, 64>()));
+    DMET_HIP(hipFuncSetAttribute((const void*)k_contract_persist_i8, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)persist_i8_lds()));
     int dev = 0;
     DMET_HIP(hipGetDevice(&dev));
     DMET_HIP(hipDeviceGetAttribute(&g_ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -2187,6 +2316,32 @@ static dmet_status batch_enqueue(BatchPlan& bp, int variant, bool prof, hipStrea
             done(ps);
         }
     }
+    if (bp.prec == DMET_BF16X6_I8) {
+        // 3. column scales and int8 digits of every fragment's Z, 4. persistent int8 contraction
+        ps = scope("batch_pack_i8");
+        fill_zero(at<unsigned>(ws, bp.off_cmax), bp.ncmax * sizeof(unsigned), st);
+        for (int f = 0; f < nfrag; ++f) {
+            const BatchFrag& F = bp.fs[f];
+            const int rows_per = 256;
+            unsigned* cm = at<unsigned>(ws, bp.off_cmax) + F.cmax_idx;
+            k_colmax<<<dim3((F.npair + 255) / 256, (F.zrows + rows_per - 1) / rows_per), 256, 0, st>>>(
+                at<float>(ws, F.off_z), (size_t)F.npair, F.zrows, F.npair, rows_per, cm);
+            k_pack_i8<<<dim3((F.npair + 255) / 256, F.kg16), 256, 0, st>>>(
+                at<float>(ws, F.off_z), (size_t)F.npair, F.zrows, F.npair, F.kg16, cm, at<int>(ws, F.off_ex),
+                at<i4v>(ws, F.off_zp));
+        }
+        done(ps);
+        DMET_LAUNCH_CHECK("batch pack i8");
+        int* qd = at<int>(ws, bp.off_q);
+        fill_zero(qd + 2 * NXCD, NXCD * sizeof(int), st);
+        const int ncu = g_ncu > 0 ? g_ncu : 256;
+        ps = scope("batch_contract_i8");
+        k_contract_persist_i8<<<dim3((unsigned)(2 * ncu)), 256, persist_i8_lds(), st>>>(
+            qd, qd + NXCD, qd + 2 * NXCD, at<BItemC>(ws, bp.off_itemsc), dfr);
+        done(ps);
+        DMET_LAUNCH_CHECK("batch contract i8");
+        return DMET_OK;
+    }
     // 3. split Z into bf16 parts
     ps = scope(NS == 3 ? "batch_pack_bf16x6" : "batch_pack_bf16x3");
     for (int f = 0; f < nfrag; ++f) {
@@ -2227,6 +2382,11 @@ static dmet_status batch_upload(BatchPlan& bp, int variant, hipStream_t st) {
         b.npair = F.npair;
         b.zrows = F.zrows;
         b.kgroups = F.kgroups;
+        const bool i8 = bp.prec == DMET_BF16X6_I8;
+        b.zp8 = i8 ? at<i4v>(ws, F.off_zp) : nullptr;
+        b.cmax = i8 ? at<unsigned>(ws, bp.off_cmax) + F.cmax_idx : nullptr;
+        b.ex = i8 ? at<int>(ws, F.off_ex) : nullptr;
+        b.kg16 = F.kg16;
         bp.h_bfrag[f] = b;
     }
     const int v = variant == 128 ? 0 : 1;
@@ -2256,14 +2416,13 @@ static dmet_status batch_upload(BatchPlan& bp, int variant, hipStream_t st) {
 }
 
 size_t batch_workspace(int nfrag, const dmet_fragment* frags, dmet_precision prec) {
-    if (prec == DMET_FP64 || prec == DMET_FP32_3M || prec == DMET_BF16X6_I8) {
+    if (prec == DMET_FP64 || prec == DMET_FP32_3M) {
         size_t mx = 256;
         for (int f = 0; f < nfrag; ++f) {
             dmet_lattice lat = frags[f].lat;
             lat.nspin = 1;
             EriPlan p = make_eri_plan(&lat, frags[f].neo, prec, frags[f].dtype);
-            mx = std::max(mx, prec == DMET_FP64 ? eri_f64_workspace(p)
-                                                : (prec == DMET_FP32_3M ? eri_f32_workspace(p) : eri_lp_workspace(p)));
+            mx = std::max(mx, prec == DMET_FP64 ? eri_f64_workspace(p) : eri_f32_workspace(p));
         }
         return mx;
     }
@@ -2311,7 +2470,7 @@ static void tune_store(const std::string& key, int v, float ms128, float ms64) {
 
 dmet_status eri_batched(int nfrag, const dmet_fragment* frags, dmet_precision prec, unsigned flags, void* ws,
                         size_t ws_bytes, hipStream_t st) {
-    if (prec == DMET_FP64 || prec == DMET_FP32_3M || prec == DMET_BF16X6_I8) {
+    if (prec == DMET_FP64 || prec == DMET_FP32_3M) {
         for (int f = 0; f < nfrag; ++f) {
             dmet_lattice lat = frags[f].lat;
             lat.nspin = 1;
@@ -2319,11 +2478,7 @@ dmet_status eri_batched(int nfrag, const dmet_fragment* frags, dmet_precision pr
             const double* ckf = static_cast<const double*>(frags[f].c_k);
             dmet_status s = prec == DMET_FP64
                                 ? eri_f64(p, frags[f].lmunu, ckf, frags[f].eri, nullptr, nullptr, ws, ws_bytes, st)
-                                : (prec == DMET_FP32_3M
-                                       ? eri_f32(p, frags[f].lmunu, ckf, frags[f].eri, nullptr, nullptr, ws, ws_bytes,
-                                                 st)
-                                       : eri_lp(p, frags[f].lmunu, ckf, frags[f].eri, nullptr, nullptr, ws, ws_bytes,
-                                                st));
+                                : eri_f32(p, frags[f].lmunu, ckf, frags[f].eri, nullptr, nullptr, ws, ws_bytes, st);
             if (s != DMET_OK) return s;
         }
         return DMET_OK;
@@ -2355,7 +2510,7 @@ dmet_status eri_batched(int nfrag, const dmet_fragment* frags, dmet_precision pr
         }
         g_batch_plans[key] = bp;
     }
-    const bool ns3 = prec == DMET_BF16X6_3M;
+    const bool ns3 = prec != DMET_BF16X3_3M;
     {
         dmet_status s = ns3 ? batch_prepare<3>() : batch_prepare<2>();
         if (s != DMET_OK) return s;
@@ -2368,7 +2523,9 @@ dmet_status eri_batched(int nfrag, const dmet_fragment* frags, dmet_precision pr
     const std::string shape = batch_key(nfrag, frags, prec, false, nullptr, 0);
     int variant = 128;
     auto itt = g_tune.find(shape);
-    if (itt != g_tune.end()) {
+    if (prec == DMET_BF16X6_I8) {
+        // one contraction variant (128 x 128 tiles) in the int8 form: nothing to tune
+    } else if (itt != g_tune.end()) {
         variant = itt->second;
     } else if (flags & DMET_BATCH_AUTOTUNE) {
         float best = 1e30f;

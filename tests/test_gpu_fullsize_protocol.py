@@ -185,7 +185,7 @@ def test_batched_fullsize_fragments(dmet):
         ck_d = to_dev(np.ascontiguousarray(bath["c_k"][0]))
         specs.append({"kmesh": wl.kmesh, "nao": wl.nao, "naux": wl.naux, "lmunu": lm_d, "c_k": ck_d})
         ref64.append(dmet.dmet_transform_eri(wl.kmesh, wl.nao, wl.naux, lm_d, ck_d[None], "fp64")["aa"])
-    for prec in ("bf16x6", "bf16x3"):
+    for prec in ("bf16x6", "bf16x3", "bf16x6_i8"):
         for rep in range(2):
             outs = [o.clone() for o in dmet.dmet_transform_eri_batched(specs, prec, graph=True)]
             torch.cuda.synchronize()
