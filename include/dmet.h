@@ -46,7 +46,9 @@
  * entry point aborts or throws across the ABI.
  *
  * Tuning (environment, read at each call; results do not depend on them beyond
- * rounding order): DMET_XF2_SMALL_NEO=n sets the largest fragment neo that the batched form
+ * rounding order): DMET_SVD_MAX_SWEEPS=n (1..60, default 60) caps the Jacobi
+ * sweeps of the bath SVD (a lower cap forces DMET_E_NOCONV on purpose);
+ * DMET_XF2_SMALL_NEO=n sets the largest fragment neo that the batched form
  * transforms with 32 x 32 stage-2 tiles (default 256); DMET_TUNE_CACHE names
  * the file of the batched autotuner's choices.
  */
@@ -193,9 +195,11 @@ dmet_status dmet_build_bath_noalloc(const dmet_lattice* lat, const void* dm_k,
  * c_k      [nspin][N_k][nao][neo] complex128.
  * op_k     [nspin][N_k][nao][nao] complex128 (h(k), F(k) or gamma(k)).
  * op_eo    out [nspin][neo][neo] float64, the real part.
- * max_imag out DEVICE [1] float64 max |Im X^{0,EO}| (0 for real-symmetric
- *          lattices), or NULL.
- * Asynchronous.
+ * max_imag out HOST [1] float64 max |Im X^{0,EO}| (zero up to rounding for
+ *          time-reversal-symmetric lattices; the imaginary part is
+ *          discarded), or NULL.  When it is given the call synchronises
+ *          `stream` before returning (and concurrent calls that ask for it
+ *          on one GPU take turns); with NULL it is asynchronous.
  * ------------------------------------------------------------------------- */
 dmet_status dmet_transform_1e(const dmet_lattice* lat, int neo, const void* c_k,
                               const void* op_k, double* op_eo, double* max_imag,
@@ -237,6 +241,25 @@ dmet_status dmet_transform_eri(const dmet_lattice* lat, int neo, const void* lmu
                                dmet_dtype dtype, const void* c_k, dmet_precision prec,
                                double* eri_aa, double* eri_bb, double* eri_ab,
                                void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Embedding ERIs of the non-interacting-bath formalism (Sec. 2.1: two-particle
+ * interactions kept on the impurity orbitals only): Alg. 1 on the first nimp
+ * columns of C^k, i.e. the impurity block of the full embedding ERIs.
+ *
+ * neo      columns of c_k ([nspin][N_k][nao][neo] complex128, as written by
+ *          dmet_build_bath: impurity columns first); 1 <= nimp <= neo.
+ * eri_*    as dmet_transform_eri with npair = nimp(nimp+1)/2.
+ * workspace/ws_bytes: at least dmet_transform_eri_impurity_workspace() (the
+ *          transform's workspace for nimp orbitals plus a copy of the
+ *          impurity columns).  Asynchronous.
+ * ------------------------------------------------------------------------- */
+dmet_status dmet_transform_eri_impurity_workspace(const dmet_lattice* lat, int neo, int nimp,
+                                                  dmet_precision prec, dmet_dtype dtype, size_t* bytes);
+dmet_status dmet_transform_eri_impurity(const dmet_lattice* lat, int neo, int nimp, const void* lmunu,
+                                        dmet_dtype dtype, const void* c_k, dmet_precision prec,
+                                        double* eri_aa, double* eri_bb, double* eri_ab,
+                                        void* workspace, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Density-fitting output of the embedding ERIs (Sec. 2.1: when the impurity

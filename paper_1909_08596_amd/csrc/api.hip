@@ -133,6 +133,14 @@ static dmet_status check_eri_args(const dmet_lattice* lat, int neo, dmet_precisi
     return DMET_OK;
 }
 
+// c_imp[s][k][mu][i] = c_k[s][k][mu][i] for i < nimp (the impurity columns)
+__global__ void k_impurity_columns(size_t rows, int neo, int nimp, const double2* __restrict__ c_k,
+                                   double2* __restrict__ c_imp) {
+    const size_t n = rows * (size_t)nimp;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+        c_imp[e] = c_k[(e / nimp) * neo + e % nimp];
+}
+
 }  // namespace dmet
 
 using namespace dmet;
@@ -257,6 +265,46 @@ dmet_status dmet_transform_eri(const dmet_lattice* lat, int neo, const void* lmu
         return eri_f32(p, lmunu, static_cast<const double*>(c_k), eri_aa, eri_bb, eri_ab, workspace, ws_bytes,
                        stream);
     return eri_lp(p, lmunu, static_cast<const double*>(c_k), eri_aa, eri_bb, eri_ab, workspace, ws_bytes, stream);
+}
+
+dmet_status dmet_transform_eri_impurity_workspace(const dmet_lattice* lat, int neo, int nimp, dmet_precision prec,
+                                                  dmet_dtype dtype, size_t* bytes) {
+    dmet_status s = check_eri_args(lat, nimp, prec, dtype);
+    if (s != DMET_OK) return s;
+    if (nimp > neo) return fail(DMET_E_ARG, "need 1 <= nimp <= neo");
+    if (!bytes) return fail(DMET_E_ARG, "bytes is NULL");
+    EriPlan p = make_eri_plan(lat, nimp, prec, dtype);
+    Carve cv(nullptr, 0);
+    cv.take<char>(eri_workspace(p));
+    cv.take<double2>((size_t)lat->nspin * p.mesh.nk * lat->nao * nimp);
+    *bytes = cv.bytes();
+    return DMET_OK;
+}
+
+dmet_status dmet_transform_eri_impurity(const dmet_lattice* lat, int neo, int nimp, const void* lmunu,
+                                        dmet_dtype dtype, const void* c_k, dmet_precision prec, double* eri_aa,
+                                        double* eri_bb, double* eri_ab, void* workspace, size_t ws_bytes,
+                                        hipStream_t stream) {
+    g_last_error.clear();
+    size_t need = 0;
+    dmet_status s = dmet_transform_eri_impurity_workspace(lat, neo, nimp, prec, dtype, &need);
+    if (s != DMET_OK) return s;
+    if (!lmunu || !c_k || !eri_aa) return fail(DMET_E_ARG, "null array argument");
+    if (lat->nspin == 2 && !eri_bb) return fail(DMET_E_ARG, "nspin == 2 requires eri_bb");
+    if (lat->nspin == 1 && (eri_bb || eri_ab)) return fail(DMET_E_ARG, "nspin == 1 takes no eri_bb / eri_ab");
+    if (!workspace || ws_bytes < need) return fail(DMET_E_WORKSPACE, "transform_eri_impurity workspace too small");
+    EriPlan p = make_eri_plan(lat, nimp, prec, dtype);
+    Carve cv(workspace, ws_bytes);
+    const size_t ews = eri_workspace(p);
+    void* eri_ws = cv.take<char>(ews);
+    const size_t rows = (size_t)lat->nspin * p.mesh.nk * lat->nao;
+    double2* c_imp = cv.take<double2>(rows * nimp);
+    k_impurity_columns<<<1024, 256, 0, stream>>>(rows, neo, nimp, static_cast<const double2*>(c_k), c_imp);
+    DMET_LAUNCH_CHECK("k_impurity_columns");
+    const double* ci = reinterpret_cast<const double*>(c_imp);
+    if (prec == DMET_FP64) return eri_f64(p, lmunu, ci, eri_aa, eri_bb, eri_ab, eri_ws, ews, stream);
+    if (prec == DMET_FP32_3M) return eri_f32(p, lmunu, ci, eri_aa, eri_bb, eri_ab, eri_ws, ews, stream);
+    return eri_lp(p, lmunu, ci, eri_aa, eri_bb, eri_ab, eri_ws, ews, stream);
 }
 
 dmet_status dmet_transform_eri_df(const dmet_lattice* lat, int neo, const void* lmunu, dmet_dtype dtype,

@@ -8,6 +8,9 @@
 // stored column-major so that every column is one contiguous vector; pairs are
 // visited in round-robin order, so the n/2 rotations of a round touch
 // disjoint columns and run on separate wavefronts of one workgroup.
+#include <stdlib.h>
+
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -531,7 +534,11 @@ dmet_status build_bath(const dmet_lattice* lat, const double2* dm_k, int nimp, c
         if (blocked) DMET_HIP(hipFuncSetAttribute(kblk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         int* rot = w.flags + 8;
         bool converged = false;
-        for (int sweep = 0; sweep < 60 && !converged; ++sweep) {
+        // at most 60 sweeps; DMET_SVD_MAX_SWEEPS lowers the limit (to force the
+        // non-convergence status from the host)
+        int max_sweeps = 60;
+        if (const char* e = getenv("DMET_SVD_MAX_SWEEPS")) max_sweeps = std::min(60, std::max(1, atoi(e)));
+        for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
             fill_zero(rot, 2 * sizeof(int), st);
             if (blocked) {
                 for (int round = 0; round < nbp - 1; ++round) {
@@ -555,7 +562,8 @@ dmet_status build_bath(const dmet_lattice* lat, const double2* dm_k, int nimp, c
             for (int sp = 0; sp < p.nspin; ++sp)
                 if (h_rot[sp] != 0) converged = false;
         }
-        if (!converged) return fail(DMET_E_NOCONV, "Jacobi SVD did not converge in 60 sweeps");
+        if (!converged)
+            return fail(DMET_E_NOCONV, "Jacobi SVD did not converge in " + std::to_string(max_sweeps) + " sweeps");
         const size_t shm = (size_t)nval * (sizeof(double) + sizeof(int));
         k_svd_finalize<<<p.nspin, 1024, shm, st>>>(p.nenv, nval, w.mt, w.ub, sv, sv_tol, w.flags);
         DMET_LAUNCH_CHECK("k_svd_finalize");

@@ -2,6 +2,8 @@
 //   X^{0,EO}_{ij} = 1/N_k sum_k sum_{mu nu} conj(C^k_{mu i}) X^k_{mu nu} C^k_{nu j}
 // and the one-body energy E1 = sum_spin Tr(h^EO gamma^EO).  FP64 vector ALU:
 // the work is N_k nao neo (nao + neo) complex MACs, a few GFLOP at most.
+#include <mutex>
+
 #include "common.h"
 
 namespace dmet {
@@ -171,15 +173,44 @@ __global__ void __launch_bounds__(1024) k_energy_1e(int nspin, int neo, const do
     }
 }
 
+// max |Im X^{0,EO}| is gathered in a device word of the library (one per GPU,
+// its address looked up once per device); a call that asks for it holds the
+// mutex from the clearing of that word to the read-back, so concurrent calls
+// on one GPU take turns and each reads its own value.
+static __device__ double imag_slot;
+
+namespace {
+std::mutex g_imag_mu;
+double* g_imag_ptr[64] = {};
+}  // namespace
+
 dmet_status transform_1e(const dmet_lattice* lat, int neo, const double2* ck, const double2* op,
                          double* out, double* max_imag, hipStream_t st) {
     Mesh mesh = make_mesh(lat->kmesh);
-    if (max_imag) fill_zero(max_imag, sizeof(double), st);
     const int ntj = (neo + OB_TJ - 1) / OB_TJ, nti = (neo + OB_TI - 1) / OB_TI;
     DMET_HIP(hipFuncSetAttribute((const void*)k_onebody, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)onebody_lds()));
-    k_onebody<<<dim3(ntj, nti, lat->nspin), 256, onebody_lds(), st>>>(mesh, lat->nao, neo, ck, op, out, max_imag);
+    if (!max_imag) {
+        k_onebody<<<dim3(ntj, nti, lat->nspin), 256, onebody_lds(), st>>>(mesh, lat->nao, neo, ck, op, out, nullptr);
+        DMET_LAUNCH_CHECK("k_onebody");
+        return DMET_OK;
+    }
+    int dev = 0;
+    DMET_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(DMET_E_UNSUPPORTED, "device ordinal above 63");
+    std::lock_guard<std::mutex> lk(g_imag_mu);
+    if (!g_imag_ptr[dev]) {
+        void* a = nullptr;
+        DMET_HIP(hipGetSymbolAddress(&a, HIP_SYMBOL(imag_slot)));
+        if (!a) return fail(DMET_E_HIP, "hipGetSymbolAddress returned a null address");
+        g_imag_ptr[dev] = static_cast<double*>(a);
+    }
+    double* slot = g_imag_ptr[dev];
+    fill_zero(slot, sizeof(double), st);
+    k_onebody<<<dim3(ntj, nti, lat->nspin), 256, onebody_lds(), st>>>(mesh, lat->nao, neo, ck, op, out, slot);
     DMET_LAUNCH_CHECK("k_onebody");
+    DMET_HIP(hipMemcpyAsync(max_imag, slot, sizeof(double), hipMemcpyDeviceToHost, st));
+    DMET_HIP(hipStreamSynchronize(st));
     return DMET_OK;
 }
 

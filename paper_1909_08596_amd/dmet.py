@@ -30,6 +30,7 @@ EXPORTS = ("dmet_last_error", "dmet_version", "dmet_build_bath_workspace", "dmet
            "dmet_transform_1e", "dmet_energy_1e", "dmet_transform_eri_workspace", "dmet_transform_eri",
            "dmet_transform_eri_batched_workspace", "dmet_transform_eri_batched",
            "dmet_transform_eri_df", "dmet_transform_eri_fftdf_workspace", "dmet_transform_eri_fftdf",
+           "dmet_transform_eri_impurity_workspace", "dmet_transform_eri_impurity",
            "dmet_fock_dc_workspace", "dmet_fock_dc", "dmet_energy_mf",
            "dmet_profile_enable", "dmet_profile_reset", "dmet_profile_report")
 DMET_BATCH_GRAPH, DMET_BATCH_AUTOTUNE = 1, 2
@@ -98,6 +99,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dmet_transform_eri_batched_workspace.argtypes = [i, fp, i, ctypes.POINTER(sz)]
     lib.dmet_transform_eri_batched.argtypes = [i, fp, i, ctypes.c_uint, vp, sz, vp]
     lib.dmet_transform_eri_df.argtypes = [lp, i, vp, i, vp, i, vp, vp, sz, vp]
+    lib.dmet_transform_eri_impurity_workspace.argtypes = [lp, i, i, i, i, ctypes.POINTER(sz)]
+    lib.dmet_transform_eri_impurity.argtypes = [lp, i, i, vp, i, vp, i, vp, vp, vp, vp, sz, vp]
     gp = ctypes.POINTER(PwGrid)
     lib.dmet_transform_eri_fftdf_workspace.argtypes = [lp, gp, i, i, ctypes.POINTER(sz)]
     lib.dmet_transform_eri_fftdf.argtypes = [lp, gp, i, vp, i, vp, vp, vp, vp, vp, sz, vp]
@@ -230,8 +233,9 @@ def dmet_build_bath_noalloc(kmesh, nao, dm_k: torch.Tensor, imp_idx=None, val_id
     return c_k, sv, [int(x) for x in neo], mi.value
 
 
-def dmet_transform_1e(kmesh, nao, c_k: torch.Tensor, op_k: torch.Tensor, want_imag: bool = True, stream=None):
-    """X^{0,EO} = 1/N_k sum_k C^k^H X^k C^k.  Returns (op_eo, max_imag or None)."""
+def dmet_transform_1e(kmesh, nao, c_k: torch.Tensor, op_k: torch.Tensor, want_imag: bool = False, stream=None):
+    """X^{0,EO} = 1/N_k sum_k C^k^H X^k C^k.  Returns (op_eo, max |Im| as a
+    float, or None); asking for max |Im| synchronises the stream."""
     lib = load()
     nk = _nk(kmesh)
     if c_k.dim() != 4 or c_k.shape[0] not in (1, 2):
@@ -243,10 +247,10 @@ def dmet_transform_1e(kmesh, nao, c_k: torch.Tensor, op_k: torch.Tensor, want_im
     _dev(op_k, torch.complex128, "op_k")
     lat = lattice(kmesh, nao, 1, nspin)
     out = torch.empty((nspin, neo, neo), dtype=torch.float64, device=c_k.device)
-    mi = torch.empty(1, dtype=torch.float64, device=c_k.device) if want_imag else None
-    _check(lib.dmet_transform_1e(ctypes.byref(lat), neo, _ptr(c_k), _ptr(op_k), _ptr(out), _ptr(mi),
-                                 _stream(stream)))
-    return out, mi
+    mi = ctypes.c_double(-1.0)
+    _check(lib.dmet_transform_1e(ctypes.byref(lat), neo, _ptr(c_k), _ptr(op_k), _ptr(out),
+                                 ctypes.byref(mi) if want_imag else None, _stream(stream)))
+    return out, (mi.value if want_imag else None)
 
 
 def dmet_energy_1e(h_eo: torch.Tensor, dm_eo: torch.Tensor, stream=None) -> torch.Tensor:
@@ -341,13 +345,30 @@ def dmet_transform_eri(kmesh, nao, naux, lmunu: torch.Tensor, c_k: torch.Tensor,
 def dmet_transform_eri_impurity(kmesh, nao, naux, lmunu: torch.Tensor, c_k: torch.Tensor, nimp: int,
                                 precision: str = "fp64", eri_ab: bool = True, stream=None):
     """ERIs of the non-interacting-bath formalism (Sec. 2.1): two-particle
-    terms on the impurity orbitals only, i.e. Alg. 1 with C^k cut to its first
-    nimp columns (the impurity block of Eq. ``C loemb k``).  Same return value
-    as dmet_transform_eri with neo = nimp."""
-    if not 1 <= nimp <= c_k.shape[-1]:
+    terms on the impurity orbitals only, i.e. Alg. 1 on the first nimp columns
+    of C^k (the impurity block of Eq. ``C loemb k``).  Same return value as
+    dmet_transform_eri with neo = nimp."""
+    lib = load()
+    nspin, neo = _eri_inputs(kmesh, nao, naux, lmunu, c_k)
+    if not 1 <= nimp <= neo:
         raise ValueError("need 1 <= nimp <= neo")
-    return dmet_transform_eri(kmesh, nao, naux, lmunu, c_k[..., :nimp].contiguous(), precision, eri_ab=eri_ab,
-                              stream=stream)
+    lat = lattice(kmesh, nao, naux, nspin)
+    dt = DMET_C128 if lmunu.dtype == torch.complex128 else DMET_C64
+    npair = nimp * (nimp + 1) // 2
+    dev = c_k.device
+    out = {"aa": torch.empty(npair * (npair + 1) // 2, dtype=torch.float64, device=dev)}
+    if nspin == 2:
+        out["bb"] = torch.empty_like(out["aa"])
+        if eri_ab:
+            out["ab"] = torch.empty((npair, npair), dtype=torch.float64, device=dev)
+    nb = ctypes.c_size_t()
+    _check(lib.dmet_transform_eri_impurity_workspace(ctypes.byref(lat), neo, int(nimp), PRECISIONS[precision], dt,
+                                                     ctypes.byref(nb)))
+    ws = _workspace(nb.value, dev)
+    _check(lib.dmet_transform_eri_impurity(ctypes.byref(lat), neo, int(nimp), _ptr(lmunu), dt, _ptr(c_k),
+                                           PRECISIONS[precision], _ptr(out["aa"]), _ptr(out.get("bb")),
+                                           _ptr(out.get("ab")), _ptr(ws), ws.numel(), _stream(stream)))
+    return out
 
 
 def dmet_transform_eri_fftdf(kmesh, nao, grid_n, cell, rho: torch.Tensor, c_k: torch.Tensor, eri_ab: bool = True,

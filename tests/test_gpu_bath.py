@@ -229,3 +229,19 @@ def test_bath_error_status(dmet):
     assert e.value.status == 4
     ck, sv, got = dmet.dmet_build_bath(wl.kmesh, wl.nao, to_dev(lat.dm_k))
     assert got == [16]
+
+
+def test_bath_noconv_status(dmet, monkeypatch):
+    """A sweep cap below what the SVD needs returns DMET_E_NOCONV (forced from
+    the host through the library's sweep limit; every kernel exits normally),
+    and the next call with the default cap succeeds."""
+    wl = synth.Workload("nc", (2, 2, 2), 20, 4, 20, 20, 1, 1.5, 65)
+    lat = synth.make_lattice(wl)
+    dm = to_dev(lat.dm_k)
+    monkeypatch.setenv("DMET_SVD_MAX_SWEEPS", "1")
+    with pytest.raises(dmet.DmetError) as e:
+        dmet.dmet_build_bath(wl.kmesh, wl.nao, dm)
+    assert e.value.status == 3 and "1 sweeps" in str(e.value)
+    monkeypatch.delenv("DMET_SVD_MAX_SWEEPS")
+    ck, sv, neo = dmet.dmet_build_bath(wl.kmesh, wl.nao, dm)
+    assert neo == [2 * wl.nao]

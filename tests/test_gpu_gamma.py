@@ -50,7 +50,7 @@ def test_gamma_bath_is_the_impurity(dmet, inputs):
     assert not sv.cpu().numpy().any()
     # with C = 1 the embedding one-body operators are the cell's own
     c = to_dev(ck[..., : WL.nao])
-    h, mi = dmet.dmet_transform_1e(WL.kmesh, WL.nao, c, to_dev(lat.h_k))
+    h, mi = dmet.dmet_transform_1e(WL.kmesh, WL.nao, c, to_dev(lat.h_k), want_imag=True)
     g, _ = dmet.dmet_transform_1e(WL.kmesh, WL.nao, c, to_dev(lat.dm_k))
     assert np.abs(h.cpu().numpy() - lat.h_k[:, 0].real).max() < 1e-14
     e1 = float(dmet.dmet_energy_1e(h, g).cpu())

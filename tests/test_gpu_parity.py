@@ -59,10 +59,10 @@ def test_onebody_parity(dmet, key):
     ck = to_dev(bath["c_k"])
     outs = {}
     for nm, op in (("h", lat.h_k), ("f", lat.f_k), ("g", lat.dm_k)):
-        x, mi = dmet.dmet_transform_1e(wl.kmesh, wl.nao, ck, to_dev(op))
+        x, mi = dmet.dmet_transform_1e(wl.kmesh, wl.nao, ck, to_dev(op), want_imag=True)
         ref, rim = ok.transform_1e(bath["c_k"], op)
         assert np.abs(x.cpu().numpy() - ref).max() < 1e-12
-        assert float(mi.cpu()) < 1e-12
+        assert mi < 1e-12
         outs[nm] = (x, ref)
     e1 = dmet.dmet_energy_1e(outs["h"][0], outs["g"][0])
     ref_e1 = ok.energy_1e(outs["h"][1], outs["g"][1])
