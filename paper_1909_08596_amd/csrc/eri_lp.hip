@@ -859,7 +859,7 @@ __global__ void k_pack_c2(const double* __restrict__ ck, int nk, int nao, int na
 template <int NS, int ROWS>
 __device__ inline void pk_issue_g(const __bf16* base, size_t pt_stride, int X, int x0, int g0, int g1, bf8* dst) {
     constexpr int CH = P2 * NS * 2 * ROWS;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int first = wave * 64; first < CH; first += 256) {
         const int pt = first / (2 * ROWS), g = (first / ROWS) % 2, row0 = first % ROWS;
         const int x = min(x0 + row0 + lane, X - 1);
@@ -883,34 +883,60 @@ __device__ inline void pk_issue(const __bf16* base, size_t pt_stride /*chunks pe
     }
 }
 
-// 4M x NS-split products of one 16-deep stage on (re, im) planes:
-// acc[0] += Ar Br, acc[1] += Ai Bi, acc[2] += Ar Bi, acc[3] += Ai Br
-// (re = acc0 - acc1, im = acc2 + acc3).  The split products of each real
-// product run smallest first: lo*hi terms, then mid*mid and hi*lo, ..., hi*hi.
+// Negated bf16 fragment: the sign bit of each of the eight values flipped (exact).
+__device__ inline bf8 neg_bf8(bf8 x) {
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    u4 u = __builtin_bit_cast(u4, x);
+    u ^= 0x80008000u;
+    return __builtin_bit_cast(bf8, u);
+}
+
+// 4M x NS-split products of one 16-deep stage on (re, im) planes, two
+// accumulators per output: acc[0] += Ar Br + (-Ai) Bi (the real part),
+// acc[1] += Ar Bi + Ai Br (the imaginary part), the negation applied to the
+// staged Ai fragment.  Each real product's split products run smallest first:
+// lo*hi terms, then mid*mid and hi*lo, ..., hi*hi; the four real products in
+// the order Ar Br, Ai Bi, Ar Bi, Ai Br.
+// The operand fragments of one 16-deep stage for a wave's TM x TN blocks.
+template <int NS, int TM, int TN>
+struct PkFrags {
+    bf8 a[P2][TM][NS], b[P2][TN][NS];
+};
+
 template <int NS, int BM, int BN, int TM, int TN>
-__device__ inline void pk_mma4(const bf8* sA, const bf8* sB, int wm0, int wn0, f16v (&acc)[4][TM][TN]) {
+__device__ inline void pk_read(const bf8* sA, const bf8* sB, int wm0, int wn0, PkFrags<NS, TM, TN>& f) {
     const int lane = threadIdx.x & 63;
     const int g = lane >> 5;
-    bf8 a[P2][TM][NS], b[P2][TN][NS];
 #pragma unroll
     for (int p = 0; p < P2; ++p)
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
 #pragma unroll
-            for (int i = 0; i < TM; ++i) a[p][i][t] = sA[((p * NS + t) * 2 + g) * BM + wm0 + i * 32 + (lane & 31)];
+            for (int i = 0; i < TM; ++i) f.a[p][i][t] = sA[((p * NS + t) * 2 + g) * BM + wm0 + i * 32 + (lane & 31)];
 #pragma unroll
-            for (int j = 0; j < TN; ++j) b[p][j][t] = sB[((p * NS + t) * 2 + g) * BN + wn0 + j * 32 + (lane & 31)];
+            for (int j = 0; j < TN; ++j) f.b[p][j][t] = sB[((p * NS + t) * 2 + g) * BN + wn0 + j * 32 + (lane & 31)];
         }
-    constexpr int PA[4] = {0, 1, 0, 1}, PB[4] = {0, 1, 1, 0};
+}
+
+template <int NS, int TM, int TN>
+__device__ inline void pk_mma_f(const PkFrags<NS, TM, TN>& f, f16v (&acc)[2][TM][TN]) {
+    if constexpr (TM == 1 && TN == 1) {
+        // every LDS read of the stage first, then the MFMAs
+        __builtin_amdgcn_sched_group_barrier(0x100, P2 * NS * (TM + TN), 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 4 * TM * TN * (NS == 3 ? 6 : 3), 0);
+    }
+    constexpr int PA[4] = {0, 1, 0, 1}, PB[4] = {0, 1, 1, 0}, DST[4] = {0, 0, 1, 1};
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
             for (int j = 0; j < TN; ++j) {
-                const bf8* x = a[PA[c]][i];
-                const bf8* y = b[PB[c]][j];
-                f16v d = acc[c][i][j];
+                bf8 x[NS];
+#pragma unroll
+                for (int t = 0; t < NS; ++t) x[t] = c == 1 ? neg_bf8(f.a[1][i][t]) : f.a[PA[c]][i][t];
+                const bf8* y = f.b[PB[c]][j];
+                f16v d = acc[DST[c]][i][j];
                 if constexpr (NS == 2) {
                     d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[1], y[0], d, 0, 0, 0);
                     d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[0], y[1], d, 0, 0, 0);
@@ -922,14 +948,21 @@ __device__ inline void pk_mma4(const bf8* sA, const bf8* sB, int wm0, int wn0, f
                     d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[0], y[1], d, 0, 0, 0);
                 }
                 d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[0], y[0], d, 0, 0, 0);
-                acc[c][i][j] = d;
+                acc[DST[c]][i][j] = d;
             }
+}
+
+template <int NS, int BM, int BN, int TM, int TN>
+__device__ inline void pk_mma4(const bf8* sA, const bf8* sB, int wm0, int wn0, f16v (&acc)[2][TM][TN]) {
+    PkFrags<NS, TM, TN> f;
+    pk_read<NS, BM, BN, TM, TN>(sA, sB, wm0, wn0, f);
+    pk_mma_f<NS, TM, TN>(f, acc);
 }
 
 // Double-buffered K loop over `nst` stages of two groups each.
 template <int NS, int BM, int BN, int TM, int TN>
 __device__ inline void pk_loop3(const __bf16* pa, size_t pa_pt, int XA, int m0, const __bf16* pb, size_t pb_pt,
-                                int XB, int n0, int nst, bf8* ring, int wm0, int wn0, f16v (&acc)[4][TM][TN]) {
+                                int XB, int n0, int nst, bf8* ring, int wm0, int wn0, f16v (&acc)[2][TM][TN]) {
     constexpr int SA = P2 * NS * 2 * BM, SB = P2 * NS * 2 * BN;
     pk_issue<NS, BM>(pa, pa_pt, XA, m0, 0, ring);
     pk_issue<NS, BN>(pb, pb_pt, XB, n0, 0, ring + SA);
@@ -947,45 +980,69 @@ __device__ inline void pk_loop3(const __bf16* pa, size_t pa_pt, int XA, int m0, 
     }
 }
 
-// K loop of stage 2 under the k <-> q-k pairing: pass 1 over the groups of
-// all kept k (A = conj C, rows i; B = T, columns (L, j)), pass 2 over the
-// paired k with the operands swapped (A = T columns (L, i), B = conj C rows j),
-// which adds the transposed terms of the partners.  The 4M products on the
-// (re, im) planes give the plain complex product of the two operands in both
-// passes.  Odd group counts are padded with group zg (zero in both operands).
-// Double-buffered stages of two groups.
-template <int NS, int BM, int BN, int TM, int TN, class KOf>
-__device__ inline void pk_loop_paired(const __bf16* pc2, size_t cst, int neo, const __bf16* ptt, size_t tst, int N2,
-                                      int L, int m0, int j0, int gpk, int zg, int npaired, int nself, KOf kof,
-                                      bf8* ring, int wm0, int wn0, f16v (&acc)[4][TM][TN]) {
-    constexpr int SA = P2 * NS * 2 * BM, SB = P2 * NS * 2 * BN;
-    const int n1 = (npaired + nself) * gpk, n2 = npaired * gpk;
-    const int s1 = (n1 + 1) / 2, nst = s1 + (n2 + 1) / 2;
-    // running position (no division per stage): pass, group j in the pass,
-    // its slot and group within the slot; stages of the current pass issued
-    int pass = 0, j = 0, slot = 0, gl = 0, cnt = 0;
-    auto next = [&](int& gc, int& gt) {
-        if (j < (pass ? n2 : n1)) {
-            gc = kof(slot) * gpk + gl;
-            gt = j;
-            ++j;
-            if (++gl == gpk) {
-                gl = 0;
-                ++slot;
+// Stage order of stage 2's two sums over the k groups: pass 0 walks the n1
+// groups of every kept slot, pass 1 the n2 groups of the paired slots (the
+// first n2 of pass 0's), two groups per stage, a zero group zg padding an odd
+// count.  Stages alternate between the passes while pass 1 has stages left, so
+// the workgroups of one fitting function read T for their i and for their j
+// columns at nearly the same time and T comes from HBM once per launch, not
+// once per pass.  Every stage-2 kernel walks this one order, so they give the
+// same bits for the same element.
+struct PairedWalk {
+    struct Cur {
+        int j, slot, gl;
+    };
+    int n1, n2, gpk, zg, s2, ist;
+    Cur c0, c1;
+    __device__ PairedWalk(int n1_, int n2_, int gpk_, int zg_)
+        : n1(n1_), n2(n2_), gpk(gpk_), zg(zg_), s2((n2_ + 1) / 2), ist(0), c0{0, 0, 0}, c1{0, 0, 0} {}
+    __device__ int stages() const { return (n1 + 1) / 2 + s2; }
+    __device__ int pass_of(int st) const { return st < 2 * s2 ? (st & 1) : 0; }
+    template <class KOf>
+    __device__ void take(Cur& c, int n, KOf kof, int& gc, int& gt) {
+        if (c.j < n) {
+            gc = kof(c.slot) * gpk + c.gl;
+            gt = c.j;
+            ++c.j;
+            if (++c.gl == gpk) {
+                c.gl = 0;
+                ++c.slot;
             }
         } else {
             gc = gt = zg;
         }
-    };
-    auto issue = [&](bf8* dst) {
-        if (pass == 0 && cnt == s1) {
-            pass = 1;
-            j = slot = gl = cnt = 0;
+    }
+    // the next stage in order: its pass, and its two groups of conj C and of T
+    template <class KOf>
+    __device__ int next(KOf kof, int& gc0, int& gt0, int& gc1, int& gt1) {
+        const int p = pass_of(ist++);
+        if (p) {
+            take(c1, n2, kof, gc0, gt0);
+            take(c1, n2, kof, gc1, gt1);
+        } else {
+            take(c0, n1, kof, gc0, gt0);
+            take(c0, n1, kof, gc1, gt1);
         }
+        return p;
+    }
+};
+
+// K loop of stage 2 under the k <-> q-k pairing: pass 0 over the groups of
+// all kept k (A = conj C, rows i; B = T, columns (L, j)), pass 1 over the
+// paired k with the operands swapped (A = T columns (L, i), B = conj C rows j),
+// which adds the transposed terms of the partners; stages in PairedWalk order.
+// The 4M products on the (re, im) planes give the plain complex product of the
+// two operands in both passes.  Double-buffered stages of two groups.
+template <int NS, int BM, int BN, int TM, int TN, class KOf>
+__device__ inline void pk_loop_paired(const __bf16* pc2, size_t cst, int neo, const __bf16* ptt, size_t tst, int N2,
+                                      int L, int m0, int j0, int gpk, int zg, int npaired, int nself, KOf kof,
+                                      bf8* ring, int wm0, int wn0, f16v (&acc)[2][TM][TN]) {
+    constexpr int SA = P2 * NS * 2 * BM, SB = P2 * NS * 2 * BN;
+    PairedWalk walk((npaired + nself) * gpk, npaired * gpk, gpk, zg);
+    const int nst = walk.stages();
+    auto issue = [&](bf8* dst) {
         int gc0, gt0, gc1, gt1;
-        next(gc0, gt0);
-        next(gc1, gt1);
-        ++cnt;
+        const int pass = walk.next(kof, gc0, gt0, gc1, gt1);
         if (!pass) {
             pk_issue_g<NS, BM>(pc2, cst, neo, m0, gc0, gc1, dst);
             pk_issue_g<NS, BN>(ptt, tst, N2, L * neo + j0, gt0, gt1, dst + SA);
@@ -1037,9 +1094,9 @@ __global__ void __launch_bounds__(256) k_xf1_pk(Mesh mesh, int q, int naux, int 
     const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
     const __bf16* pa = plm + ((size_t)q * nk + k) * P2 * NS * (size_t)ngv * M1 * 8;
     const __bf16* pb = pc1 + (size_t)kmq * P2 * NS * (size_t)ngv * NB * 8;
-    f16v acc[4][TM][TN];
+    f16v acc[2][TM][TN];
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -1068,10 +1125,8 @@ __global__ void __launch_bounds__(256) k_xf1_pk(Mesh mesh, int q, int naux, int 
                     for (int r = 0; r < 4; ++r) {
                         // 4M: re = Ar Br - Ai Bi, im = Ar Bi + Ai Br
                         const int ra = 4 * qq + r, rb = 4 * (qq + 1) + r;
-                        const float va = p3 == 0 ? acc[0][i][j][ra] - acc[1][i][j][ra]
-                                                 : acc[2][i][j][ra] + acc[3][i][j][ra];
-                        const float vb = p3 == 0 ? acc[0][i][j][rb] - acc[1][i][j][rb]
-                                                 : acc[2][i][j][rb] + acc[3][i][j][rb];
+                        const float va = acc[p3][i][j][ra];
+                        const float vb = acc[p3][i][j][rb];
                         mine[r] = h == 0 ? va : vb;
                         send[r] = h == 0 ? vb : va;
                     }
@@ -1114,44 +1169,94 @@ __global__ void __launch_bounds__(256) k_xf1_pk(Mesh mesh, int q, int naux, int 
 // the second sum being the transposed terms of the partners q-k (a symmetric
 // rank-2k update).  Tiles of 64 x 64 per L; tiles with every i < every j are
 // skipped.  Group zg is a zero group of both operands (pads odd counts).
+
+// One stage of a stage-2 operand region of ROWS rows made of ROWS / 64
+// segments of 64 rows starting at x00 and x01 (rows clamped to X - 1),
+// laid out [plane*NS + part][group][ROWS] as pk_mma4 reads it; NW waves share
+// the loads.
+template <int NS, int ROWS, int NW>
+__device__ inline void pk_issue_seg(const __bf16* base, size_t pt_stride, int X, int x00, int x01, int g0, int g1,
+                                    bf8* dst) {
+    static_assert(ROWS == 64 || ROWS == 128, "one or two segments");
+    constexpr int CH = P2 * NS * 2 * ROWS;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int first = wave * 64; first < CH; first += 64 * NW) {
+        const int pt = first / (2 * ROWS), g = (first / ROWS) % 2, row0 = first % ROWS;
+        const int x = min((row0 >= 64 ? x01 : x00) + (row0 & 63) + lane, X - 1);
+        const __bf16* src = base + ((size_t)pt * pt_stride + (size_t)(g ? g1 : g0) * X + x) * 8;
+        __builtin_amdgcn_global_load_lds((const void*)src, DMET_LDS_PTR(dst + first), 16, 0, 0);
+    }
+}
+
+// Stage 2 for one q and spin on two fitting functions per workgroup: the 64 x 64
+// tile (i, j) of X_L for L = L0 and L0 + 1, eight waves with a 32 x 32 sub-tile
+// each (wave w: L0 + w / 4, rows 32 ((w / 2) % 2), columns 32 (w % 2)).  The conj C
+// rows of a stage serve both fitting functions, so a stage stages 192 rows for
+// 192 MFMAs (128 rows for 96 with one fitting function), and two workgroups fit
+// a CU (four waves per SIMD).  Stages in PairedWalk order with the products of
+// pk_mma4 per element: the same bits as the batched kernel k_xf2_batched.
 template <int NS>
-__global__ void __launch_bounds__(256) k_xf2_pk(int naux, int neo, int ng2, int gpk, int zg, KSlots ks,
-                                                int self_conj, size_t zrow0, float wq,
-                                                const __bf16* __restrict__ pc2, const __bf16* __restrict__ ptt,
-                                                float* __restrict__ z, size_t ldz) {
-    constexpr int BM = 64, BN = 64, TM = 1, TN = 1;
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4))) k_xf2_pk2(int naux, int neo, int ng2, int gpk, int zg, KSlots ks,
+                                                 int self_conj, size_t zrow0, float wq,
+                                                 const __bf16* __restrict__ pc2, const __bf16* __restrict__ ptt,
+                                                 float* __restrict__ z, size_t ldz) {
+    constexpr int RC = 64, RT = 128;                  // conj C rows and T columns (two L) per stage
+    constexpr int SC = P2 * NS * 2 * RC, ST = P2 * NS * 2 * RT;
     extern __shared__ __align__(16) bf8 ring[];
-    const int njt = (neo + BN - 1) / BN, nit = (neo + BM - 1) / BM;
-    // tile id -> (L, jt, it); consecutive ids share L (and so T columns in L2)
+    const int nt = (neo + 63) / 64;
     const long tid_ = xcd_logical(blockIdx.x, gridDim.x);
-    const int per_l = njt * nit;
-    const int L = (int)(tid_ / per_l), rem = (int)(tid_ % per_l);
-    const int jt = rem / nit, it = rem % nit;
-    if (L >= naux) return;
-    const int m0 = it * BM, j0 = jt * BN;
-    if (m0 + BM - 1 < j0) return;
+    const int per_l = nt * nt;
+    const int LP = (int)(tid_ / per_l), rem = (int)(tid_ % per_l);
+    const int jt = rem / nt, it = rem % nt;
+    const int L0 = 2 * LP;
+    if (L0 >= naux) return;
+    const int m0 = it * 64, j0 = jt * 64;
+    if (m0 + 63 < j0) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
+    const int lw = wave >> 2, si = (wave >> 1) & 1, sj = wave & 1;
+    const int L1 = min(L0 + 1, naux - 1);              // odd naux: the second half is computed, not stored
     const int N2 = naux * neo;
-    // the slot -> k table in LDS: read there, a lookup per stage costs no memory round trip
     __shared__ short ksh[KP_MAX];
     for (int t = threadIdx.x; t < ks.npaired + ks.nself; t += blockDim.x) ksh[t] = ks.k[t];
     __syncthreads();
-    f16v acc[4][TM][TN];
+    f16v acc[2][1][1];
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[p][0][0][r] = 0.f;
-    pk_loop_paired<NS, BM, BN, TM, TN>(pc2, (size_t)ng2 * neo, neo, ptt, (size_t)ng2 * N2, N2, L, m0, j0, gpk, zg,
-                                       ks.npaired, ks.nself, [&](int sl) { return (int)ksh[sl]; }, ring, wm0, wn0,
-                                       acc);
+    const size_t cst = (size_t)ng2 * neo, tst = (size_t)ng2 * N2;
+    PairedWalk walk((ks.npaired + ks.nself) * gpk, ks.npaired * gpk, gpk, zg);
+    const int nst = walk.stages();
+    auto kof = [&](int sl) { return (int)ksh[sl]; };
+    auto issue = [&](bf8* dst) {
+        int gc0, gt0, gc1, gt1;
+        if (!walk.next(kof, gc0, gt0, gc1, gt1)) {   // A = conj C rows i, B = T columns (L, j)
+            pk_issue_seg<NS, RC, 8>(pc2, cst, neo, m0, m0, gc0, gc1, dst);
+            pk_issue_seg<NS, RT, 8>(ptt, tst, N2, L0 * neo + j0, L1 * neo + j0, gt0, gt1, dst + SC);
+        } else {                                      // A = T columns (L, i), B = conj C rows j
+            pk_issue_seg<NS, RT, 8>(ptt, tst, N2, L0 * neo + m0, L1 * neo + m0, gt0, gt1, dst);
+            pk_issue_seg<NS, RC, 8>(pc2, cst, neo, j0, j0, gc0, gc1, dst + ST);
+        }
+    };
+    issue(ring);
+    for (int st = 0; st < nst; ++st) {
+        bf8* cur = ring + (size_t)(st & 1) * (SC + ST);
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // own loads of stage st landed
+        __builtin_amdgcn_s_barrier();         // everyone's loads landed; stage st-1 fully read
+        __builtin_amdgcn_sched_barrier(0);
+        if (st + 1 < nst) issue(ring + (size_t)((st + 1) & 1) * (SC + ST));
+        if (!walk.pass_of(st)) pk_mma4<NS, RC, RT, 1, 1>(cur, cur + SC, 32 * si, 64 * lw + 32 * sj, acc);
+        else pk_mma4<NS, RT, RC, 1, 1>(cur, cur + ST, 64 * lw + 32 * si, 32 * sj, acc);
+    }
+    const int L = L0 + lw;
+    if (L >= naux) return;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        const int i = m0 + wm0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int j = j0 + wn0 + (lane & 31);
+        const int i = m0 + 32 * si + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int j = j0 + 32 * sj + (lane & 31);
         if (i >= neo || j >= neo || j > i) continue;
         const size_t pair = (size_t)i * (i + 1) / 2 + j;
-        const float xr = acc[0][0][0][r] - acc[1][0][0][r], xi = acc[2][0][0][r] + acc[3][0][0][r];
+        const float xr = acc[0][0][0][r], xi = acc[1][0][0][r];
         if (self_conj) {
             z[(zrow0 + L) * ldz + pair] = wq * xr;
         } else {
@@ -1160,6 +1265,9 @@ __global__ void __launch_bounds__(256) k_xf2_pk(int naux, int neo, int ng2, int 
         }
     }
 }
+
+template <int NS>
+constexpr size_t xf2_pk2_lds() { return (size_t)2 * P2 * NS * 2 * (64 + 128) * 16; }
 
 // ------------------------------------------------------------------ batched pipeline
 // Per-fragment data read by the batched kernels.
@@ -1219,9 +1327,9 @@ __global__ void __launch_bounds__(256) k_xf1_batched(Mesh mesh, int q, int naux,
     const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
     const __bf16* pa = plm + ((size_t)q * nk + k) * P2 * NS * (size_t)ngv * M1 * 8;
     const __bf16* pb = pc1 + (size_t)kmq * P2 * NS * (size_t)ngv * NB * 8;
-    f16v acc[4][TM][TN];
+    f16v acc[2][TM][TN];
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -1248,10 +1356,8 @@ __global__ void __launch_bounds__(256) k_xf1_batched(Mesh mesh, int q, int naux,
                     for (int r = 0; r < 4; ++r) {
                         // 4M: re = Ar Br - Ai Bi, im = Ar Bi + Ai Br
                         const int ra = 4 * qq + r, rb = 4 * (qq + 1) + r;
-                        const float va = p3 == 0 ? acc[0][i][j][ra] - acc[1][i][j][ra]
-                                                 : acc[2][i][j][ra] + acc[3][i][j][ra];
-                        const float vb = p3 == 0 ? acc[0][i][j][rb] - acc[1][i][j][rb]
-                                                 : acc[2][i][j][rb] + acc[3][i][j][rb];
+                        const float va = acc[p3][i][j][ra];
+                        const float vb = acc[p3][i][j][rb];
                         mine[r] = h == 0 ? va : vb;
                         send[r] = h == 0 ? vb : va;
                     }
@@ -1306,9 +1412,9 @@ __global__ void __launch_bounds__(256) k_xf2_batched(int nitems, const BItem2* _
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
     const int N2 = naux * neo;
-    f16v acc[4][TM][TN];
+    f16v acc[2][TM][TN];
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[p][0][0][r] = 0.f;
     __shared__ short ksh[KP_MAX];   // the slot -> k table, staged once
@@ -1324,7 +1430,7 @@ __global__ void __launch_bounds__(256) k_xf2_batched(int nitems, const BItem2* _
         const int j = j0 + wn0 + (lane & 31);
         if (i >= neo || j >= neo || j > i) continue;
         const size_t pair = (size_t)i * (i + 1) / 2 + j;
-        const float xr = acc[0][0][0][r] - acc[1][0][0][r], xi = acc[2][0][0][r] + acc[3][0][0][r];
+        const float xr = acc[0][0][0][r], xi = acc[1][0][0][r];
         if (qb.self_conj) {
             fr.z[(qb.zrow0 + L) * ldz + pair] = qb.wq * xr;
         } else {
@@ -1378,42 +1484,21 @@ __global__ void __launch_bounds__(256) k_xf2_batched_l4(int nitems, const BItem2
     const int m0 = item.it * L4_ROWS, j0 = item.jt * L4_ROWS;
     const int N2 = naux * neo;
     const size_t cst = (size_t)fr.ng2 * neo, tst = (size_t)fr.ng2 * N2;
-    const int gpk = qb.gpk, zg = qb.zg;
-    const int n1 = (qb.npaired + qb.nself) * gpk, n2 = qb.npaired * gpk;
-    const int s1 = (n1 + 1) / 2, nst = s1 + (n2 + 1) / 2;
     __shared__ short ksh[KP_MAX];   // the slot -> k table, staged once
     for (int t = threadIdx.x; t < qb.npaired + qb.nself; t += blockDim.x) ksh[t] = qb.k[t];
     __syncthreads();
-    f16v acc[4][1][1];
+    f16v acc[2][1][1];
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < 2; ++c)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[c][0][0][r] = 0.f;
-    // running group walk (as in pk_loop_paired)
-    int pass = 0, j = 0, slot = 0, gl = 0, cnt = 0;
-    auto next = [&](int& gc, int& gt) {
-        if (j < (pass ? n2 : n1)) {
-            gc = (int)ksh[slot] * gpk + gl;
-            gt = j;
-            ++j;
-            if (++gl == gpk) {
-                gl = 0;
-                ++slot;
-            }
-        } else {
-            gc = gt = zg;
-        }
-    };
+    PairedWalk walk((qb.npaired + qb.nself) * qb.gpk, qb.npaired * qb.gpk, qb.gpk, qb.zg);
+    const int nst = walk.stages();
+    auto kof = [&](int sl) { return (int)ksh[sl]; };
     // wave w stages the T tile of its own L; wave 0 also the conj C tile
     auto issue = [&](bf8* dst) {
-        if (pass == 0 && cnt == s1) {
-            pass = 1;
-            j = slot = gl = cnt = 0;
-        }
         int gc0, gt0, gc1, gt1;
-        next(gc0, gt0);
-        next(gc1, gt1);
-        ++cnt;
+        const int pass = walk.next(kof, gc0, gt0, gc1, gt1);
         const int xc = pass ? j0 : m0;                        // conj C rows
         const int xt = Lc * neo + (pass ? m0 : j0);            // T columns of this wave's L
         if (wave == 0) l4_issue<NS>(fr.pc2, cst, neo, xc, gc0, gc1, dst);
@@ -1428,7 +1513,7 @@ __global__ void __launch_bounds__(256) k_xf2_batched_l4(int nitems, const BItem2
         if (st + 1 < nst) issue(ring + (size_t)((st + 1) & 1) * STAGE);
         const bf8* sc = cur;                      // conj C tile
         const bf8* stt = cur + (1 + wave) * TCH;  // T tile of this wave's L
-        if (st < s1) pk_mma4<NS, L4_ROWS, L4_ROWS, 1, 1>(sc, stt, 0, 0, acc);
+        if (!walk.pass_of(st)) pk_mma4<NS, L4_ROWS, L4_ROWS, 1, 1>(sc, stt, 0, 0, acc);
         else pk_mma4<NS, L4_ROWS, L4_ROWS, 1, 1>(stt, sc, 0, 0, acc);
     }
     if (L >= naux) return;
@@ -1439,7 +1524,7 @@ __global__ void __launch_bounds__(256) k_xf2_batched_l4(int nitems, const BItem2
         const int jj = j0 + (lane & 31);
         if (i >= neo || jj >= neo || jj > i) continue;
         const size_t pair = (size_t)i * (i + 1) / 2 + jj;
-        const float xr = acc[0][0][0][r] - acc[1][0][0][r], xi = acc[2][0][0][r] + acc[3][0][0][r];
+        const float xr = acc[0][0][0][r], xi = acc[1][0][0][r];
         if (qb.self_conj) {
             fr.z[(qb.zrow0 + L) * ldz + pair] = qb.wq * xr;
         } else {
@@ -1787,9 +1872,10 @@ static dmet_status xform_packed(const EriPlan& p, const void* lmunu, const doubl
     }
     DMET_LAUNCH_CHECK("pack inputs");
     auto k1 = k_xf1_pk<NS>;
-    auto k2 = k_xf2_pk<NS>;
+    auto k2 = k_xf2_pk2<NS>;
+    DMET_HIP(hipFuncSetAttribute((const void*)k2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)xf2_pk2_lds<NS>()));
     DMET_HIP(hipFuncSetAttribute((const void*)k1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)xf1_lds<NS>()));
-    DMET_HIP(hipFuncSetAttribute((const void*)k2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)xf2_lds<NS>()));
+
     const char* n1 = NS == 3 ? "xform1_bf16x6" : "xform1_bf16x3";
     const char* n2 = NS == 3 ? "xform2_bf16x6" : "xform2_bf16x3";
     const size_t ldz = (size_t)p.npair;
@@ -1807,8 +1893,8 @@ static dmet_status xform_packed(const EriPlan& p, const void* lmunu, const doubl
         DMET_LAUNCH_CHECK(n1);
         for (int s = 0; s < p.nspin; ++s) {
             ProfScope ps2(n2, st);
-            const long nb2 = ((long)p.naux * njt * nit + NXCD - 1) / NXCD * NXCD;
-            k2<<<dim3((unsigned)nb2), 256, xf2_lds<NS>(), st>>>(p.naux, p.neo, d.ng2, gpk, zg, ks, qb.self_conj,
+            const long nb2 = ((long)((p.naux + 1) / 2) * njt * nit + NXCD - 1) / NXCD * NXCD;
+            k2<<<dim3((unsigned)nb2), 512, xf2_pk2_lds<NS>(), st>>>(p.naux, p.neo, d.ng2, gpk, zg, ks, qb.self_conj,
                                                                 qb.zrow0, (float)qb.weight, pc2 + s * c2_spin,
                                                                 ptt + s * t_spin, z + (size_t)s * p.zrows * ldz, ldz);
             ps2.stop();
