@@ -279,8 +279,10 @@ dmet_status dmet_transform_eri_df(const dmet_lattice* lat, int neo, const void* 
  * Plane-wave (FFTDF) embedding ERIs, App. B, Eq. "FFTDF" and Alg. 2.
  *
  * The fitting functions are the points r of a real-space grid of the
- * reference cell (orthorhombic, `cell` lengths in bohr, n[0] x n[1] x n[2]
- * points, row-major), so lat->naux must equal n[0] n[1] n[2].  Input:
+ * reference cell, r = sum_d (t_d / n[d]) a_d for t_d = 0 .. n[d] - 1 (n[0] x
+ * n[1] x n[2] points, row-major over t), with a_d the lattice vectors (the rows
+ * of `cell`, bohr; any non-degenerate cell, orthorhombic or not), so
+ * lat->naux must equal n[0] n[1] n[2].  Input:
  *   rho [N_k q][N_k k][nr][nao][nao]  (complex128 or complex64, per dtype)
  *       rho[q][k][r][mu][nu] = (r | mu k, nu k-q), the AO pair density on the
  *       grid with the conventions of dmet_transform_eri (k-q wrapped per axis);
@@ -290,16 +292,22 @@ dmet_status dmet_transform_eri_df(const dmet_lattice* lat, int neo, const void* 
  * grid with the phase of q (W(G) = sum_r e^{+i(q+G).r} X(r)), weighted by the
  * Coulomb kernel 4 pi / (Omega |q+G|^2) (the q+G = 0 term dropped) and
  * contracted:
- *   (ij|kl) = dV^2 / (N_k Omega) sum_{q,G} 4 pi/|q+G|^2 conj(W_ij) W_kl,
- * dV = Omega / nr, i.e. the Coulomb integral of the EO pair densities on the
- * Born-von Karman supercell.  Outputs as dmet_transform_eri (s8 / s4 float64).
- * FP64 throughout.  Returns DMET_E_ARG for a grid that does not match naux or
- * a non-positive cell, DMET_E_WORKSPACE if the workspace is too small.
+ *   (ij|kl) = dV^2 / (N_k Omega) sum_{q,G} 4 pi/|q+G|^2 Re[conj(W_ij) W_kl],
+ * dV = Omega / nr, Omega = |det cell|, i.e. the Coulomb integral of the EO
+ * pair densities on the Born-von Karman supercell.  The supercell frequency j_d
+ * along axis d is taken in (-L/2, L/2], L = N_d n[d] (the FFT order; an even L
+ * keeps -L/2), and q + G = sum_d (j_d / N_d) b_d with a_c . b_d = 2 pi delta_cd.
+ * On a non-orthogonal cell an even L leaves that Nyquist plane without a -G
+ * partner of the same |q+G|^2, and the result is the real part of a form that
+ * is then not exactly Hermitian: odd N_d n[d] avoid this.  Outputs as
+ * dmet_transform_eri (s8 / s4 float64).  FP64 throughout.  Returns DMET_E_ARG
+ * for a grid that does not match naux or a cell whose vectors are not finite
+ * or are linearly dependent, DMET_E_WORKSPACE if the workspace is too small.
  * Asynchronous; the workspace must stay valid until the work completes.
  * ------------------------------------------------------------------------- */
 typedef struct {
     int n[3];          /* grid points per cell axis */
-    double cell[3];    /* orthorhombic cell lengths (bohr) */
+    double cell[3][3]; /* lattice vectors a_1, a_2, a_3 as rows (bohr); diagonal for an orthorhombic cell */
 } dmet_pw_grid;
 
 dmet_status dmet_transform_eri_fftdf_workspace(const dmet_lattice* lat, const dmet_pw_grid* grid, int neo,

@@ -333,11 +333,24 @@ def fftdf_frequencies(kmesh, grid_n, q):
     return np.stack([jx.ravel(), jy.ravel(), jz.ravel()], axis=1)
 
 
+def cell_vectors(cell):
+    """Lattice vectors of the reference cell as the rows a_1, a_2, a_3 (bohr);
+    three numbers are the edge lengths of an orthorhombic cell."""
+    a = np.asarray(cell, float)
+    return np.diag(a) if a.shape == (3,) else a.reshape(3, 3)
+
+
+def reciprocal_vectors(cell):
+    """Rows b_1, b_2, b_3 of the reciprocal lattice, a_i . b_j = 2 pi delta_ij."""
+    return 2.0 * np.pi * np.linalg.inv(cell_vectors(cell)).T
+
+
 def coulomb_kernel(kmesh, grid_n, cell, q):
-    """4 pi / |q + G|^2 on the cell grid of G (orthorhombic cell lengths in
-    bohr); the q + G = 0 term is dropped (neutralising background)."""
+    """4 pi / |q + G|^2 on the cell grid of G; the q + G = 0 term is dropped
+    (neutralising background).  A supercell frequency j (per axis, as
+    fftdf_frequencies orders them) is the vector q + G = sum_d (j_d / N_d) b_d."""
     j = fftdf_frequencies(kmesh, grid_n, q).astype(float)
-    kvec = 2.0 * np.pi * j / (np.asarray(kmesh, float) * np.asarray(cell, float))[None, :]
+    kvec = (j / np.asarray(kmesh, float)[None, :]) @ reciprocal_vectors(cell)
     k2 = (kvec * kvec).sum(axis=1)
     out = np.zeros_like(k2)
     nz = k2 > 0
@@ -361,7 +374,7 @@ def alg2_eri(rho, c_k_a, kmesh, grid_n, cell, c_k_b=None):
     nk = rho.shape[0]
     grid_n = tuple(grid_n)
     nr = int(np.prod(grid_n))
-    omega = float(np.prod(cell))
+    omega = abs(float(np.linalg.det(cell_vectors(cell))))
     dv = omega / nr
     idx = np.indices(grid_n).reshape(3, -1).T
     eri = 0

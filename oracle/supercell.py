@@ -162,11 +162,16 @@ def fftdf_eri(chi_sup, c_sup_a, kmesh, grid_n, cell, c_sup_b=None):
     shape = tuple(int(a) * int(b) for a, b in zip(kmesh, grid_n))
     assert nx == int(np.prod(shape))
     cell = np.asarray(cell, float)
-    omega_sup = float(np.prod(cell)) * nk
-    dv = float(np.prod(cell)) / int(np.prod(grid_n))
-    freqs = [np.fft.fftfreq(shape[d], 1.0 / shape[d]) for d in range(3)]
-    g = [2.0 * np.pi * freqs[d] / (kmesh[d] * cell[d]) for d in range(3)]
-    g2 = g[0][:, None, None] ** 2 + g[1][None, :, None] ** 2 + g[2][None, None, :] ** 2
+    a_cell = np.diag(cell) if cell.shape == (3,) else cell.reshape(3, 3)   # rows: lattice vectors
+    a_sup = np.asarray(kmesh, float)[:, None] * a_cell                      # supercell lattice vectors
+    omega_sup = abs(float(np.linalg.det(a_sup)))
+    dv = omega_sup / nx
+    # plane waves of the supercell: G = sum_d f_d b_d, b_d the supercell's reciprocal vectors
+    b_sup = 2.0 * np.pi * np.linalg.inv(a_sup).T
+    freqs = np.stack(np.meshgrid(*[np.fft.fftfreq(shape[d], 1.0 / shape[d]) for d in range(3)], indexing="ij"),
+                     axis=-1).reshape(-1, 3)
+    gvec = freqs @ b_sup
+    g2 = (gvec * gvec).sum(axis=1).reshape(shape)
     kern = np.zeros_like(g2)
     kern[g2 > 0] = 4.0 * np.pi / g2[g2 > 0]
 

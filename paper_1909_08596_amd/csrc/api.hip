@@ -332,10 +332,22 @@ static dmet_status check_pw(const dmet_lattice* lat, const dmet_pw_grid* grid) {
     long nr = 1;
     for (int a = 0; a < 3; ++a) {
         if (grid->n[a] < 1) return fail(DMET_E_ARG, "grid points per axis must be >= 1");
-        if (!(grid->cell[a] > 0.0)) return fail(DMET_E_ARG, "cell lengths must be positive");
         nr *= grid->n[a];
     }
     if (nr != lat->naux) return fail(DMET_E_ARG, "naux must equal the number of grid points");
+    // volume against the product of the vector lengths: a flat or degenerate cell is refused
+    const double(*c)[3] = grid->cell;
+    double len = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        for (int b = 0; b < 3; ++b)
+            if (!std::isfinite(c[a][b])) return fail(DMET_E_ARG, "cell vectors must be finite");
+        len *= sqrt(c[a][0] * c[a][0] + c[a][1] * c[a][1] + c[a][2] * c[a][2]);
+    }
+    const double det = c[0][0] * (c[1][1] * c[2][2] - c[1][2] * c[2][1]) -
+                       c[0][1] * (c[1][0] * c[2][2] - c[1][2] * c[2][0]) +
+                       c[0][2] * (c[1][0] * c[2][1] - c[1][1] * c[2][0]);
+    if (!(len > 0.0) || !(fabs(det) > 1e-10 * len))
+        return fail(DMET_E_ARG, "cell vectors must be linearly independent");
     return DMET_OK;
 }
 

@@ -10,7 +10,9 @@
 // its line, the phases read from a table of the L = N_d n_d roots of unity of
 // the supercell axis held in LDS), and scaled by
 // dV sqrt(4 pi / (Omega |q+G|^2)) into two real rows (Re W, Im W) per G.  The
-// FP64 contraction of those rows gives the ERIs.
+// FP64 contraction of those rows gives the ERIs.  The DFT runs in fractional
+// coordinates, so only |q+G|^2 (through the reciprocal vectors) and Omega see
+// the shape of the cell.
 #include <math.h>
 
 #include <algorithm>
@@ -33,20 +35,39 @@ struct PwAxis {
 
 struct PwScale {
     int n[3], nmesh[3], m[3];
-    double cell[3];
+    double b[3][3];    // reciprocal vectors of the reference cell (rows), a_c . b_d = 2 pi delta_cd
     double dv, omega;
 };
 
-// dV sqrt(4 pi / (Omega |q+G|^2)) for the grid frequency x (0 at q+G = 0)
+// dV sqrt(4 pi / (Omega |q+G|^2)) for the grid frequency x (0 at q+G = 0):
+// q + G = sum_d (j_d / N_d) b_d with j_d the supercell frequency in FFT order
 __device__ inline double pw_scale(const PwScale& k, const int x[3]) {
-    double k2 = 0.0;
+    double v[3] = {0.0, 0.0, 0.0};
     for (int d = 0; d < 3; ++d) {
         const long L = (long)k.nmesh[d] * k.n[d], j = (long)k.nmesh[d] * x[d] + k.m[d];
         const long jp = j <= (L - 1) / 2 ? j : j - L;   // supercell FFT order
-        const double kd = 2.0 * M_PI * (double)jp / ((double)k.nmesh[d] * k.cell[d]);
-        k2 += kd * kd;
+        const double f = (double)jp / (double)k.nmesh[d];
+        for (int c = 0; c < 3; ++c) v[c] += f * k.b[d][c];
     }
+    const double k2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
     return k2 > 0.0 ? k.dv * sqrt(4.0 * M_PI / (k.omega * k2)) : 0.0;
+}
+
+// Reciprocal vectors (rows of 2 pi (A^-1)^T, A the lattice vectors as rows)
+// and |det A|, by cofactors.
+void reciprocal(const double (&a)[3][3], double (&b)[3][3], double& vol) {
+    const double det = a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
+                       a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+                       a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+    // b_d = 2 pi (a_{d+1} x a_{d+2}) / det
+    for (int d = 0; d < 3; ++d) {
+        const double* u = a[(d + 1) % 3];
+        const double* w = a[(d + 2) % 3];
+        b[d][0] = 2.0 * M_PI * (u[1] * w[2] - u[2] * w[1]) / det;
+        b[d][1] = 2.0 * M_PI * (u[2] * w[0] - u[0] * w[2]) / det;
+        b[d][2] = 2.0 * M_PI * (u[0] * w[1] - u[1] * w[0]) / det;
+    }
+    vol = fabs(det);
 }
 
 // One axis of W: out[.., g, ..][p] = sum_t exp(+2 pi i (N g + m) t / (N n)) in[.., t, ..][p]
@@ -165,9 +186,8 @@ dmet_status fftdf_eri(const EriPlan& p, const dmet_pw_grid* grid, const void* rh
     for (int a = 0; a < 3; ++a) {
         ks.n[a] = grid->n[a];
         ks.nmesh[a] = p.mesh.n[a];
-        ks.cell[a] = grid->cell[a];
     }
-    ks.omega = grid->cell[0] * grid->cell[1] * grid->cell[2];
+    reciprocal(grid->cell, ks.b, ks.omega);
     ks.dv = ks.omega / (double)d.nr;
     {   // root tables above 64 KB of LDS need the larger dynamic allocation
         int lmax = 0;

@@ -56,14 +56,27 @@ def lattice(kmesh: Sequence[int], nao: int, naux: int = 1, nspin: int = 1) -> La
 
 
 class PwGrid(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_int * 3), ("cell", ctypes.c_double * 3)]
+    _fields_ = [("n", ctypes.c_int * 3), ("cell", (ctypes.c_double * 3) * 3)]
 
 
-def pw_grid(n: Sequence[int], cell: Sequence[float]) -> PwGrid:
+def pw_grid(n: Sequence[int], cell) -> PwGrid:
+    """Grid of the plane-wave entry points: n points per axis; cell the three
+    lattice vectors as rows (bohr), or three edge lengths of an orthorhombic cell."""
     g = PwGrid()
+    rows = list(cell)
+    if len(rows) != 3:
+        raise ValueError("cell: three edge lengths or three lattice vectors")
     for d in range(3):
         g.n[d] = int(n[d])
-        g.cell[d] = float(cell[d])
+        if isinstance(rows[d], (int, float)):
+            for c in range(3):
+                g.cell[d][c] = float(rows[d]) if c == d else 0.0
+        else:
+            vec = [float(x) for x in rows[d]]
+            if len(vec) != 3:
+                raise ValueError("cell: each lattice vector has three components")
+            for c in range(3):
+                g.cell[d][c] = vec[c]
     return g
 
 
@@ -375,8 +388,9 @@ def dmet_transform_eri_fftdf(kmesh, nao, grid_n, cell, rho: torch.Tensor, c_k: t
                              workspace: Optional[torch.Tensor] = None, stream=None):
     """Plane-wave (FFTDF) embedding ERIs (App. B, Alg. 2), FP64.  rho is the
     AO pair density on the cell grid [q][k][r][mu][nu] = (r|mu k, nu k-q),
-    grid_n the grid points per axis and cell the orthorhombic cell lengths
-    (bohr).  Same return value as dmet_transform_eri."""
+    grid_n the grid points per axis and cell the three lattice vectors as rows
+    (bohr) or the three edge lengths of an orthorhombic cell.  Same return value
+    as dmet_transform_eri."""
     lib = load()
     nr = int(grid_n[0]) * int(grid_n[1]) * int(grid_n[2])
     nspin, neo = _eri_inputs(kmesh, nao, nr, rho, c_k, "rho")

@@ -361,25 +361,36 @@ def batched_fragments(nfrag=64, seed=1004, neo_range=(20, 200), lattices=("b222"
 
 
 # --------------------------------------------------------------------------
-# Plane-wave (FFTDF) workloads: Gaussian AOs sampled on a real-space grid of an
-# orthorhombic cell.  The "fitting functions" are the grid points r of the
-# reference cell; the 3-index input is the AO pair density
+# Plane-wave (FFTDF) workloads: Gaussian AOs sampled on a real-space grid of a
+# cell (orthorhombic, or any lattice given by its three vectors).  The "fitting
+# functions" are the grid points r of the reference cell; the 3-index input is
+# the AO pair density
 #   rho[q][k][r][mu][nu] = sum_{R1,R2} e^{-i k.R1} e^{+i (k-q).R2} chi_mu(r - R1) chi_nu(r - R2)
 #                        = A_mu(k, r) conj(A_nu(k-q, r)),  A_mu(k, r) = sum_R e^{-i k.R} chi_mu(r - R),
-# with chi_mu periodic on the Born-von Karman supercell (minimum image).
+# with chi_mu periodic on the Born-von Karman supercell (each displacement wrapped to the nearest image in supercell fractional coordinates).
 # --------------------------------------------------------------------------
 @dataclass(frozen=True)
 class FftGrid:
     n: tuple             # grid points per cell axis
-    cell: tuple          # orthorhombic cell lengths (bohr)
+    cell: tuple          # orthorhombic edge lengths, or the lattice vectors as rows (bohr)
 
     @property
     def nr(self) -> int:
         return int(np.prod(self.n))
 
     @property
+    def lattice(self) -> np.ndarray:
+        a = np.asarray(self.cell, float)
+        return np.diag(a) if a.shape == (3,) else a.reshape(3, 3)
+
+    @property
     def volume(self) -> float:
-        return float(np.prod(self.cell))
+        return abs(float(np.linalg.det(self.lattice)))
+
+
+# hexagonal reference cell (the shape of the paper's hBN layer cell): a_1 = (a, 0, 0),
+# a_2 = (a/2, a sqrt(3)/2, 0), a_3 = (0, 0, c)
+HEX_CELL = ((2.6, 0.0, 0.0), (1.3, 1.3 * 3 ** 0.5, 0.0), (0.0, 0.0, 3.2))
 
 
 # (workload, grid): naux of the workload is the number of grid points
@@ -387,6 +398,9 @@ FFT_CONFIGS = {
     "fft_tiny": (Workload("fft_tiny", (2, 2, 1), 4, 216, 4, 4, 1, 1.5, 1010), FftGrid((6, 6, 6), (3.0, 3.0, 3.0))),
     "fft_odd": (Workload("fft_odd", (3, 2, 1), 5, 240, 5, 5, 1, 1.5, 1011), FftGrid((6, 5, 8), (3.0, 2.6, 3.4))),
     "fft_si": (Workload("fft_si", (2, 2, 2), 26, 4096, 26, 26, 1, 2.0, 1012), FftGrid((16, 16, 16), (5.1, 5.1, 5.1))),
+    # odd N_d n_d on every axis: with a non-orthogonal cell the Nyquist plane of an even
+    # axis has no -G partner of the same |q+G|^2
+    "fft_hex": (Workload("fft_hex", (3, 3, 1), 5, 175, 5, 5, 1, 1.5, 1015), FftGrid((5, 5, 7), HEX_CELL)),
 }
 
 
@@ -401,23 +415,25 @@ def _fft_gaussians(wl: Workload, grid: FftGrid):
 
 def _chi_on_points(wl: Workload, grid: FftGrid, pts_cart, shift_cells):
     """chi_mu(x - R) for cartesian points x [np][3] and cell shifts R [nR][3]
-    (integer cell coordinates): [nR][nao][np], minimum image on the supercell."""
+    (integer cell coordinates): [nR][nao][np], the image nearest in supercell fractional coordinates."""
     centres, alpha, norm = _fft_gaussians(wl, grid)
-    cell = np.asarray(grid.cell)
-    sup = cell * np.asarray(wl.kmesh)
+    a = grid.lattice
+    a_sup = np.asarray(wl.kmesh, float)[:, None] * a
+    inv_sup = np.linalg.inv(a_sup)
     out = np.empty((len(shift_cells), wl.nao, len(pts_cart)))
     for ir, rc in enumerate(shift_cells):
         for mu in range(wl.nao):
-            c = (np.asarray(rc) + centres[mu]) * cell
-            d = pts_cart - c[None, :]
-            d -= sup[None, :] * np.round(d / sup[None, :])
+            c = (np.asarray(rc) + centres[mu]) @ a
+            f = (pts_cart - c[None, :]) @ inv_sup      # supercell fractional displacement
+            f -= np.round(f)                            # periodic image nearest in fractional terms
+            d = f @ a_sup
             out[ir, mu] = norm[mu] * np.exp(-alpha[mu] * (d * d).sum(axis=1))
     return out
 
 
 def _cell_grid(grid: FftGrid):
     idx = np.indices(grid.n).reshape(3, -1).T
-    return idx * (np.asarray(grid.cell) / np.asarray(grid.n))[None, :]
+    return (idx / np.asarray(grid.n, float)[None, :]) @ grid.lattice
 
 
 def fftdf_pair_density(wl: Workload, grid: FftGrid, dtype=np.complex128) -> np.ndarray:
@@ -440,5 +456,5 @@ def fftdf_ao_supercell(wl: Workload, grid: FftGrid) -> np.ndarray:
     axis): [N_k R'][nao][N_k nr] real."""
     n = np.asarray(grid.n) * np.asarray(wl.kmesh)
     idx = np.indices(tuple(n)).reshape(3, -1).T
-    pts = idx * (np.asarray(grid.cell) / np.asarray(grid.n))[None, :]
+    pts = (idx / np.asarray(grid.n, float)[None, :]) @ grid.lattice
     return _chi_on_points(wl, grid, pts, cells(wl.kmesh))

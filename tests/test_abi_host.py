@@ -127,6 +127,22 @@ def test_fftdf_argument_validation(lib):
     bad_c = dmet.pw_grid((6, 6, 6), (3.0, 0.0, 3.0))
     assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(bad_c), 16, 0,
                                                   ctypes.byref(nb)) == E_ARG
+    # a general (hexagonal) cell is accepted; linearly dependent or non-finite vectors are not
+    hexa = dmet.pw_grid((6, 6, 6), ((2.6, 0, 0), (1.3, 2.25, 0), (0, 0, 3.2)))
+    assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(hexa), 16, 0,
+                                                  ctypes.byref(nb)) == 0
+    flat = dmet.pw_grid((6, 6, 6), ((2.6, 0, 0), (1.3, 2.25, 0), (3.9, 2.25, 0)))   # a_3 = a_1 + a_2
+    assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(flat), 16, 0,
+                                                  ctypes.byref(nb)) == E_ARG
+    assert b"linearly independent" in lib.dmet_last_error()
+    nan = dmet.pw_grid((6, 6, 6), ((2.6, 0, 0), (1.3, float("nan"), 0), (0, 0, 3.2)))
+    assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(nan), 16, 0,
+                                                  ctypes.byref(nb)) == E_ARG
+    # edge lengths are the diagonal cell
+    g = dmet.pw_grid((2, 3, 4), (3.0, 4.0, 5.0))
+    assert [[g.cell[a][b] for b in range(3)] for a in range(3)] == [[3, 0, 0], [0, 4, 0], [0, 0, 5]]
+    with pytest.raises(ValueError):
+        dmet.pw_grid((2, 3, 4), ((1.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0)))
     assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), None, 16, 0, ctypes.byref(nb)) == E_ARG
     # null arrays are rejected before any launch
     assert lib.dmet_transform_eri_fftdf(ctypes.byref(lat), ctypes.byref(good), 16, None, 0, None, None, None,

@@ -7,7 +7,10 @@ their pair densities): the k-blocking of the grid is exact, so the two agree to
 rounding.  Planted mistakes in the k-space steps (the e^{iq.r} phase, the
 kernel's q shift, the side of the conjugation) break that agreement, and the
 result has the symmetry, realness and positive semidefiniteness of a Coulomb
-ERI.
+ERI.  Non-orthogonal cells: the reciprocal vectors satisfy a_i . b_j = 2 pi
+delta_ij and have the closed form of the hexagonal lattice, and the ERIs do not
+change when the whole cell is rotated (which a transposed reciprocal metric
+would break).
 """
 import numpy as np
 import pytest
@@ -17,7 +20,7 @@ from oracle import kspace as ok
 from oracle import supercell as sc
 
 
-@pytest.fixture(scope="module", params=["fft_tiny", "fft_odd"])
+@pytest.fixture(scope="module", params=["fft_tiny", "fft_odd", "fft_hex"])
 def fcase(request):
     wl, g = synth.FFT_CONFIGS[request.param]
     lat = synth.make_lattice(wl)
@@ -101,3 +104,48 @@ def test_planted_mistakes_break_parity(mistake):
     es = sc.fftdf_eri(chi, cr, wl.kmesh, g.n, g.cell)
     bad = _alg2_planted(rho, bath["c_k"][0], wl.kmesh, g.n, g.cell, mistake)
     assert np.abs(bad - es).max() > 1e-4 * np.abs(es).max()
+
+
+def test_reciprocal_vectors():
+    rng = np.random.default_rng(5)
+    a = np.eye(3) * 3.0 + rng.uniform(-0.8, 0.8, (3, 3))
+    b = ok.reciprocal_vectors(a)
+    assert np.abs(a @ b.T - 2 * np.pi * np.eye(3)).max() < 1e-12
+    # hexagonal lattice, a_1 = (a, 0, 0), a_2 = (a/2, a sqrt3/2, 0), a_3 = (0, 0, c):
+    # |b_1| = |b_2| = 4 pi / (a sqrt 3) and b_1 . b_2 = -|b_1|^2 / 2 (120 degrees)
+    h = np.asarray(synth.HEX_CELL)
+    alen, c = h[0, 0], h[2, 2]
+    bh = ok.reciprocal_vectors(h)
+    gm = bh @ bh.T
+    b2 = (4 * np.pi / (alen * np.sqrt(3))) ** 2
+    assert np.allclose(np.diag(gm), [b2, b2, (2 * np.pi / c) ** 2], rtol=1e-13)
+    assert abs(gm[0, 1] + 0.5 * b2) < 1e-12 * b2 and abs(gm[0, 2]) < 1e-12 and abs(gm[1, 2]) < 1e-12
+    # three lengths are the orthorhombic cell
+    assert np.array_equal(ok.cell_vectors((2.0, 3.0, 4.0)), np.diag([2.0, 3.0, 4.0]))
+
+
+def _rotation(seed):
+    q, r = np.linalg.qr(np.random.default_rng(seed).standard_normal((3, 3)))
+    q = q * np.sign(np.diag(r))[None, :]
+    return q if np.linalg.det(q) > 0 else -q
+
+
+def test_alg2_rotation_invariant():
+    """Rotating every lattice vector (and with them the AO centres, which are
+    fractional) leaves the pair densities on the grid and the ERIs unchanged."""
+    wl, g = synth.FFT_CONFIGS["fft_hex"]
+    rot = _rotation(11)
+    g_rot = synth.FftGrid(g.n, tuple(map(tuple, g.lattice @ rot.T)))
+    lat = synth.make_lattice(wl)
+    ck = ok.build_bath(lat.dm_k, wl.kmesh, wl.nao)["c_k"][0]
+    rho = synth.fftdf_pair_density(wl, g)
+    rho_rot = synth.fftdf_pair_density(wl, g_rot)
+    assert np.abs(rho - rho_rot).max() < 1e-12 * np.abs(rho).max()
+    e, _ = ok.alg2_eri(rho, ck, wl.kmesh, g.n, g.cell)
+    e_rot, _ = ok.alg2_eri(rho_rot, ck, wl.kmesh, g_rot.n, g_rot.cell)
+    assert np.abs(e - e_rot).max() < 1e-12 * np.abs(e).max()
+    # the same check fails for a kernel built on the transposed metric b^T b
+    bt = ok.reciprocal_vectors(g.lattice)
+    brt = ok.reciprocal_vectors(g_rot.lattice)
+    assert np.abs(bt.T @ bt - brt.T @ brt).max() > 1e-3 * np.abs(bt).max() ** 2
+    assert np.abs(bt @ bt.T - brt @ brt.T).max() < 1e-12 * np.abs(bt).max() ** 2

@@ -1,8 +1,8 @@
 """GPU parity of the plane-wave (FFTDF) route, App. B / Alg. 2, through the
 C-ABI, against the k-space oracle (itself pinned to a supercell FFT).  FP64:
 bound 1e-10 of max|ERI| element-wise, on small grids (even and odd grid and
-mesh sizes, UHF with the alpha-beta block) and at the full plane-wave size the
-benchmark times (2x2x2 mesh, 16^3 grid, 52 EOs)."""
+mesh sizes, a hexagonal cell, UHF with the alpha-beta block) and at the full
+plane-wave size the benchmark times (2x2x2 mesh, 16^3 grid, 52 EOs)."""
 import numpy as np
 import pytest
 import torch
@@ -33,7 +33,7 @@ def _run(dmet, wl, g):
     return rho, ck, out
 
 
-@pytest.mark.parametrize("name", ["fft_tiny", "fft_odd"])
+@pytest.mark.parametrize("name", ["fft_tiny", "fft_odd", "fft_hex"])
 def test_fftdf_parity_small(dmet, name):
     wl, g = synth.FFT_CONFIGS[name]
     rho, ck, out = _run(dmet, wl, g)
@@ -78,3 +78,17 @@ def test_fftdf_long_axis(dmet):
     err = np.abs(out["aa"].cpu().numpy() - refp).max()
     print(f"fft_long fftdf max err {err:.3e} (max {np.abs(refp).max():.3f})")
     assert err < 1e-10 * np.abs(refp).max()
+
+
+def test_fftdf_triclinic_uhf(dmet):
+    """A general triclinic cell (no two lattice vectors orthogonal), UHF with
+    the alpha-beta block, odd supercell axes."""
+    wl = synth.Workload("fft_tri", (3, 1, 1), 5, 5 * 3 * 3, 5, 5, 2, 1.5, 1016)
+    g = synth.FftGrid((5, 3, 3), ((3.1, 0.0, 0.0), (0.9, 2.8, 0.0), (0.7, -0.6, 2.9)))
+    rho, ck, out = _run(dmet, wl, g)
+    for key, (a, b) in {"aa": (0, None), "bb": (1, None), "ab": (0, 1)}.items():
+        ref, im = ok.alg2_eri(rho, ck[a], wl.kmesh, g.n, g.cell, None if b is None else ck[b])
+        ref = ok.pack_s8(ref) if b is None else ok.pack_s4(ref)
+        err = np.abs(out[key].cpu().numpy().reshape(ref.shape) - ref).max()
+        print(f"fft_tri {key}: max err {err:.3e} (max {np.abs(ref).max():.3f}, im {im:.1e})")
+        assert err < 1e-10 * np.abs(ref).max(), (key, err)
