@@ -869,13 +869,14 @@ __device__ inline void pk_issue_g(const __bf16* base, size_t pt_stride, int X, i
 }
 
 // One stage of a packed operand (P2 planes x NS parts x 2 groups x ROWS rows)
-// moved to LDS [plane*NS + part][group][row] by direct loads; rows clamped.
-template <int NS, int ROWS>
+// moved to LDS [plane*NS + part][group][row] by direct loads of NW waves; rows
+// clamped.
+template <int NS, int ROWS, int NW = 4>
 __device__ inline void pk_issue(const __bf16* base, size_t pt_stride /*chunks per part*/, int X, int x0, int g0,
                                 bf8* dst) {
     constexpr int CH = P2 * NS * 2 * ROWS;  // chunks in the stage
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int first = wave * 64; first < CH; first += 256) {
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int first = wave * 64; first < CH; first += 64 * NW) {
         const int pt = first / (2 * ROWS), g = (first / ROWS) % 2, row0 = first % ROWS;
         const int x = min(x0 + row0 + lane, X - 1);
         const __bf16* src = base + ((size_t)pt * pt_stride + (size_t)(g0 + g) * X + x) * 8;
@@ -959,13 +960,13 @@ __device__ inline void pk_mma4(const bf8* sA, const bf8* sB, int wm0, int wn0, f
     pk_mma_f<NS, TM, TN>(f, acc);
 }
 
-// Double-buffered K loop over `nst` stages of two groups each.
-template <int NS, int BM, int BN, int TM, int TN>
+// Double-buffered K loop over `nst` stages of two groups each (NW waves).
+template <int NS, int BM, int BN, int TM, int TN, int NW = 4>
 __device__ inline void pk_loop3(const __bf16* pa, size_t pa_pt, int XA, int m0, const __bf16* pb, size_t pb_pt,
                                 int XB, int n0, int nst, bf8* ring, int wm0, int wn0, f16v (&acc)[2][TM][TN]) {
     constexpr int SA = P2 * NS * 2 * BM, SB = P2 * NS * 2 * BN;
-    pk_issue<NS, BM>(pa, pa_pt, XA, m0, 0, ring);
-    pk_issue<NS, BN>(pb, pb_pt, XB, n0, 0, ring + SA);
+    pk_issue<NS, BM, NW>(pa, pa_pt, XA, m0, 0, ring);
+    pk_issue<NS, BN, NW>(pb, pb_pt, XB, n0, 0, ring + SA);
     for (int st = 0; st < nst; ++st) {
         bf8* cur = ring + (size_t)(st & 1) * (SA + SB);
         __builtin_amdgcn_s_waitcnt(0x0F70);   // own loads of stage st landed
@@ -973,8 +974,8 @@ __device__ inline void pk_loop3(const __bf16* pa, size_t pa_pt, int XA, int m0, 
         __builtin_amdgcn_sched_barrier(0);
         if (st + 1 < nst) {
             bf8* nxt = ring + (size_t)((st + 1) & 1) * (SA + SB);
-            pk_issue<NS, BM>(pa, pa_pt, XA, m0, 2 * (st + 1), nxt);
-            pk_issue<NS, BN>(pb, pb_pt, XB, n0, 2 * (st + 1), nxt + SA);
+            pk_issue<NS, BM, NW>(pa, pa_pt, XA, m0, 2 * (st + 1), nxt);
+            pk_issue<NS, BN, NW>(pb, pb_pt, XB, n0, 2 * (st + 1), nxt + SA);
         }
         pk_mma4<NS, BM, BN, TM, TN>(cur, cur + SA, wm0, wn0, acc);
     }
@@ -1069,13 +1070,15 @@ __device__ inline void pk_loop_paired(const __bf16* pc2, size_t cst, int neo, co
 // Lanes l and l+32 hold rows 0-3 and 4-7 of each 8-row group of a 32x32
 // result tile; one exchange gives each lane a full 8-row column chunk.
 // Only the kept k of the k <-> q-k pairing are formed; T slot `slot` (groups
-// slot * nao_p / 8 ...) holds k = ks.k[slot].
-template <int NS>
-__global__ void __launch_bounds__(256) k_xf1_pk(Mesh mesh, int q, int naux, int nao_p, int neo, int nspin, int ngv,
-                                                int ng2, KSlots ks,
-                                                const __bf16* __restrict__ plm, const __bf16* __restrict__ pc1,
-                                                __bf16* __restrict__ pt) {
-    constexpr int BM = 128, BN = 128, TM = 2, TN = 2;
+// slot * nao_p / 8 ...) holds k = ks.k[slot].  NW = 8 runs the 128 x 128
+// tile as eight 64 x 32 waves (two per SIMD) instead of four 64 x 64.
+template <int NS, int NW>
+__global__ void __launch_bounds__(64 * NW) k_xf1_pk(Mesh mesh, int q, int naux, int nao_p, int neo, int nspin,
+                                                    int ngv, int ng2, KSlots ks,
+                                                    const __bf16* __restrict__ plm, const __bf16* __restrict__ pc1,
+                                                    __bf16* __restrict__ pt) {
+    static_assert(NW == 4 || NW == 8, "four waves of 64 x 64 or eight of 64 x 32");
+    constexpr int BM = 128, BN = 128, TM = 2, TN = NW == 4 ? 2 : 1;
     extern __shared__ __align__(16) bf8 ring[];
     const int nk = mesh.nk;
     const int M1 = naux * nao_p, NB = nspin * neo;
@@ -1091,7 +1094,8 @@ __global__ void __launch_bounds__(256) k_xf1_pk(Mesh mesh, int q, int naux, int 
     const int m0 = (rem / nnt) * BM, n0 = (rem % nnt) * BN;
     const int kmq = mesh_sub(mesh, k, q);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
+    const int wm0 = NW == 4 ? (wave >> 1) * 64 : (wave >> 2) * 64;
+    const int wn0 = NW == 4 ? (wave & 1) * 64 : (wave & 3) * 32;
     const __bf16* pa = plm + ((size_t)q * nk + k) * P2 * NS * (size_t)ngv * M1 * 8;
     const __bf16* pb = pc1 + (size_t)kmq * P2 * NS * (size_t)ngv * NB * 8;
     f16v acc[2][TM][TN];
@@ -1103,7 +1107,7 @@ __global__ void __launch_bounds__(256) k_xf1_pk(Mesh mesh, int q, int naux, int 
             for (int j = 0; j < TN; ++j)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[p][i][j][r] = 0.f;
-    pk_loop3<NS, BM, BN, TM, TN>(pa, (size_t)ngv * M1, M1, m0, pb, (size_t)ngv * NB, NB, n0, ngv / 2, ring, wm0,
+    pk_loop3<NS, BM, BN, TM, TN, NW>(pa, (size_t)ngv * M1, M1, m0, pb, (size_t)ngv * NB, NB, n0, ngv / 2, ring, wm0,
                                  wn0, acc);
     const int h = lane >> 5;
     const size_t N2 = (size_t)naux * neo;
@@ -1306,12 +1310,12 @@ struct BItemC {
 
 // Stage 1 of a group of fragments sharing one 3-index tensor: columns of the
 // concatenated C^{k-q} are routed to their fragment by `colmap` (slot, j).
-template <int NS>
-__global__ void __launch_bounds__(256) k_xf1_batched(Mesh mesh, int q, int naux, int nao_p, int nbtot, int ngv,
+template <int NS, int NW>
+__global__ void __launch_bounds__(64 * NW) k_xf1_batched(Mesh mesh, int q, int naux, int nao_p, int nbtot, int ngv,
                                                      KSlots ks, const int2* __restrict__ colmap,
                                                      const BFrag* __restrict__ frags,
                                                      const __bf16* __restrict__ plm, const __bf16* __restrict__ pc1) {
-    constexpr int BM = 128, BN = 128, TM = 2, TN = 2;
+    constexpr int BM = 128, BN = 128, TM = 2, TN = NW == 4 ? 2 : 1;
     extern __shared__ __align__(16) bf8 ring[];
     const int nk = mesh.nk;
     const int M1 = naux * nao_p, NB = nbtot;
@@ -1324,7 +1328,8 @@ __global__ void __launch_bounds__(256) k_xf1_batched(Mesh mesh, int q, int naux,
     const int m0 = (rem / nnt) * BM, n0 = (rem % nnt) * BN;
     const int kmq = mesh_sub(mesh, k, q);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
+    const int wm0 = NW == 4 ? (wave >> 1) * 64 : (wave >> 2) * 64;
+    const int wn0 = NW == 4 ? (wave & 1) * 64 : (wave & 3) * 32;
     const __bf16* pa = plm + ((size_t)q * nk + k) * P2 * NS * (size_t)ngv * M1 * 8;
     const __bf16* pb = pc1 + (size_t)kmq * P2 * NS * (size_t)ngv * NB * 8;
     f16v acc[2][TM][TN];
@@ -1336,7 +1341,7 @@ __global__ void __launch_bounds__(256) k_xf1_batched(Mesh mesh, int q, int naux,
             for (int j = 0; j < TN; ++j)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[p][i][j][r] = 0.f;
-    pk_loop3<NS, BM, BN, TM, TN>(pa, (size_t)ngv * M1, M1, m0, pb, (size_t)ngv * NB, NB, n0, ngv / 2, ring, wm0,
+    pk_loop3<NS, BM, BN, TM, TN, NW>(pa, (size_t)ngv * M1, M1, m0, pb, (size_t)ngv * NB, NB, n0, ngv / 2, ring, wm0,
                                  wn0, acc);
     const int h = lane >> 5;
 #pragma unroll
@@ -1773,6 +1778,7 @@ constexpr size_t persist_i8_lds() { return (size_t)3 * 2 * 3 * 2 * 128 * 16; }
 
 template <int NS>
 constexpr size_t xf1_lds() { return (size_t)2 * P2 * NS * 2 * (128 + 128) * 16; }
+constexpr int XF1_NW = 8;   // waves per stage-1 workgroup
 template <int NS>
 constexpr size_t xf2_lds() { return (size_t)2 * P2 * NS * 2 * (64 + 64) * 16; }
 
@@ -1871,7 +1877,7 @@ static dmet_status xform_packed(const EriPlan& p, const void* lmunu, const doubl
         ps.stop();
     }
     DMET_LAUNCH_CHECK("pack inputs");
-    auto k1 = k_xf1_pk<NS>;
+    auto k1 = k_xf1_pk<NS, XF1_NW>;
     auto k2 = k_xf2_pk2<NS>;
     DMET_HIP(hipFuncSetAttribute((const void*)k2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)xf2_pk2_lds<NS>()));
     DMET_HIP(hipFuncSetAttribute((const void*)k1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)xf1_lds<NS>()));
@@ -1887,7 +1893,7 @@ static dmet_status xform_packed(const EriPlan& p, const void* lmunu, const doubl
         ProfScope ps1(n1, st);
         const long nb1 = ((long)(ks.npaired + ks.nself) * ((d.M1 + 127) / 128) * ((d.NB + 127) / 128) + NXCD - 1) /
                          NXCD * NXCD;
-        k1<<<dim3((unsigned)nb1), 256, xf1_lds<NS>(), st>>>(p.mesh, qb.q, p.naux, d.nao_p, p.neo, p.nspin, d.ngv,
+        k1<<<dim3((unsigned)nb1), 64 * XF1_NW, xf1_lds<NS>(), st>>>(p.mesh, qb.q, p.naux, d.nao_p, p.neo, p.nspin, d.ngv,
                                                             d.ng2, ks, plm, pc1, ptt);
         ps1.stop();
         DMET_LAUNCH_CHECK(n1);
@@ -2300,7 +2306,7 @@ static int g_ncu = 0;
 
 template <int NS>
 static dmet_status batch_prepare() {
-    DMET_HIP(hipFuncSetAttribute((const void*)k_xf1_batched<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    DMET_HIP(hipFuncSetAttribute((const void*)k_xf1_batched<NS, XF1_NW>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)xf1_lds<NS>()));
     DMET_HIP(hipFuncSetAttribute((const void*)k_xf2_batched<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)xf2_lds<NS>()));
@@ -2323,7 +2329,7 @@ static dmet_status batch_enqueue(BatchPlan& bp, int variant, bool prof, hipStrea
     void* ws = bp.ws;
     const int nfrag = (int)bp.frags.size();
     BFrag* dfr = at<BFrag>(ws, bp.off_bfrag);
-    auto k1 = k_xf1_batched<NS>;
+    auto k1 = k_xf1_batched<NS, XF1_NW>;
     auto k2 = k_xf2_batched<NS>;
     auto kc = variant == 128 ? k_contract_persist<NS, 128> : k_contract_persist<NS, 64>;
     const size_t lc = variant == 128 ? persist_lds<NS, 128>() : persist_lds<NS, 64>();
@@ -2377,7 +2383,7 @@ static dmet_status batch_enqueue(BatchPlan& bp, int variant, bool prof, hipStrea
             const KSlots ks = kpair_slots(G.mesh, G.qbs[r].q);
             const long nb = ((long)(ks.npaired + ks.nself) * ((G.M1 + 127) / 128) * ((G.nbtot + 127) / 128) + NXCD - 1) /
                             NXCD * NXCD;
-            k1<<<dim3((unsigned)nb), 256, xf1_lds<NS>(), st>>>(G.mesh, G.qbs[r].q, G.naux, G.nao_p, G.nbtot, G.ngv, ks,
+            k1<<<dim3((unsigned)nb), 64 * XF1_NW, xf1_lds<NS>(), st>>>(G.mesh, G.qbs[r].q, G.naux, G.nao_p, G.nbtot, G.ngv, ks,
                                                                at<int2>(ws, G.off_colmap), dfr,
                                                                at<__bf16>(ws, G.off_plm), at<__bf16>(ws, G.off_pc1));
         }
