@@ -580,6 +580,13 @@ def main():
                      "launch_ms": round(avg_ms, 4), "flop_per_launch": kf},
         "eri_build_ms": round(eri_ms, 3),
         "kernels_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in prof.items()},
+        # every ERI kernel with an algorithmic flop count, on the same convention as `roofline`
+        "rooflines": {k: {"launches_per_step": round(n / args.steps, 2), "launch_ms": round(t / n, 4),
+                          "achieved": round(kernel_flops(wl, k) / (t / n * 1e-3) / 1e12, 3),
+                          "peak": kernel_peak(args.precision, k),
+                          "frac": round(kernel_flops(wl, k) / (t / n * 1e-3) / 1e12 / kernel_peak(args.precision, k), 4),
+                          "traffic": traffic_bytes(k, wl.name)}
+                      for k, (n, t) in prof.items() if kernel_flops(wl, k) is not None and n > 0},
         "bath_ms": round(t_bath, 3), "onebody_ms": round(t_1e, 3),
         "df_output_ms": round(t_df, 3), "fock_dc_ms": round(t_dc, 3),
         "h2d_s": round(t_h2d, 2), "h2d_GBps": round(lm.nbytes / 1e9 / t_h2d, 2),

@@ -365,8 +365,10 @@ dmet_status dmet_energy_mf(int nspin, int neo, const double* f_tilde, const doub
  * prec     DMET_BF16X3_3M, DMET_BF16X6_3M or DMET_BF16X6_I8 run the batched
  *          pipeline above (the last with the int8 contraction, at most 44032
  *          rows N_k*naux per fragment); DMET_FP64 and DMET_FP32_3M run the
- *          single-fragment path for each fragment in turn (same results as
- *          dmet_transform_eri).
+ *          single-fragment path of each fragment on four concurrent internal
+ *          streams (default priority; forked from and joined to `stream` by
+ *          events), fragments assigned largest first, each stream with a slice
+ *          of the workspace (same results as dmet_transform_eri, bit for bit).
  * flags    DMET_BATCH_GRAPH: capture the whole submission into a hipGraph on the
  *            first call with a given batch (descriptors, precision, workspace)
  *            and replay it on later calls (inputs may change, pointers may not);

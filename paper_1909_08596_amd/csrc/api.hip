@@ -51,9 +51,18 @@ bool g_prof_on = false;
 std::vector<ProfRecord> g_prof;
 }  // namespace
 
+static bool g_prof_suspended = false;
+
+bool prof_suspend(bool on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    const bool was = g_prof_suspended;
+    g_prof_suspended = on;
+    return was;
+}
+
 ProfScope::ProfScope(const char* name, hipStream_t s) : slot(-1), st(s) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    if (!g_prof_on) return;
+    if (!g_prof_on || g_prof_suspended) return;
     ProfRecord r;
     r.name = name;
     if (hipEventCreate(&r.start) != hipSuccess) return;

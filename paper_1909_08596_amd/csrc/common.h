@@ -118,6 +118,10 @@ struct ProfScope {
     void stop();
 };
 
+// Suspends the profiler's event records (during a graph capture: events
+// recorded into a graph cannot be timed).  Returns the previous state.
+bool prof_suspend(bool on);
+
 // small fill kernel (used instead of hipMemsetAsync so callers may capture)
 void fill_zero(void* p, size_t bytes, hipStream_t s);
 

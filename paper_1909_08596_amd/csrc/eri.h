@@ -80,6 +80,8 @@ __host__ __device__ inline bool kpair_needed(const Mesh& m, int q, int k) {
 // df_out != NULL: write the FP64 DF factors Z [nspin][zrows][npair] there and
 // skip the contraction (eri pointers unused).
 size_t eri_f64_workspace(const EriPlan& p);
+dmet_status eri_f64_prepare();
+dmet_status eri_f32_prepare();
 dmet_status eri_f64(const EriPlan& p, const void* lmunu, const double* ck, double* eri_aa, double* eri_bb,
                     double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st, double* df_out = nullptr);
 

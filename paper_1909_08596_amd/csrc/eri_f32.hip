@@ -10,6 +10,7 @@
 // partials into FP64 every 256 rows.
 #include <stdio.h>
 
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -486,6 +487,28 @@ F32Dims f32_dims(const EriPlan& p) {
 
 }  // namespace
 
+// Dynamic LDS limits of the FP32 kernels, set once per device (a host call,
+// kept out of graph captures: the batched driver calls this before capturing).
+dmet_status eri_f32_prepare() {
+    static std::mutex mu;
+    static bool done[64] = {};
+    int dev = 0;
+    DMET_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    if (dev >= 0 && dev < 64 && done[dev]) return DMET_OK;
+    constexpr size_t lds1 = (size_t)2 * 3 * S1_BK * (S1_BM + S1_BN) * 4;
+    constexpr size_t lds2 = (size_t)2 * 3 * S2_BK * (S2_BM + S2_BN) * 4;
+    constexpr size_t lds3 = (size_t)C_NBUF * C_BK * 256 * 4;
+    DMET_HIP(hipFuncSetAttribute((const void*)k_f32_xf1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds1));
+    DMET_HIP(hipFuncSetAttribute((const void*)k_f32_xf2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
+    DMET_HIP(hipFuncSetAttribute((const void*)k_f32_contract<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds3));
+    DMET_HIP(hipFuncSetAttribute((const void*)k_f32_contract<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds3));
+    if (dev >= 0 && dev < 64) done[dev] = true;
+    return DMET_OK;
+}
+
 size_t eri_f32_workspace(const EriPlan& p) {
     F32Dims d = f32_dims(p);
     Carve cv(nullptr, 0);
@@ -538,8 +561,10 @@ dmet_status eri_f32(const EriPlan& p, const void* lmunu, const double* ck, doubl
     constexpr size_t lds1 = (size_t)2 * 3 * S1_BK * (S1_BM + S1_BN) * 4;
     constexpr size_t lds2 = (size_t)2 * 3 * S2_BK * (S2_BM + S2_BN) * 4;
     constexpr size_t lds3 = (size_t)C_NBUF * C_BK * 256 * 4;
-    DMET_HIP(hipFuncSetAttribute((const void*)k_f32_xf1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds1));
-    DMET_HIP(hipFuncSetAttribute((const void*)k_f32_xf2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
+    {
+        dmet_status sp = eri_f32_prepare();
+        if (sp != DMET_OK) return sp;
+    }
     const size_t tsp = (size_t)3 * d.K2 * d.N2p, c2sp = (size_t)3 * d.K2 * d.neo_p;
     const size_t zsp = (size_t)d.rows_p * d.ldz;
     const int njt = (p.neo + S2_BN - 1) / S2_BN, nit = (p.neo + S2_BM - 1) / S2_BM;
@@ -569,8 +594,6 @@ dmet_status eri_f32(const EriPlan& p, const void* lmunu, const double* ck, doubl
     }
     auto kc0 = k_f32_contract<0>;
     auto kc1 = k_f32_contract<1>;
-    DMET_HIP(hipFuncSetAttribute((const void*)kc0, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds3));
-    DMET_HIP(hipFuncSetAttribute((const void*)kc1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds3));
     const int ntile = (p.npair + 127) / 128;
     for (int s = 0; s < p.nspin; ++s) {
         const long nb = f32_grid<0>(ntile);

@@ -11,6 +11,7 @@
 // then the contraction (ij|kl) = sum_rows Z[r][ij] Z[r][kl] as a packed SYRK
 // (same spin) or GEMM (alpha-beta).
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -441,8 +442,30 @@ dmet_status eri_f64(const EriPlan& p, const void* lmunu, const double* ck, doubl
     return contract_f64(p.nspin, p.npair, (int)ldz, krows_p, z, eri_aa, eri_bb, eri_ab, part, st);
 }
 
+// Dynamic LDS limit of the FP64 contraction, set once per device (a host call,
+// kept out of graph captures: the batched driver calls this before capturing).
+dmet_status eri_f64_prepare() {
+    static std::mutex mu;
+    static bool done[64] = {};
+    int dev = 0;
+    DMET_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    if (dev >= 0 && dev < 64 && done[dev]) return DMET_OK;
+    const size_t lds = (size_t)2 * 2 * R_BK * R_LD * sizeof(double);
+    DMET_HIP(hipFuncSetAttribute((const void*)k_contract_f64r<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds));
+    DMET_HIP(hipFuncSetAttribute((const void*)k_contract_f64r<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds));
+    if (dev >= 0 && dev < 64) done[dev] = true;
+    return DMET_OK;
+}
+
 dmet_status contract_f64(int nspin, int npair, int ldz, int krows_p, const double* z, double* eri_aa,
                          double* eri_bb, double* eri_ab, double* part, hipStream_t st) {
+    {
+        dmet_status sp = eri_f64_prepare();
+        if (sp != DMET_OK) return sp;
+    }
     const size_t zsp = (size_t)krows_p * ldz;
     const size_t lds = (size_t)2 * 2 * R_BK * R_LD * sizeof(double);
     const int ntile = (npair + R_BM - 1) / R_BM;
@@ -453,7 +476,6 @@ dmet_status contract_f64(int nspin, int npair, int ldz, int krows_p, const doubl
         const long per = mode == 0 ? r_tiles_per_split<0>(ntile) : r_tiles_per_split<1>(ntile);
         const long nb = (per * ns + R_NXCD - 1) / R_NXCD * R_NXCD;
         auto kern = mode == 0 ? k_contract_f64r<0> : k_contract_f64r<1>;
-        DMET_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         for (int s = 0; s < (mode == 0 ? nspin : 1); ++s) {
             const double* za = z + (mode == 0 ? s * zsp : 0);
             const double* zb = z + (mode == 0 ? s * zsp : zsp);

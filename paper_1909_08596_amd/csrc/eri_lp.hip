@@ -2507,16 +2507,112 @@ static dmet_status batch_upload(BatchPlan& bp, int variant, hipStream_t st) {
     return DMET_OK;
 }
 
+// FP64 and FP32-3M batches run the per-fragment drivers on NBR concurrent
+// branches (internal streams forked from and joined to the caller's stream by
+// events): fragments go largest first to the branch with the least work so
+// far, and each branch has a workspace slice of its own.  With
+// DMET_BATCH_GRAPH the fork / join is captured once per plan and replayed.
+constexpr int NBR = 4;
+
+struct LoopPlan {
+    std::vector<std::vector<int>> branch;   // fragment indices per branch, in run order
+    std::vector<size_t> off;                // workspace offset per branch
+    size_t bytes = 0;
+    hipGraphExec_t exec = nullptr;
+};
+
+static EriPlan frag_plan(const dmet_fragment& f, dmet_precision prec) {
+    dmet_lattice lat = f.lat;
+    lat.nspin = 1;
+    return make_eri_plan(&lat, f.neo, prec, f.dtype);
+}
+
+static void plan_loop(int nfrag, const dmet_fragment* frags, dmet_precision prec, LoopPlan& lp) {
+    std::vector<double> cost(nfrag);
+    std::vector<int> order(nfrag);
+    for (int f = 0; f < nfrag; ++f) {
+        const double nk = (double)frags[f].lat.kmesh[0] * frags[f].lat.kmesh[1] * frags[f].lat.kmesh[2];
+        const double nao = frags[f].lat.nao, naux = frags[f].lat.naux, neo = frags[f].neo;
+        const double npair = neo * (neo + 1) / 2;
+        cost[f] = nk * nk * naux * nao * neo * (nao + neo) + nk * naux * npair * npair;   // transform + contraction
+        order[f] = f;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    const int nb = std::min(NBR, std::max(1, nfrag));
+    lp.branch.assign(nb, {});
+    std::vector<double> load(nb, 0.0);
+    std::vector<size_t> ws(nb, 256);
+    for (int f : order) {
+        const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        lp.branch[b].push_back(f);
+        load[b] += cost[f];
+        const EriPlan p = frag_plan(frags[f], prec);
+        ws[b] = std::max(ws[b], prec == DMET_FP64 ? eri_f64_workspace(p) : eri_f32_workspace(p));
+    }
+    lp.off.assign(nb, 0);
+    size_t cur = 0;
+    for (int b = 0; b < nb; ++b) {
+        lp.off[b] = cur;
+        cur += (ws[b] + 255) & ~size_t(255);
+    }
+    lp.bytes = cur;
+}
+
+static std::map<std::string, LoopPlan*> g_loop_plans;
+
+// branch streams and events of the current device (created once, default priority)
+struct Branches {
+    hipStream_t st[NBR] = {};
+    hipEvent_t fork = nullptr, join[NBR] = {};
+};
+
+static dmet_status branches_of_device(Branches*& out) {
+    static Branches per_dev[64];
+    static bool made[64] = {};
+    int dev = 0;
+    DMET_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(DMET_E_UNSUPPORTED, "device index above 63");
+    Branches& b = per_dev[dev];
+    if (!made[dev]) {
+        for (int i = 0; i < NBR; ++i) {
+            DMET_HIP(hipStreamCreateWithFlags(&b.st[i], hipStreamNonBlocking));
+            DMET_HIP(hipEventCreateWithFlags(&b.join[i], hipEventDisableTiming));
+        }
+        DMET_HIP(hipEventCreateWithFlags(&b.fork, hipEventDisableTiming));
+        made[dev] = true;
+    }
+    out = &b;
+    return DMET_OK;
+}
+
+static dmet_status loop_enqueue(int nfrag, const dmet_fragment* frags, dmet_precision prec, const LoopPlan& lp,
+                                void* ws, Branches& br, hipStream_t st) {
+    (void)nfrag;
+    DMET_HIP(hipEventRecord(br.fork, st));
+    for (size_t b = 0; b < lp.branch.size(); ++b) {
+        hipStream_t bs = br.st[b];
+        DMET_HIP(hipStreamWaitEvent(bs, br.fork, 0));
+        void* slice = static_cast<char*>(ws) + lp.off[b];
+        const size_t cap = (b + 1 < lp.branch.size() ? lp.off[b + 1] : lp.bytes) - lp.off[b];
+        for (int f : lp.branch[b]) {
+            const EriPlan p = frag_plan(frags[f], prec);
+            const double* ckf = static_cast<const double*>(frags[f].c_k);
+            dmet_status s = prec == DMET_FP64
+                                ? eri_f64(p, frags[f].lmunu, ckf, frags[f].eri, nullptr, nullptr, slice, cap, bs)
+                                : eri_f32(p, frags[f].lmunu, ckf, frags[f].eri, nullptr, nullptr, slice, cap, bs);
+            if (s != DMET_OK) return s;
+        }
+        DMET_HIP(hipEventRecord(br.join[b], bs));
+    }
+    for (size_t b = 0; b < lp.branch.size(); ++b) DMET_HIP(hipStreamWaitEvent(st, br.join[b], 0));
+    return DMET_OK;
+}
+
 size_t batch_workspace(int nfrag, const dmet_fragment* frags, dmet_precision prec) {
     if (prec == DMET_FP64 || prec == DMET_FP32_3M) {
-        size_t mx = 256;
-        for (int f = 0; f < nfrag; ++f) {
-            dmet_lattice lat = frags[f].lat;
-            lat.nspin = 1;
-            EriPlan p = make_eri_plan(&lat, frags[f].neo, prec, frags[f].dtype);
-            mx = std::max(mx, prec == DMET_FP64 ? eri_f64_workspace(p) : eri_f32_workspace(p));
-        }
-        return mx;
+        LoopPlan lp;
+        plan_loop(nfrag, frags, prec, lp);
+        return lp.bytes;
     }
     BatchPlan bp;
     bp.frags.assign(frags, frags + nfrag);
@@ -2563,16 +2659,59 @@ static void tune_store(const std::string& key, int v, float ms128, float ms64) {
 dmet_status eri_batched(int nfrag, const dmet_fragment* frags, dmet_precision prec, unsigned flags, void* ws,
                         size_t ws_bytes, hipStream_t st) {
     if (prec == DMET_FP64 || prec == DMET_FP32_3M) {
-        for (int f = 0; f < nfrag; ++f) {
-            dmet_lattice lat = frags[f].lat;
-            lat.nspin = 1;
-            EriPlan p = make_eri_plan(&lat, frags[f].neo, prec, frags[f].dtype);
-            const double* ckf = static_cast<const double*>(frags[f].c_k);
-            dmet_status s = prec == DMET_FP64
-                                ? eri_f64(p, frags[f].lmunu, ckf, frags[f].eri, nullptr, nullptr, ws, ws_bytes, st)
-                                : eri_f32(p, frags[f].lmunu, ckf, frags[f].eri, nullptr, nullptr, ws, ws_bytes, st);
+        std::lock_guard<std::mutex> lk(g_batch_mu);
+        const std::string key = batch_key(nfrag, frags, prec, true, ws, ws_bytes);
+        LoopPlan* lp = nullptr;
+        auto it = g_loop_plans.find(key);
+        if (it != g_loop_plans.end()) {
+            lp = it->second;
+        } else {
+            lp = new LoopPlan();
+            plan_loop(nfrag, frags, prec, *lp);
+            if (lp->bytes > ws_bytes) {
+                delete lp;
+                return fail(DMET_E_WORKSPACE, "batched workspace too small");
+            }
+            if (g_loop_plans.size() >= 32) {   // bounded cache of plans / captured graphs
+                for (auto& kv : g_loop_plans) {
+                    if (kv.second->exec) (void)hipGraphExecDestroy(kv.second->exec);
+                    delete kv.second;
+                }
+                g_loop_plans.clear();
+            }
+            g_loop_plans[key] = lp;
+        }
+        Branches* br = nullptr;
+        {
+            dmet_status s = branches_of_device(br);
+            if (s != DMET_OK) return s;
+            s = prec == DMET_FP64 ? eri_f64_prepare() : eri_f32_prepare();
             if (s != DMET_OK) return s;
         }
+        if (!(flags & DMET_BATCH_GRAPH)) return loop_enqueue(nfrag, frags, prec, *lp, ws, *br, st);
+        if (!lp->exec) {
+            // capture on a private stream (the caller's may be the legacy null
+            // stream, which cannot be captured); nothing executes during capture
+            static hipStream_t cap = nullptr;
+            if (!cap) DMET_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            hipGraph_t g = nullptr;
+            const bool was = prof_suspend(true);
+            DMET_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+            dmet_status s = loop_enqueue(nfrag, frags, prec, *lp, ws, *br, cap);
+            hipError_t e = hipStreamEndCapture(cap, &g);
+            prof_suspend(was);
+            if (s != DMET_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return s;
+            }
+            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&lp->exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        }
+        ProfScope ps("batch_graph", st);
+        DMET_HIP(hipGraphLaunch(lp->exec, st));
+        ps.stop();
         return DMET_OK;
     }
     std::lock_guard<std::mutex> lk(g_batch_mu);

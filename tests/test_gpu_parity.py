@@ -194,7 +194,7 @@ def _small_batch():
     return frags
 
 
-@pytest.mark.parametrize("prec", ["bf16x6", "bf16x3", "fp32", "bf16x6_i8"])
+@pytest.mark.parametrize("prec", ["bf16x6", "bf16x3", "fp32", "bf16x6_i8", "fp64"])
 def test_batched_matches_single_and_oracle(dmet, prec):
     frags = _small_batch()
     dev_lm = {}
@@ -211,7 +211,41 @@ def test_batched_matches_single_and_oracle(dmet, prec):
         assert torch.equal(single, got)   # same kernels' arithmetic, same order
         ref, _ = ok.alg1_eri(lm.astype(np.complex64).astype(np.complex128), ck, wl.kmesh)
         err = np.abs(got.cpu().numpy() - ok.pack_s8(ref)).max()
-        assert err < (1e-5 if prec == "bf16x3" else LP_TOL), err
+        tol = 1e-10 * max(1.0, np.abs(ref).max()) if prec == "fp64" else (1e-5 if prec == "bf16x3" else LP_TOL)
+        assert err < tol, err
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batched_fp_branches_graph_replay(dmet, prec):
+    """FP32 / FP64 batches run the per-fragment kernels on concurrent branches
+    (9 fragments over 4 branches, each with its own workspace slice); eager,
+    graph-captured replays and single calls give the same bits, with other
+    work and synchronisations between the replays."""
+    frags = _small_batch()
+    dev_lm = {}
+    specs = []
+    for wl, lm, ck in frags:
+        if id(lm) not in dev_lm:
+            dev_lm[id(lm)] = to_dev(lm.astype(np.complex64))
+        specs.append({"kmesh": wl.kmesh, "nao": wl.nao, "naux": wl.naux, "lmunu": dev_lm[id(lm)],
+                      "c_k": to_dev(np.ascontiguousarray(ck))})
+    eager = [o.clone() for o in dmet.dmet_transform_eri_batched(specs, prec)]
+    torch.cuda.synchronize()
+    singles = [dmet.dmet_transform_eri(wl.kmesh, wl.nao, wl.naux, sp["lmunu"], sp["c_k"][None], prec)["aa"]
+               for (wl, _, _), sp in zip(frags, specs)]
+    for a, b in zip(eager, singles):
+        assert torch.equal(a, b)
+    ws = torch.empty(dmet.dmet_transform_eri_batched_workspace(specs, prec), dtype=torch.uint8, device="cuda:0")
+    for rep in range(3):
+        for sp in specs:
+            sp["eri"].zero_()
+        junk = torch.randn(1 << 20, device="cuda:0").sum()   # eager work between replays
+        torch.cuda.synchronize()
+        outs = dmet.dmet_transform_eri_batched(specs, prec, graph=True, workspace=ws)
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+        for a, b in zip(eager, outs):
+            assert torch.equal(a, b), rep
 
 
 def test_batched_graph_replay_and_autotune(dmet, tmp_path, monkeypatch):
@@ -409,4 +443,38 @@ def test_batched_64x64_stage2_tiles(dmet, prec, monkeypatch):
         assert torch.equal(single, got)
         ref, _ = ok.alg1_eri(lm.astype(np.complex64).astype(np.complex128), ck, wl.kmesh)
         err = np.abs(got.cpu().numpy() - ok.pack_s8(ref)).max()
-        assert err < (1e-5 if prec == "bf16x3" else LP_TOL), err
+        tol = 1e-10 * max(1.0, np.abs(ref).max()) if prec == "fp64" else (1e-5 if prec == "bf16x3" else LP_TOL)
+        assert err < tol, err
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batched_fp_branches_graph_replay(dmet, prec):
+    """FP32 / FP64 batches run the per-fragment kernels on concurrent branches
+    (9 fragments over 4 branches, each with its own workspace slice); eager,
+    graph-captured replays and single calls give the same bits, with other
+    work and synchronisations between the replays."""
+    frags = _small_batch()
+    dev_lm = {}
+    specs = []
+    for wl, lm, ck in frags:
+        if id(lm) not in dev_lm:
+            dev_lm[id(lm)] = to_dev(lm.astype(np.complex64))
+        specs.append({"kmesh": wl.kmesh, "nao": wl.nao, "naux": wl.naux, "lmunu": dev_lm[id(lm)],
+                      "c_k": to_dev(np.ascontiguousarray(ck))})
+    eager = [o.clone() for o in dmet.dmet_transform_eri_batched(specs, prec)]
+    torch.cuda.synchronize()
+    singles = [dmet.dmet_transform_eri(wl.kmesh, wl.nao, wl.naux, sp["lmunu"], sp["c_k"][None], prec)["aa"]
+               for (wl, _, _), sp in zip(frags, specs)]
+    for a, b in zip(eager, singles):
+        assert torch.equal(a, b)
+    ws = torch.empty(dmet.dmet_transform_eri_batched_workspace(specs, prec), dtype=torch.uint8, device="cuda:0")
+    for rep in range(3):
+        for sp in specs:
+            sp["eri"].zero_()
+        junk = torch.randn(1 << 20, device="cuda:0").sum()   # eager work between replays
+        torch.cuda.synchronize()
+        outs = dmet.dmet_transform_eri_batched(specs, prec, graph=True, workspace=ws)
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+        for a, b in zip(eager, outs):
+            assert torch.equal(a, b), rep
