@@ -316,8 +316,10 @@ def run_batched(args, dev):
 
 
 def run_fftdf(args, dev):
-    """Plane-wave (FFTDF) embedding ERIs, App. B / Alg. 2, FP64: Gaussian AOs on
-    a 16^3 grid of a 5.1 bohr cubic cell, 2x2x2 mesh, 26 AOs, 52 EOs."""
+    """Plane-wave (FFTDF) embedding ERIs, App. B / Alg. 2: Gaussian AOs on a 16^3
+    grid of a 5.1 bohr cubic cell, 2x2x2 mesh, 26 AOs, 52 EOs; FP64, or with
+    --precision bf16x6 / bf16x3 the split-bf16 transform and contraction (the
+    grid DFT in FP64), then also compared with FP64 on every element."""
     import torch
     import synth
     from paper_1909_08596_amd import dmet
@@ -328,10 +330,17 @@ def run_fftdf(args, dev):
     rho_d = torch.from_numpy(rho).to(dev)
     dm_d = torch.from_numpy(lat.dm_k).to(dev)
     ck, _, _ = dmet.dmet_build_bath(wl.kmesh, wl.nao, dm_d)
+    prec = args.precision if args.precision in ("fp64", "bf16x6", "bf16x3") else "fp64"
     ws = torch.empty(1, dtype=torch.uint8, device=dev)
-    out = dmet.dmet_transform_eri_fftdf(wl.kmesh, wl.nao, g.n, g.cell, rho_d, ck)
+    err64 = None
+    if prec != "fp64":
+        ref = dmet.dmet_transform_eri_fftdf(wl.kmesh, wl.nao, g.n, g.cell, rho_d, ck)["aa"]
+        got = dmet.dmet_transform_eri_fftdf(wl.kmesh, wl.nao, g.n, g.cell, rho_d, ck, precision=prec)["aa"]
+        err64 = float((got - ref).abs().max())
+        del ref, got
+    out = dmet.dmet_transform_eri_fftdf(wl.kmesh, wl.nao, g.n, g.cell, rho_d, ck, precision=prec)
     for _ in range(max(0, args.warmup - 1)):
-        out = dmet.dmet_transform_eri_fftdf(wl.kmesh, wl.nao, g.n, g.cell, rho_d, ck)
+        out = dmet.dmet_transform_eri_fftdf(wl.kmesh, wl.nao, g.n, g.cell, rho_d, ck, precision=prec)
     torch.cuda.synchronize()
     dmet.dmet_profile_reset()
     dmet.dmet_profile_enable(True)
@@ -339,7 +348,7 @@ def run_fftdf(args, dev):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(st)
     for _ in range(args.steps):
-        out = dmet.dmet_transform_eri_fftdf(wl.kmesh, wl.nao, g.n, g.cell, rho_d, ck)
+        out = dmet.dmet_transform_eri_fftdf(wl.kmesh, wl.nao, g.n, g.cell, rho_d, ck, precision=prec)
     e1.record(st)
     torch.cuda.synchronize()
     dmet.dmet_profile_enable(False)
@@ -353,23 +362,26 @@ def run_fftdf(args, dev):
     wc = nk * nr * npair * (npair + 1.0)
     dname, (dn, dms) = max(prof.items(), key=lambda kv: kv[1][1])
     avg = dms / dn
-    kflops = {"xform1_f64": 8.0 * nk * nr * nao * nao * neo, "xform2_f64": 8.0 * nk * nr * nao * neo * (neo + 1) / 2,
-              "contract_s8_f64": wc}
-    kf = kflops.get(dname)
+    kflops = {"xform1": 8.0 * nk * nr * nao * nao * neo, "xform2": 8.0 * nk * nr * nao * neo * (neo + 1) / 2,
+              "contract_s8": wc}
+    kf = kflops.get(dname.rsplit("_", 1)[0])
+    peak = PEAK[prec] if kf is not None and not dname.endswith("f64") else PEAK["fp64"]
     line = {
         "metric": METRIC, "value": round((wt + wfft + wc) / (ms * 1e-3) / 1e12, 4), "unit": "TFLOP/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[prec], "data": "synthetic",
         "config": {"workload": f"{wl.name}: plane-wave density fitting (App. B), k-mesh {'x'.join(map(str, wl.kmesh))}, "
                                f"grid {'x'.join(map(str, g.n))} in a {g.cell[0]} bohr cell, nao {nao}, neo {neo}, "
                                f"Gaussian AOs, pair density complex128",
-                   "precision": "fp64", "W_flop": wt + wfft + wc, "W_T": wt, "W_FFT": wfft, "W_C": wc},
+                   "precision": prec, "W_flop": wt + wfft + wc, "W_T": wt, "W_FFT": wfft, "W_C": wc},
         "roofline": {"bound": "mfma", "kernel": dname, "achieved": None if kf is None else round(kf / (avg * 1e-3) / 1e12, 3),
-                     "peak": PEAK["fp64"], "unit": "TFLOP/s",
-                     "frac": None if kf is None else round(kf / (avg * 1e-3) / 1e12 / PEAK["fp64"], 4),
+                     "peak": peak, "unit": "TFLOP/s",
+                     "frac": None if kf is None else round(kf / (avg * 1e-3) / 1e12 / peak, 4),
                      "traffic": None, "launch_ms": round(avg, 4), "flop_per_launch": kf},
         "kernels_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in prof.items()},
     }
+    if err64 is not None:
+        line["max_abs_err_vs_fp64"] = err64
     if not args.no_cpu_baseline:
         from oracle import kspace as ok
         from threadpoolctl import threadpool_info

@@ -300,9 +300,15 @@ dmet_status dmet_transform_eri_df(const dmet_lattice* lat, int neo, const void* 
  * On a non-orthogonal cell an even L leaves that Nyquist plane without a -G
  * partner of the same |q+G|^2, and the result is the real part of a form that
  * is then not exactly Hermitian: odd N_d n[d] avoid this.  Outputs as
- * dmet_transform_eri (s8 / s4 float64).  FP64 throughout.  Returns DMET_E_ARG
- * for a grid that does not match naux or a cell whose vectors are not finite
- * or are linearly dependent, DMET_E_WORKSPACE if the workspace is too small.
+ * dmet_transform_eri (s8 / s4 float64).  prec: DMET_FP64 (FP64 throughout),
+ * or DMET_BF16X6_3M / DMET_BF16X3_3M: the transform and the contraction in
+ * that split-bf16 form (as dmet_transform_eri), the grid DFT and the Coulomb
+ * weights in FP64 between them (the int8 contraction is not offered here: the
+ * plane-wave rows, 2 n_r per q, exceed its exact-sum limit on real grids;
+ * DMET_FP32_3M is not offered either; both give DMET_E_UNSUPPORTED).  Returns
+ * DMET_E_ARG for a grid that does not match naux or a cell whose vectors are
+ * not finite or are linearly dependent, DMET_E_WORKSPACE if the workspace is
+ * too small (the workspace depends on prec).
  * Asynchronous; the workspace must stay valid until the work completes.
  * ------------------------------------------------------------------------- */
 typedef struct {
@@ -311,10 +317,10 @@ typedef struct {
 } dmet_pw_grid;
 
 dmet_status dmet_transform_eri_fftdf_workspace(const dmet_lattice* lat, const dmet_pw_grid* grid, int neo,
-                                               dmet_dtype dtype, size_t* bytes);
+                                               dmet_dtype dtype, dmet_precision prec, size_t* bytes);
 dmet_status dmet_transform_eri_fftdf(const dmet_lattice* lat, const dmet_pw_grid* grid, int neo,
-                                     const void* rho, dmet_dtype dtype, const void* c_k,
-                                     double* eri_aa, double* eri_bb, double* eri_ab,
+                                     const void* rho, dmet_dtype dtype, dmet_precision prec,
+                                     const void* c_k, double* eri_aa, double* eri_bb, double* eri_ab,
                                      void* workspace, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------

@@ -360,22 +360,34 @@ static dmet_status check_pw(const dmet_lattice* lat, const dmet_pw_grid* grid) {
     return DMET_OK;
 }
 
+static dmet_status check_pw_prec(dmet_precision prec) {
+    if (prec == DMET_FP64 || prec == DMET_BF16X6_3M || prec == DMET_BF16X3_3M) return DMET_OK;
+    if (prec == DMET_FP32_3M || prec == DMET_BF16X6_I8)
+        return fail(DMET_E_UNSUPPORTED, "fftdf: precision forms FP64, BF16X6_3M and BF16X3_3M");
+    return fail(DMET_E_ARG, "unknown precision");
+}
+
 dmet_status dmet_transform_eri_fftdf_workspace(const dmet_lattice* lat, const dmet_pw_grid* grid, int neo,
-                                               dmet_dtype dtype, size_t* bytes) {
-    dmet_status s = check_eri_args(lat, neo, DMET_FP64, dtype);
+                                               dmet_dtype dtype, dmet_precision prec, size_t* bytes) {
+    dmet_status s = check_pw_prec(prec);
+    if (s != DMET_OK) return s;
+    s = check_eri_args(lat, neo, prec, dtype);
     if (s != DMET_OK) return s;
     s = check_pw(lat, grid);
     if (s != DMET_OK) return s;
     if (!bytes) return fail(DMET_E_ARG, "bytes is NULL");
-    *bytes = fftdf_workspace(make_eri_plan(lat, neo, DMET_FP64, dtype));
+    *bytes = fftdf_workspace(make_eri_plan(lat, neo, prec, dtype));
     return DMET_OK;
 }
 
 dmet_status dmet_transform_eri_fftdf(const dmet_lattice* lat, const dmet_pw_grid* grid, int neo, const void* rho,
-                                     dmet_dtype dtype, const void* c_k, double* eri_aa, double* eri_bb,
-                                     double* eri_ab, void* workspace, size_t ws_bytes, hipStream_t stream) {
+                                     dmet_dtype dtype, dmet_precision prec, const void* c_k, double* eri_aa,
+                                     double* eri_bb, double* eri_ab, void* workspace, size_t ws_bytes,
+                                     hipStream_t stream) {
     g_last_error.clear();
-    dmet_status s = check_eri_args(lat, neo, DMET_FP64, dtype);
+    dmet_status s = check_pw_prec(prec);
+    if (s != DMET_OK) return s;
+    s = check_eri_args(lat, neo, prec, dtype);
     if (s != DMET_OK) return s;
     s = check_pw(lat, grid);
     if (s != DMET_OK) return s;
@@ -383,7 +395,7 @@ dmet_status dmet_transform_eri_fftdf(const dmet_lattice* lat, const dmet_pw_grid
     if (lat->nspin == 2 && !eri_bb) return fail(DMET_E_ARG, "nspin == 2 requires eri_bb");
     if (lat->nspin == 1 && (eri_bb || eri_ab)) return fail(DMET_E_ARG, "nspin == 1 takes no eri_bb / eri_ab");
     if (!workspace) return fail(DMET_E_WORKSPACE, "workspace is NULL");
-    EriPlan p = make_eri_plan(lat, neo, DMET_FP64, dtype);
+    EriPlan p = make_eri_plan(lat, neo, prec, dtype);
     if (fftdf_workspace(p) > ws_bytes) return fail(DMET_E_WORKSPACE, "fftdf workspace too small");
     return fftdf_eri(p, grid, rho, static_cast<const double*>(c_k), eri_aa, eri_bb, eri_ab, workspace, ws_bytes,
                      stream);

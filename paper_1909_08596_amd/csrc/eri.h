@@ -82,6 +82,14 @@ __host__ __device__ inline bool kpair_needed(const Mesh& m, int q, int k) {
 size_t eri_f64_workspace(const EriPlan& p);
 dmet_status eri_f64_prepare();
 dmet_status eri_f32_prepare();
+// split-bf16 pieces used by the plane-wave route
+size_t lp_transform_workspace(const EriPlan& p);
+dmet_status lp_transform(const EriPlan& p, const void* lmunu, const double* ck, float* z, void* ws, size_t ws_bytes,
+                         hipStream_t st);
+size_t lp_rows_contract_workspace(int nspin, int npair, int krows, int ns);
+dmet_status lp_rows_contract(int ns, int nspin, int npair, int krows, const double* z, size_t zsp, size_t ldz,
+                             double* eri_aa, double* eri_bb, double* eri_ab, void* ws, size_t ws_bytes,
+                             hipStream_t st);
 dmet_status eri_f64(const EriPlan& p, const void* lmunu, const double* ck, double* eri_aa, double* eri_bb,
                     double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st, double* df_out = nullptr);
 

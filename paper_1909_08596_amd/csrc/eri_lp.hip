@@ -54,9 +54,10 @@ __device__ inline void split_bf16(float x, __bf16 (&part)[NS]) {
 // ------------------------------------------------------------------ packed split operands
 // P[t][g][x][v] (bf16) = part t of Z[8 g + v][x]: the k-index in groups of 8 so
 // that one MFMA operand fragment (8 consecutive k of one row) is one aligned
-// 16-byte chunk.  Rows beyond krows are zero.
-template <int NS>
-__global__ void k_pack_parts(const float* __restrict__ z, size_t ldz, int krows, int ncol, int kgroups,
+// 16-byte chunk.  Rows beyond krows are zero.  FP64 rows are rounded to FP32
+// first (the three parts carry FP32's 24 bits).
+template <int NS, class T = float>
+__global__ void k_pack_parts(const T* __restrict__ z, size_t ldz, int krows, int ncol, int kgroups,
                              __bf16* __restrict__ out) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int g = blockIdx.y;
@@ -65,7 +66,7 @@ __global__ void k_pack_parts(const float* __restrict__ z, size_t ldz, int krows,
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
         const int k = 8 * g + v;
-        const float val = k < krows ? z[(size_t)k * ldz + x] : 0.f;
+        const float val = k < krows ? (float)z[(size_t)k * ldz + x] : 0.f;
         __bf16 sp[NS];
         split_bf16<NS>(val, sp);
 #pragma unroll
@@ -2043,6 +2044,79 @@ dmet_status eri_lp(const EriPlan& p, const void* lmunu, const double* ck, double
     __bf16* zp = cv.take<__bf16>((size_t)p.nspin * packed_elems(p));
     if (p.prec == DMET_BF16X3_3M) return eri_lp_run<2>(p, lmunu, ck, eri_aa, eri_bb, eri_ab, z, zp, pre, st, df_out);
     return eri_lp_run<3>(p, lmunu, ck, eri_aa, eri_bb, eri_ab, z, zp, pre, st, df_out);
+}
+
+// The split-bf16 transform alone: FP32 rows z[nspin][zrows][npair] (the rows of
+// eri_lp before its contraction).  Workspace: the packed transform operands.
+size_t lp_transform_workspace(const EriPlan& p) {
+    Carve cv(nullptr, 0);
+    PkDims d = pk_dims(p);
+    cv.take<__bf16>(d.lm_elems);
+    cv.take<__bf16>(d.c1_elems);
+    cv.take<__bf16>(d.c2_elems);
+    cv.take<__bf16>(d.t_elems);
+    return cv.bytes();
+}
+
+dmet_status lp_transform(const EriPlan& p, const void* lmunu, const double* ck, float* z, void* ws, size_t ws_bytes,
+                         hipStream_t st) {
+    if (lp_transform_workspace(p) > ws_bytes) return fail(DMET_E_WORKSPACE, "split-bf16 transform workspace");
+    Carve cv(ws, ws_bytes);
+    return p.prec == DMET_BF16X3_3M ? xform_packed<2>(p, lmunu, ck, z, cv, st) : xform_packed<3>(p, lmunu, ck, z, cv, st);
+}
+
+// The packed split-bf16 contraction (s8 per spin, s4 alpha-beta) of FP64 rows
+// made elsewhere: z[s] is krows x ldz (row-major, npair used columns).
+size_t lp_rows_contract_workspace(int nspin, int npair, int krows, int ns) {
+    return (size_t)nspin * ns * kgroups_of(krows) * 8 * npair * sizeof(__bf16) + 256;
+}
+
+template <int NS>
+static dmet_status lp_rows_contract_run(int nspin, int npair, int krows, const double* z, size_t zsp, size_t ldz,
+                                        double* eri_aa, double* eri_bb, double* eri_ab, __bf16* zp,
+                                        hipStream_t st) {
+    const int kg = kgroups_of(krows);
+    const size_t per_spin = (size_t)NS * kg * 8 * npair;
+    for (int s = 0; s < nspin; ++s) {
+        ProfScope ps(NS == 2 ? "pack_bf16x3" : "pack_bf16x6", st);
+        k_pack_parts<NS, double><<<dim3((npair + 255) / 256, kg), 256, 0, st>>>(z + s * zsp, ldz, krows, npair, kg,
+                                                                               zp + s * per_spin);
+        ps.stop();
+        DMET_LAUNCH_CHECK("k_pack_parts");
+    }
+    constexpr int G = 4, NB = NS == 3 ? 2 : 3;
+    auto kw0 = k_contract_w8<NS, 0, G, NB>;
+    auto kw1 = k_contract_w8<NS, 1, G, NB>;
+    constexpr size_t lds = w8_lds<NS, G, NB>();
+    DMET_HIP(hipFuncSetAttribute((const void*)kw0, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    DMET_HIP(hipFuncSetAttribute((const void*)kw1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    for (int s = 0; s < nspin; ++s) {
+        const long nb = w8_grid(0, npair);
+        ProfScope ps(NS == 3 ? "contract_s8_bf16x6" : "contract_s8_bf16x3", st);
+        kw0<<<dim3((unsigned)nb), 512, lds, st>>>(npair, kg, zp + s * per_spin, zp + s * per_spin, FLUSH_K, nb,
+                                                  s == 0 ? eri_aa : eri_bb);
+        ps.stop();
+        DMET_LAUNCH_CHECK("contract_s8 rows");
+    }
+    if (nspin == 2 && eri_ab) {
+        const long nb = w8_grid(1, npair);
+        ProfScope ps(NS == 3 ? "contract_s4_bf16x6" : "contract_s4_bf16x3", st);
+        kw1<<<dim3((unsigned)nb), 512, lds, st>>>(npair, kg, zp, zp + per_spin, FLUSH_K, nb, eri_ab);
+        ps.stop();
+        DMET_LAUNCH_CHECK("contract_s4 rows");
+    }
+    return DMET_OK;
+}
+
+dmet_status lp_rows_contract(int ns, int nspin, int npair, int krows, const double* z, size_t zsp, size_t ldz,
+                             double* eri_aa, double* eri_bb, double* eri_ab, void* ws, size_t ws_bytes,
+                             hipStream_t st) {
+    if (ns != 2 && ns != 3) return fail(DMET_E_ARG, "split-bf16 contraction: two or three parts");
+    if (lp_rows_contract_workspace(nspin, npair, krows, ns) > ws_bytes)
+        return fail(DMET_E_WORKSPACE, "split-bf16 contraction workspace");
+    __bf16* zp = static_cast<__bf16*>(ws);
+    return ns == 3 ? lp_rows_contract_run<3>(nspin, npair, krows, z, zsp, ldz, eri_aa, eri_bb, eri_ab, zp, st)
+                   : lp_rows_contract_run<2>(nspin, npair, krows, z, zsp, ldz, eri_aa, eri_bb, eri_ab, zp, st);
 }
 
 }  // namespace dmet

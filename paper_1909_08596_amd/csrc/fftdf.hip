@@ -72,11 +72,12 @@ void reciprocal(const double (&a)[3][3], double (&b)[3][3], double& vol) {
 
 // One axis of W: out[.., g, ..][p] = sum_t exp(+2 pi i (N g + m) t / (N n)) in[.., t, ..][p]
 // over a [x0][x1][x2][pair] layout.  IN: 0 complex buffer, 1 real rows
-// (row zrow0 + r), 2 interleaved Re/Im rows (row zrow0 + 2 r + part).  OUT: 0
-// complex buffer, 1 scaled rows zg0 + 2 G + part.
-template <int IN, int OUT>
+// (row zrow0 + r), 2 interleaved Re/Im rows (row zrow0 + 2 r + part), rows of
+// type T (FP64, or FP32 from the split-bf16 transform).  OUT: 0 complex buffer,
+// 1 scaled rows zg0 + 2 G + part.  The sums run in FP64.
+template <int IN, int OUT, class T = double>
 __global__ void __launch_bounds__(256) k_pw_axis(PwAxis ax, int npair, const double2* __restrict__ cin,
-                                                 const double* __restrict__ zin, size_t zrow0, size_t ldz,
+                                                 const T* __restrict__ zin, size_t zrow0, size_t ldz,
                                                  double2* __restrict__ cout, double* __restrict__ zout, size_t zg0,
                                                  PwScale ks) {
     extern __shared__ double2 tw[];   // tw[j] = exp(2 pi i j / L), L = N_d n_d entries
@@ -113,11 +114,11 @@ __global__ void __launch_bounds__(256) k_pw_axis(PwAxis ax, int npair, const dou
                 vr = v.x;
                 vi = v.y;
             } else if (IN == 1) {
-                vr = zin[(zrow0 + rt) * ldz + p];
+                vr = (double)zin[(zrow0 + rt) * ldz + p];
                 vi = 0.0;
             } else {
-                vr = zin[(zrow0 + 2 * rt) * ldz + p];
-                vi = zin[(zrow0 + 2 * rt + 1) * ldz + p];
+                vr = (double)zin[(zrow0 + 2 * rt) * ldz + p];
+                vi = (double)zin[(zrow0 + 2 * rt + 1) * ldz + p];
             }
             re += w.x * vr - w.y * vi;
             im += w.x * vi + w.y * vr;
@@ -133,21 +134,26 @@ __global__ void __launch_bounds__(256) k_pw_axis(PwAxis ax, int npair, const dou
 }
 
 struct PwDims {
-    size_t nr, eri_ws, zr, buf, zg, part;
+    size_t nr, eri_ws, zr, buf, zg, part;   // zr in elements of the row type; eri_ws, part in bytes
     int zrows_g, krows_p, ldz;
+    bool split;                               // split-bf16 transform and contraction
+    int ns;
 };
 
 PwDims pw_dims(const EriPlan& p) {
     PwDims d;
+    d.split = p.prec == DMET_BF16X6_3M || p.prec == DMET_BF16X3_3M;
+    d.ns = p.prec == DMET_BF16X3_3M ? 2 : 3;
     d.nr = (size_t)p.naux;
     d.zrows_g = (int)(2 * d.nr * p.qblocks.size());
     d.krows_p = (d.zrows_g + 15) / 16 * 16;
     d.ldz = (p.npair + 1) / 2 * 2;
-    d.eri_ws = eri_f64_workspace(p);
+    d.eri_ws = d.split ? lp_transform_workspace(p) : eri_f64_workspace(p);
     d.zr = (size_t)p.nspin * p.zrows * p.npair;
     d.buf = d.nr * p.npair;
     d.zg = (size_t)p.nspin * d.krows_p * d.ldz;
-    d.part = contract_f64_workspace(p.nspin, p.npair, d.krows_p);
+    d.part = d.split ? lp_rows_contract_workspace(p.nspin, p.npair, d.krows_p, d.ns)
+                     : contract_f64_workspace(p.nspin, p.npair, d.krows_p) * sizeof(double);
     return d;
 }
 
@@ -157,30 +163,35 @@ size_t fftdf_workspace(const EriPlan& p) {
     PwDims d = pw_dims(p);
     Carve cv(nullptr, 0);
     cv.take<char>(d.eri_ws);
-    cv.take<double>(d.zr);
+    if (d.split) cv.take<float>(d.zr);
+    else cv.take<double>(d.zr);
     cv.take<double2>(d.buf);
     cv.take<double2>(d.buf);
     cv.take<double>(d.zg);
-    cv.take<double>(d.part);
+    cv.take<char>(d.part);
     return cv.bytes();
 }
 
 dmet_status fftdf_eri(const EriPlan& p, const dmet_pw_grid* grid, const void* rho, const double* ck, double* eri_aa,
                       double* eri_bb, double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st) {
     PwDims d = pw_dims(p);
+    if (p.prec != DMET_FP64 && !d.split)
+        return fail(DMET_E_UNSUPPORTED, "fftdf: FP64, BF16X6_3M or BF16X3_3M");
     Carve cv(ws, ws_bytes);
     void* ews = cv.take<char>(d.eri_ws);
-    double* zr = cv.take<double>(d.zr);
+    double* zr = d.split ? nullptr : cv.take<double>(d.zr);
+    float* zf = d.split ? cv.take<float>(d.zr) : nullptr;
     double2* b1 = cv.take<double2>(d.buf);
     double2* b2 = cv.take<double2>(d.buf);
     double* zg = cv.take<double>(d.zg);
-    double* part = cv.take<double>(d.part);
+    void* part = cv.take<char>(d.part);
     if (cv.bytes() > ws_bytes) return fail(DMET_E_WORKSPACE, "fftdf workspace too small");
     for (int a = 0; a < 3; ++a)
         if ((long)grid->n[a] * p.mesh.n[a] > PW_MAXL)
             return fail(DMET_E_UNSUPPORTED, "fftdf: at most 8192 supercell grid points per axis (N_d n_d)");
     // embedded pair densities on the grid, real rows per q block (Alg. 1 transform)
-    dmet_status s = eri_f64(p, rho, ck, nullptr, nullptr, nullptr, ews, d.eri_ws, st, zr);
+    dmet_status s = d.split ? lp_transform(p, rho, ck, zf, ews, d.eri_ws, st)
+                            : eri_f64(p, rho, ck, nullptr, nullptr, nullptr, ews, d.eri_ws, st, zr);
     if (s != DMET_OK) return s;
     PwScale ks;
     for (int a = 0; a < 3; ++a) {
@@ -192,14 +203,16 @@ dmet_status fftdf_eri(const EriPlan& p, const dmet_pw_grid* grid, const void* rh
     {   // root tables above 64 KB of LDS need the larger dynamic allocation
         int lmax = 0;
         for (int a = 0; a < 3; ++a) lmax = std::max(lmax, grid->n[a] * p.mesh.n[a] * (int)sizeof(double2));
-        const void* ks4[4] = {(const void*)k_pw_axis<1, 0>, (const void*)k_pw_axis<2, 0>, (const void*)k_pw_axis<0, 0>,
-                              (const void*)k_pw_axis<0, 1>};
-        for (const void* kf : ks4) DMET_HIP(hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, lmax));
+        const void* ks6[6] = {(const void*)k_pw_axis<1, 0>,        (const void*)k_pw_axis<2, 0>,
+                              (const void*)k_pw_axis<1, 0, float>, (const void*)k_pw_axis<2, 0, float>,
+                              (const void*)k_pw_axis<0, 0>,        (const void*)k_pw_axis<0, 1>};
+        for (const void* kf : ks6) DMET_HIP(hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, lmax));
     }
     const long total = (long)d.nr * p.npair;
     const unsigned nb = (unsigned)std::min<long>((total + 255) / 256, 65535L * 4);
     for (int sp = 0; sp < p.nspin; ++sp) {
-        const double* zs = zr + (size_t)sp * p.zrows * p.npair;
+        const double* zs = d.split ? nullptr : zr + (size_t)sp * p.zrows * p.npair;
+        const float* zsf = d.split ? zf + (size_t)sp * p.zrows * p.npair : nullptr;
         double* zgs = zg + (size_t)sp * d.krows_p * d.ldz;
         if (d.krows_p > d.zrows_g)   // zero rows up to a multiple of 16 for the contraction
             fill_zero(zgs + (size_t)d.zrows_g * d.ldz, (size_t)(d.krows_p - d.zrows_g) * d.ldz * sizeof(double), st);
@@ -216,7 +229,13 @@ dmet_status fftdf_eri(const EriPlan& p, const dmet_pw_grid* grid, const void* rh
             ax.axis = 0;
             ax.nmesh = p.mesh.n[0];
             ax.m = m[0];
-            if (qb.self_conj)
+            if (d.split && qb.self_conj)
+                k_pw_axis<1, 0, float><<<nb, 256, lds(0), st>>>(ax, p.npair, nullptr, zsf, qb.zrow0, p.npair, b1,
+                                                                nullptr, 0, ks);
+            else if (d.split)
+                k_pw_axis<2, 0, float><<<nb, 256, lds(0), st>>>(ax, p.npair, nullptr, zsf, qb.zrow0, p.npair, b1,
+                                                                nullptr, 0, ks);
+            else if (qb.self_conj)
                 k_pw_axis<1, 0><<<nb, 256, lds(0), st>>>(ax, p.npair, nullptr, zs, qb.zrow0, p.npair, b1, nullptr, 0,
                                                          ks);
             else
@@ -225,17 +244,21 @@ dmet_status fftdf_eri(const EriPlan& p, const dmet_pw_grid* grid, const void* rh
             ax.axis = 1;
             ax.nmesh = p.mesh.n[1];
             ax.m = m[1];
-            k_pw_axis<0, 0><<<nb, 256, lds(1), st>>>(ax, p.npair, b1, nullptr, 0, p.npair, b2, nullptr, 0, ks);
+            k_pw_axis<0, 0, double><<<nb, 256, lds(1), st>>>(ax, p.npair, b1, nullptr, 0, p.npair, b2, nullptr, 0, ks);
             ax.axis = 2;
             ax.nmesh = p.mesh.n[2];
             ax.m = m[2];
-            k_pw_axis<0, 1><<<nb, 256, lds(2), st>>>(ax, p.npair, b2, nullptr, 0, d.ldz, nullptr, zgs, 2 * d.nr * b,
+            k_pw_axis<0, 1, double><<<nb, 256, lds(2), st>>>(ax, p.npair, b2, nullptr, 0, d.ldz, nullptr, zgs, 2 * d.nr * b,
                                                      ks);
             ps.stop();
             DMET_LAUNCH_CHECK("k_pw_axis");
         }
     }
-    return contract_f64(p.nspin, p.npair, d.ldz, d.krows_p, zg, eri_aa, eri_bb, eri_ab, part, st);
+    if (d.split)
+        return lp_rows_contract(d.ns, p.nspin, p.npair, d.krows_p, zg, (size_t)d.krows_p * d.ldz, (size_t)d.ldz,
+                                eri_aa, eri_bb, eri_ab, part, d.part, st);
+    return contract_f64(p.nspin, p.npair, d.ldz, d.krows_p, zg, eri_aa, eri_bb, eri_ab, static_cast<double*>(part),
+                        st);
 }
 
 }  // namespace dmet

@@ -115,8 +115,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dmet_transform_eri_impurity_workspace.argtypes = [lp, i, i, i, i, ctypes.POINTER(sz)]
     lib.dmet_transform_eri_impurity.argtypes = [lp, i, i, vp, i, vp, i, vp, vp, vp, vp, sz, vp]
     gp = ctypes.POINTER(PwGrid)
-    lib.dmet_transform_eri_fftdf_workspace.argtypes = [lp, gp, i, i, ctypes.POINTER(sz)]
-    lib.dmet_transform_eri_fftdf.argtypes = [lp, gp, i, vp, i, vp, vp, vp, vp, vp, sz, vp]
+    lib.dmet_transform_eri_fftdf_workspace.argtypes = [lp, gp, i, i, i, ctypes.POINTER(sz)]
+    lib.dmet_transform_eri_fftdf.argtypes = [lp, gp, i, vp, i, i, vp, vp, vp, vp, vp, sz, vp]
     lib.dmet_fock_dc_workspace.argtypes = [i, i, i, ctypes.POINTER(sz)]
     lib.dmet_fock_dc.argtypes = [i, i, i, vp, vp, vp, vp, vp, sz, vp]
     lib.dmet_energy_mf.argtypes = [i, i, vp, vp, vp, vp, vp]
@@ -385,12 +385,13 @@ def dmet_transform_eri_impurity(kmesh, nao, naux, lmunu: torch.Tensor, c_k: torc
 
 
 def dmet_transform_eri_fftdf(kmesh, nao, grid_n, cell, rho: torch.Tensor, c_k: torch.Tensor, eri_ab: bool = True,
-                             workspace: Optional[torch.Tensor] = None, stream=None):
-    """Plane-wave (FFTDF) embedding ERIs (App. B, Alg. 2), FP64.  rho is the
-    AO pair density on the cell grid [q][k][r][mu][nu] = (r|mu k, nu k-q),
-    grid_n the grid points per axis and cell the three lattice vectors as rows
-    (bohr) or the three edge lengths of an orthorhombic cell.  Same return value
-    as dmet_transform_eri."""
+                             workspace: Optional[torch.Tensor] = None, stream=None, precision: str = "fp64"):
+    """Plane-wave (FFTDF) embedding ERIs (App. B, Alg. 2).  rho is the AO pair
+    density on the cell grid [q][k][r][mu][nu] = (r|mu k, nu k-q), grid_n the
+    grid points per axis and cell the three lattice vectors as rows (bohr) or
+    the three edge lengths of an orthorhombic cell; precision "fp64", "bf16x6"
+    or "bf16x3" (the transform and contraction in that form, the grid DFT in
+    FP64).  Same return value as dmet_transform_eri."""
     lib = load()
     nr = int(grid_n[0]) * int(grid_n[1]) * int(grid_n[2])
     nspin, neo = _eri_inputs(kmesh, nao, nr, rho, c_k, "rho")
@@ -405,11 +406,13 @@ def dmet_transform_eri_fftdf(kmesh, nao, grid_n, cell, rho: torch.Tensor, c_k: t
         if eri_ab:
             out["ab"] = torch.empty((npair, npair), dtype=torch.float64, device=dev)
     nb = ctypes.c_size_t()
-    _check(lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(grid), neo, dt, ctypes.byref(nb)))
+    prec = PRECISIONS[precision]
+    _check(lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(grid), neo, dt, prec,
+                                                  ctypes.byref(nb)))
     if workspace is None:
         workspace = _workspace(nb.value, dev)
     _workspace_ok(workspace, nb.value)
-    _check(lib.dmet_transform_eri_fftdf(ctypes.byref(lat), ctypes.byref(grid), neo, _ptr(rho), dt, _ptr(c_k),
+    _check(lib.dmet_transform_eri_fftdf(ctypes.byref(lat), ctypes.byref(grid), neo, _ptr(rho), dt, prec, _ptr(c_k),
                                         _ptr(out["aa"]), _ptr(out.get("bb")), _ptr(out.get("ab")), _ptr(workspace),
                                         workspace.numel(), _stream(stream)))
     return out

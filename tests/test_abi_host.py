@@ -118,35 +118,47 @@ def test_fftdf_argument_validation(lib):
     nb = ctypes.c_size_t()
     lat = _lat(naux=216)
     good = dmet.pw_grid((6, 6, 6), (3.0, 3.0, 3.0))
-    assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(good), 16, 0,
+    assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(good), 16, 0, 0,
                                                   ctypes.byref(nb)) == 0
     assert nb.value > 0
     bad_n = dmet.pw_grid((6, 6, 5), (3.0, 3.0, 3.0))          # 180 points != naux
-    assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(bad_n), 16, 0,
+    assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(bad_n), 16, 0, 0,
                                                   ctypes.byref(nb)) == E_ARG
     bad_c = dmet.pw_grid((6, 6, 6), (3.0, 0.0, 3.0))
-    assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(bad_c), 16, 0,
+    assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(bad_c), 16, 0, 0,
                                                   ctypes.byref(nb)) == E_ARG
     # a general (hexagonal) cell is accepted; linearly dependent or non-finite vectors are not
     hexa = dmet.pw_grid((6, 6, 6), ((2.6, 0, 0), (1.3, 2.25, 0), (0, 0, 3.2)))
-    assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(hexa), 16, 0,
+    assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(hexa), 16, 0, 0,
                                                   ctypes.byref(nb)) == 0
     flat = dmet.pw_grid((6, 6, 6), ((2.6, 0, 0), (1.3, 2.25, 0), (3.9, 2.25, 0)))   # a_3 = a_1 + a_2
-    assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(flat), 16, 0,
+    assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(flat), 16, 0, 0,
                                                   ctypes.byref(nb)) == E_ARG
     assert b"linearly independent" in lib.dmet_last_error()
     nan = dmet.pw_grid((6, 6, 6), ((2.6, 0, 0), (1.3, float("nan"), 0), (0, 0, 3.2)))
-    assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(nan), 16, 0,
+    assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(nan), 16, 0, 0,
                                                   ctypes.byref(nb)) == E_ARG
     # edge lengths are the diagonal cell
     g = dmet.pw_grid((2, 3, 4), (3.0, 4.0, 5.0))
     assert [[g.cell[a][b] for b in range(3)] for a in range(3)] == [[3, 0, 0], [0, 4, 0], [0, 0, 5]]
     with pytest.raises(ValueError):
         dmet.pw_grid((2, 3, 4), ((1.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0)))
-    assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), None, 16, 0, ctypes.byref(nb)) == E_ARG
+    assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), None, 16, 0, 0, ctypes.byref(nb)) == E_ARG
     # null arrays are rejected before any launch
-    assert lib.dmet_transform_eri_fftdf(ctypes.byref(lat), ctypes.byref(good), 16, None, 0, None, None, None,
+    assert lib.dmet_transform_eri_fftdf(ctypes.byref(lat), ctypes.byref(good), 16, None, 0, 0, None, None, None,
                                         None, None, 0, None) == E_ARG
+    # precision forms: the split-bf16 ones are accepted (larger workspace than FP64), FP32 and the int8
+    # contraction are not offered on the plane-wave route
+    nb64 = ctypes.c_size_t()
+    assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(good), 16, 0, dmet.DMET_FP64,
+                                                  ctypes.byref(nb64)) == 0
+    for prec in (dmet.DMET_BF16X6_3M, dmet.DMET_BF16X3_3M):
+        assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(good), 16, 0, prec,
+                                                      ctypes.byref(nb)) == 0
+        assert nb.value > 0
+    for prec in (dmet.DMET_FP32_3M, dmet.DMET_BF16X6_I8):
+        assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(good), 16, 0, prec,
+                                                      ctypes.byref(nb)) == 7   # DMET_E_UNSUPPORTED
 
 
 def test_binding_rejects_mismatched_shapes():

@@ -23,14 +23,50 @@ def dmet():
     return d
 
 
-def _run(dmet, wl, g):
+def _run(dmet, wl, g, precision="fp64"):
     lat = synth.make_lattice(wl)
     rho = synth.fftdf_pair_density(wl, g)
     bath = ok.build_bath(lat.dm_k, wl.kmesh, wl.nao)
     ck = bath["c_k"]
-    out = dmet.dmet_transform_eri_fftdf(wl.kmesh, wl.nao, g.n, g.cell, to_dev(rho), to_dev(ck))
+    out = dmet.dmet_transform_eri_fftdf(wl.kmesh, wl.nao, g.n, g.cell, to_dev(rho), to_dev(ck), precision=precision)
     torch.cuda.synchronize()
     return rho, ck, out
+
+
+# split-bf16 forms on the plane-wave route: max-abs bound relative to max|ERI| (~1 Ha here)
+SPLIT_TOL = {"bf16x6": 1e-6, "bf16x3": 1e-5}
+
+
+@pytest.mark.parametrize("prec", ["bf16x6", "bf16x3"])
+@pytest.mark.parametrize("name", ["fft_tiny", "fft_odd", "fft_hex"])
+def test_fftdf_split_forms_small(dmet, name, prec):
+    wl, g = synth.FFT_CONFIGS[name]
+    rho, ck, out = _run(dmet, wl, g, prec)
+    ref, im = ok.alg2_eri(rho, ck[0], wl.kmesh, g.n, g.cell)
+    refp = ok.pack_s8(ref)
+    err = np.abs(out["aa"].cpu().numpy() - refp).max()
+    print(f"{name} fftdf {prec}: max err {err:.3e} (max {np.abs(refp).max():.3f})")
+    assert err < SPLIT_TOL[prec] * max(1.0, np.abs(refp).max())
+
+
+def test_fftdf_split_uhf_and_fullsize(dmet):
+    """BF16x6 on the UHF case with the alpha-beta block, and at the benchmark's
+    plane-wave size (2x2x2 mesh, 16^3 grid, 52 EOs) on every element."""
+    wl = synth.Workload("fft_u", (3, 2, 1), 6, 240, 6, 6, 2, 1.5, 1013)
+    g = synth.FftGrid((6, 5, 8), (3.0, 2.6, 3.4))
+    rho, ck, out = _run(dmet, wl, g, "bf16x6")
+    for key, (a, b) in {"aa": (0, None), "bb": (1, None), "ab": (0, 1)}.items():
+        ref, _ = ok.alg2_eri(rho, ck[a], wl.kmesh, g.n, g.cell, None if b is None else ck[b])
+        ref = ok.pack_s8(ref) if b is None else ok.pack_s4(ref)
+        err = np.abs(out[key].cpu().numpy().reshape(ref.shape) - ref).max()
+        assert err < 1e-6 * max(1.0, np.abs(ref).max()), (key, err)
+    wl, g = synth.FFT_CONFIGS["fft_si"]
+    rho, ck, out = _run(dmet, wl, g, "bf16x6")
+    ref, _ = ok.alg2_eri(rho, ck[0], wl.kmesh, g.n, g.cell)
+    refp = ok.pack_s8(ref)
+    err = np.abs(out["aa"].cpu().numpy() - refp).max()
+    print(f"fft_si fftdf bf16x6: max err {err:.3e} (max {np.abs(refp).max():.3f})")
+    assert err < 1e-6 * max(1.0, np.abs(refp).max())
 
 
 @pytest.mark.parametrize("name", ["fft_tiny", "fft_odd", "fft_hex"])
