@@ -464,3 +464,46 @@ def test_eri_block_and_diag_forms():
     full, _ = ok.alg1_eri(lm, ck[0], wl.kmesh)
     d = ok.alg1_eri_diag(xa, tri)
     assert np.abs(d - np.array([full[i, j, i, j] for (i, j) in tri])).max() < 1e-13 * np.abs(full).max()
+
+
+def test_energy_1e_against_supercell(odd):
+    """E1 (Eq. emb Ham) from the k-space transforms equals the trace of the
+    supercell operators projected on the embedding orbitals, and does not
+    change under a rotation of the embedding orbitals."""
+    wl, lat, lm, b, bath = odd
+    h1, _ = ok.transform_1e(bath["c_k"], lat.h_k)
+    g1, _ = ok.transform_1e(bath["c_k"], lat.dm_k)
+    cr = bath["c_r"][0].reshape(wl.nk * wl.nao, wl.neo)
+    hsup = sc.supercell_operator(lat.t_h, wl.kmesh)
+    gsup, _ = sc.supercell_dm(lat.dm_k[0], wl.kmesh)
+    e_sup = float(np.trace((cr.T @ hsup @ cr) @ (cr.T @ gsup @ cr)))
+    assert abs(ok.energy_1e(h1, g1) - e_sup) < 1e-12 * max(1.0, abs(e_sup))
+    q, _ = np.linalg.qr(np.random.default_rng(3).standard_normal((wl.neo, wl.neo)))
+    rot = lambda x: np.einsum("ai,sab,bj->sij", q, x, q)
+    assert abs(ok.energy_1e(rot(h1), rot(g1)) - e_sup) < 1e-12 * max(1.0, abs(e_sup))
+
+
+def test_pair_packing_brute_force():
+    """pair_index enumerates i >= j row by row; pack_s4 holds [ij][kl] over those
+    pairs (both spins have the same neo) and pack_s8 the lower triangle
+    IJ >= KL, element by element, on tensors without any symmetry."""
+    n = m = 4
+    pairs_n = [(i, j) for i in range(n) for j in range(i + 1)]
+    pairs_m = [(k, l) for k in range(m) for l in range(k + 1)]
+    assert [ok.pair_index(i, j) for i, j in pairs_n] == list(range(len(pairs_n)))
+    assert all(ok.pair_index(j, i) == ok.pair_index(i, j) for i, j in pairs_n)
+    rng = np.random.default_rng(9)
+    e4 = rng.standard_normal((n, n, m, m))
+    p4 = ok.pack_s4(e4)
+    assert p4.shape == (len(pairs_n), len(pairs_m))
+    for a, (i, j) in enumerate(pairs_n):
+        for c, (k, l) in enumerate(pairs_m):
+            assert p4[a, c] == e4[i, j, k, l]
+    e8 = rng.standard_normal((n, n, n, n))
+    p8 = ok.pack_s8(e8)
+    pos = 0
+    for a, (i, j) in enumerate(pairs_n):
+        for c, (k, l) in enumerate(pairs_n[: a + 1]):
+            assert p8[pos] == e8[i, j, k, l]
+            pos += 1
+    assert pos == p8.size
