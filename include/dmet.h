@@ -50,7 +50,9 @@
  * sweeps of the bath SVD (a lower cap forces DMET_E_NOCONV on purpose);
  * DMET_XF2_SMALL_NEO=n sets the largest fragment neo that the batched form
  * transforms with 32 x 32 stage-2 tiles (default 256); DMET_TUNE_CACHE names
- * the file of the batched autotuner's choices.
+ * the file of the batched autotuner's choices; DMET_I8_CHUNK_ROWS=n (a
+ * multiple of 64 up to 44032, the default) sets the rows per launch of the
+ * int8 contraction.
  */
 #ifndef DMET_H
 #define DMET_H
@@ -92,8 +94,11 @@ typedef enum {
                                 digits (fixed point, ~2^-23 of the column's
                                 largest entry), the six digit products of
                                 level <= 2 summed exactly in int32 and combined
-                                in FP64.  At most N_k*naux = 44032 rows
-                                (DMET_E_UNSUPPORTED above)                     */
+                                in FP64; the sums stay exact for 44032 rows per
+                                launch, and longer Z (N_k*naux rows) runs in
+                                chunks of up to 44032 rows whose scaled FP64
+                                results are added in order (the batched form
+                                takes at most 44032 rows per fragment)         */
 } dmet_precision;
 
 typedef enum {

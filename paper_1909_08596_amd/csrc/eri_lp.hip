@@ -523,11 +523,14 @@ __global__ void k_pack_i8(const float* __restrict__ z, size_t ldz, int krows, in
 // per stage for three digit planes) moved by buffer loads straight into LDS,
 // as in k_contract_w8; per 32-row k-step 24 MFMAs into three int32
 // accumulator sets (levels 0, 1, 2).  No partial flush: the sums are exact.
-template <int MODE>
+// A launch sums the kgroups 16-row groups it is given (a chunk of at most
+// I8_KMAX rows of planes holding kplane groups each); with accumulate the
+// scaled chunk result is added to out (ACC), so longer Z runs chunk by chunk.
+template <int MODE, bool ACC>
 __global__ void __launch_bounds__(512) k_contract_i8(int npair, int kgroups, const i4v* __restrict__ pa,
                                                      const i4v* __restrict__ pb, const int* __restrict__ exa,
                                                      const int* __restrict__ exb, long nblocks,
-                                                     double* __restrict__ out) {
+                                                     double* __restrict__ out, int kplane) {
     constexpr int NS = 3, G = 4, NBUF = 2;
     constexpr int BM = 128, BN = 256;
     constexpr int TM = 2, TN = 2;
@@ -544,7 +547,7 @@ __global__ void __launch_bounds__(512) k_contract_i8(int npair, int kgroups, con
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wm0 = (wave >> 2) * 64, wn0 = (wave & 3) * 64;
-    const size_t plane = (size_t)kgroups * npair;
+    const size_t plane = (size_t)kplane * npair;
     const int nkt = kgroups / G;
     const int fa = wave * CA;
     const unsigned offa = (unsigned)min(m0 + fa % BM + (lane & (CA - 1)), npair - 1) * 16u;
@@ -672,8 +675,9 @@ __global__ void __launch_bounds__(512) k_contract_i8(int npair, int kgroups, con
                 const int ea = exa[IJ];
                 double v = (double)acc0[i][j][r] + ((double)acc1[i][j][r] + (double)acc2[i][j][r] * inv_b) * inv_b;
                 v = (ea == I8_EBAD || eb == I8_EBAD) ? __builtin_nan("") : ldexp(v * inv_b0sq, ea + eb);
-                if constexpr (MODE == 0) out[(size_t)IJ * (IJ + 1) / 2 + KL] = v;
-                else out[(size_t)IJ * npair + KL] = v;
+                double& o = MODE == 0 ? out[(size_t)IJ * (IJ + 1) / 2 + KL] : out[(size_t)IJ * npair + KL];
+                if constexpr (ACC) o += v;
+                else o = v;
             }
     }
 }
@@ -1795,6 +1799,14 @@ static size_t packed_elems(const EriPlan& p) {
 
 // int8 digit planes: groups of 16 rows, a multiple of the 4 groups of a stage
 static int kgroups16_of(int krows) { return (krows + 63) / 64 * 4; }
+
+// Rows per int8 contraction launch: I8_KMAX, or DMET_I8_CHUNK_ROWS (a multiple
+// of 64 in [64, I8_KMAX]) to run Z in smaller chunks.
+static int i8_chunk_rows() {
+    const char* e = getenv("DMET_I8_CHUNK_ROWS");
+    const int v = e ? atoi(e) : I8_KMAX;
+    return v >= 64 && v <= I8_KMAX && v % 64 == 0 ? v : I8_KMAX;
+}
 static size_t i8_chunks(const EriPlan& p) { return (size_t)3 * kgroups16_of(p.zrows) * p.npair; }
 
 // padded sizes of the packed transform operands
@@ -1996,22 +2008,33 @@ static dmet_status eri_i8_run(const EriPlan& p, const void* lmunu, const double*
     }
     constexpr size_t lds = i8_lds();
     static_assert(lds <= 160 * 1024, "LDS per workgroup");
-    DMET_HIP(hipFuncSetAttribute((const void*)k_contract_i8<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    DMET_HIP(hipFuncSetAttribute((const void*)k_contract_i8<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const void* kc[4] = {(const void*)k_contract_i8<0, false>, (const void*)k_contract_i8<0, true>,
+                         (const void*)k_contract_i8<1, false>, (const void*)k_contract_i8<1, true>};
+    for (const void* f : kc) DMET_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    // chunks of at most I8_KMAX rows (exact int32 sums each), added in FP64 in order
+    const int kg_chunk = i8_chunk_rows() / 16;
     for (int s = 0; s < p.nspin; ++s) {
         const long nb = w8_grid(0, p.npair);
         ProfScope ps("contract_s8_i8", st);
-        k_contract_i8<0><<<dim3((unsigned)nb), 512, lds, st>>>(p.npair, kg, zp + s * per_spin, zp + s * per_spin,
-                                                               ex + (size_t)s * p.npair, ex + (size_t)s * p.npair, nb,
-                                                               s == 0 ? eri_aa : eri_bb);
+        for (int g0 = 0; g0 < kg; g0 += kg_chunk) {
+            const size_t off = (size_t)g0 * p.npair;
+            auto k8 = g0 > 0 ? k_contract_i8<0, true> : k_contract_i8<0, false>;
+            k8<<<dim3((unsigned)nb), 512, lds, st>>>(p.npair, std::min(kg_chunk, kg - g0), zp + s * per_spin + off,
+                                                     zp + s * per_spin + off, ex + (size_t)s * p.npair,
+                                                     ex + (size_t)s * p.npair, nb, s == 0 ? eri_aa : eri_bb, kg);
+        }
         ps.stop();
         DMET_LAUNCH_CHECK("contract_s8_i8");
     }
     if (p.nspin == 2 && eri_ab) {
         const long nb = w8_grid(1, p.npair);
         ProfScope ps("contract_s4_i8", st);
-        k_contract_i8<1><<<dim3((unsigned)nb), 512, lds, st>>>(p.npair, kg, zp, zp + per_spin, ex, ex + p.npair, nb,
-                                                               eri_ab);
+        for (int g0 = 0; g0 < kg; g0 += kg_chunk) {
+            const size_t off = (size_t)g0 * p.npair;
+            auto k4 = g0 > 0 ? k_contract_i8<1, true> : k_contract_i8<1, false>;
+            k4<<<dim3((unsigned)nb), 512, lds, st>>>(p.npair, std::min(kg_chunk, kg - g0), zp + off,
+                                                     zp + per_spin + off, ex, ex + p.npair, nb, eri_ab, kg);
+        }
         ps.stop();
         DMET_LAUNCH_CHECK("contract_s4_i8");
     }
@@ -2033,9 +2056,6 @@ dmet_status eri_lp(const EriPlan& p, const void* lmunu, const double* ck, double
     cv.take<__bf16>(d.t_elems);
     float* z = cv.take<float>((size_t)p.nspin * p.zrows * p.npair);
     if (p.prec == DMET_BF16X6_I8) {
-        if (p.zrows > I8_KMAX && !df_out)
-            return fail(DMET_E_UNSUPPORTED, "the int8 contraction holds exact sums for at most 44032 rows "
-                                            "(N_k * naux); use DMET_BF16X6_3M");
         i4v* zp8 = cv.take<i4v>((size_t)p.nspin * i8_chunks(p));
         unsigned* cmax = cv.take<unsigned>((size_t)p.nspin * p.npair);
         int* ex = cv.take<int>((size_t)p.nspin * p.npair);

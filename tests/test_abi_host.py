@@ -223,13 +223,19 @@ def test_binding_rejects_bad_output_blocks():
 
 def test_int8_contraction_row_limit(lib):
     """The int8 contraction keeps exact int32 sums for at most 44032 rows
-    (3 * K * 127^2 < 2^31); a larger N_k * naux is refused on the host."""
+    (3 * K * 127^2 < 2^31).  A single call with more rows runs them in chunks
+    (its workspace query accepts them); the batched pipeline, one contraction
+    launch over all fragments, refuses a fragment above the limit on the host."""
     from paper_1909_08596_amd import dmet
-    fake = ctypes.c_void_p(0x1000)
-    lat = _lat(kmesh=(4, 4, 4), nao=4, naux=700)           # 44800 rows
-    st = lib.dmet_transform_eri(ctypes.byref(lat), 4, fake, 0, fake, dmet.DMET_BF16X6_I8, fake, None, None, fake,
-                                1 << 60, None)
-    assert st == 7 and b"44032" in lib.dmet_last_error()
     nb = ctypes.c_size_t()
-    lat = _lat(kmesh=(4, 4, 4), nao=4, naux=688)           # 44032 rows: accepted
+    lat = _lat(kmesh=(4, 4, 4), nao=4, naux=700)           # 44800 rows
     assert lib.dmet_transform_eri_workspace(ctypes.byref(lat), 4, dmet.DMET_BF16X6_I8, 0, ctypes.byref(nb)) == 0
+    assert nb.value > 0
+    fake = ctypes.c_void_p(0x1000)
+    fr = (dmet.Fragment * 1)()
+    fr[0].lat = _lat(kmesh=(4, 4, 4), nao=4, naux=700)
+    fr[0].neo, fr[0].lmunu, fr[0].dtype, fr[0].c_k, fr[0].eri = 4, fake, 0, fake, fake
+    assert lib.dmet_transform_eri_batched_workspace(1, fr, dmet.DMET_BF16X6_I8, ctypes.byref(nb)) == 7
+    assert b"44032" in lib.dmet_last_error()
+    fr[0].lat = _lat(kmesh=(4, 4, 4), nao=4, naux=688)     # 44032 rows: accepted
+    assert lib.dmet_transform_eri_batched_workspace(1, fr, dmet.DMET_BF16X6_I8, ctypes.byref(nb)) == 0

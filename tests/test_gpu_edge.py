@@ -80,3 +80,32 @@ def test_nonfinite_input_gives_nan_output(dmet, prec):
     clean = dmet.dmet_transform_eri(kmesh, nao, naux, to_dev(_inputs("odd_mesh")[4]), to_dev(c_k), prec)
     torch.cuda.synchronize()
     assert bool(torch.isfinite(clean["aa"]).all()), prec
+
+
+def test_int8_contraction_in_chunks(dmet, monkeypatch):
+    """Z longer than one int8 launch: forced 64-row chunks (3 on 160 rows) agree
+    with the oracle and, to FP64 rounding, with one chunk; and a 4x4x4 mesh with
+    700 fitting functions (44800 rows, above the 44032 of one launch) runs in two
+    chunks and agrees with the oracle."""
+    wl = synth.Workload("chunks", (2, 2, 1), 6, 40, 6, 6, 1, 1.5, 41)
+    lm = synth.three_index(wl)
+    rng = np.random.default_rng(41)
+    ck = np.stack([ok.emb_coeffs_k(rng.standard_normal((wl.nk, wl.nao, 5)) / np.sqrt(wl.nk * wl.nao), wl.kmesh)])
+    whole = dmet.dmet_transform_eri(wl.kmesh, wl.nao, wl.naux, to_dev(lm), to_dev(ck), "bf16x6_i8")["aa"].cpu().numpy()
+    monkeypatch.setenv("DMET_I8_CHUNK_ROWS", "64")
+    parts = dmet.dmet_transform_eri(wl.kmesh, wl.nao, wl.naux, to_dev(lm), to_dev(ck), "bf16x6_i8")["aa"].cpu().numpy()
+    monkeypatch.delenv("DMET_I8_CHUNK_ROWS")
+    ref, _ = ok.alg1_eri(lm, ck[0], wl.kmesh)
+    refp = ok.pack_s8(ref)
+    assert np.abs(parts - whole).max() < 1e-13 * np.abs(refp).max()
+    assert np.abs(parts - refp).max() < 1e-6 * max(1.0, np.abs(refp).max())
+    wl = synth.Workload("k64", (4, 4, 4), 2, 700, 2, 2, 1, 1.5, 42)
+    lm = synth.three_index(wl)
+    rng = np.random.default_rng(42)
+    ck = np.stack([ok.emb_coeffs_k(rng.standard_normal((wl.nk, wl.nao, 2)) / np.sqrt(wl.nk * wl.nao), wl.kmesh)])
+    got = dmet.dmet_transform_eri(wl.kmesh, wl.nao, wl.naux, to_dev(lm), to_dev(ck), "bf16x6_i8")["aa"].cpu().numpy()
+    ref, _ = ok.alg1_eri(lm, ck[0], wl.kmesh)
+    refp = ok.pack_s8(ref)
+    err = np.abs(got - refp).max()
+    print(f"44800 rows, int8 contraction in two chunks: max err {err:.3e} (max {np.abs(refp).max():.3f})")
+    assert err < 1e-6 * max(1.0, np.abs(refp).max())
