@@ -428,10 +428,11 @@ static dmet_status check_batch(int nfrag, const dmet_fragment* frags, dmet_preci
         dmet_status s = check_eri_args(&d.lat, d.neo, prec, d.dtype);
         if (s != DMET_OK) return fail(s, "fragment " + std::to_string(f) + ": " + dmet_last_error());
         const long nk = (long)d.lat.kmesh[0] * d.lat.kmesh[1] * d.lat.kmesh[2];
-        const bool split = prec == DMET_BF16X3_3M || prec == DMET_BF16X6_3M || prec == DMET_BF16X6_I8;
-        if (split && nk > KP_MAX)
+        const bool slots = prec == DMET_BF16X3_3M || prec == DMET_BF16X6_3M || prec == DMET_BF16X6_I8 ||
+                           prec == DMET_FP32_3M;
+        if (slots && nk > KP_MAX)
             return fail(DMET_E_UNSUPPORTED, "fragment " + std::to_string(f) +
-                                                ": the split-bf16 batched transform supports at most 256 k-points");
+                                                ": the split-bf16 and FP32 transforms support at most 256 k-points");
         if (d.lat.nspin != 1) return fail(DMET_E_ARG, "fragment " + std::to_string(f) + ": nspin must be 1");
         if (prec == DMET_BF16X6_I8 && nk * (long)d.lat.naux > 44032)
             return fail(DMET_E_UNSUPPORTED, "fragment " + std::to_string(f) +

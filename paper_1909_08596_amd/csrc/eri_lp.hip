@@ -2683,23 +2683,29 @@ static dmet_status loop_enqueue(int nfrag, const dmet_fragment* frags, dmet_prec
                                 void* ws, Branches& br, hipStream_t st) {
     (void)nfrag;
     DMET_HIP(hipEventRecord(br.fork, st));
-    for (size_t b = 0; b < lp.branch.size(); ++b) {
+    dmet_status s = DMET_OK;
+    size_t forked = 0;
+    for (size_t b = 0; b < lp.branch.size() && s == DMET_OK; ++b) {
         hipStream_t bs = br.st[b];
         DMET_HIP(hipStreamWaitEvent(bs, br.fork, 0));
+        ++forked;
         void* slice = static_cast<char*>(ws) + lp.off[b];
         const size_t cap = (b + 1 < lp.branch.size() ? lp.off[b + 1] : lp.bytes) - lp.off[b];
         for (int f : lp.branch[b]) {
             const EriPlan p = frag_plan(frags[f], prec);
             const double* ckf = static_cast<const double*>(frags[f].c_k);
-            dmet_status s = prec == DMET_FP64
-                                ? eri_f64(p, frags[f].lmunu, ckf, frags[f].eri, nullptr, nullptr, slice, cap, bs)
-                                : eri_f32(p, frags[f].lmunu, ckf, frags[f].eri, nullptr, nullptr, slice, cap, bs);
-            if (s != DMET_OK) return s;
+            s = prec == DMET_FP64 ? eri_f64(p, frags[f].lmunu, ckf, frags[f].eri, nullptr, nullptr, slice, cap, bs)
+                                  : eri_f32(p, frags[f].lmunu, ckf, frags[f].eri, nullptr, nullptr, slice, cap, bs);
+            if (s != DMET_OK) break;
         }
-        DMET_HIP(hipEventRecord(br.join[b], bs));
     }
-    for (size_t b = 0; b < lp.branch.size(); ++b) DMET_HIP(hipStreamWaitEvent(st, br.join[b], 0));
-    return DMET_OK;
+    // every forked branch joins the caller's stream, also after an error, so
+    // that later work on `stream` is ordered after whatever was enqueued
+    for (size_t b = 0; b < forked; ++b) {
+        DMET_HIP(hipEventRecord(br.join[b], br.st[b]));
+        DMET_HIP(hipStreamWaitEvent(st, br.join[b], 0));
+    }
+    return s;
 }
 
 size_t batch_workspace(int nfrag, const dmet_fragment* frags, dmet_precision prec) {

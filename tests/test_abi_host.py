@@ -98,6 +98,9 @@ def test_batched_kpoint_limit(lib):
     nb = ctypes.c_size_t()
     assert lib.dmet_transform_eri_batched_workspace(1, fr, dmet.DMET_BF16X6_3M, ctypes.byref(nb)) == 7
     assert b"256 k-points" in lib.dmet_last_error()
+    # FP32 batches too (checked before any branch is forked); FP64 has no such limit
+    assert lib.dmet_transform_eri_batched_workspace(1, fr, dmet.DMET_FP32_3M, ctypes.byref(nb)) == 7
+    assert lib.dmet_transform_eri_batched_workspace(1, fr, dmet.DMET_FP64, ctypes.byref(nb)) == 0
     fr[0].lat = _lat(kmesh=(4, 4, 4), nao=4, naux=4)
     assert lib.dmet_transform_eri_batched_workspace(1, fr, dmet.DMET_BF16X6_3M, ctypes.byref(nb)) == 0
 
