@@ -362,10 +362,15 @@ def run_fftdf(args, dev):
     wc = nk * nr * npair * (npair + 1.0)
     dname, (dn, dms) = max(prof.items(), key=lambda kv: kv[1][1])
     avg = dms / dn
+    # per launch (group): stage 1 / stage 2 of one q over all k, the contraction of one spin block, and the
+    # grid DFT of one q block (three axis passes, each output an n_d-point complex sum: 8 flop per term)
     kflops = {"xform1": 8.0 * nk * nr * nao * nao * neo, "xform2": 8.0 * nk * nr * nao * neo * (neo + 1) / 2,
-              "contract_s8": wc}
+              "contract_s8": wc, "fftdf": 8.0 * npair * nr * sum(g.n)}
     kf = kflops.get(dname.rsplit("_", 1)[0])
-    peak = PEAK[prec] if kf is not None and not dname.endswith("f64") else PEAK["fp64"]
+    peak = kernel_peak(prec, dname) if kf is not None and not dname.endswith("f64") else PEAK["fp64"]
+    bound = "mfma"
+    if dname == "fftdf_dft":
+        bound, peak = "alu", PEAK["fp64"]   # FP64 vector arithmetic: 78.6 TFLOP/s on MI355X
     line = {
         "metric": METRIC, "value": round((wt + wfft + wc) / (ms * 1e-3) / 1e12, 4), "unit": "TFLOP/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
@@ -374,7 +379,7 @@ def run_fftdf(args, dev):
                                f"grid {'x'.join(map(str, g.n))} in a {g.cell[0]} bohr cell, nao {nao}, neo {neo}, "
                                f"Gaussian AOs, pair density complex128",
                    "precision": prec, "W_flop": wt + wfft + wc, "W_T": wt, "W_FFT": wfft, "W_C": wc},
-        "roofline": {"bound": "mfma", "kernel": dname, "achieved": None if kf is None else round(kf / (avg * 1e-3) / 1e12, 3),
+        "roofline": {"bound": bound, "kernel": dname, "achieved": None if kf is None else round(kf / (avg * 1e-3) / 1e12, 3),
                      "peak": peak, "unit": "TFLOP/s",
                      "frac": None if kf is None else round(kf / (avg * 1e-3) / 1e12 / peak, 4),
                      "traffic": None, "launch_ms": round(avg, 4), "flop_per_launch": kf},

@@ -52,7 +52,8 @@
  * transforms with 32 x 32 stage-2 tiles (default 256); DMET_TUNE_CACHE names
  * the file of the batched autotuner's choices; DMET_I8_CHUNK_ROWS=n (a
  * multiple of 64 up to 44032, the default) sets the rows per launch of the
- * int8 contraction.
+ * int8 contraction; DMET_ROW_SPLIT=0 turns off the row split of the
+ * split-bf16 contraction of few-tile blocks on the plane-wave route.
  */
 #ifndef DMET_H
 #define DMET_H
@@ -308,9 +309,14 @@ dmet_status dmet_transform_eri_df(const dmet_lattice* lat, int neo, const void* 
  * dmet_transform_eri (s8 / s4 float64).  prec: DMET_FP64 (FP64 throughout),
  * or DMET_BF16X6_3M / DMET_BF16X3_3M: the transform and the contraction in
  * that split-bf16 form (as dmet_transform_eri), the grid DFT and the Coulomb
- * weights in FP64 between them (the int8 contraction is not offered here: the
- * plane-wave rows, 2 n_r per q, exceed its exact-sum limit on real grids;
- * DMET_FP32_3M is not offered either; both give DMET_E_UNSUPPORTED).  Returns
+ * weights in FP64 between them (the rows, 2 n_r per q, enter the contraction
+ * rounded to FP32).  When a spin block has few output tiles for the CUs, its
+ * split-bf16 contraction is split over the rows into partial outputs in the
+ * workspace, added in row order afterwards (deterministic).  DMET_BF16X6_I8 is
+ * not offered here: its int8 contraction is exact only to about 2^-23 of the
+ * column scales per row, and in the plane-wave rows a few small |q+G| rows
+ * dominate every sum, so its error exceeds 1e-6 Ha (1.5e-6 on a 6x5x8 grid);
+ * nor is DMET_FP32_3M (both give DMET_E_UNSUPPORTED).  Returns
  * DMET_E_ARG for a grid that does not match naux or a cell whose vectors are
  * not finite or are linearly dependent, DMET_E_WORKSPACE if the workspace is
  * too small (the workspace depends on prec).

@@ -86,9 +86,9 @@ dmet_status eri_f32_prepare();
 size_t lp_transform_workspace(const EriPlan& p);
 dmet_status lp_transform(const EriPlan& p, const void* lmunu, const double* ck, float* z, void* ws, size_t ws_bytes,
                          hipStream_t st);
-size_t lp_rows_contract_workspace(int nspin, int npair, int krows, int ns);
-dmet_status lp_rows_contract(int ns, int nspin, int npair, int krows, const double* z, size_t zsp, size_t ldz,
-                             double* eri_aa, double* eri_bb, double* eri_ab, void* ws, size_t ws_bytes,
+size_t lp_rows_contract_workspace(dmet_precision prec, int nspin, int npair, int krows);
+dmet_status lp_rows_contract(dmet_precision prec, int nspin, int npair, int krows, const double* z, size_t zsp,
+                             size_t ldz, double* eri_aa, double* eri_bb, double* eri_ab, void* ws, size_t ws_bytes,
                              hipStream_t st);
 dmet_status eri_f64(const EriPlan& p, const void* lmunu, const double* ck, double* eri_aa, double* eri_bb,
                     double* eri_ab, void* ws, size_t ws_bytes, hipStream_t st, double* df_out = nullptr);

@@ -55,28 +55,33 @@ __device__ inline void split_bf16(float x, __bf16 (&part)[NS]) {
 // P[t][g][x][v] (bf16) = part t of Z[8 g + v][x]: the k-index in groups of 8 so
 // that one MFMA operand fragment (8 consecutive k of one row) is one aligned
 // 16-byte chunk.  Rows beyond krows are zero.  FP64 rows are rounded to FP32
-// first (the three parts carry FP32's 24 bits).
+// first (the three parts carry FP32's 24 bits).  Groups g = blockIdx.y +
+// j gridDim.y (the grid's y extent is capped at 65535).
 template <int NS, class T = float>
 __global__ void k_pack_parts(const T* __restrict__ z, size_t ldz, int krows, int ncol, int kgroups,
                              __bf16* __restrict__ out) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int g = blockIdx.y;
     if (x >= ncol) return;
-    bf8 part[NS];
-#pragma unroll
-    for (int v = 0; v < 8; ++v) {
-        const int k = 8 * g + v;
-        const float val = k < krows ? (float)z[(size_t)k * ldz + x] : 0.f;
-        __bf16 sp[NS];
-        split_bf16<NS>(val, sp);
-#pragma unroll
-        for (int t = 0; t < NS; ++t) part[t][v] = sp[t];
-    }
     const size_t plane = (size_t)kgroups * ncol;
+    for (int g = blockIdx.y; g < kgroups; g += gridDim.y) {
+        bf8 part[NS];
 #pragma unroll
-    for (int t = 0; t < NS; ++t)
-        *reinterpret_cast<bf8*>(out + ((size_t)t * plane + (size_t)g * ncol + x) * 8) = part[t];
+        for (int v = 0; v < 8; ++v) {
+            const int k = 8 * g + v;
+            const float val = k < krows ? (float)z[(size_t)k * ldz + x] : 0.f;
+            __bf16 sp[NS];
+            split_bf16<NS>(val, sp);
+#pragma unroll
+            for (int t = 0; t < NS; ++t) part[t][v] = sp[t];
+        }
+#pragma unroll
+        for (int t = 0; t < NS; ++t)
+            *reinterpret_cast<bf8*>(out + ((size_t)t * plane + (size_t)g * ncol + x) * 8) = part[t];
+    }
 }
+
+// grid y extent for a kernel that loops over row groups
+inline unsigned group_grid(int groups) { return (unsigned)std::min(groups, 65535); }
 
 // Tile order: super-blocks of SB x SB output tiles, visited (for s8) in
 // lower-triangular order; logical ids are assigned so that each XCD (the
@@ -197,10 +202,14 @@ inline long w8_grid(int mode, int npair) {
 // loads straight into LDS: each buffer resource spans one row group of one
 // part, so the hardware range check bounds every load, and (unlike the FLAT
 // form) the compiler keeps exact lgkmcnt waits for the LDS reads behind them.
+// Row split: the workgroups of blockIdx.y = y sum the row groups
+// [y ksplit, min((y + 1) ksplit, kgroups)) (parts kplane groups apart) into
+// out + y out_split; one split (ksplit = kgroups, out_split 0) is the plain sum.
 template <int NS, int MODE, int G, int NBUF>
 __global__ void __launch_bounds__(512) k_contract_w8(int npair, int kgroups, const __bf16* __restrict__ pa,
                                                      const __bf16* __restrict__ pb, int flush_k, long nblocks,
-                                                     double* __restrict__ out) {
+                                                     double* __restrict__ out, int kplane, int ksplit,
+                                                     size_t out_split) {
     constexpr int BM = 128, BN = 256;
     constexpr int TM = 2, TN = 2;
     constexpr int PA = G * BM, PB = G * BN;      // 16-byte chunks of one part of A / B per stage
@@ -220,8 +229,12 @@ __global__ void __launch_bounds__(512) k_contract_w8(int npair, int kgroups, con
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: scalar registers
     const int wm0 = (wave >> 2) * 64, wn0 = (wave & 3) * 64;
-    const size_t plane = (size_t)kgroups * npair;
-    const int nkt = kgroups / G;
+    const int kbeg = blockIdx.y * ksplit;
+    pa += (size_t)kbeg * npair * 8;
+    pb += (size_t)kbeg * npair * 8;
+    out += blockIdx.y * out_split;
+    const size_t plane = (size_t)kplane * npair;
+    const int nkt = min(ksplit, kgroups - kbeg) / G;
     // this lane's byte offset within its rows (fixed over stages) and the
     // wave-uniform row pointers of the next stage to issue
     const int fa = wave * CA;
@@ -458,7 +471,10 @@ constexpr size_t w8_lds() { return (size_t)NBUF * NS * G * (128 + 256) * 16; }
 // are exact in int32, summed per level l = t + u in its own accumulator:
 //   L0 = d0.d0,  L1 = d0.d1 + d1.d0,  L2 = d0.d2 + d1.d1 + d2.d0,
 // and (ij|kl) = 2^(e_ij + e_kl) / 127^2 * (L0 + (L1 + L2 / 254) / 254) in FP64.
-// Level 3 and 4 products (below 2^-24 of the largest) are dropped.  The int32
+// Level 3 and 4 products are dropped: at most 2 / 254^3 (about 2^-23) of
+// 2^(e_ij + e_kl) per row, so the error is relative to the column scales, not
+// to each element: small while the rows are of one magnitude (density-fitting
+// rows), too large where a few rows dominate every sum.  The int32
 // sums are exact while 3 * K * 127^2 < 2^31, i.e. for K <= I8_KMAX rows.  The
 // operands move as the bf16 ones do: 16-byte chunks = 16 consecutive rows of
 // one column of one digit plane, one MFMA fragment of v_mfma_i32_32x32x32_i8.
@@ -488,34 +504,35 @@ __global__ void k_colmax(const float* __restrict__ z, size_t ldz, int krows, int
 __global__ void k_pack_i8(const float* __restrict__ z, size_t ldz, int krows, int ncol, int kg16,
                           const unsigned* __restrict__ cmax, int* __restrict__ ex, i4v* __restrict__ out) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int g = blockIdx.y;
     if (x >= ncol) return;
     const unsigned cb = cmax[x];
     int e = 0;
     if (cb >= 0x7f800000u) e = I8_EBAD;
     else if (cb != 0u) frexpf(__uint_as_float(cb), &e);   // cmax = m 2^e, m in [0.5, 1): cmax < 2^e
-    if (g == 0) ex[x] = e;
+    if (blockIdx.y == 0) ex[x] = e;
     const double sc = e == I8_EBAD ? 0.0 : ldexp(127.0, -e);
-    union {
-        signed char c[16];
-        i4v v;
-    } d[3];
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int k = 16 * g + v;
-        double r = k < krows ? (double)z[(size_t)k * ldz + x] * sc : 0.0;   // |r| < 127, exact
-        const double d0 = rint(r);
-        r = (r - d0) * 254.0;
-        const double d1 = rint(r);
-        r = (r - d1) * 254.0;
-        const double d2 = rint(r);
-        d[0].c[v] = (signed char)(int)d0;
-        d[1].c[v] = (signed char)(int)d1;
-        d[2].c[v] = (signed char)(int)d2;
-    }
     const size_t plane = (size_t)kg16 * ncol;
+    for (int g = blockIdx.y; g < kg16; g += gridDim.y) {   // the grid's y extent is capped at 65535
+        union {
+            signed char c[16];
+            i4v v;
+        } d[3];
 #pragma unroll
-    for (int t = 0; t < 3; ++t) out[(size_t)t * plane + (size_t)g * ncol + x] = d[t].v;
+        for (int v = 0; v < 16; ++v) {
+            const int k = 16 * g + v;
+            double r = k < krows ? (double)z[(size_t)k * ldz + x] * sc : 0.0;   // |r| < 127, exact
+            const double d0 = rint(r);
+            r = (r - d0) * 254.0;
+            const double d1 = rint(r);
+            r = (r - d1) * 254.0;
+            const double d2 = rint(r);
+            d[0].c[v] = (signed char)(int)d0;
+            d[1].c[v] = (signed char)(int)d1;
+            d[2].c[v] = (signed char)(int)d2;
+        }
+#pragma unroll
+        for (int t = 0; t < 3; ++t) out[(size_t)t * plane + (size_t)g * ncol + x] = d[t].v;
+    }
 }
 
 // 128 x 256 output tiles, 8 waves as 2 x 4, wave tile 64 x 64 (2 x 2 blocks of
@@ -1947,8 +1964,8 @@ static dmet_status eri_lp_run(const EriPlan& p, const void* lmunu, const double*
     const size_t per_spin = (size_t)NS * kg * 8 * p.npair;
     for (int s = 0; s < p.nspin; ++s) {
         ProfScope ps(NS == 2 ? "pack_bf16x3" : "pack_bf16x6", st);
-        k_pack_parts<NS><<<dim3((p.npair + 255) / 256, kg), 256, 0, st>>>(z + (size_t)s * p.zrows * ldz, ldz,
-                                                                         p.zrows, p.npair, kg, zp + s * per_spin);
+        k_pack_parts<NS><<<dim3((p.npair + 255) / 256, group_grid(kg)), 256, 0, st>>>(
+            z + (size_t)s * p.zrows * ldz, ldz, p.zrows, p.npair, kg, zp + s * per_spin);
         ps.stop();
         DMET_LAUNCH_CHECK("k_pack_parts");
     }
@@ -1964,14 +1981,14 @@ static dmet_status eri_lp_run(const EriPlan& p, const void* lmunu, const double*
         const long nb = w8_grid(0, p.npair);
         ProfScope ps(n3, st);
         kw0<<<dim3((unsigned)nb), 512, lds, st>>>(p.npair, kg, zp + s * per_spin, zp + s * per_spin, FLUSH_K, nb,
-                                                  s == 0 ? eri_aa : eri_bb);
+                                                  s == 0 ? eri_aa : eri_bb, kg, kg, 0);
         ps.stop();
         DMET_LAUNCH_CHECK(n3);
     }
     if (p.nspin == 2 && eri_ab) {
         const long nb = w8_grid(1, p.npair);
         ProfScope ps(n4, st);
-        kw1<<<dim3((unsigned)nb), 512, lds, st>>>(p.npair, kg, zp, zp + per_spin, FLUSH_K, nb, eri_ab);
+        kw1<<<dim3((unsigned)nb), 512, lds, st>>>(p.npair, kg, zp, zp + per_spin, FLUSH_K, nb, eri_ab, kg, kg, 0);
         ps.stop();
         DMET_LAUNCH_CHECK(n4);
     }
@@ -2000,7 +2017,7 @@ static dmet_status eri_i8_run(const EriPlan& p, const void* lmunu, const double*
         const float* zs = z + (size_t)s * p.zrows * ldz;
         k_colmax<<<dim3((p.npair + 255) / 256, (p.zrows + rows_per - 1) / rows_per), 256, 0, st>>>(
             zs, ldz, p.zrows, p.npair, rows_per, cmax + (size_t)s * p.npair);
-        k_pack_i8<<<dim3((p.npair + 255) / 256, kg), 256, 0, st>>>(zs, ldz, p.zrows, p.npair, kg,
+        k_pack_i8<<<dim3((p.npair + 255) / 256, group_grid(kg)), 256, 0, st>>>(zs, ldz, p.zrows, p.npair, kg,
                                                                      cmax + (size_t)s * p.npair,
                                                                      ex + (size_t)s * p.npair, zp + s * per_spin);
         ps.stop();
@@ -2018,10 +2035,11 @@ static dmet_status eri_i8_run(const EriPlan& p, const void* lmunu, const double*
         ProfScope ps("contract_s8_i8", st);
         for (int g0 = 0; g0 < kg; g0 += kg_chunk) {
             const size_t off = (size_t)g0 * p.npair;
+            const int kc = std::min(kg_chunk, kg - g0);
             auto k8 = g0 > 0 ? k_contract_i8<0, true> : k_contract_i8<0, false>;
-            k8<<<dim3((unsigned)nb), 512, lds, st>>>(p.npair, std::min(kg_chunk, kg - g0), zp + s * per_spin + off,
-                                                     zp + s * per_spin + off, ex + (size_t)s * p.npair,
-                                                     ex + (size_t)s * p.npair, nb, s == 0 ? eri_aa : eri_bb, kg);
+            k8<<<dim3((unsigned)nb), 512, lds, st>>>(p.npair, kc, zp + s * per_spin + off, zp + s * per_spin + off,
+                                                     ex + (size_t)s * p.npair, ex + (size_t)s * p.npair, nb,
+                                                     s == 0 ? eri_aa : eri_bb, kg);
         }
         ps.stop();
         DMET_LAUNCH_CHECK("contract_s8_i8");
@@ -2031,9 +2049,10 @@ static dmet_status eri_i8_run(const EriPlan& p, const void* lmunu, const double*
         ProfScope ps("contract_s4_i8", st);
         for (int g0 = 0; g0 < kg; g0 += kg_chunk) {
             const size_t off = (size_t)g0 * p.npair;
+            const int kc = std::min(kg_chunk, kg - g0);
             auto k4 = g0 > 0 ? k_contract_i8<1, true> : k_contract_i8<1, false>;
-            k4<<<dim3((unsigned)nb), 512, lds, st>>>(p.npair, std::min(kg_chunk, kg - g0), zp + off,
-                                                     zp + per_spin + off, ex, ex + p.npair, nb, eri_ab, kg);
+            k4<<<dim3((unsigned)nb), 512, lds, st>>>(p.npair, kc, zp + off, zp + per_spin + off, ex, ex + p.npair, nb,
+                                                     eri_ab, kg);
         }
         ps.stop();
         DMET_LAUNCH_CHECK("contract_s4_i8");
@@ -2086,21 +2105,99 @@ dmet_status lp_transform(const EriPlan& p, const void* lmunu, const double* ck, 
 }
 
 // The packed split-bf16 contraction (s8 per spin, s4 alpha-beta) of FP64 rows
-// made elsewhere: z[s] is krows x ldz (row-major, npair used columns).
-size_t lp_rows_contract_workspace(int nspin, int npair, int krows, int ns) {
-    return (size_t)nspin * ns * kgroups_of(krows) * 8 * npair * sizeof(__bf16) + 256;
+// made elsewhere (the plane-wave route), z[s] krows x ldz (row-major, npair used
+// columns).  Few output tiles over many rows (2 n_r rows per q there) would
+// leave most CUs idle, so such launches split the rows (blockIdx.y) into slices
+// of the output that k_sum_slices adds in row order (deterministic).
+
+constexpr int NCU = 256;   // compute units of an MI355X: one contraction workgroup each
+
+// Output tiles (128 x 256) of one contraction launch that hold outputs.
+static long w8_tiles(int mode, int npair) {
+    const int ntm = (npair + 127) / 128, ntn = (npair + 255) / 256;
+    if (mode == 1) return (long)ntm * ntn;
+    long n = 0;
+    for (int mt = 0; mt < ntm; ++mt) n += std::min(ntn, (mt * 128 + 127) / 256 + 1);
+    return n;
+}
+
+static size_t out_elems(int mode, int npair) {
+    return mode == 0 ? (size_t)npair * (npair + 1) / 2 : (size_t)npair * npair;
+}
+
+struct RowSplit {
+    int n = 1;        // row splits (slices of the output)
+    int groups = 0;   // 8-row groups per split
+};
+
+// As many splits as tiles x splits workgroups fit on the CUs at once; a launch
+// with half a tile per CU or more keeps one split.  Splits are whole FP32
+// flush windows (FLUSH_K rows), so every split forms the FP32 partial sums of
+// the unsplit launch and the results differ only in the order of FP64 adds.
+static RowSplit row_split(int mode, int npair, int kg) {
+    constexpr int W = FLUSH_K / 8;
+    RowSplit r;
+    r.groups = kg;
+    const char* e = getenv("DMET_ROW_SPLIT");
+    if (e && atoi(e) == 0) return r;
+    const long tiles = w8_tiles(mode, npair);
+    if (2 * tiles > NCU) return r;
+    const int windows = (kg + W - 1) / W;
+    const int n = std::min((int)(NCU / tiles), windows);
+    if (n < 2) return r;
+    r.groups = (windows + n - 1) / n * W;
+    r.n = (kg + r.groups - 1) / r.groups;
+    return r;
+}
+
+// out[i] = sum over the slices y of part[y n + i], in slice (row) order
+__global__ void k_sum_slices(const double* __restrict__ part, size_t n, int nsl, double* __restrict__ out) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        double v = part[i];
+        for (int y = 1; y < nsl; ++y) v += part[(size_t)y * n + i];
+        out[i] = v;
+    }
+}
+
+struct RowsWs {
+    __bf16* parts = nullptr;
+    double* slices = nullptr;
+};
+
+// Workspace layout of the rows contraction (sizes only when ws is null).
+static size_t rows_layout(dmet_precision prec, int nspin, int npair, int krows, void* ws, size_t ws_bytes,
+                          RowsWs& w) {
+    Carve cv(ws, ws_bytes);
+    const int kg = kgroups_of(krows);
+    const int ns = prec == DMET_BF16X3_3M ? 2 : 3;
+    w.parts = cv.take<__bf16>((size_t)nspin * ns * kg * 8 * npair);
+    size_t sl = 0;
+    const RowSplit a = row_split(0, npair, kg);
+    if (a.n > 1) sl = (size_t)a.n * out_elems(0, npair);
+    if (nspin == 2) {
+        const RowSplit b = row_split(1, npair, kg);
+        if (b.n > 1) sl = std::max(sl, (size_t)b.n * out_elems(1, npair));
+    }
+    w.slices = cv.take<double>(sl);
+    return cv.bytes();
+}
+
+size_t lp_rows_contract_workspace(dmet_precision prec, int nspin, int npair, int krows) {
+    RowsWs w;
+    return rows_layout(prec, nspin, npair, krows, nullptr, 0, w);
 }
 
 template <int NS>
-static dmet_status lp_rows_contract_run(int nspin, int npair, int krows, const double* z, size_t zsp, size_t ldz,
-                                        double* eri_aa, double* eri_bb, double* eri_ab, __bf16* zp,
-                                        hipStream_t st) {
+static dmet_status rows_contract_bf16(int nspin, int npair, int krows, const double* z, size_t zsp, size_t ldz,
+                                      double* eri_aa, double* eri_bb, double* eri_ab, const RowsWs& w,
+                                      hipStream_t st) {
     const int kg = kgroups_of(krows);
+    __bf16* zp = w.parts;
     const size_t per_spin = (size_t)NS * kg * 8 * npair;
     for (int s = 0; s < nspin; ++s) {
         ProfScope ps(NS == 2 ? "pack_bf16x3" : "pack_bf16x6", st);
-        k_pack_parts<NS, double><<<dim3((npair + 255) / 256, kg), 256, 0, st>>>(z + s * zsp, ldz, krows, npair, kg,
-                                                                               zp + s * per_spin);
+        k_pack_parts<NS, double><<<dim3((npair + 255) / 256, group_grid(kg)), 256, 0, st>>>(
+            z + s * zsp, ldz, krows, npair, kg, zp + s * per_spin);
         ps.stop();
         DMET_LAUNCH_CHECK("k_pack_parts");
     }
@@ -2110,33 +2207,44 @@ static dmet_status lp_rows_contract_run(int nspin, int npair, int krows, const d
     constexpr size_t lds = w8_lds<NS, G, NB>();
     DMET_HIP(hipFuncSetAttribute((const void*)kw0, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     DMET_HIP(hipFuncSetAttribute((const void*)kw1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    auto block = [&](int mode, const __bf16* a, const __bf16* b, double* out) -> dmet_status {
+        const RowSplit r = row_split(mode, npair, kg);
+        const long nb = w8_grid(mode, npair);
+        const size_t n = out_elems(mode, npair);
+        ProfScope ps(mode == 0 ? (NS == 3 ? "contract_s8_bf16x6" : "contract_s8_bf16x3")
+                               : (NS == 3 ? "contract_s4_bf16x6" : "contract_s4_bf16x3"),
+                     st);
+        auto kf = mode == 0 ? kw0 : kw1;
+        kf<<<dim3((unsigned)nb, (unsigned)r.n), 512, lds, st>>>(npair, kg, a, b, FLUSH_K, nb, r.n > 1 ? w.slices : out,
+                                                              kg, r.groups, r.n > 1 ? n : 0);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess && r.n > 1) {
+            k_sum_slices<<<(unsigned)std::min<size_t>((n + 255) / 256, 4096), 256, 0, st>>>(w.slices, n, r.n, out);
+            e = hipGetLastError();
+        }
+        ps.stop();
+        if (e != hipSuccess) return hip_fail(e, "contract rows");
+        return DMET_OK;
+    };
     for (int s = 0; s < nspin; ++s) {
-        const long nb = w8_grid(0, npair);
-        ProfScope ps(NS == 3 ? "contract_s8_bf16x6" : "contract_s8_bf16x3", st);
-        kw0<<<dim3((unsigned)nb), 512, lds, st>>>(npair, kg, zp + s * per_spin, zp + s * per_spin, FLUSH_K, nb,
-                                                  s == 0 ? eri_aa : eri_bb);
-        ps.stop();
-        DMET_LAUNCH_CHECK("contract_s8 rows");
+        const dmet_status bs = block(0, zp + s * per_spin, zp + s * per_spin, s == 0 ? eri_aa : eri_bb);
+        if (bs != DMET_OK) return bs;
     }
-    if (nspin == 2 && eri_ab) {
-        const long nb = w8_grid(1, npair);
-        ProfScope ps(NS == 3 ? "contract_s4_bf16x6" : "contract_s4_bf16x3", st);
-        kw1<<<dim3((unsigned)nb), 512, lds, st>>>(npair, kg, zp, zp + per_spin, FLUSH_K, nb, eri_ab);
-        ps.stop();
-        DMET_LAUNCH_CHECK("contract_s4 rows");
-    }
+    if (nspin == 2 && eri_ab) return block(1, zp, zp + per_spin, eri_ab);
     return DMET_OK;
 }
 
-dmet_status lp_rows_contract(int ns, int nspin, int npair, int krows, const double* z, size_t zsp, size_t ldz,
-                             double* eri_aa, double* eri_bb, double* eri_ab, void* ws, size_t ws_bytes,
+dmet_status lp_rows_contract(dmet_precision prec, int nspin, int npair, int krows, const double* z, size_t zsp,
+                             size_t ldz, double* eri_aa, double* eri_bb, double* eri_ab, void* ws, size_t ws_bytes,
                              hipStream_t st) {
-    if (ns != 2 && ns != 3) return fail(DMET_E_ARG, "split-bf16 contraction: two or three parts");
-    if (lp_rows_contract_workspace(nspin, npair, krows, ns) > ws_bytes)
-        return fail(DMET_E_WORKSPACE, "split-bf16 contraction workspace");
-    __bf16* zp = static_cast<__bf16*>(ws);
-    return ns == 3 ? lp_rows_contract_run<3>(nspin, npair, krows, z, zsp, ldz, eri_aa, eri_bb, eri_ab, zp, st)
-                   : lp_rows_contract_run<2>(nspin, npair, krows, z, zsp, ldz, eri_aa, eri_bb, eri_ab, zp, st);
+    if (prec != DMET_BF16X3_3M && prec != DMET_BF16X6_3M)
+        return fail(DMET_E_ARG, "split-bf16 rows contraction: BF16X3_3M or BF16X6_3M");
+    RowsWs w;
+    if (rows_layout(prec, nspin, npair, krows, ws, ws_bytes, w) > ws_bytes)
+        return fail(DMET_E_WORKSPACE, "split-bf16 rows contraction workspace");
+    if (prec == DMET_BF16X3_3M)
+        return rows_contract_bf16<2>(nspin, npair, krows, z, zsp, ldz, eri_aa, eri_bb, eri_ab, w, st);
+    return rows_contract_bf16<3>(nspin, npair, krows, z, zsp, ldz, eri_aa, eri_bb, eri_ab, w, st);
 }
 
 }  // namespace dmet
@@ -2512,7 +2620,7 @@ static dmet_status batch_enqueue(BatchPlan& bp, int variant, bool prof, hipStrea
             unsigned* cm = at<unsigned>(ws, bp.off_cmax) + F.cmax_idx;
             k_colmax<<<dim3((F.npair + 255) / 256, (F.zrows + rows_per - 1) / rows_per), 256, 0, st>>>(
                 at<float>(ws, F.off_z), (size_t)F.npair, F.zrows, F.npair, rows_per, cm);
-            k_pack_i8<<<dim3((F.npair + 255) / 256, F.kg16), 256, 0, st>>>(
+            k_pack_i8<<<dim3((F.npair + 255) / 256, group_grid(F.kg16)), 256, 0, st>>>(
                 at<float>(ws, F.off_z), (size_t)F.npair, F.zrows, F.npair, F.kg16, cm, at<int>(ws, F.off_ex),
                 at<i4v>(ws, F.off_zp));
         }
@@ -2532,7 +2640,7 @@ static dmet_status batch_enqueue(BatchPlan& bp, int variant, bool prof, hipStrea
     ps = scope(NS == 3 ? "batch_pack_bf16x6" : "batch_pack_bf16x3");
     for (int f = 0; f < nfrag; ++f) {
         const BatchFrag& F = bp.fs[f];
-        k_pack_parts<NS><<<dim3((F.npair + 255) / 256, F.kgroups), 256, 0, st>>>(
+        k_pack_parts<NS><<<dim3((F.npair + 255) / 256, group_grid(F.kgroups)), 256, 0, st>>>(
             at<float>(ws, F.off_z), (size_t)F.npair, F.zrows, F.npair, F.kgroups, at<__bf16>(ws, F.off_zp));
     }
     done(ps);

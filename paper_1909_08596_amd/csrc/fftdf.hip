@@ -1,7 +1,8 @@
 // Plane-wave (FFTDF) embedding ERIs, App. B, Eq. "FFTDF" and Alg. 2.
 //
 // The grid points r of the reference cell play the role of the fitting
-// functions: the FP64 transform of Alg. 1 turns the AO pair densities
+// functions: the transform of Alg. 1 (FP64, or the split-bf16 transform of the
+// reduced forms) turns the AO pair densities
 // (r|mu k, nu k-q) into the real rows Z_r = w_q (Re X, Im X) of the embedded
 // pair densities X(q)[r][ij] (q and -q combined as for GDF).  For each q the
 // rows are Fourier transformed over the grid with the phase of q,
@@ -9,8 +10,10 @@
 // one axis at a time (a separable 3-D DFT; each output sums the n_d points of
 // its line, the phases read from a table of the L = N_d n_d roots of unity of
 // the supercell axis held in LDS), and scaled by
-// dV sqrt(4 pi / (Omega |q+G|^2)) into two real rows (Re W, Im W) per G.  The
-// FP64 contraction of those rows gives the ERIs.  The DFT runs in fractional
+// dV sqrt(4 pi / (Omega |q+G|^2)) into two real rows (Re W, Im W) per G (FP64).
+// The contraction of those rows gives the ERIs: FP64, or on split-bf16 parts of
+// the rows, split over the rows when there are few output tiles.
+// The DFT runs in fractional
 // coordinates, so only |q+G|^2 (through the reciprocal vectors) and Omega see
 // the shape of the cell.
 #include <math.h>
@@ -74,7 +77,12 @@ void reciprocal(const double (&a)[3][3], double (&b)[3][3], double& vol) {
 // over a [x0][x1][x2][pair] layout.  IN: 0 complex buffer, 1 real rows
 // (row zrow0 + r), 2 interleaved Re/Im rows (row zrow0 + 2 r + part), rows of
 // type T (FP64, or FP32 from the split-bf16 transform).  OUT: 0 complex buffer,
-// 1 scaled rows zg0 + 2 G + part.  The sums run in FP64.
+// 1 scaled rows zg0 + 2 G + part.  The sums run in FP64, t in increasing order.
+// A thread takes one line along the axis and one pair: it reads the line's
+// inputs once per PW_GT outputs (consecutive pairs in the lanes: coalesced) and
+// the twiddle of an (output, term) is the same in every lane (an LDS broadcast).
+constexpr int PW_GT = 16;
+
 template <int IN, int OUT, class T = double>
 __global__ void __launch_bounds__(256) k_pw_axis(PwAxis ax, int npair, const double2* __restrict__ cin,
                                                  const T* __restrict__ zin, size_t zrow0, size_t ldz,
@@ -89,46 +97,79 @@ __global__ void __launch_bounds__(256) k_pw_axis(PwAxis ax, int npair, const dou
         tw[j] = make_double2(c, s);
     }
     __syncthreads();
-    const long n12 = (long)ax.n[1] * ax.n[2];
-    const long nr = (long)ax.n[0] * n12;
-    const long stride = ax.axis == 0 ? n12 : (ax.axis == 1 ? ax.n[2] : 1);
-    const long total = nr * npair;
+    const int n1 = ax.n[1], n2 = ax.n[2];
+    const long n12 = (long)n1 * n2;
+    const long stride = ax.axis == 0 ? n12 : (ax.axis == 1 ? n2 : 1);
+    const long total = (long)ax.n[0] * n12 / nd * npair;   // lines x pairs
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
         const int p = (int)(e % npair);
-        const long r = e / npair;
-        int x[3] = {(int)(r / n12), (int)((r / ax.n[2]) % ax.n[1]), (int)(r % ax.n[2])};
-        const int g = x[ax.axis];
-        const long base = r - (long)g * stride;
-        // the phase of point t is (N g + m) t mod L, advanced exactly in integers
-        const int step = (ax.nmesh * g + ax.m) % L;
-        int ph = 0;
-        double re = 0.0, im = 0.0;
-        for (int t = 0; t < nd; ++t) {
-            const double2 w = tw[ph];
-            ph += step;
-            ph -= ph >= L ? L : 0;
-            const long rt = base + (long)t * stride;
-            double vr, vi;
-            if (IN == 0) {
-                const double2 v = cin[rt * npair + p];
-                vr = v.x;
-                vi = v.y;
-            } else if (IN == 1) {
-                vr = (double)zin[(zrow0 + rt) * ldz + p];
-                vi = 0.0;
-            } else {
-                vr = (double)zin[(zrow0 + 2 * rt) * ldz + p];
-                vi = (double)zin[(zrow0 + 2 * rt + 1) * ldz + p];
-            }
-            re += w.x * vr - w.y * vi;
-            im += w.x * vi + w.y * vr;
-        }
-        if (OUT == 0) {
-            cout[r * npair + p] = make_double2(re, im);
+        const long line = e / npair;
+        // grid coordinates of the line's first point (coordinate `axis` = 0)
+        int x[3];
+        if (ax.axis == 0) {
+            x[0] = 0;
+            x[1] = (int)(line / n2);
+            x[2] = (int)(line % n2);
+        } else if (ax.axis == 1) {
+            x[0] = (int)(line / n2);
+            x[1] = 0;
+            x[2] = (int)(line % n2);
         } else {
-            const double sc = pw_scale(ks, x);
-            zout[(zg0 + 2 * r) * ldz + p] = sc * re;
-            zout[(zg0 + 2 * r + 1) * ldz + p] = sc * im;
+            x[0] = (int)(line / n1);
+            x[1] = (int)(line % n1);
+            x[2] = 0;
+        }
+        const long base = (long)x[0] * n12 + (long)x[1] * n2 + x[2];
+        for (int g0 = 0; g0 < nd; g0 += PW_GT) {
+            double re[PW_GT], im[PW_GT];
+            int ph[PW_GT], step[PW_GT];
+#pragma unroll
+            for (int u = 0; u < PW_GT; ++u) {
+                re[u] = 0.0;
+                im[u] = 0.0;
+                ph[u] = 0;
+                // the phase of term t is (N g + m) t mod L, advanced exactly in integers
+                step[u] = (ax.nmesh * (g0 + u) + ax.m) % L;
+            }
+            for (int t = 0; t < nd; ++t) {
+                const long rt = base + (long)t * stride;
+                double vr, vi;
+                if (IN == 0) {
+                    const double2 v = cin[rt * npair + p];
+                    vr = v.x;
+                    vi = v.y;
+                } else if (IN == 1) {
+                    vr = (double)zin[(zrow0 + rt) * ldz + p];
+                    vi = 0.0;
+                } else {
+                    vr = (double)zin[(zrow0 + 2 * rt) * ldz + p];
+                    vi = (double)zin[(zrow0 + 2 * rt + 1) * ldz + p];
+                }
+#pragma unroll
+                for (int u = 0; u < PW_GT; ++u) {
+                    const double2 w = tw[ph[u]];
+                    ph[u] += step[u];
+                    ph[u] -= ph[u] >= L ? L : 0;
+                    re[u] += w.x * vr - w.y * vi;
+                    im[u] += w.x * vi + w.y * vr;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < PW_GT; ++u) {
+                const int g = g0 + u;
+                if (g < nd) {
+                    const long r = base + (long)g * stride;
+                    if (OUT == 0) {
+                        cout[r * npair + p] = make_double2(re[u], im[u]);
+                    } else {
+                        int xg[3] = {x[0], x[1], x[2]};
+                        xg[ax.axis] = g;
+                        const double sc = pw_scale(ks, xg);
+                        zout[(zg0 + 2 * r) * ldz + p] = sc * re[u];
+                        zout[(zg0 + 2 * r + 1) * ldz + p] = sc * im[u];
+                    }
+                }
+            }
         }
     }
 }
@@ -137,13 +178,11 @@ struct PwDims {
     size_t nr, eri_ws, zr, buf, zg, part;   // zr in elements of the row type; eri_ws, part in bytes
     int zrows_g, krows_p, ldz;
     bool split;                               // split-bf16 transform and contraction
-    int ns;
 };
 
 PwDims pw_dims(const EriPlan& p) {
     PwDims d;
     d.split = p.prec == DMET_BF16X6_3M || p.prec == DMET_BF16X3_3M;
-    d.ns = p.prec == DMET_BF16X3_3M ? 2 : 3;
     d.nr = (size_t)p.naux;
     d.zrows_g = (int)(2 * d.nr * p.qblocks.size());
     d.krows_p = (d.zrows_g + 15) / 16 * 16;
@@ -152,7 +191,7 @@ PwDims pw_dims(const EriPlan& p) {
     d.zr = (size_t)p.nspin * p.zrows * p.npair;
     d.buf = d.nr * p.npair;
     d.zg = (size_t)p.nspin * d.krows_p * d.ldz;
-    d.part = d.split ? lp_rows_contract_workspace(p.nspin, p.npair, d.krows_p, d.ns)
+    d.part = d.split ? lp_rows_contract_workspace(p.prec, p.nspin, p.npair, d.krows_p)
                      : contract_f64_workspace(p.nspin, p.npair, d.krows_p) * sizeof(double);
     return d;
 }
@@ -208,8 +247,10 @@ dmet_status fftdf_eri(const EriPlan& p, const dmet_pw_grid* grid, const void* rh
                               (const void*)k_pw_axis<0, 0>,        (const void*)k_pw_axis<0, 1>};
         for (const void* kf : ks6) DMET_HIP(hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, lmax));
     }
-    const long total = (long)d.nr * p.npair;
-    const unsigned nb = (unsigned)std::min<long>((total + 255) / 256, 65535L * 4);
+    // one thread per line along the axis and pair
+    auto nb = [&](int a) {
+        return (unsigned)std::min<long>(((long)d.nr / grid->n[a] * p.npair + 255) / 256, 65535L * 4);
+    };
     for (int sp = 0; sp < p.nspin; ++sp) {
         const double* zs = d.split ? nullptr : zr + (size_t)sp * p.zrows * p.npair;
         const float* zsf = d.split ? zf + (size_t)sp * p.zrows * p.npair : nullptr;
@@ -230,32 +271,32 @@ dmet_status fftdf_eri(const EriPlan& p, const dmet_pw_grid* grid, const void* rh
             ax.nmesh = p.mesh.n[0];
             ax.m = m[0];
             if (d.split && qb.self_conj)
-                k_pw_axis<1, 0, float><<<nb, 256, lds(0), st>>>(ax, p.npair, nullptr, zsf, qb.zrow0, p.npair, b1,
+                k_pw_axis<1, 0, float><<<nb(0), 256, lds(0), st>>>(ax, p.npair, nullptr, zsf, qb.zrow0, p.npair, b1,
                                                                 nullptr, 0, ks);
             else if (d.split)
-                k_pw_axis<2, 0, float><<<nb, 256, lds(0), st>>>(ax, p.npair, nullptr, zsf, qb.zrow0, p.npair, b1,
+                k_pw_axis<2, 0, float><<<nb(0), 256, lds(0), st>>>(ax, p.npair, nullptr, zsf, qb.zrow0, p.npair, b1,
                                                                 nullptr, 0, ks);
             else if (qb.self_conj)
-                k_pw_axis<1, 0><<<nb, 256, lds(0), st>>>(ax, p.npair, nullptr, zs, qb.zrow0, p.npair, b1, nullptr, 0,
+                k_pw_axis<1, 0><<<nb(0), 256, lds(0), st>>>(ax, p.npair, nullptr, zs, qb.zrow0, p.npair, b1, nullptr, 0,
                                                          ks);
             else
-                k_pw_axis<2, 0><<<nb, 256, lds(0), st>>>(ax, p.npair, nullptr, zs, qb.zrow0, p.npair, b1, nullptr, 0,
+                k_pw_axis<2, 0><<<nb(0), 256, lds(0), st>>>(ax, p.npair, nullptr, zs, qb.zrow0, p.npair, b1, nullptr, 0,
                                                          ks);
             ax.axis = 1;
             ax.nmesh = p.mesh.n[1];
             ax.m = m[1];
-            k_pw_axis<0, 0, double><<<nb, 256, lds(1), st>>>(ax, p.npair, b1, nullptr, 0, p.npair, b2, nullptr, 0, ks);
+            k_pw_axis<0, 0, double><<<nb(1), 256, lds(1), st>>>(ax, p.npair, b1, nullptr, 0, p.npair, b2, nullptr, 0, ks);
             ax.axis = 2;
             ax.nmesh = p.mesh.n[2];
             ax.m = m[2];
-            k_pw_axis<0, 1, double><<<nb, 256, lds(2), st>>>(ax, p.npair, b2, nullptr, 0, d.ldz, nullptr, zgs, 2 * d.nr * b,
+            k_pw_axis<0, 1, double><<<nb(2), 256, lds(2), st>>>(ax, p.npair, b2, nullptr, 0, d.ldz, nullptr, zgs, 2 * d.nr * b,
                                                      ks);
             ps.stop();
             DMET_LAUNCH_CHECK("k_pw_axis");
         }
     }
     if (d.split)
-        return lp_rows_contract(d.ns, p.nspin, p.npair, d.krows_p, zg, (size_t)d.krows_p * d.ldz, (size_t)d.ldz,
+        return lp_rows_contract(p.prec, p.nspin, p.npair, d.krows_p, zg, (size_t)d.krows_p * d.ldz, (size_t)d.ldz,
                                 eri_aa, eri_bb, eri_ab, part, d.part, st);
     return contract_f64(p.nspin, p.npair, d.ldz, d.krows_p, zg, eri_aa, eri_bb, eri_ab, static_cast<double*>(part),
                         st);

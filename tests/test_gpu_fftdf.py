@@ -33,7 +33,9 @@ def _run(dmet, wl, g, precision="fp64"):
     return rho, ck, out
 
 
-# split-bf16 forms on the plane-wave route: max-abs bound relative to max|ERI| (~1 Ha here)
+# split-bf16 forms on the plane-wave route: max-abs bound relative to max|ERI| (~1 Ha here).
+# The small grids have few output tiles for many rows, so these run the row-split
+# contraction (partial outputs added in row order).
 SPLIT_TOL = {"bf16x6": 1e-6, "bf16x3": 1e-5}
 
 
@@ -51,22 +53,77 @@ def test_fftdf_split_forms_small(dmet, name, prec):
 
 def test_fftdf_split_uhf_and_fullsize(dmet):
     """BF16x6 on the UHF case with the alpha-beta block, and at the benchmark's
-    plane-wave size (2x2x2 mesh, 16^3 grid, 52 EOs) on every element."""
+    plane-wave size (2x2x2 mesh, 16^3 grid, 52 EOs: 36 output tiles over 65536
+    rows, contracted in seven row slices) on every element."""
     wl = synth.Workload("fft_u", (3, 2, 1), 6, 240, 6, 6, 2, 1.5, 1013)
     g = synth.FftGrid((6, 5, 8), (3.0, 2.6, 3.4))
-    rho, ck, out = _run(dmet, wl, g, "bf16x6")
+    lat = synth.make_lattice(wl)
+    rho = synth.fftdf_pair_density(wl, g)
+    ck = ok.build_bath(lat.dm_k, wl.kmesh, wl.nao)["c_k"]
+    refs = {}
     for key, (a, b) in {"aa": (0, None), "bb": (1, None), "ab": (0, 1)}.items():
         ref, _ = ok.alg2_eri(rho, ck[a], wl.kmesh, g.n, g.cell, None if b is None else ck[b])
-        ref = ok.pack_s8(ref) if b is None else ok.pack_s4(ref)
-        err = np.abs(out[key].cpu().numpy().reshape(ref.shape) - ref).max()
-        assert err < 1e-6 * max(1.0, np.abs(ref).max()), (key, err)
+        refs[key] = ok.pack_s8(ref) if b is None else ok.pack_s4(ref)
+    for prec in ("bf16x6",):
+        out = dmet.dmet_transform_eri_fftdf(wl.kmesh, wl.nao, g.n, g.cell, to_dev(rho), to_dev(ck), precision=prec)
+        torch.cuda.synchronize()
+        for key, ref in refs.items():
+            err = np.abs(out[key].cpu().numpy().reshape(ref.shape) - ref).max()
+            print(f"fft_u fftdf {prec} {key}: max err {err:.3e}")
+            assert err < 1e-6 * max(1.0, np.abs(ref).max()), (prec, key, err)
     wl, g = synth.FFT_CONFIGS["fft_si"]
-    rho, ck, out = _run(dmet, wl, g, "bf16x6")
+    lat = synth.make_lattice(wl)
+    rho = synth.fftdf_pair_density(wl, g)
+    ck = ok.build_bath(lat.dm_k, wl.kmesh, wl.nao)["c_k"]
     ref, _ = ok.alg2_eri(rho, ck[0], wl.kmesh, g.n, g.cell)
     refp = ok.pack_s8(ref)
-    err = np.abs(out["aa"].cpu().numpy() - refp).max()
-    print(f"fft_si fftdf bf16x6: max err {err:.3e} (max {np.abs(refp).max():.3f})")
-    assert err < 1e-6 * max(1.0, np.abs(refp).max())
+    for prec in ("bf16x6",):
+        out = dmet.dmet_transform_eri_fftdf(wl.kmesh, wl.nao, g.n, g.cell, to_dev(rho), to_dev(ck), precision=prec)
+        torch.cuda.synchronize()
+        err = np.abs(out["aa"].cpu().numpy() - refp).max()
+        print(f"fft_si fftdf {prec}: max err {err:.3e} (max {np.abs(refp).max():.3f})")
+        assert err < 1e-6 * max(1.0, np.abs(refp).max())
+
+
+@pytest.mark.parametrize("prec", ["bf16x6", "bf16x3"])
+def test_fftdf_row_split(dmet, monkeypatch, prec):
+    """The split-bf16 contraction of a few-tile block (UHF 3x2x1, 55 pairs:
+    one output tile per spin block over 1920 rows) in row slices added after
+    the launch, against one launch over all rows (DMET_ROW_SPLIT=0): slices are
+    whole FP32 flush windows, so the two differ only in the order of FP64 adds;
+    both within the form's bound of the oracle."""
+    wl = synth.Workload("fft_u", (3, 2, 1), 6, 240, 6, 6, 2, 1.5, 1013)
+    g = synth.FftGrid((6, 5, 8), (3.0, 2.6, 3.4))
+    lat = synth.make_lattice(wl)
+    rho = synth.fftdf_pair_density(wl, g)
+    ck = ok.build_bath(lat.dm_k, wl.kmesh, wl.nao)["c_k"]
+    outs = {}
+    for split in ("1", "0"):
+        monkeypatch.setenv("DMET_ROW_SPLIT", split)
+        out = dmet.dmet_transform_eri_fftdf(wl.kmesh, wl.nao, g.n, g.cell, to_dev(rho), to_dev(ck), precision=prec)
+        torch.cuda.synchronize()
+        outs[split] = {k: v.cpu().numpy() for k, v in out.items()}
+    ref, _ = ok.alg2_eri(rho, ck[0], wl.kmesh, g.n, g.cell, ck[1])
+    ref = ok.pack_s4(ref)
+    scale = max(1.0, np.abs(ref).max())
+    for key in ("aa", "bb", "ab"):
+        d = np.abs(outs["1"][key] - outs["0"][key]).max()
+        print(f"fft_u {prec} {key}: split vs one launch {d:.2e}")
+        assert d < 1e-12 * scale, (key, d)
+    err = np.abs(outs["1"]["ab"].reshape(ref.shape) - ref).max()
+    assert err < SPLIT_TOL[prec] * scale, err
+    # the library's own timing of the split launches (profiler events recorded on both sides)
+    monkeypatch.setenv("DMET_ROW_SPLIT", "1")
+    dmet.dmet_profile_reset()
+    dmet.dmet_profile_enable(True)
+    try:
+        dmet.dmet_transform_eri_fftdf(wl.kmesh, wl.nao, g.n, g.cell, to_dev(rho), to_dev(ck), precision=prec)
+        torch.cuda.synchronize()
+        rep = dmet.dmet_profile_report()
+    finally:
+        dmet.dmet_profile_enable(False)
+        dmet.dmet_profile_reset()
+    assert rep[f"contract_s8_{prec}"][0] == 2 and rep[f"contract_s4_{prec}"][0] == 1, rep
 
 
 @pytest.mark.parametrize("name", ["fft_tiny", "fft_odd", "fft_hex"])
