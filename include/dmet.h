@@ -53,7 +53,9 @@
  * the file of the batched autotuner's choices; DMET_I8_CHUNK_ROWS=n (a
  * multiple of 64 up to 44032, the default) sets the rows per launch of the
  * int8 contraction; DMET_ROW_SPLIT=0 turns off the row split of the
- * split-bf16 contraction of few-tile blocks on the plane-wave route.
+ * split-bf16 contraction of few-tile blocks on the plane-wave route;
+ * DMET_F64_SPLIT_WG=n (default 2048) is the workgroup count the FP64
+ * contraction's row split aims at when a block has few output tiles.
  */
 #ifndef DMET_H
 #define DMET_H

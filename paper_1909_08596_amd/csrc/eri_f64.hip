@@ -361,13 +361,17 @@ constexpr int X2_BM = 64, X2_BN = 64, X2_BK = 16;
 static inline int f64_ldz(int npair) { return (npair + 1) / 2 * 2; }
 static inline int f64_krows_p(int krows) { return (krows + R_BK - 1) / R_BK * R_BK; }
 
-// split of the row range for the tile counts of s8 and s4 (at least ~512
-// workgroups, at least 32 stages per split)
+// split of the row range for the tile counts of s8 and s4: at least about
+// DMET_F64_SPLIT_WG workgroups (default 2048, four rounds of the two per CU;
+// on 66 tiles over 65536 rows 512 / 1024 / 2048 / 4096 took 3.79 / 2.97 /
+// 2.82 / 2.84 ms), at least 32 stages per split
 static void f64_split(int npair, int krows_p, int mode, int& nsplit, int& kchunk) {
     const long ntile = (npair + R_BM - 1) / R_BM;
     const long tiles = mode == 0 ? ntile * (ntile + 1) / 2 : ntile * ntile;
     const int stages = krows_p / R_BK;
-    long s = (512 + tiles - 1) / tiles;
+    const char* e = getenv("DMET_F64_SPLIT_WG");
+    const long target = e ? std::max(1, atoi(e)) : 2048;
+    long s = (target + tiles - 1) / tiles;
     s = std::min<long>(s, std::max(1, stages / 32));
     nsplit = (int)std::max<long>(1, s);
     kchunk = (stages + nsplit - 1) / nsplit * R_BK;
