@@ -154,7 +154,7 @@ def host_info():
     return model, mem
 
 
-def cpu_baseline(wl, lat, lm, n_l, n_rows, imp_idx=None, val_idx=None, w_flop=None):
+def cpu_baseline(wl, lat, lm, n_l, n_rows, imp_idx=None, val_idx=None, w_flop=None, one_thread=False):
     """Time the FP64 oracle on a bounded sample of the same workload, phase by
     phase, and extrapolate its time for the whole workload:
 
@@ -169,28 +169,35 @@ def cpu_baseline(wl, lat, lm, n_l, n_rows, imp_idx=None, val_idx=None, w_flop=No
       blocks (aa, or aa, bb and ab).
 
     ``value`` = W / t_oracle(extrapolated) on the same useful-work convention W
-    as the GPU's value; the sample's own executed rate is reported too."""
-    from threadpoolctl import threadpool_info
+    as the GPU's value; the sample's own executed rate is reported too.  With
+    one_thread (the small workloads) the same sample is timed again with the
+    BLAS held to one thread."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import kspace as ok
-    t0 = time.perf_counter()
-    bath = ok.build_bath(lat.dm_k, wl.kmesh, wl.nao, imp_idx=imp_idx, val_idx=val_idx)
-    t1 = time.perf_counter()
-    ok.transform_1e(bath["c_k"], lat.h_k)
-    ok.transform_1e(bath["c_k"], lat.dm_k)
-    t2 = time.perf_counter()
-    ck = bath["c_k"][0]
-    sub = lm[:, :, :n_l]
-    t3 = time.perf_counter()
-    x = ok.alg1_embedded_3index(sub, ck, wl.kmesh, 0)
-    t4 = time.perf_counter()
-    xm = x.reshape(n_l, -1)
-    e = (xm[:, :n_rows].conj().T @ xm) / wl.nk
-    t5 = time.perf_counter()
-    del e
     n = wl.neo
     nblocks = 3 if wl.nspin == 2 else 1
-    t_tr = (t4 - t3) * wl.nk * (wl.naux / n_l) * wl.nspin
-    t_co = (t5 - t4) * (n * n / n_rows) * (wl.naux / n_l) * wl.nk * nblocks
+
+    def sample():
+        t0 = time.perf_counter()
+        bath = ok.build_bath(lat.dm_k, wl.kmesh, wl.nao, imp_idx=imp_idx, val_idx=val_idx)
+        t1 = time.perf_counter()
+        ok.transform_1e(bath["c_k"], lat.h_k)
+        ok.transform_1e(bath["c_k"], lat.dm_k)
+        t2 = time.perf_counter()
+        ck = bath["c_k"][0]
+        sub = lm[:, :, :n_l]
+        t3 = time.perf_counter()
+        x = ok.alg1_embedded_3index(sub, ck, wl.kmesh, 0)
+        t4 = time.perf_counter()
+        xm = x.reshape(n_l, -1)
+        e = (xm[:, :n_rows].conj().T @ xm) / wl.nk
+        t5 = time.perf_counter()
+        del e
+        t_tr = (t4 - t3) * wl.nk * (wl.naux / n_l) * wl.nspin
+        t_co = (t5 - t4) * (n * n / n_rows) * (wl.naux / n_l) * wl.nk * nblocks
+        return t0, t1, t2, t3, t4, t5, t_tr, t_co
+
+    t0, t1, t2, t3, t4, t5, t_tr, t_co = sample()
     t_all = (t1 - t0) + (t2 - t1) + t_tr + t_co
     flops = 8.0 * wl.nk * n_l * (wl.nao * wl.nao * n + wl.nao * n * n) + 8.0 * n_l * n_rows * n * n
     info = threadpool_info()
@@ -206,7 +213,36 @@ def cpu_baseline(wl, lat, lm, n_l, n_rows, imp_idx=None, val_idx=None, w_flop=No
                         "transform_extrapolated": round(t_tr, 1), "contraction_extrapolated": round(t_co, 1)},
            "sample_rate_TFLOPs": round(flops / ((t5 - t3)) / 1e12, 4), "blas": blas}
     out["value"] = (w_flop / t_all / 1e12) if w_flop else out["sample_rate_TFLOPs"]
+    if one_thread:
+        with threadpool_limits(limits=1):
+            u0, u1, u2, u3, u4, u5, u_tr, u_co = sample()
+        u_all = (u1 - u0) + (u2 - u1) + u_tr + u_co
+        out["one_thread"] = {"seconds": round(u5 - u0, 3), "extrapolated_s": round(u_all, 2),
+                             "phases_s": {"bath": round(u1 - u0, 3), "onebody": round(u2 - u1, 3),
+                                          "transform_extrapolated": round(u_tr, 2),
+                                          "contraction_extrapolated": round(u_co, 2)}}
     return out
+
+
+def hbm_copy_rate(dev, gib=2.0, reps=5):
+    """HBM rate of a plain device-to-device copy measured on this GPU: bytes
+    read plus bytes written per second (TB/s), for comparison with the 8 TB/s
+    spec that the rooflines use."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(st)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3
+    del a, b
+    return round(2.0 * 4 * n * reps / t / 1e12, 3)
 
 
 def run_batched(args, dev):
@@ -565,6 +601,7 @@ def main():
     print(f"[bench] DF output {t_df:.2f} ms, double-counting Fock and mean-field energy {t_dc:.2f} ms "
           f"(E_mf = {float(e_mf.cpu()):.10f})", file=sys.stderr, flush=True)
     del z, ws_df, ft
+    hbm_tbs = hbm_copy_rate(dev)
 
     wt, wc = work_counts(wl)
     ms, wall, prof, _, eri_ms = results[args.precision]
@@ -607,6 +644,7 @@ def main():
         "bath_ms": round(t_bath, 3), "onebody_ms": round(t_1e, 3),
         "df_output_ms": round(t_df, 3), "fock_dc_ms": round(t_dc, 3),
         "h2d_s": round(t_h2d, 2), "h2d_GBps": round(lm.nbytes / 1e9 / t_h2d, 2),
+        "hbm_copy_TBs_measured": hbm_tbs,
     }
     if len(forms) > 1:
         cmp = {}
@@ -631,7 +669,7 @@ def main():
         n_l = args.cpu_sample_l or max(1, wl.naux // 2)
         line["cpu_baseline"] = cpu_baseline(wl, lat, lm, min(n_l, wl.naux),
                                             min(args.cpu_sample_rows, wl.neo * wl.neo), imp_idx, val_idx,
-                                            w_flop=wt + wc)
+                                            w_flop=wt + wc, one_thread=wl.name in ("tiny", "hbn"))
         model, mem = host_info()
         line["cpu_baseline"]["host"] = {"model": model, "os_cpu_count": os.cpu_count(), "ram_gb": mem}
     print(json.dumps(line), flush=True)
