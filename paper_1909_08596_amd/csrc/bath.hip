@@ -71,10 +71,15 @@ __device__ inline int rr_player(int seat, int round, int n) {
 // pairs of a round are disjoint, so a round is one launch).  The three dot
 // products are reduced over the block in a fixed order; rot[s] counts the
 // rotations applied (a sweep with none has converged: |a.b| <= tol |a||b|
-// for every pair).
+// for every pair).  A sweep after one with no rotation for spin s (prev[s] ==
+// 0; prev null in the first sweep) would apply none either and returns at
+// once, and so does every sweep when the density was not finite: the host can
+// enqueue several sweeps between its reads of the counts.
 __global__ void __launch_bounds__(256) k_jacobi_round(int m, int n, int np, int round,
-                                                      double* __restrict__ mt, double tol, int* rot) {
+                                                      double* __restrict__ mt, double tol, int* rot,
+                                                      const int* __restrict__ prev, const int* __restrict__ flags) {
     const int pr = blockIdx.x, s = blockIdx.y;
+    if ((prev && prev[s] == 0) || (flags[0] & FLAG_NONFINITE)) return;
     const int ca = rr_player(pr, round, np), cb = rr_player(np - 1 - pr, round, np);
     if (ca >= n || cb >= n) return;   // the dummy column of an odd count (whole block)
     double* a = mt + ((size_t)s * n + ca) * m;
@@ -153,10 +158,13 @@ constexpr int jb_maxm(int jb) { return JB_LDS / (2 * jb * 8) / 2 * 2; }   // row
 
 template <int JB>
 __global__ void __launch_bounds__(64 * JB) k_jacobi_block(int m, int n, int nbp, int round,
-                                                          double* __restrict__ mt, double tol, int* rot) {
+                                                          double* __restrict__ mt, double tol, int* rot,
+                                                          const int* __restrict__ prev,
+                                                          const int* __restrict__ flags) {
     extern __shared__ __align__(16) double colsh[];   // [2 JB][mp], rows m..mp-1 zero
     const int mp = m + (m & 1);                        // even stride: rows move in pairs
     const int pr = blockIdx.x, s = blockIdx.y;
+    if ((prev && prev[s] == 0) || (flags[0] & FLAG_NONFINITE)) return;   // as in k_jacobi_round
     const int nb = (n + JB - 1) / JB;
     const int ba = rr_player(pr, round, nbp), bb = rr_player(nbp - 1 - pr, round, nbp);
     auto colof = [&](int e) {   // column of slot e, or n if it takes no part
@@ -406,9 +414,12 @@ struct BathPlan {
     int nao, nspin, nimp, nval, nenv, ldc, nsup;
 };
 
+constexpr int BATH_MAX_SWEEPS = 60;
+
 struct BathWs {
     double* dm_r;
-    int* flags;        // [0] status bits, [4+s] kept bath, [8+s] rotations of the current sweep
+    int* flags;        // [0] status bits, [4+s] kept bath
+    int* rots;         // [sweep][s] rotations applied by each sweep (at most BATH_MAX_SWEEPS)
     double* scal;      // [0] max |Im gamma^R|, [1] max |S - I|
     int* env;
     int* cols;
@@ -425,11 +436,13 @@ static BathWs carve_bath(Carve& cv, const BathPlan& p, bool with_ao_lo) {
     BathWs w;
     w.dm_r = cv.take<double>((size_t)p.nspin * p.mesh.nk * p.nao * p.nao);
     w.flags = cv.take<int>(16);
+    w.rots = cv.take<int>(2 * BATH_MAX_SWEEPS);
     w.scal = cv.take<double>(4);
-    w.env = cv.take<int>(p.nenv);
-    w.cols = cv.take<int>(p.nval);
-    w.imp = cv.take<int>(p.nimp);
-    w.envpos = cv.take<int>(p.nsup);
+    // the four index lists back to back: one upload
+    w.env = cv.take<int>((size_t)p.nenv + p.nval + p.nimp + p.nsup);
+    w.cols = w.env + p.nenv;
+    w.imp = w.cols + p.nval;
+    w.envpos = w.imp + p.nimp;
     w.mt = cv.take<double>((size_t)p.nspin * p.nval * p.nenv);
     w.ub = cv.take<double>((size_t)p.nspin * p.nval * p.nenv);
     w.emat = cv.take<double>((size_t)p.nspin * p.nval * p.nval);
@@ -496,32 +509,29 @@ dmet_status build_bath(const dmet_lattice* lat, const double2* dm_k, int nimp, c
     BathWs w = carve_bath(cv, p, c_ao_lo != nullptr);
     if (cv.bytes() > ws_bytes) return fail(DMET_E_WORKSPACE, "build_bath workspace too small");
 
-    if (!env.empty())
-        DMET_HIP(hipMemcpyAsync(w.env, env.data(), sizeof(int) * env.size(), hipMemcpyHostToDevice, st));
-    DMET_HIP(hipMemcpyAsync(w.cols, cols.data(), sizeof(int) * nval, hipMemcpyHostToDevice, st));
-    DMET_HIP(hipMemcpyAsync(w.imp, imp.data(), sizeof(int) * nimp, hipMemcpyHostToDevice, st));
-    DMET_HIP(hipMemcpyAsync(w.envpos, envpos.data(), sizeof(int) * p.nsup, hipMemcpyHostToDevice, st));
+    {
+        std::vector<int> lists;
+        lists.reserve(env.size() + cols.size() + imp.size() + envpos.size());
+        for (const std::vector<int>* v : {&env, &cols, &imp, &envpos}) lists.insert(lists.end(), v->begin(), v->end());
+        DMET_HIP(hipMemcpyAsync(w.env, lists.data(), sizeof(int) * lists.size(), hipMemcpyHostToDevice, st));
+    }
     fill_zero(w.flags, 16 * sizeof(int), st);
+    fill_zero(w.rots, 2 * BATH_MAX_SWEEPS * sizeof(int), st);
     fill_zero(w.scal, 4 * sizeof(double), st);
 
     const int nn = p.nao * p.nao;
     k_dm_real<<<dim3((nn + 255) / 256, p.mesh.nk, p.nspin), 256, 0, st>>>(p.mesh, p.nao, dm_k, w.dm_r,
                                                                           w.flags, w.scal);
     DMET_LAUNCH_CHECK("k_dm_real");
-    {   // a non-finite density is reported before the SVD sweeps would spin on it
-        int f0 = 0;
-        DMET_HIP(hipMemcpyAsync(&f0, w.flags, sizeof(int), hipMemcpyDeviceToHost, st));
-        DMET_HIP(hipStreamSynchronize(st));
-        if (f0 & FLAG_NONFINITE) return fail(DMET_E_NONFINITE, "non-finite entry in dm_k");
-    }
     if (p.nenv > 0) {
         k_build_m<<<dim3((p.nenv + 255) / 256, nval, p.nspin), 256, 0, st>>>(
             p.mesh, p.nao, p.nenv, nval, w.env, w.cols, w.dm_r, w.mt);
         DMET_LAUNCH_CHECK("k_build_m");
     }
     if (p.nenv > 0) {
-        // sweeps of np - 1 rounds until a sweep applies no rotation (the
-        // rotation counts of the sweep are read back, at most 60 sweeps)
+        // sweeps of np - 1 rounds until a sweep applies no rotation, at most
+        // 60; the counts are read back after six sweeps, then after every two
+        // (a sweep that follows one without rotation returns at once)
         const double tol = fmax(1e-15, sqrt((double)p.nenv) * 2.220446049250313e-16);
         const int np = nval + (nval & 1);
         // block form when the 2 JB columns of a block pair fit in LDS
@@ -532,35 +542,45 @@ dmet_status build_bath(const dmet_lattice* lat, const double2* dm_k, int nimp, c
         const size_t lds = (size_t)2 * JB * mp * sizeof(double);
         const void* kblk = JB == 8 ? (const void*)k_jacobi_block<8> : (const void*)k_jacobi_block<4>;
         if (blocked) DMET_HIP(hipFuncSetAttribute(kblk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        int* rot = w.flags + 8;
         bool converged = false;
         // at most 60 sweeps; DMET_SVD_MAX_SWEEPS lowers the limit (to force the
         // non-convergence status from the host)
-        int max_sweeps = 60;
-        if (const char* e = getenv("DMET_SVD_MAX_SWEEPS")) max_sweeps = std::min(60, std::max(1, atoi(e)));
-        for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
-            fill_zero(rot, 2 * sizeof(int), st);
-            if (blocked) {
-                for (int round = 0; round < nbp - 1; ++round) {
-                    if (JB == 8)
-                        k_jacobi_block<8><<<dim3(nbp / 2, p.nspin), 512, lds, st>>>(p.nenv, nval, nbp, round, w.mt,
-                                                                                    tol, rot);
-                    else
-                        k_jacobi_block<4><<<dim3(nbp / 2, p.nspin), 256, lds, st>>>(p.nenv, nval, nbp, round, w.mt,
-                                                                                    tol, rot);
+        int max_sweeps = BATH_MAX_SWEEPS;
+        if (const char* e = getenv("DMET_SVD_MAX_SWEEPS"))
+            max_sweeps = std::min(BATH_MAX_SWEEPS, std::max(1, atoi(e)));
+        for (int s0 = 0; s0 < max_sweeps && !converged;) {
+            const int s1 = std::min(max_sweeps, s0 + (s0 == 0 ? 6 : 2));
+            for (int sweep = s0; sweep < s1; ++sweep) {
+                int* rot = w.rots + 2 * sweep;
+                const int* prev = sweep > 0 ? w.rots + 2 * (sweep - 1) : nullptr;
+                if (blocked) {
+                    for (int round = 0; round < nbp - 1; ++round) {
+                        if (JB == 8)
+                            k_jacobi_block<8><<<dim3(nbp / 2, p.nspin), 512, lds, st>>>(
+                                p.nenv, nval, nbp, round, w.mt, tol, rot, prev, w.flags);
+                        else
+                            k_jacobi_block<4><<<dim3(nbp / 2, p.nspin), 256, lds, st>>>(
+                                p.nenv, nval, nbp, round, w.mt, tol, rot, prev, w.flags);
+                    }
+                    DMET_LAUNCH_CHECK("k_jacobi_block");
+                } else {
+                    for (int round = 0; round < np - 1; ++round)
+                        k_jacobi_round<<<dim3(np / 2, p.nspin), 256, 0, st>>>(p.nenv, nval, np, round, w.mt, tol,
+                                                                               rot, prev, w.flags);
+                    DMET_LAUNCH_CHECK("k_jacobi_round");
                 }
-                DMET_LAUNCH_CHECK("k_jacobi_block");
-            } else {
-                for (int round = 0; round < np - 1; ++round)
-                    k_jacobi_round<<<dim3(np / 2, p.nspin), 256, 0, st>>>(p.nenv, nval, np, round, w.mt, tol, rot);
-                DMET_LAUNCH_CHECK("k_jacobi_round");
             }
-            int h_rot[2] = {0, 0};
-            DMET_HIP(hipMemcpyAsync(h_rot, rot, sizeof(int) * p.nspin, hipMemcpyDeviceToHost, st));
+            int h_rot[2 * BATH_MAX_SWEEPS], f0 = 0;
+            DMET_HIP(hipMemcpyAsync(h_rot, w.rots + 2 * s0, sizeof(int) * 2 * (s1 - s0), hipMemcpyDeviceToHost, st));
+            DMET_HIP(hipMemcpyAsync(&f0, w.flags, sizeof(int), hipMemcpyDeviceToHost, st));
             DMET_HIP(hipStreamSynchronize(st));
-            converged = true;
-            for (int sp = 0; sp < p.nspin; ++sp)
-                if (h_rot[sp] != 0) converged = false;
+            if (f0 & FLAG_NONFINITE) return fail(DMET_E_NONFINITE, "non-finite entry in dm_k");
+            for (int sweep = s0; sweep < s1 && !converged; ++sweep) {
+                converged = true;
+                for (int sp = 0; sp < p.nspin; ++sp)
+                    if (h_rot[2 * (sweep - s0) + sp] != 0) converged = false;
+            }
+            s0 = s1;
         }
         if (!converged)
             return fail(DMET_E_NOCONV, "Jacobi SVD did not converge in " + std::to_string(max_sweeps) + " sweeps");
