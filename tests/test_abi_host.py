@@ -164,6 +164,36 @@ def test_fftdf_argument_validation(lib):
                                                       ctypes.byref(nb)) == 7   # DMET_E_UNSUPPORTED
 
 
+def test_fftdf_row_split_workspace(lib, monkeypatch):
+    """A few-tile plane-wave block has its split-bf16 contraction split over the
+    rows into partial outputs kept in the workspace (added in row order
+    afterwards).  At the benchmark's plane-wave shape (2x2x2 mesh, 16^3 grid,
+    52 EOs: 36 output tiles of 128 x 256 for 65536 rows, so 256 // 36 = 7 splits)
+    the workspace holds exactly seven packed outputs more than with the split
+    turned off (DMET_ROW_SPLIT=0), up to the 256-byte alignment of its regions;
+    the FP64 form is not affected."""
+    from paper_1909_08596_amd import dmet
+    lat = _lat(kmesh=(2, 2, 2), nao=26, naux=16 ** 3)
+    grid = dmet.pw_grid((16, 16, 16), (5.1, 5.1, 5.1))
+
+    def ws(prec):
+        nb = ctypes.c_size_t()
+        assert lib.dmet_transform_eri_fftdf_workspace(ctypes.byref(lat), ctypes.byref(grid), 52, 0, prec,
+                                                      ctypes.byref(nb)) == 0
+        return nb.value
+
+    forms = (dmet.DMET_BF16X6_3M, dmet.DMET_BF16X3_3M)
+    split = [ws(p) for p in forms]
+    f64 = ws(dmet.DMET_FP64)
+    monkeypatch.setenv("DMET_ROW_SPLIT", "0")
+    one = [ws(p) for p in forms]
+    assert ws(dmet.DMET_FP64) == f64
+    npair = 52 * 53 // 2
+    slices = 7 * (npair * (npair + 1) // 2) * 8
+    for a, b in zip(split, one):
+        assert 0 <= (a - b) - slices < 256, (a - b, slices)
+
+
 def test_binding_rejects_mismatched_shapes():
     """The ctypes binding checks every tensor's extent against kmesh, nao,
     naux and neo before calling the library (a wrong shape would otherwise
