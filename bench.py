@@ -33,6 +33,10 @@ PEAK_I8 = 5000.0   # dense int8 MFMA TOP/s (MI355X spec): the peak of the int8 c
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "bf16x6": "bf16x6", "bf16x6_i8": "bf16x6+int8x3"}
 
 
+def _nk3(kmesh):
+    return int(kmesh[0]) * int(kmesh[1]) * int(kmesh[2])
+
+
 def kernel_peak(prec, name):
     """Dense MFMA peak of the dtype the named kernel multiplies in."""
     return PEAK_I8 if name.endswith("_i8") else PEAK[prec]
@@ -297,6 +301,7 @@ def run_batched(args, dev):
     print(f"[bench] batched fp64: {ms_64:.2f} ms", file=sys.stderr, flush=True)
     for prec in forms:
         ws = torch.empty(dmet.dmet_transform_eri_batched_workspace(frags, prec), dtype=torch.uint8, device=dev)
+        ws_b = ws
         for _ in range(max(1, args.warmup)):
             dmet.dmet_transform_eri_batched(frags, prec, graph=True, autotune=True, workspace=ws)
         torch.cuda.synchronize()
@@ -334,9 +339,29 @@ def run_batched(args, dev):
                      "speedup_batched_vs_loop": round(ms_l / ms_b, 3),
                      "TFLOP/s": round(wsum / (ms_b * 1e-3) / 1e12, 3), "batched_equals_loop": bool(same),
                      "speedup_vs_fp64": round(ms_64 / ms_b, 3), "max_abs_err_vs_fp64": err64}
+        # one eager submission with the library's phase timing (a graph replay is one span), and the
+        # contraction phase against its MFMA peak: algorithmic flops summed over the fragments
+        dmet.dmet_profile_reset()
+        dmet.dmet_profile_enable(True)
+        dmet.dmet_transform_eri_batched(frags, prec, graph=False, autotune=True, workspace=ws_b)
+        torch.cuda.synchronize()
+        dmet.dmet_profile_enable(False)
+        prof = dmet.dmet_profile_report()
+        out[prec]["phases_ms_eager"] = {k: round(v[1], 3) for k, v in prof.items()}
+        cname = [k for k in prof if k.startswith("batch_contract")]
+        if cname:
+            t_c = prof[cname[0]][1]
+            w_c = sum(_nk3(f["kmesh"]) * f["naux"] * (n * (n + 1) // 2) * (n * (n + 1) // 2 + 1.0)
+                      for f in frags for n in [f["c_k"].shape[-1]])
+            peak = PEAK_I8 if prec == "bf16x6_i8" else PEAK[prec]
+            ach = w_c / (t_c * 1e-3) / 1e12
+            out[prec]["contraction_roofline"] = {
+                "bound": "mfma", "kernel": cname[0], "ms": round(t_c, 3), "flop": w_c, "achieved": round(ach, 3),
+                "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+                "mfma_util": round(ach * MFMA_PRODUCTS[prec] / peak, 4), "traffic": None}
         print(f"[bench] batched {prec}: {ms_b:.2f} ms vs loop {ms_l:.2f} ms; equal={same}; "
               f"{ms_64 / ms_b:.2f}x fp64, max err {err64:.2e}", file=sys.stderr, flush=True)
-        del ws, loop_ws
+        del ws, ws_b, loop_ws
     head = out[args.precision]
     line = {
         "metric": METRIC, "value": head["TFLOP/s"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
@@ -348,6 +373,8 @@ def run_batched(args, dev):
                                f"supercell impurities, 3-index complex64", "W_flop": wsum},
         "forms": out, "bath_s_all_fragments": round(t_bath, 3),
     }
+    if "contraction_roofline" in head:
+        line["roofline"] = head["contraction_roofline"]
     print(json.dumps(line), flush=True)
 
 
